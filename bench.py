@@ -1,0 +1,206 @@
+"""Throughput of the Kalman-MPC hot path on one MI355X.
+
+One step = one closed-loop MPC step: a full solve (Algorithm 1: rollout, means,
+pooled statistics, FP64 gain, analysis of every stored slice) through the C ABI
+with device-resident inputs and device-generated noise, followed by the plant
+step X_{k+1} = CNN(X_k, U_hat_k).  Default workload: 64x64 field, l = 8, CNN
+2-16-16-1 (tanh), N = 128 members, horizon H = 10, FP32.
+
+Prints one JSON line: metric member-steps/s (= N H solves/s), with solves/s,
+p50/p99 solve latency, the roofline of the dominant kernel class (from HIP
+events recorded by the library on its stream over the timed region) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"hbm": 8.0e12, "fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15}
+
+
+def workload_name(p):
+    ch = "-".join(str(c) for c in p.channels)
+    act = "tanh" if p.activation == 0 else "gelu"
+    return (f"{p.name}: {p.n}x{p.m} field, l={p.l}, CNN {ch} ({act}), N={p.N}, H={p.H}, "
+            f"closed-loop MPC steps")
+
+
+def algorithmic_work(p, H):
+    """Per kernel class: (FLOP, HBM bytes) the method needs in one solve, summed over
+    the launches of that class.  FLOP counts multiply-adds as 2."""
+    n, m, l, N = p.n, p.m, p.l, p.N
+    rr = pp = n + l
+    NM = N * m
+    work = {}
+
+    def add(k, f, b):
+        f0, b0 = work.get(k, (0.0, 0.0))
+        work[k] = (f0 + f, b0 + b)
+
+    L = len(p.channels) - 1
+    for t in range(1, H + 1):
+        Ma = (t + 1) * rr
+        for k, (ci, co) in enumerate(zip(p.channels[:-1], p.channels[1:])):
+            cls = "conv_first" if k == 0 else ("conv_last" if k == L - 1 else "conv_mid")
+            add(cls, 2.0 * 9 * ci * co * n * m * N, 4.0 * n * m * N * (ci + co))
+        add("stats", 2.0 * (Ma + pp) * pp * NM, 4.0 * (Ma + pp) * NM)
+        add("update", 2.0 * Ma * pp * NM, 4.0 * (2 * Ma + pp) * NM)
+        add("means", float(Ma + pp) * NM, 4.0 * (Ma + pp) * NM)
+        add("gain", pp ** 3 / 3.0 + 2.0 * pp * pp * Ma, 8.0 * (Ma + pp) * pp)
+    return work
+
+
+def roofline_for(cls, flops, nbytes, ms, launches, precision):
+    sec = ms * 1e-3
+    fpeak = PEAK["fp64"] if cls in ("stats", "gain") else (
+        PEAK["bf16"] if (precision == "bf16" and cls.startswith("conv")) else PEAK["fp32"])
+    t_f = flops / fpeak
+    t_b = nbytes / PEAK["hbm"]
+    if t_b > t_f:
+        ach = nbytes / sec / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": ach / (PEAK["hbm"] / 1e9), "traffic": None, "kernel_class": cls,
+                "launches": launches, "avg_launch_us": 1e3 * ms / max(launches, 1)}
+    ach = flops / sec / 1e12
+    kind = "mfma" if cls.startswith("conv") and precision == "bf16" else "alu"
+    return {"bound": kind, "achieved": ach, "peak": fpeak / 1e12, "unit": "TFLOP/s",
+            "frac": ach / (fpeak / 1e12), "traffic": None, "kernel_class": cls,
+            "launches": launches, "avg_launch_us": 1e3 * ms / max(launches, 1)}
+
+
+def cpu_baseline(p, prob, seconds_budget=25.0):
+    """The FP64 oracle on the host cores: closed-loop solves of the same workload
+    until about `seconds_budget` seconds of work (at least one)."""
+    from oracle import enks, philox
+    from paper_2410_09663_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = len(os.sched_getaffinity(0))
+    X = prob.X0.astype(np.float64)
+    Up = np.zeros((p.l, p.m))
+    t0 = time.perf_counter()
+    solves = 0
+    first = None
+    while True:
+        z = philox.solve_noise(p.noise_seed_base + solves, p.n, p.m, p.l, p.N, p.H)
+        res = enks.solve(prob.B, prob.weights, p.activation, X, wl.reference_window(p, solves),
+                         prob.Q, prob.Q, prob.R, p.N, p.H, *z, U_prev=Up)
+        if first is None:
+            first = res
+        Up = res.U_mean[0]
+        X = enks.plant_step(X, Up, prob.B, prob.weights, p.activation)
+        solves += 1
+        if time.perf_counter() - t0 > seconds_budget or solves >= 20:
+            break
+    el = time.perf_counter() - t0
+    return {"value": p.N * p.H * solves / el, "unit": "member-steps/s", "cores": int(threads),
+            "kind": "oracle", "solves_per_s": solves / el,
+            "sample": f"{solves} closed-loop solve(s) of the same workload, FP64 NumPy, "
+                      f"{el:.1f} s wall"}, first
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(member sharding over several GPUs is a design, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2410_09663_amd import oic
+    from paper_2410_09663_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    p = wl.PRESETS[args.workload]
+    prec = oic.OIC_PREC_BF16 if args.precision == "bf16" else oic.OIC_PREC_FP32
+    prob = wl.make_problem(p)
+    K, W = args.steps, args.warmup
+    refs = torch.from_numpy(np.stack([wl.reference_window(p, k) for k in range(W + K + 1)])).to(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctrl = oic.controller_for(prob, precision=prec, mem_mode=oic.OIC_MEM_DEVICE, stream=stream)
+    X0 = torch.from_numpy(prob.X0).to(dev)
+    Ubuf = torch.empty((p.H + 1, p.l, p.m), dtype=torch.float32, device=dev)
+
+    def step(k, X):
+        ctrl.solve(X, refs[k], prob.Q, prob.R, p.N, p.H, p.noise_seed_base + k, U_out=Ubuf)
+        return ctrl.plant_step(X, Ubuf[0])
+
+    X = X0
+    for k in range(W):
+        X = step(k, X)
+    torch.cuda.synchronize()
+    ctrl.timing(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(W, W + K):
+        ts = time.perf_counter()
+        X = step(k, X)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stats = ctrl.kernel_stats()
+    ctrl.timing(False)
+
+    work = algorithmic_work(p, p.H)
+    per_class = {}
+    for cls, (cnt, ms) in stats.items():
+        if cnt == 0:
+            continue
+        f, b = work.get(cls, (0.0, 0.0))
+        per_class[cls] = {"launches": cnt, "total_ms": ms, "flop": f * K, "bytes": b * K}
+    dom = max((c for c in per_class if c in work), key=lambda c: per_class[c]["total_ms"])
+    d = per_class[dom]
+    roof = roofline_for(dom, d["flop"], d["bytes"], d["total_ms"], d["launches"], args.precision)
+
+    lat_ms = np.array(lat) * 1e3
+    solves_per_s = K / el
+    out = {
+        "metric": "member-steps/s", "value": p.N * p.H * solves_per_s, "unit": "member-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * el / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == oic.OIC_PREC_FP32 else "bf16", "data": "synthetic",
+        "config": {"workload": workload_name(p), "n": p.n, "m": p.m, "l": p.l, "N": p.N, "H": p.H,
+                   "channels": p.channels, "precision": args.precision},
+        "solves_per_s": solves_per_s, "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "roofline": roof,
+        "kernel_ms_per_solve": {c: v["total_ms"] / K for c, v in sorted(per_class.items())},
+    }
+    if not args.no_cpu_baseline:
+        cb, first = cpu_baseline(p, prob, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        # parity of the first closed-loop solve of the same stream, for the record
+        c2 = oic.controller_for(prob, precision=prec)
+        U, _ = c2.solve(prob.X0, wl.reference_window(p, 0), prob.Q, prob.R, p.N, p.H,
+                        p.noise_seed_base)
+        c2.close()
+        out["relerr_U_vs_fp64_oracle"] = float(np.linalg.norm(U - first.U_mean) /
+                                               np.linalg.norm(first.U_mean))
+    ctrl.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

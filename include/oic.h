@@ -1,0 +1,175 @@
+/*
+ * oic.h - C ABI of liboic, the MI355X (gfx950) Kalman-MPC library.
+ *
+ * Kalman-MPC ("Optimal Inferential Control of Convolutional Neural Networks",
+ * Vaziri & Fang, Algorithm 1) controls a CNN surrogate X_{k+1} = CNN(X_k, U_k)
+ * (Eq. (1)) by recasting the reference-tracking MPC problem (Eq. (3)) as state
+ * smoothing of a virtual system (Eqs. (4)-(5)) and solving that with a
+ * single-pass ensemble Kalman smoother over matrix-valued members
+ * (Eqs. (11)-(15)).  One call of oic_solve is one MPC solve at one time k.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are row-major FP32.  The state X is n x m, the control U is l x m.
+ *  - The CNN takes two input channels, X and B U (B is n x l), applies
+ *    zero-padded 3x3 cross-correlations with the chosen activation between
+ *    layers (none after the last) and returns one channel, the next state.
+ *  - R (n x n) is the row covariance of the state observation noise V_X; Q
+ *    (l x l) is the row covariance of both the control-increment noise W and
+ *    the control observation noise V_U (the paper's Q_dU and Q_U taken equal);
+ *    the column covariance is the identity.  The control reference U^ref is 0.
+ *    R and Q are always HOST pointers; they are factorised on the host in FP64.
+ *  - Weights and B are always HOST pointers; the library copies them.
+ *  - Every other array argument is a host pointer when the handle was created
+ *    with OIC_MEM_HOST and a device pointer (on the handle's device) with
+ *    OIC_MEM_DEVICE; device-pointer work is ordered on the handle's stream.
+ *  - The caller owns every buffer it passes; the library keeps no pointer to
+ *    caller memory after a call returns.
+ *  - Return values: OIC_OK (0) or a negative error code.  On error no output
+ *    buffer is written and oic_last_error(h) describes the reason.  No C++
+ *    exception crosses the ABI.
+ *  - A handle is not thread-safe: one handle per controller per thread.  The
+ *    same inputs, seed and precision give bitwise-identical outputs.
+ */
+#ifndef OIC_H
+#define OIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OIC_OK 0
+#define OIC_EINVAL (-1)   /* bad dimension, pointer, non-finite input, or weights not set */
+#define OIC_ENOMEM (-2)   /* device allocation failed or the request exceeds the handle's capacity */
+#define OIC_EDEVICE (-3)  /* a HIP runtime call failed */
+#define OIC_ENOTSPD (-4)  /* Sigma^Ybar was not positive definite at some horizon step */
+
+#define OIC_ACT_TANH 0
+#define OIC_ACT_GELU 1    /* exact form 0.5 x (1 + erf(x / sqrt 2)) */
+
+#define OIC_PREC_FP32 0   /* rollout in FP32 */
+#define OIC_PREC_BF16 1   /* rollout in BF16 x BF16 products with FP32 accumulation */
+
+#define OIC_MEM_HOST 0
+#define OIC_MEM_DEVICE 1
+
+#define OIC_MAX_LAYERS 8
+
+typedef struct oic_ctx* oic_handle;
+
+/* Static description of one controller.  channels[0] must be 2 and
+ * channels[n_layers] must be 1; hidden widths are at most 128. */
+typedef struct {
+  int n, m, l;                            /* state n x m, control l x m; n, m >= 4; 1 <= l <= n */
+  int n_layers;                           /* 1..OIC_MAX_LAYERS */
+  int channels[OIC_MAX_LAYERS + 1];
+  int activation;                         /* OIC_ACT_* */
+  int precision;                          /* OIC_PREC_*; statistics stay FP32/FP64, the gain solve FP64 */
+  int max_N;                              /* largest ensemble size a solve may use (>= 2) */
+  int max_H;                              /* largest horizon a solve may use (>= 1) */
+  int mem_mode;                           /* OIC_MEM_HOST or OIC_MEM_DEVICE */
+  void* stream;                           /* hipStream_t to order work on, or NULL for a private stream */
+} oic_config;
+
+/* Create a handle and allocate all device memory a solve of up to max_N
+ * members and max_H steps needs.  *out receives the handle.  Errors:
+ * OIC_EINVAL for a bad config, OIC_ENOMEM, OIC_EDEVICE. */
+int oic_create(const oic_config* cfg, oic_handle* out);
+
+/* Release the handle and its device memory.  NULL-safe. */
+void oic_destroy(oic_handle h);
+
+/* Human-readable reason for the last error on this handle ("" if none).
+ * The string stays valid until the next call on the handle. */
+const char* oic_last_error(oic_handle h);
+
+/* Set the surrogate of Eq. (1).  B: n x l.  W[k]: layer k weights in
+ * [C_out][C_in][3][3] order.  bias: NULL, or bias[k] NULL or C_out floats.
+ * Host pointers, copied (and re-laid out or converted for the chosen
+ * precision) before return.  Errors: OIC_EINVAL for NULL or non-finite values. */
+int oic_set_weights(oic_handle h, const float* B, const float* const* W, const float* const* bias);
+
+/* The control applied before time k, U_{k-1} (l x m), which seeds the initial
+ * ensemble U_k^i = U_prev + W_0^i, dU_k^i = W_0^i (Algorithm 1, line 4).  It
+ * starts at zero and every successful solve sets it to the applied control
+ * U_hat_k (line 14).  Memory per mem_mode. */
+int oic_set_u_prev(oic_handle h, const float* U_prev);
+int oic_get_u_prev(oic_handle h, float* U_prev);
+
+/* One MPC solve at time k (Algorithm 1, lines 4-13).
+ *   X0:        n x m, the measured state X_k.
+ *   reference: (horizon+1) x n x m, X^ref_t for t = k..k+horizon.
+ *   Q, R:      l x l and n x n SPD (host).
+ *   N:         ensemble size, 2..max_N, with (N-1) m >= n + l.
+ *   horizon:   H, 1..max_H.
+ *   seed:      key of the Philox4x32-10 stream the noise is drawn from: the
+ *              normal with C-order index e in the (H, N, rows, m) array of noise
+ *              kind c (0: initial control spread, shape (N, l, m); 1: W_t; 2: V_X,t;
+ *              3: V_U,t) uses counter (e mod 2^32, e div 2^32, c, 0) and key
+ *              (seed mod 2^32, seed div 2^32); two 53-bit uniforms feed the
+ *              Box-Muller cosine branch in FP64, rounded to FP32.
+ *   U_out:     (horizon+1) x l x m, the smoothed control means U_hat_{k..k+H}.
+ *   X_out:     (horizon+1) x n x m smoothed state means, or NULL.
+ * Errors: OIC_EINVAL, OIC_ENOMEM (N or H beyond capacity), OIC_ENOTSPD, OIC_EDEVICE. */
+int oic_solve(oic_handle h, const float* X0, const float* reference, const float* Q,
+              const float* R, int N, int horizon, uint64_t seed, float* U_out, float* X_out);
+
+/* oic_solve with explicit noise.  When Z_init, Z_W, Z_VX and Z_VU are all
+ * non-NULL they are used instead of the seeded stream (standard normals,
+ * member-major: Z_init N x l x m; Z_W and Z_VU H x N x l x m; Z_VX H x N x n x m;
+ * index t-1 of the leading axis belongs to horizon step t).  They must be all
+ * NULL or all non-NULL.  U_prev, when non-NULL, replaces the handle's stored
+ * value for this solve (and is then overwritten by U_hat_k as usual). */
+typedef struct {
+  const float* X0;
+  const float* reference;
+  const float* Q;
+  const float* R;
+  int N;
+  int horizon;
+  uint64_t seed;
+  const float* U_prev;
+  const float* Z_init;
+  const float* Z_W;
+  const float* Z_VX;
+  const float* Z_VU;
+  float* U_out;
+  float* X_out;
+} oic_solve_args;
+
+int oic_solve_ex(oic_handle h, const oic_solve_args* a);
+
+/* The surrogate alone, Eq. (1), on `batch` independent fields:
+ * X: batch x n x m, U: batch x l x m, X_next: batch x n x m (memory per
+ * mem_mode).  batch <= max_N.  Runs the same rollout kernels a solve runs. */
+int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, float* X_next);
+
+/* The nominal plant of the closed loop (Algorithm 1, line 14): the applied
+ * control drives the surrogate itself, X_{k+1} = CNN(X_k, U_k).  Same as
+ * oic_cnn_forward with batch 1. */
+int oic_plant_step(oic_handle h, const float* X, const float* U, float* X_next);
+
+/* The normals of one noise kind of the seeded stream (see oic_solve), count
+ * values in C order from element index 0, written to `out` (memory per
+ * mem_mode).  count <= the handle's noise capacity. */
+int oic_normals(oic_handle h, uint64_t seed, int kind, size_t count, float* out);
+
+/* Per-kernel timing.  When enabled, every launch of the library's kernels is
+ * bracketed by HIP events on the handle's stream and its duration is added to
+ * its kernel class.  oic_kernel_stats reports, for class `id`
+ * (0 <= id < oic_kernel_class_count()), the class name, number of launches
+ * and total milliseconds since the last reset (oic_timing(h, 1) resets). */
+int oic_timing(oic_handle h, int enable);
+int oic_kernel_class_count(void);
+int oic_kernel_stats(oic_handle h, int id, const char** name, long long* launches, double* total_ms);
+
+/* Stream the handle orders its work on (a hipStream_t). */
+void* oic_stream(oic_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OIC_H */

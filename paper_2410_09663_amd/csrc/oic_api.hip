@@ -1,0 +1,624 @@
+// liboic: C ABI and host orchestration of one Kalman-MPC solve (Algorithm 1).
+//
+// Per solve, on one stream:
+//   init slice k (line 4)                      k_init_slice0
+//   for t = k+1..k+H (line 5):
+//     forecast X rows through the CNN (15b)   k_lift, conv layers (last one writes slice t)
+//     forecast U rows, U_t = U_{t-1} + W_t    k_assemble_u
+//     perturbed observations (12)             k_observe
+//     means of slices k..t and of Ybar (11)   k_means
+//     pooled cross-covariances (13b,c)        k_stats (+ split-K reduction)
+//     Cholesky + gain (14b)                   k_chol, k_gain_rows (FP64)
+//     analysis of all slices k..t (14b)       k_update
+//   smoothed means of every slice (line 13)    k_means, k_extract
+// The stream is synchronised once at the end to check the positive-definiteness
+// flag before any output is written.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "oic_internal.h"
+
+namespace oic {
+
+const char* const kKernelClassNames[KC_COUNT] = {
+    "noise", "init", "lift", "conv_first", "conv_mid", "conv_last", "assemble", "observe",
+    "means", "stats", "stats_reduce", "chol", "gain", "update", "extract"};
+
+void Timer::reset() {
+  cursor = 0;
+  pending_class.clear();
+  for (int c = 0; c < KC_COUNT; ++c) {
+    launches[c] = 0;
+    total_ms[c] = 0.0;
+  }
+}
+
+int Timer::begin(int c, hipStream_t s) {
+  if (!enabled) return -1;
+  if (2 * cursor + 2 > pool.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      pool.push_back(e);
+    }
+  }
+  const int idx = (int)cursor++;
+  pending_class.push_back(c);
+  hipEventRecord(pool[2 * idx], s);
+  return idx;
+}
+
+void Timer::end(int idx, hipStream_t s) {
+  if (idx < 0) return;
+  hipEventRecord(pool[2 * idx + 1], s);
+}
+
+void Timer::harvest() {
+  for (size_t k = 0; k < cursor; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
+      total_ms[pending_class[k]] += ms;
+      launches[pending_class[k]] += 1;
+    }
+  }
+  cursor = 0;
+  pending_class.clear();
+}
+
+void Timer::destroy() {
+  for (auto e : pool) hipEventDestroy(e);
+  pool.clear();
+}
+
+}  // namespace oic
+
+using namespace oic;
+
+struct oic_ctx {
+  oic_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  Timer timer;
+
+  // surrogate
+  bool weights_set = false;
+  float* dB = nullptr;
+  float* dW[OIC_MAX_LAYERS] = {};
+  float* dBias[OIC_MAX_LAYERS] = {};
+  int cmax = 2;
+
+  // solve buffers (capacity max_N, max_H)
+  float* traj = nullptr;
+  float* Y = nullptr;
+  float* act[2] = {nullptr, nullptr};
+  float* mu_traj = nullptr;
+  float* muY = nullptr;
+  double* S = nullptr;
+  double* part = nullptr;
+  int max_splits = 32;
+  double* Lwork = nullptr;
+  float* K = nullptr;
+  int* flag = nullptr;
+  float* Z[4] = {};  // 0 init (N,l,m); 1 W (H,N,l,m); 2 V_X (H,N,n,m); 3 V_U (H,N,l,m)
+  float* Uprev = nullptr;
+  float* Uprev_new = nullptr;
+  float* fac = nullptr;  // [Q factor (l*l)][R factor (n*n)]
+  bool q_diag = true, r_diag = true;
+  std::vector<float> q_cached, r_cached;  // inputs the factors were computed from
+  float* io = nullptr;                    // staging for host-memory inputs and outputs
+  size_t io_floats = 0;
+  float* out_stage = nullptr;             // solve outputs before the success check
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      h->err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
+      return OIC_EDEVICE;                                                    \
+    }                                                                        \
+  } while (0)
+
+int fail(oic_ctx* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+bool finite_all(const float* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+size_t noise_floats(const oic_config& c, int kind) {
+  const size_t N = c.max_N, H = c.max_H, m = c.m;
+  switch (kind) {
+    case 0: return N * c.l * m;
+    case 1: return H * N * c.l * m;
+    case 2: return H * N * c.n * m;
+    default: return H * N * c.l * m;
+  }
+}
+
+// Lower Cholesky factor in FP64 on the host; returns false if not SPD.
+bool host_cholesky(const float* A, int k, std::vector<double>& L) {
+  L.assign((size_t)k * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    double s = A[(size_t)j * k + j];
+    for (int c = 0; c < j; ++c) s -= L[(size_t)j * k + c] * L[(size_t)j * k + c];
+    if (!(s > 0.0) || !std::isfinite(s)) return false;
+    const double d = sqrt(s);
+    L[(size_t)j * k + j] = d;
+    for (int i = j + 1; i < k; ++i) {
+      double v = A[(size_t)i * k + j];
+      for (int c = 0; c < j; ++c) v -= L[(size_t)i * k + c] * L[(size_t)j * k + c];
+      L[(size_t)i * k + j] = v / d;
+    }
+  }
+  return true;
+}
+
+bool is_symmetric(const float* A, int k) {
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < i; ++j)
+      if (A[(size_t)i * k + j] != A[(size_t)j * k + i]) return false;
+  return true;
+}
+
+bool is_diagonal(const float* A, int k) {
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j)
+      if (i != j && A[(size_t)i * k + j] != 0.f) return false;
+  return true;
+}
+
+// Factor Q and R (host), upload the FP32 factors (or diagonal scales) when they changed.
+int prepare_factors(oic_ctx* h, const float* Q, const float* R) {
+  const int l = h->cfg.l, n = h->cfg.n;
+  if (!Q || !R) return fail(h, OIC_EINVAL, "Q and R must be non-NULL host pointers");
+  if (!finite_all(Q, (size_t)l * l) || !finite_all(R, (size_t)n * n))
+    return fail(h, OIC_EINVAL, "Q or R has a non-finite entry");
+  const bool same = h->q_cached.size() == (size_t)l * l && h->r_cached.size() == (size_t)n * n &&
+                    memcmp(h->q_cached.data(), Q, sizeof(float) * l * l) == 0 &&
+                    memcmp(h->r_cached.data(), R, sizeof(float) * n * n) == 0;
+  if (same) return OIC_OK;
+  if (!is_symmetric(Q, l) || !is_symmetric(R, n))
+    return fail(h, OIC_EINVAL, "Q and R must be symmetric");
+  std::vector<double> Lq, Lr;
+  if (!host_cholesky(Q, l, Lq)) return fail(h, OIC_EINVAL, "Q is not positive definite");
+  if (!host_cholesky(R, n, Lr)) return fail(h, OIC_EINVAL, "R is not positive definite");
+  std::vector<float> f((size_t)l * l + (size_t)n * n, 0.f);
+  h->q_diag = is_diagonal(Q, l);
+  h->r_diag = is_diagonal(R, n);
+  // Diagonal factors are stored as the first l (n) entries; dense ones row-major.
+  if (h->q_diag)
+    for (int a = 0; a < l; ++a) f[a] = (float)Lq[(size_t)a * l + a];
+  else
+    for (size_t e = 0; e < (size_t)l * l; ++e) f[e] = (float)Lq[e];
+  float* fr = f.data() + (size_t)l * l;
+  if (h->r_diag)
+    for (int a = 0; a < n; ++a) fr[a] = (float)Lr[(size_t)a * n + a];
+  else
+    for (size_t e = 0; e < (size_t)n * n; ++e) fr[e] = (float)Lr[e];
+  HIP_TRY(hipMemcpyAsync(h->fac, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->q_cached.assign(Q, Q + (size_t)l * l);
+  h->r_cached.assign(R, R + (size_t)n * n);
+  return OIC_OK;
+}
+
+NoiseRef noise_ref(oic_ctx* h, const float* Z, bool is_q) {
+  NoiseRef r;
+  r.Z = Z;
+  const int l = h->cfg.l;
+  if (is_q) {
+    r.rows = l;
+    r.diag = h->q_diag ? h->fac : nullptr;
+    r.L = h->q_diag ? nullptr : h->fac;
+  } else {
+    r.rows = h->cfg.n;
+    const float* fr = h->fac + (size_t)l * l;
+    r.diag = h->r_diag ? fr : nullptr;
+    r.L = h->r_diag ? nullptr : fr;
+  }
+  return r;
+}
+
+template <typename T>
+int dalloc(oic_ctx* h, T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    h->err = std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes failed: " +
+             hipGetErrorString(e);
+    return OIC_ENOMEM;
+  }
+  return OIC_OK;
+}
+
+void free_all(oic_ctx* h) {
+  auto f = [](void* p) {
+    if (p) hipFree(p);
+  };
+  f(h->dB);
+  for (int k = 0; k < OIC_MAX_LAYERS; ++k) {
+    f(h->dW[k]);
+    f(h->dBias[k]);
+  }
+  f(h->traj);
+  f(h->Y);
+  f(h->act[0]);
+  f(h->act[1]);
+  f(h->mu_traj);
+  f(h->muY);
+  f(h->S);
+  f(h->part);
+  f(h->Lwork);
+  f(h->K);
+  f(h->flag);
+  for (int k = 0; k < 4; ++k) f(h->Z[k]);
+  f(h->Uprev);
+  f(h->Uprev_new);
+  f(h->fac);
+  f(h->io);
+  f(h->out_stage);
+}
+
+// Runs the CNN of Eq. (1) on `batch` fields given as strided sources, writing the
+// single output channel to `out`.
+void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out) {
+  const oic_config& c = h->cfg;
+  const int L = c.n_layers;
+  launch_lift(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, h->act[0]);
+  int cur = 0;
+  for (int k = 0; k < L; ++k) {
+    const int cin = c.channels[k], cout = c.channels[k + 1];
+    const bool last = k == L - 1;
+    const int cls = k == 0 ? KC_CONV_FIRST : (last ? KC_CONV_LAST : KC_CONV_MID);
+    FieldOut fo = last ? out : FieldOut{nullptr, 0, 0};
+    launch_conv(h->stream, h->timer, cls, batch, c.n, c.m, cin, cout, h->act[cur], h->dW[k],
+                h->dBias[k], c.activation, last ? nullptr : h->act[1 - cur], fo);
+    cur = 1 - cur;
+  }
+}
+
+int copy_in(oic_ctx* h, float* dst, const float* src, size_t count) {
+  if (h->cfg.mem_mode == OIC_MEM_HOST)
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  else
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+  return OIC_OK;
+}
+
+int copy_out(oic_ctx* h, float* dst, const float* src, size_t count) {
+  if (h->cfg.mem_mode == OIC_MEM_HOST)
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+  else
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+  return OIC_OK;
+}
+
+int solve_impl(oic_ctx* h, const oic_solve_args* a) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  if (!a) return fail(h, OIC_EINVAL, "NULL argument block");
+  const oic_config& c = h->cfg;
+  if (!h->weights_set) return fail(h, OIC_EINVAL, "weights not set (call oic_set_weights first)");
+  const int N = a->N, H = a->horizon;
+  if (N < 2) return fail(h, OIC_EINVAL, "N must be at least 2");
+  if (H < 1) return fail(h, OIC_EINVAL, "horizon must be at least 1");
+  if (N > c.max_N || H > c.max_H)
+    return fail(h, OIC_ENOMEM, "N or horizon exceeds the capacity the handle was created with");
+  if ((long long)(N - 1) * c.m < c.n + c.l)
+    return fail(h, OIC_EINVAL, "(N-1)*m < n+l: Sigma^Ybar cannot be positive definite");
+  if (!a->X0 || !a->reference || !a->U_out) return fail(h, OIC_EINVAL, "NULL X0, reference or U_out");
+  const bool explicit_noise = a->Z_init || a->Z_W || a->Z_VX || a->Z_VU;
+  if (explicit_noise && !(a->Z_init && a->Z_W && a->Z_VX && a->Z_VU))
+    return fail(h, OIC_EINVAL, "noise arrays must be all NULL or all non-NULL");
+  if (c.mem_mode == OIC_MEM_HOST) {
+    if (!finite_all(a->X0, (size_t)c.n * c.m) ||
+        !finite_all(a->reference, (size_t)(H + 1) * c.n * c.m))
+      return fail(h, OIC_EINVAL, "X0 or reference has a non-finite entry");
+  }
+  int rc = prepare_factors(h, a->Q, a->R);
+  if (rc) return rc;
+
+  Dims d{c.n, c.m, c.l, N, H};
+  const int n = c.n, m = c.m, l = c.l, rr = d.rr(), p = d.p();
+  const long long NM = d.NM();
+  hipStream_t s = h->stream;
+
+  // Inputs into device memory.
+  float* dX0 = h->io;
+  float* dRef = dX0 + (size_t)n * m;
+  float* dUp = dRef + (size_t)(c.max_H + 1) * n * m;
+  if ((rc = copy_in(h, dX0, a->X0, (size_t)n * m))) return rc;
+  if ((rc = copy_in(h, dRef, a->reference, (size_t)(H + 1) * n * m))) return rc;
+  if (a->U_prev) {
+    if ((rc = copy_in(h, dUp, a->U_prev, (size_t)l * m))) return rc;
+  } else {
+    HIP_TRY(hipMemcpyAsync(dUp, h->Uprev, (size_t)l * m * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  const size_t cnt[4] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
+                         (size_t)H * N * l * m};
+  const float* zsrc[4] = {a->Z_init, a->Z_W, a->Z_VX, a->Z_VU};
+  const float* Zd[4];
+  for (int k = 0; k < 4; ++k) {
+    if (explicit_noise) {
+      if (c.mem_mode == OIC_MEM_HOST) {
+        if ((rc = copy_in(h, h->Z[k], zsrc[k], cnt[k]))) return rc;
+        Zd[k] = h->Z[k];
+      } else {
+        Zd[k] = zsrc[k];
+      }
+    } else {
+      launch_normals(s, h->timer, h->Z[k], cnt[k], a->seed, (uint32_t)k);
+      Zd[k] = h->Z[k];
+    }
+  }
+  HIP_TRY(hipMemsetAsync(h->flag, 0, sizeof(int), s));
+
+  // Line 4: initial ensemble.
+  launch_init_slice0(s, h->timer, d, h->traj, dX0, dUp, noise_ref(h, Zd[0], true));
+  for (int t = 1; t <= H; ++t) {
+    const size_t slice = (size_t)rr * NM;
+    float* prev = h->traj + (size_t)(t - 1) * slice;
+    float* cur = h->traj + (size_t)t * slice;
+    // Line 6 / Eq. (15b): X rows of slice t through the CNN, from the analysed slice t-1.
+    rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
+            FieldOut{cur, m, NM});
+    launch_assemble_u(s, h->timer, d, h->traj, t,
+                      noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true));
+    // Line 9 / Eq. (12).
+    launch_observe(s, h->timer, d, h->traj, t, h->Y,
+                   noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
+                   noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true));
+    // Eqs. (11), (13a): means of slices k..t and of Ybar.
+    const int Ma = (t + 1) * rr;
+    launch_means(s, h->timer, h->traj, Ma, N, m, h->mu_traj);
+    launch_means(s, h->timer, h->Y, p, N, m, h->muY);
+    // Eqs. (13b), (13c).
+    launch_stats(s, h->timer, d, h->traj, h->mu_traj, Ma, h->Y, h->muY, h->part, h->max_splits, h->S);
+    // Eq. (14b): gain, then line 10: analysis of every stored slice.
+    launch_chol_gain(s, h->timer, d, Ma, h->S, h->Lwork, h->part, h->K, h->flag);
+    launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m);
+  }
+  // Line 13: smoothed means of every slice.
+  launch_means(s, h->timer, h->traj, (H + 1) * rr, N, m, h->mu_traj);
+  float* sU = h->out_stage;
+  float* sX = sU + (size_t)(c.max_H + 1) * l * m;
+  launch_extract(s, h->timer, d, h->mu_traj, sU, sX, h->Uprev_new);
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  h->timer.harvest();
+  if (flag) return fail(h, OIC_ENOTSPD, "Sigma^Ybar is not positive definite at some horizon step");
+  if ((rc = copy_out(h, a->U_out, sU, (size_t)(H + 1) * l * m))) return rc;
+  if (a->X_out && (rc = copy_out(h, a->X_out, sX, (size_t)(H + 1) * n * m))) return rc;
+  HIP_TRY(hipMemcpyAsync(h->Uprev, h->Uprev_new, (size_t)l * m * sizeof(float),
+                         hipMemcpyDeviceToDevice, s));
+  if (c.mem_mode == OIC_MEM_HOST) HIP_TRY(hipStreamSynchronize(s));
+  return OIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oic_create(const oic_config* cfg, oic_handle* out) {
+  if (!cfg || !out) return OIC_EINVAL;
+  *out = nullptr;
+  const oic_config& c = *cfg;
+  if (c.n < 4 || c.m < 4 || c.l < 1 || c.l > c.n || c.n_layers < 1 || c.n_layers > OIC_MAX_LAYERS ||
+      c.max_N < 2 || c.max_H < 1 || (c.activation != OIC_ACT_TANH && c.activation != OIC_ACT_GELU) ||
+      (c.precision != OIC_PREC_FP32 && c.precision != OIC_PREC_BF16) ||
+      (c.mem_mode != OIC_MEM_HOST && c.mem_mode != OIC_MEM_DEVICE))
+    return OIC_EINVAL;
+  if (c.channels[0] != 2 || c.channels[c.n_layers] != 1) return OIC_EINVAL;
+  for (int k = 1; k < c.n_layers; ++k)
+    if (c.channels[k] < 1 || c.channels[k] > 128) return OIC_EINVAL;
+  oic_ctx* h = new (std::nothrow) oic_ctx();
+  if (!h) return OIC_ENOMEM;
+  h->cfg = c;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return OIC_EDEVICE;
+  }
+  if (c.stream) {
+    h->stream = (hipStream_t)c.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return OIC_EDEVICE;
+    }
+    h->own_stream = true;
+  }
+  for (int k = 1; k < c.n_layers; ++k) h->cmax = std::max(h->cmax, c.channels[k]);
+  const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l;
+  const size_t NM = N * m;
+  const size_t Ma_max = Hs * rr;
+  int rc = OIC_OK;
+  rc = rc ? rc : dalloc(h, &h->traj, Hs * rr * NM);
+  rc = rc ? rc : dalloc(h, &h->Y, p * NM);
+  rc = rc ? rc : dalloc(h, &h->act[0], N * n * m * (size_t)h->cmax);
+  rc = rc ? rc : dalloc(h, &h->act[1], N * n * m * (size_t)h->cmax);
+  rc = rc ? rc : dalloc(h, &h->mu_traj, Ma_max * m);
+  rc = rc ? rc : dalloc(h, &h->muY, p * m);
+  rc = rc ? rc : dalloc(h, &h->S, (Ma_max + p) * p);
+  rc = rc ? rc : dalloc(h, &h->part, std::max((size_t)h->max_splits * (Ma_max + p) * p, Ma_max * p));
+  rc = rc ? rc : dalloc(h, &h->Lwork, p * p);
+  rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
+  rc = rc ? rc : dalloc(h, &h->flag, 1);
+  for (int k = 0; k < 4 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));
+  rc = rc ? rc : dalloc(h, &h->Uprev, l * m);
+  rc = rc ? rc : dalloc(h, &h->Uprev_new, l * m);
+  rc = rc ? rc : dalloc(h, &h->fac, l * l + n * n);
+  // staging: X0, reference window, U_prev, and batched CNN inputs/outputs
+  h->io_floats = n * m + Hs * n * m + l * m + N * (n + l) * m + N * n * m;
+  rc = rc ? rc : dalloc(h, &h->io, h->io_floats);
+  rc = rc ? rc : dalloc(h, &h->out_stage, Hs * (l + n) * m);
+  if (!rc && hipMemsetAsync(h->Uprev, 0, l * m * sizeof(float), h->stream) != hipSuccess)
+    rc = OIC_EDEVICE;
+  if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = OIC_EDEVICE;
+  if (rc) {
+    free_all(h);
+    if (h->own_stream) hipStreamDestroy(h->stream);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return OIC_OK;
+}
+
+void oic_destroy(oic_handle h) {
+  if (!h) return;
+  hipStreamSynchronize(h->stream);
+  free_all(h);
+  h->timer.destroy();
+  if (h->own_stream) hipStreamDestroy(h->stream);
+  delete h;
+}
+
+const char* oic_last_error(oic_handle h) { return h ? h->err.c_str() : "NULL handle"; }
+
+int oic_set_weights(oic_handle h, const float* B, const float* const* W, const float* const* bias) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  const oic_config& c = h->cfg;
+  if (!B || !W) return fail(h, OIC_EINVAL, "NULL B or W");
+  if (!finite_all(B, (size_t)c.n * c.l)) return fail(h, OIC_EINVAL, "B has a non-finite entry");
+  for (int k = 0; k < c.n_layers; ++k) {
+    const size_t cnt = (size_t)c.channels[k + 1] * c.channels[k] * 9;
+    if (!W[k] || !finite_all(W[k], cnt)) return fail(h, OIC_EINVAL, "NULL or non-finite layer weights");
+    if (bias && bias[k] && !finite_all(bias[k], c.channels[k + 1]))
+      return fail(h, OIC_EINVAL, "non-finite bias");
+  }
+  int rc;
+  if (!h->dB && (rc = dalloc(h, &h->dB, (size_t)c.n * c.l))) return rc;
+  HIP_TRY(hipMemcpyAsync(h->dB, B, (size_t)c.n * c.l * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  for (int k = 0; k < c.n_layers; ++k) {
+    const size_t cnt = (size_t)c.channels[k + 1] * c.channels[k] * 9;
+    if (!h->dW[k] && (rc = dalloc(h, &h->dW[k], cnt))) return rc;
+    HIP_TRY(hipMemcpyAsync(h->dW[k], W[k], cnt * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    if (bias && bias[k]) {
+      if (!h->dBias[k] && (rc = dalloc(h, &h->dBias[k], (size_t)c.channels[k + 1]))) return rc;
+      HIP_TRY(hipMemcpyAsync(h->dBias[k], bias[k], c.channels[k + 1] * sizeof(float),
+                             hipMemcpyHostToDevice, h->stream));
+    } else if (h->dBias[k]) {
+      hipFree(h->dBias[k]);
+      h->dBias[k] = nullptr;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->weights_set = true;
+  return OIC_OK;
+}
+
+int oic_set_u_prev(oic_handle h, const float* U_prev) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  if (!U_prev) return fail(h, OIC_EINVAL, "NULL U_prev");
+  int rc = copy_in(h, h->Uprev, U_prev, (size_t)h->cfg.l * h->cfg.m);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return OIC_OK;
+}
+
+int oic_get_u_prev(oic_handle h, float* U_prev) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  if (!U_prev) return fail(h, OIC_EINVAL, "NULL U_prev");
+  int rc = copy_out(h, U_prev, h->Uprev, (size_t)h->cfg.l * h->cfg.m);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return OIC_OK;
+}
+
+int oic_solve(oic_handle h, const float* X0, const float* reference, const float* Q, const float* R,
+              int N, int horizon, uint64_t seed, float* U_out, float* X_out) {
+  oic_solve_args a{};
+  a.X0 = X0;
+  a.reference = reference;
+  a.Q = Q;
+  a.R = R;
+  a.N = N;
+  a.horizon = horizon;
+  a.seed = seed;
+  a.U_out = U_out;
+  a.X_out = X_out;
+  return solve_impl(h, &a);
+}
+
+int oic_solve_ex(oic_handle h, const oic_solve_args* a) { return solve_impl(h, a); }
+
+int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, float* X_next) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  const oic_config& c = h->cfg;
+  if (!h->weights_set) return fail(h, OIC_EINVAL, "weights not set");
+  if (batch < 1 || batch > c.max_N) return fail(h, OIC_EINVAL, "batch must be in 1..max_N");
+  if (!X || !U || !X_next) return fail(h, OIC_EINVAL, "NULL pointer");
+  const size_t n = c.n, m = c.m, l = c.l;
+  float* dX = h->io + n * m + (size_t)(c.max_H + 1) * n * m + l * m;
+  float* dU = dX + (size_t)c.max_N * n * m;
+  float* dO = dU + (size_t)c.max_N * l * m;
+  int rc;
+  if ((rc = copy_in(h, dX, X, batch * n * m))) return rc;
+  if ((rc = copy_in(h, dU, U, batch * l * m))) return rc;
+  rollout(h, batch, FieldRef{dX, (long long)(n * m), (long long)m},
+          FieldRef{dU, (long long)(l * m), (long long)m}, FieldOut{dO, (long long)(n * m), (long long)m});
+  if ((rc = copy_out(h, X_next, dO, batch * n * m))) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->timer.harvest();
+  return OIC_OK;
+}
+
+int oic_plant_step(oic_handle h, const float* X, const float* U, float* X_next) {
+  return oic_cnn_forward(h, 1, X, U, X_next);
+}
+
+int oic_normals(oic_handle h, uint64_t seed, int kind, size_t count, float* out) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  if (kind < 0 || kind > 3 || !out) return fail(h, OIC_EINVAL, "bad kind or NULL output");
+  if (count > noise_floats(h->cfg, kind)) return fail(h, OIC_ENOMEM, "count exceeds the noise capacity");
+  launch_normals(h->stream, h->timer, h->Z[kind], count, seed, (uint32_t)kind);
+  int rc = copy_out(h, out, h->Z[kind], count);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->timer.harvest();
+  return OIC_OK;
+}
+
+int oic_timing(oic_handle h, int enable) {
+  if (!h) return OIC_EINVAL;
+  hipStreamSynchronize(h->stream);
+  h->timer.harvest();
+  h->timer.reset();
+  h->timer.enabled = enable != 0;
+  return OIC_OK;
+}
+
+int oic_kernel_class_count(void) { return KC_COUNT; }
+
+int oic_kernel_stats(oic_handle h, int id, const char** name, long long* launches, double* total_ms) {
+  if (!h || id < 0 || id >= KC_COUNT) return OIC_EINVAL;
+  if (name) *name = kKernelClassNames[id];
+  if (launches) *launches = h->timer.launches[id];
+  if (total_ms) *total_ms = h->timer.total_ms[id];
+  return OIC_OK;
+}
+
+void* oic_stream(oic_handle h) { return h ? (void*)h->stream : nullptr; }
+
+}  // extern "C"

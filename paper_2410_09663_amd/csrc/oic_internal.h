@@ -1,0 +1,126 @@
+// Internal declarations of liboic: the handle, the device buffer layout and the
+// kernel launchers.  Not part of the ABI.
+//
+// Device layout of one solve (N members, horizon H, rows per slice rr = n + l):
+//   traj  : (H+1) slices x rr rows x (N*m) columns, FP32, row-major.  Slice s,
+//           row q, member i, column x sits at ((s*rr + q)*N + i)*m + x, i.e. the
+//           members of one row lie side by side, [X^1 X^2 ... X^N], so that the
+//           pooled sums of Eq. (13), sum_i A^i D^iT, are plain row-by-row dot
+//           products over the N*m columns.  The dU rows of the augmented state
+//           are not stored: no other row, gain or output depends on them.
+//   Y     : p = n + l rows x (N*m) columns, the perturbed observations of Eq. (12).
+//   act   : two NHWC activation buffers [N][n][m][C] for the rollout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/oic.h"
+
+namespace oic {
+
+enum KernelClass {
+  KC_NOISE = 0,
+  KC_INIT,
+  KC_LIFT,
+  KC_CONV_FIRST,
+  KC_CONV_MID,
+  KC_CONV_LAST,
+  KC_ASSEMBLE,
+  KC_OBSERVE,
+  KC_MEANS,
+  KC_STATS,
+  KC_STATS_REDUCE,
+  KC_CHOL,
+  KC_GAIN,
+  KC_UPDATE,
+  KC_EXTRACT,
+  KC_COUNT
+};
+
+extern const char* const kKernelClassNames[KC_COUNT];
+
+// Per-kernel-class timing with HIP events on the handle's stream.
+struct Timer {
+  bool enabled = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> pending_class;  // class of each recorded pair, in order
+  size_t cursor = 0;
+  long long launches[KC_COUNT] = {};
+  double total_ms[KC_COUNT] = {};
+  void reset();
+  // Records the start event of a launch of class c; returns the pair index or -1.
+  int begin(int c, hipStream_t s);
+  void end(int idx, hipStream_t s);
+  // Call after the stream is synchronised: folds every pending pair into the totals.
+  void harvest();
+  void destroy();
+};
+
+// Noise source for one kind at one horizon step: standard normals Z laid out
+// [member][row][col] (row stride m, member stride rows*m), and the row factor:
+// either a diagonal scale (diag != null) or a dense lower-triangular L (rows x rows).
+struct NoiseRef {
+  const float* Z;
+  const float* diag;
+  const float* L;
+  int rows;
+};
+
+struct Dims {
+  int n, m, l, N, H;
+  __host__ __device__ int rr() const { return n + l; }
+  __host__ __device__ int p() const { return n + l; }
+  __host__ __device__ long long NM() const { return (long long)N * m; }
+};
+
+// ---- kernel launchers (defined in the .hip files) ----
+void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, uint64_t seed, uint32_t kind);
+
+void launch_init_slice0(hipStream_t s, Timer& t, const Dims& d, float* traj, const float* X0,
+                        const float* Uprev, NoiseRef w0);
+void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int step, NoiseRef w);
+void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
+                    NoiseRef vx, NoiseRef vu);
+
+// Rollout.  Field element (i, y, x) of a strided source sits at base + i*si + y*sy + x.
+struct FieldRef {
+  const float* base;
+  long long si, sy;
+};
+struct FieldOut {
+  float* base;
+  long long si, sy;
+};
+void launch_lift(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
+                 const float* B, float* out_nhwc);
+void launch_conv(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
+                 const float* in_nhwc, const float* w_oihw, const float* bias, int act,
+                 float* out_nhwc, FieldOut final_out);
+
+// Statistics and update.
+void launch_means(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, float* mean);
+void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, const float* mu_traj,
+                  int Ma, const float* Y, const float* muY, double* part, int max_splits,
+                  double* S);
+// Factor Sigma^Ybar (rows Ma..Ma+p-1 of S) in FP64 and solve K Sigma^Ybar = S[0:Ma] for the gain.
+// `scratch` holds p*Ma doubles.  flag is set to 1 when a pivot is not positive and finite.
+void launch_chol_gain(hipStream_t s, Timer& t, const Dims& d, int Ma, const double* S, double* Lwork,
+                      double* scratch, float* K, int* flag);
+void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
+                   const float* Y, const float* xref_t);
+void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,
+                    float* Xout, float* Uprev);
+
+}  // namespace oic
+
+// Launch `kernel` on `stream`, bracketed by timing events of class `cls` when enabled.
+#define OIC_LAUNCH(timer, cls, stream, kernel, grid, block, shmem, ...)          \
+  do {                                                                         \
+    int oic_ti_ = (timer).begin((cls), (stream));                              \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);       \
+    (timer).end(oic_ti_, (stream));                                            \
+  } while (0)

@@ -1,0 +1,302 @@
+"""Thin ctypes binding of liboic (include/oic.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels; this module only
+converts NumPy arrays (host memory) or torch CUDA tensors (device memory) to
+pointers and checks return codes.  It fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liboic.so")
+
+OIC_OK = 0
+OIC_EINVAL = -1
+OIC_ENOMEM = -2
+OIC_EDEVICE = -3
+OIC_ENOTSPD = -4
+
+OIC_ACT_TANH = 0
+OIC_ACT_GELU = 1
+OIC_PREC_FP32 = 0
+OIC_PREC_BF16 = 1
+OIC_MEM_HOST = 0
+OIC_MEM_DEVICE = 1
+OIC_MAX_LAYERS = 8
+
+_ERRNAMES = {OIC_EINVAL: "OIC_EINVAL", OIC_ENOMEM: "OIC_ENOMEM", OIC_EDEVICE: "OIC_EDEVICE",
+             OIC_ENOTSPD: "OIC_ENOTSPD"}
+
+
+class OicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class oic_config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("m", ctypes.c_int), ("l", ctypes.c_int),
+                ("n_layers", ctypes.c_int), ("channels", ctypes.c_int * (OIC_MAX_LAYERS + 1)),
+                ("activation", ctypes.c_int), ("precision", ctypes.c_int),
+                ("max_N", ctypes.c_int), ("max_H", ctypes.c_int), ("mem_mode", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+class oic_solve_args(ctypes.Structure):
+    _fields_ = [("X0", ctypes.c_void_p), ("reference", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+                ("R", ctypes.c_void_p), ("N", ctypes.c_int), ("horizon", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("U_prev", ctypes.c_void_p),
+                ("Z_init", ctypes.c_void_p), ("Z_W", ctypes.c_void_p), ("Z_VX", ctypes.c_void_p),
+                ("Z_VU", ctypes.c_void_p), ("U_out", ctypes.c_void_p), ("X_out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liboic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2410_09663_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ci, cu64, cs = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
+        sig = {
+            "oic_create": (ci, [ctypes.POINTER(oic_config), ctypes.POINTER(vp)]),
+            "oic_destroy": (None, [vp]),
+            "oic_last_error": (ctypes.c_char_p, [vp]),
+            "oic_set_weights": (ci, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+            "oic_set_u_prev": (ci, [vp, vp]),
+            "oic_get_u_prev": (ci, [vp, vp]),
+            "oic_solve": (ci, [vp, vp, vp, vp, vp, ci, ci, cu64, vp, vp]),
+            "oic_solve_ex": (ci, [vp, ctypes.POINTER(oic_solve_args)]),
+            "oic_cnn_forward": (ci, [vp, ci, vp, vp, vp]),
+            "oic_plant_step": (ci, [vp, vp, vp, vp]),
+            "oic_normals": (ci, [vp, cu64, ci, cs, vp]),
+            "oic_timing": (ci, [vp, ci]),
+            "oic_kernel_class_count": (ci, []),
+            "oic_kernel_stats": (ci, [vp, ci, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_double)]),
+            "oic_stream": (vp, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
+            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_cnn_forward", "oic_plant_step",
+            "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream"]
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class Controller:
+    """One handle of liboic.  mem_mode OIC_MEM_HOST takes and returns float32 NumPy
+    arrays; OIC_MEM_DEVICE takes float32 torch CUDA tensors (contiguous)."""
+
+    def __init__(self, n: int, m: int, l: int, channels: Sequence[int], activation: int,
+                 max_N: int, max_H: int, precision: int = OIC_PREC_FP32,
+                 mem_mode: int = OIC_MEM_HOST, stream: Optional[int] = None):
+        self._h = None
+        cfg = oic_config()
+        cfg.n, cfg.m, cfg.l = n, m, l
+        cfg.n_layers = len(channels) - 1
+        for k, c in enumerate(channels):
+            cfg.channels[k] = c
+        cfg.activation, cfg.precision = activation, precision
+        cfg.max_N, cfg.max_H, cfg.mem_mode = max_N, max_H, mem_mode
+        cfg.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib().oic_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != OIC_OK:
+            raise OicError(rc, "oic_create failed")
+        self._h = h
+        self.n, self.m, self.l = n, m, l
+        self.channels = list(channels)
+        self.mem_mode = mem_mode
+        self.max_N, self.max_H = max_N, max_H
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, rc: int):
+        if rc != OIC_OK:
+            raise OicError(rc, lib().oic_last_error(self._h).decode())
+
+    def _ptr(self, a, shape, writable=False):
+        """Pointer to a float32 array/tensor of the given shape (checked)."""
+        if a is None:
+            return None
+        if self.mem_mode == OIC_MEM_DEVICE:
+            if not _is_torch(a) or not a.is_cuda:
+                raise TypeError("device mode takes torch CUDA tensors")
+            import torch
+            if a.dtype != torch.float32 or not a.is_contiguous() or tuple(a.shape) != tuple(shape):
+                raise ValueError(f"expected contiguous float32 tensor of shape {shape}")
+            return a.data_ptr()
+        if not isinstance(a, np.ndarray) or a.dtype != np.float32 or not a.flags.c_contiguous:
+            raise TypeError("host mode takes C-contiguous float32 NumPy arrays")
+        if tuple(a.shape) != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        if writable and not a.flags.writeable:
+            raise ValueError("output array is read-only")
+        return a.ctypes.data
+
+    def _new(self, shape):
+        if self.mem_mode == OIC_MEM_DEVICE:
+            import torch
+            return torch.empty(shape, dtype=torch.float32, device="cuda")
+        return np.empty(shape, dtype=np.float32)
+
+    @staticmethod
+    def _host(a, shape):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.shape != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        return a
+
+    # -- API -----------------------------------------------------------------
+    def set_weights(self, B, weights, biases=None):
+        B = self._host(B, (self.n, self.l))
+        ws = [self._host(w, (co, ci, 3, 3)) for w, ci, co in
+              zip(weights, self.channels[:-1], self.channels[1:])]
+        if len(ws) != len(self.channels) - 1:
+            raise ValueError("one weight tensor per layer")
+        wp = (ctypes.c_void_p * len(ws))(*[w.ctypes.data for w in ws])
+        bp = None
+        keep = [B, ws]
+        if biases is not None:
+            bs = [None if b is None else self._host(b, (co,)) for b, co in
+                  zip(biases, self.channels[1:])]
+            keep.append(bs)
+            bp = (ctypes.c_void_p * len(bs))(*[None if b is None else b.ctypes.data for b in bs])
+        self._check(lib().oic_set_weights(self._h, B.ctypes.data, wp, bp))
+
+    def set_u_prev(self, U):
+        self._check(lib().oic_set_u_prev(self._h, self._ptr(U, (self.l, self.m))))
+
+    def get_u_prev(self):
+        out = self._new((self.l, self.m))
+        self._check(lib().oic_get_u_prev(self._h, self._ptr(out, (self.l, self.m), True)))
+        return out
+
+    def solve(self, X0, reference, Q, R, N: int, H: int, seed: int, want_X: bool = False,
+              U_out=None, X_out=None):
+        """Seeded solve (device-generated Philox noise).  Returns (U_hat, X_hat or None)."""
+        Q = self._host(Q, (self.l, self.l))
+        R = self._host(R, (self.n, self.n))
+        U_out = self._new((H + 1, self.l, self.m)) if U_out is None else U_out
+        if want_X and X_out is None:
+            X_out = self._new((H + 1, self.n, self.m))
+        rc = lib().oic_solve(self._h, self._ptr(X0, (self.n, self.m)),
+                             self._ptr(reference, (H + 1, self.n, self.m)), Q.ctypes.data,
+                             R.ctypes.data, N, H, seed,
+                             self._ptr(U_out, (H + 1, self.l, self.m), True),
+                             self._ptr(X_out, (H + 1, self.n, self.m), True))
+        self._check(rc)
+        return U_out, X_out
+
+    def solve_ex(self, X0, reference, Q, R, N: int, H: int, seed: int = 0, U_prev=None,
+                 noise=None, want_X: bool = True):
+        """Solve with explicit noise (a workloads.Noise or a 4-tuple) or, if noise is None,
+        the seeded stream.  Returns (U_hat, X_hat)."""
+        Q = self._host(Q, (self.l, self.l))
+        R = self._host(R, (self.n, self.n))
+        a = oic_solve_args()
+        a.X0 = self._ptr(X0, (self.n, self.m))
+        a.reference = self._ptr(reference, (H + 1, self.n, self.m))
+        a.Q, a.R = Q.ctypes.data, R.ctypes.data
+        a.N, a.horizon, a.seed = N, H, seed
+        a.U_prev = self._ptr(U_prev, (self.l, self.m))
+        if noise is not None:
+            z = (noise.Z_init, noise.Z_W, noise.Z_VX, noise.Z_VU) if hasattr(noise, "Z_init") else noise
+            a.Z_init = self._ptr(z[0], (N, self.l, self.m))
+            a.Z_W = self._ptr(z[1], (H, N, self.l, self.m))
+            a.Z_VX = self._ptr(z[2], (H, N, self.n, self.m))
+            a.Z_VU = self._ptr(z[3], (H, N, self.l, self.m))
+        U_out = self._new((H + 1, self.l, self.m))
+        X_out = self._new((H + 1, self.n, self.m)) if want_X else None
+        a.U_out = self._ptr(U_out, U_out.shape, True)
+        a.X_out = self._ptr(X_out, (H + 1, self.n, self.m), True) if want_X else None
+        self._check(lib().oic_solve_ex(self._h, ctypes.byref(a)))
+        return U_out, X_out
+
+    def cnn_forward(self, X, U):
+        b = X.shape[0]
+        out = self._new((b, self.n, self.m))
+        self._check(lib().oic_cnn_forward(self._h, b, self._ptr(X, (b, self.n, self.m)),
+                                          self._ptr(U, (b, self.l, self.m)),
+                                          self._ptr(out, (b, self.n, self.m), True)))
+        return out
+
+    def plant_step(self, X, U):
+        out = self._new((self.n, self.m))
+        self._check(lib().oic_plant_step(self._h, self._ptr(X, (self.n, self.m)),
+                                         self._ptr(U, (self.l, self.m)),
+                                         self._ptr(out, (self.n, self.m), True)))
+        return out
+
+    def normals(self, seed: int, kind: int, count: int):
+        out = self._new((count,))
+        self._check(lib().oic_normals(self._h, seed, kind, count, self._ptr(out, (count,), True)))
+        return out
+
+    def timing(self, enable: bool):
+        self._check(lib().oic_timing(self._h, 1 if enable else 0))
+
+    def kernel_stats(self):
+        """{class name: (launches, total ms)} since timing was last enabled."""
+        out = {}
+        for k in range(lib().oic_kernel_class_count()):
+            name = ctypes.c_char_p()
+            cnt = ctypes.c_longlong()
+            ms = ctypes.c_double()
+            self._check(lib().oic_kernel_stats(self._h, k, ctypes.byref(name), ctypes.byref(cnt),
+                                               ctypes.byref(ms)))
+            out[name.value.decode()] = (cnt.value, ms.value)
+        return out
+
+    def stream(self) -> int:
+        return lib().oic_stream(self._h)
+
+    def close(self):
+        if self._h is not None:
+            lib().oic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def controller_for(problem, max_N=None, max_H=None, precision=None, mem_mode=OIC_MEM_HOST,
+                   stream=None) -> Controller:
+    """A Controller sized for a workloads.Problem, with its weights set."""
+    p = problem.preset
+    c = Controller(p.n, p.m, p.l, p.channels, p.activation, max_N or p.N, max_H or p.H,
+                   precision=p.precision if precision is None else precision,
+                   mem_mode=mem_mode, stream=stream)
+    c.set_weights(problem.B, problem.weights)
+    return c

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every entry point include/oic.h declares
+(CPU only: no call here touches a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_09663_amd import oic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "oic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(oic_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ["oic_create", "oic_set_weights", "oic_solve", "oic_destroy", "oic_solve_ex",
+                 "oic_last_error"]:
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(oic.LIB_PATH), reason="liboic.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(oic.LIB_PATH)
+    for name in declared():
+        assert hasattr(L, name), name
+    assert sorted(oic.EXPORTED) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(oic.LIB_PATH), reason="liboic.so not built")
+def test_host_side_validation_needs_no_device():
+    L = oic.lib()
+    assert L.oic_kernel_class_count() >= 10
+    L.oic_destroy(None)  # NULL-safe
+    assert L.oic_last_error(None) == b"NULL handle"
+    cfg = oic.oic_config()
+    h = ctypes.c_void_p()
+    # invalid configurations are rejected before any device call
+    cfg.n, cfg.m, cfg.l, cfg.n_layers = 2, 16, 1, 1
+    cfg.channels[0], cfg.channels[1] = 2, 1
+    cfg.max_N, cfg.max_H = 4, 2
+    assert L.oic_create(ctypes.byref(cfg), ctypes.byref(h)) == oic.OIC_EINVAL
+    cfg.n = 16
+    cfg.channels[1] = 3  # last layer must have one channel
+    assert L.oic_create(ctypes.byref(cfg), ctypes.byref(h)) == oic.OIC_EINVAL
+    cfg.channels[1] = 1
+    cfg.activation = 7
+    assert L.oic_create(ctypes.byref(cfg), ctypes.byref(h)) == oic.OIC_EINVAL
+    assert L.oic_solve(None, None, None, None, None, 2, 1, 0, None, None) == oic.OIC_EINVAL

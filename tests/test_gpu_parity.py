@@ -1,0 +1,226 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (normwise relative, ||gpu - oracle||_F / ||oracle||_F):
+  * FP32 solve: 1e-5 on the smoothed control means U_hat_{k..k+H} and on X_hat;
+  * CNN rollout alone: 1e-5 per field batch;
+  * device normals: bitwise FP32 equality (both sides round the same FP64 value;
+    a 1-ulp FP64 difference in log/cos may flip an FP32 rounding, so at most
+    1 in 10^5 values may differ, by 1 ulp).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cnn as ocnn
+from oracle import enks, philox
+from paper_2410_09663_amd import oic
+from paper_2410_09663_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+def relerr(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def oracle_solve(prob, Xref, z, U_prev=None, Q=None, R=None, N=None, H=None):
+    p = prob.preset
+    Q = prob.Q if Q is None else Q
+    R = prob.R if R is None else R
+    return enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, Q, Q, R,
+                      N or p.N, H or p.H, *z, U_prev=U_prev)
+
+
+def tiny(n=6, m=5, l=2, channels=(2, 3, 1), act=wl.ACT_TANH, N=7, H=3):
+    return wl.small_preset(n=n, m=m, l=l, channels=channels, activation=act, N=N, H=H)
+
+
+@pytest.mark.parametrize("kind,count", [(0, 1), (1, 4097), (2, 100003), (3, 30001)])
+def test_device_normals_match_oracle(kind, count):
+    prob = wl.make_problem(wl.PRESETS["C1"])
+    with oic.controller_for(prob, max_N=64, max_H=8) as c:
+        seed = (123 << 32) | 77
+        got = c.normals(seed, kind, count)
+    ref = philox.normals(seed, kind, (count,))
+    diff = got != ref
+    assert diff.sum() <= max(1, count // 100000)
+    if diff.any():
+        assert np.all(np.abs(got[diff].view(np.int32) - ref[diff].view(np.int32)) <= 1)
+
+
+@pytest.mark.parametrize("preset", ["C1", "C2", "tiny", "tiny_gelu", "wide"])
+def test_cnn_forward_matches_oracle(preset):
+    if preset == "tiny":
+        p = tiny()
+    elif preset == "tiny_gelu":
+        p = tiny(n=5, m=7, l=3, channels=(2, 5, 4, 1), act=wl.ACT_GELU)
+    elif preset == "wide":
+        p = wl.small_preset(n=12, m=20, l=3, channels=(2, 40, 1), activation=wl.ACT_GELU, N=9)
+    else:
+        p = wl.PRESETS[preset]
+    prob = wl.make_problem(p)
+    rng = np.random.default_rng(0)
+    b = min(p.N, 16)
+    X = rng.standard_normal((b, p.n, p.m)).astype(np.float32)
+    U = rng.standard_normal((b, p.l, p.m)).astype(np.float32)
+    with oic.controller_for(prob, max_N=b) as c:
+        got = c.cnn_forward(X, U)
+        one = c.plant_step(X[0], U[0])
+    ref = ocnn.cnn_forward(X, U, prob.B, prob.weights, p.activation)
+    assert relerr(got, ref) < TOL_FP32
+    assert np.array_equal(one, got[0])
+
+
+@pytest.mark.parametrize("preset", ["C1", "tiny", "tiny_gelu", "tiny_l1", "C2"])
+def test_solve_explicit_noise_matches_oracle(preset):
+    if preset == "tiny":
+        p = tiny()
+    elif preset == "tiny_gelu":
+        p = tiny(n=5, m=7, l=3, channels=(2, 5, 4, 1), act=wl.ACT_GELU, N=6, H=4)
+    elif preset == "tiny_l1":
+        p = tiny(n=9, m=4, l=1, channels=(2, 2, 1), N=5, H=2)
+    else:
+        p = wl.PRESETS[preset]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=11)
+    Up = (0.1 * np.random.default_rng(1).standard_normal((p.l, p.m))).astype(np.float32)
+    with oic.controller_for(prob) as c:
+        U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, U_prev=Up, noise=z)
+        U_applied = c.get_u_prev()
+    ref = oracle_solve(prob, Xref, (z.Z_init, z.Z_W, z.Z_VX, z.Z_VU), U_prev=Up)
+    eu, ex = relerr(U, ref.U_mean), relerr(X, ref.X_mean)
+    print(f"{preset}: relerr U {eu:.2e} X {ex:.2e}", flush=True)
+    assert eu < TOL_FP32
+    assert ex < TOL_FP32
+    assert relerr(U[0], ref.U_mean[0]) < TOL_FP32
+    assert np.array_equal(U_applied, U[0])
+
+
+def test_seeded_solve_matches_oracle_with_philox_noise():
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    seed = 2024
+    z = philox.solve_noise(seed, p.n, p.m, p.l, p.N, p.H)
+    with oic.controller_for(prob) as c:
+        U, X = c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, seed, want_X=True)
+    ref = oracle_solve(prob, Xref, z)
+    assert relerr(U, ref.U_mean) < TOL_FP32
+    assert relerr(X, ref.X_mean) < TOL_FP32
+
+
+def test_dense_Q_and_R():
+    p = tiny(n=8, m=6, l=3, channels=(2, 4, 1), N=10, H=3)
+    prob = wl.make_problem(p)
+    Q = wl.random_spd(p.l, 5, scale=0.05, cond=3.0)
+    R = wl.random_spd(p.n, 6, scale=0.01, cond=5.0)
+    Xref = wl.reference_window(p, 0)
+    z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=4)
+    with oic.controller_for(prob) as c:
+        U, X = c.solve_ex(prob.X0, Xref, Q, R, p.N, p.H, noise=z)
+    ref = oracle_solve(prob, Xref, (z.Z_init, z.Z_W, z.Z_VX, z.Z_VU), Q=Q, R=R)
+    assert relerr(U, ref.U_mean) < TOL_FP32
+    assert relerr(X, ref.X_mean) < TOL_FP32
+
+
+def test_device_memory_mode_matches_host_mode_bitwise():
+    import torch
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    with oic.controller_for(prob) as c:
+        U_h, X_h = c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, seed=5, want_X=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    with oic.controller_for(prob, mem_mode=oic.OIC_MEM_DEVICE, stream=stream) as c:
+        U_d, X_d = c.solve(torch.from_numpy(prob.X0).cuda(), torch.from_numpy(Xref).cuda(),
+                           prob.Q, prob.R, p.N, p.H, seed=5, want_X=True)
+        torch.cuda.synchronize()
+        U_d, X_d = U_d.cpu().numpy(), X_d.cpu().numpy()
+    assert np.array_equal(U_h, U_d) and np.array_equal(X_h, X_d)
+
+
+def test_repeat_solves_are_bitwise_identical():
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    with oic.controller_for(prob, max_N=64, max_H=8) as c:
+        outs = []
+        for _ in range(3):
+            c.set_u_prev(np.zeros((p.l, p.m), np.float32))
+            outs.append(c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, seed=9, want_X=True))
+    for U, X in outs[1:]:
+        assert np.array_equal(U, outs[0][0]) and np.array_equal(X, outs[0][1])
+
+
+def test_smaller_solve_in_larger_handle():
+    """A handle sized for (max_N, max_H) solves smaller N and H correctly, before and
+    after a larger solve (no stale state leaks between solves)."""
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    with oic.controller_for(prob, max_N=48, max_H=7) as c:
+        for N, H in [(48, 7), (9, 2), (33, 5)]:
+            Xref = wl.reference_window(p, 0, H)
+            z = wl.host_noise(p.n, p.m, p.l, N, H, seed=N)
+            c.set_u_prev(np.zeros((p.l, p.m), np.float32))
+            U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, N, H, noise=z)
+            ref = oracle_solve(prob, Xref, (z.Z_init, z.Z_W, z.Z_VX, z.Z_VU), N=N, H=H)
+            assert relerr(U, ref.U_mean) < TOL_FP32, (N, H)
+
+
+def test_error_paths_leave_outputs_untouched():
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    with oic.controller_for(prob) as c:
+        with pytest.raises(oic.OicError) as e:
+            c.solve(prob.X0, Xref, prob.Q, prob.R, 1, p.H, 0)
+        assert e.value.code == oic.OIC_EINVAL
+        with pytest.raises(oic.OicError) as e:
+            c.solve(prob.X0, Xref, prob.Q, prob.R, p.N + 1, p.H, 0)
+        assert e.value.code == oic.OIC_ENOMEM
+        with pytest.raises(oic.OicError) as e:
+            c.solve(prob.X0, Xref, -prob.Q, prob.R, p.N, p.H, 0)
+        assert e.value.code == oic.OIC_EINVAL
+        bad = prob.X0.copy()
+        bad[3, 3] = np.nan
+        with pytest.raises(oic.OicError) as e:
+            c.solve(bad, Xref, prob.Q, prob.R, p.N, p.H, 0)
+        assert e.value.code == oic.OIC_EINVAL
+        # zero noise: no spread anywhere, Sigma^Ybar = 0 -> not positive definite
+        zero = wl.Noise(*(np.zeros_like(a) for a in wl.host_noise(p.n, p.m, p.l, p.N, p.H, 0).__dict__.values()))
+        before = c.get_u_prev()
+        with pytest.raises(oic.OicError) as e:
+            c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=zero)
+        assert e.value.code == oic.OIC_ENOTSPD
+        assert np.array_equal(c.get_u_prev(), before)
+        # the handle still works afterwards
+        U, _ = c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, 1)
+        assert np.all(np.isfinite(U))
+
+
+def test_closed_loop_teacher_forced():
+    """Three closed-loop steps of C2-shaped dynamics at C1 size: at each step the
+    oracle solves from the library's own state X_k and applied U_{k-1}."""
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    X = prob.X0.copy()
+    Up = np.zeros((p.l, p.m), np.float32)
+    with oic.controller_for(prob) as c:
+        for k in range(3):
+            Xref = wl.reference_window(p, k)
+            z = philox.solve_noise(100 + k, p.n, p.m, p.l, p.N, p.H)
+            U, _ = c.solve(X, Xref, prob.Q, prob.R, p.N, p.H, 100 + k)
+            ref = enks.solve(prob.B, prob.weights, p.activation, X, Xref, prob.Q, prob.Q, prob.R,
+                             p.N, p.H, *z, U_prev=Up)
+            assert relerr(U, ref.U_mean) < TOL_FP32, k
+            Up = c.get_u_prev()
+            assert np.array_equal(Up, U[0])
+            Xn = c.plant_step(X, Up)
+            assert relerr(Xn, enks.plant_step(X, Up, prob.B, prob.weights, p.activation)) < TOL_FP32
+            X = Xn
