@@ -23,23 +23,31 @@ def conv3x3(x: np.ndarray, w: np.ndarray, b=None) -> np.ndarray:
 
     x: (..., C_in, n, m); w: (C_out, C_in, 3, 3); returns (..., C_out, n, m) with
     out[o, y, x] = sum_c sum_{a,b in 0..2} w[o, c, a, b] * in[c, y+a-1, x+b-1].
+    Written as one matrix product of the (C_out, 9 C_in) weights with the
+    (9 C_in, n m) matrix of shifted copies of the input (im2col), in batch chunks.
     """
     x = np.asarray(x, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
     *lead, cin, n, m = x.shape
     cout = w.shape[0]
     assert w.shape == (cout, cin, 3, 3)
-    pad = np.zeros(tuple(lead) + (cin, n + 2, m + 2))
-    pad[..., 1:n + 1, 1:m + 1] = x
-    out = np.zeros(tuple(lead) + (cout, n, m))
-    for a in range(3):
-        for b_ in range(3):
-            patch = pad[..., a:a + n, b_:b_ + m]  # in[c, y+a-1, x+b-1]
-            # contract the channel axis of the patch with w[:, :, a, b]
-            out += np.moveaxis(np.tensordot(patch, w[:, :, a, b_], axes=([-3], [1])), -1, -3)
+    xb = x.reshape(-1, cin, n, m)
+    B = xb.shape[0]
+    pad = np.zeros((B, cin, n + 2, m + 2))
+    pad[:, :, 1:n + 1, 1:m + 1] = xb
+    out = np.empty((B, cout, n * m))
+    step = max(1, (1 << 23) // (cin * 9 * n * m))
+    for s in range(0, B, step):
+        e = min(B, s + step)
+        cols = np.empty((e - s, cin, 9, n * m))
+        for a in range(3):
+            for b_ in range(3):
+                # row (c, 3a+b) of the column matrix holds in[c, y+a-1, x+b-1]
+                cols[:, :, 3 * a + b_, :] = pad[s:e, :, a:a + n, b_:b_ + m].reshape(e - s, cin, n * m)
+        np.matmul(w.reshape(cout, cin * 9), cols.reshape(e - s, cin * 9, n * m), out=out[s:e])
     if b is not None:
-        out += np.asarray(b, dtype=np.float64)[:, None, None]
-    return out
+        out += np.asarray(b, dtype=np.float64)[:, None]
+    return out.reshape(tuple(lead) + (cout, n, m))
 
 
 def activation(x: np.ndarray, kind: int) -> np.ndarray:

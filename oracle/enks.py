@@ -61,8 +61,9 @@ def analysis(Xcal, Y, Ybar_t):
     Ymean = Y.mean(axis=0)             # Eq. (13a), with 1/N
     A = Xcal - Xcal_mean
     D = Y - Ymean
-    Syy = (lam / N) * np.einsum("iam,ibm->ab", D, D)   # Eq. (13b)
-    Sxy = (lam / N) * np.einsum("iam,ibm->ab", A, D)   # Eq. (13c)
+    # Eqs. (13b), (13c): sum over members i and columns of A^i D^iT (a library contraction)
+    Syy = (lam / N) * np.tensordot(D, D, axes=([0, 2], [0, 2]))
+    Sxy = (lam / N) * np.tensordot(A, D, axes=([0, 2], [0, 2]))
     # Eq. (14b): gain Sigma^{XY} (Sigma^Y)^{-1}, through the Cholesky factor of Sigma^Y.
     Ly = _chol_lower(Syy)
     K = np.linalg.solve(Ly.T, np.linalg.solve(Ly, Sxy.T)).T
