@@ -55,14 +55,16 @@ def algorithmic_work(p, H):
             add(cls, 2.0 * 9 * ci * co * n * m * N, 4.0 * n * m * N * (ci + co))
         add("stats", 2.0 * (Ma + pp) * pp * NM, 4.0 * (Ma + pp) * NM)
         add("update", 2.0 * Ma * pp * NM, 4.0 * (2 * Ma + pp) * NM)
-        add("means", float(Ma + pp) * NM, 4.0 * (Ma + pp) * NM)
-        add("gain", pp ** 3 / 3.0 + 2.0 * pp * pp * Ma, 8.0 * (Ma + pp) * pp)
+        add("means", float(pp) * NM, 4.0 * pp * NM)
+        add("chol", float(pp) ** 3, 16.0 * pp * pp)  # Cholesky, triangular inverse, W^T W
+        add("gain", 2.0 * pp * pp * Ma, 8.0 * (Ma * pp + pp * pp) + 4.0 * Ma * pp)
+    add("means", float((H + 1) * rr) * NM, 4.0 * (H + 1) * rr * NM)  # final smoothed means
     return work
 
 
 def roofline_for(cls, flops, nbytes, ms, launches, precision):
     sec = ms * 1e-3
-    fpeak = PEAK["fp64"] if cls in ("stats", "gain") else (
+    fpeak = PEAK["fp64"] if cls in ("stats", "gain", "chol") else (
         PEAK["bf16"] if (precision == "bf16" and cls.startswith("conv")) else PEAK["fp32"])
     t_f = flops / fpeak
     t_b = nbytes / PEAK["hbm"]
@@ -72,7 +74,7 @@ def roofline_for(cls, flops, nbytes, ms, launches, precision):
                 "frac": ach / (PEAK["hbm"] / 1e9), "traffic": None, "kernel_class": cls,
                 "launches": launches, "avg_launch_us": 1e3 * ms / max(launches, 1)}
     ach = flops / sec / 1e12
-    kind = "mfma" if cls.startswith("conv") and precision == "bf16" else "alu"
+    kind = "mfma" if cls in ("conv_mid", "stats", "gain", "update") else "alu"
     return {"bound": kind, "achieved": ach, "peak": fpeak / 1e12, "unit": "TFLOP/s",
             "frac": ach / (fpeak / 1e12), "traffic": None, "kernel_class": cls,
             "launches": launches, "avg_launch_us": 1e3 * ms / max(launches, 1)}
@@ -141,9 +143,12 @@ def main():
     ctrl = oic.controller_for(prob, precision=prec, mem_mode=oic.OIC_MEM_DEVICE, stream=stream)
     X0 = torch.from_numpy(prob.X0).to(dev)
     Ubuf = torch.empty((p.H + 1, p.l, p.m), dtype=torch.float32, device=dev)
+    Xbuf = torch.empty((p.H + 1, p.n, p.m), dtype=torch.float32, device=dev)
 
     def step(k, X):
-        ctrl.solve(X, refs[k], prob.Q, prob.R, p.N, p.H, p.noise_seed_base + k, U_out=Ubuf)
+        # full smoother output: U_hat and X_hat of every slice (Algorithm 1, line 13)
+        ctrl.solve(X, refs[k], prob.Q, prob.R, p.N, p.H, p.noise_seed_base + k, U_out=Ubuf,
+                   X_out=Xbuf)
         return ctrl.plant_step(X, Ubuf[0])
 
     X = X0
@@ -170,7 +175,7 @@ def main():
             continue
         f, b = work.get(cls, (0.0, 0.0))
         per_class[cls] = {"launches": cnt, "total_ms": ms, "flop": f * K, "bytes": b * K}
-    dom = max((c for c in per_class if c in work), key=lambda c: per_class[c]["total_ms"])
+    dom = max(per_class, key=lambda c: per_class[c]["total_ms"])
     d = per_class[dom]
     roof = roofline_for(dom, d["flop"], d["bytes"], d["total_ms"], d["launches"], args.precision)
 

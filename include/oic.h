@@ -168,6 +168,12 @@ int oic_kernel_stats(oic_handle h, int id, const char** name, long long* launche
 /* Stream the handle orders its work on (a hipStream_t). */
 void* oic_stream(oic_handle h);
 
+/* Replay the kernel sequence of a solve from a HIP graph, captured on the first
+ * solve of each (N, horizon, seeded or explicit noise) and reused while those stay
+ * the same.  On by default.  While per-kernel timing is enabled the sequence is
+ * launched kernel by kernel instead.  Results are identical either way. */
+int oic_set_graph(oic_handle h, int enable);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,7 +45,11 @@ __device__ __forceinline__ float philox_normal(uint64_t seed, uint32_t kind, uin
   return (float)z;
 }
 
-__global__ void k_normals(float* __restrict__ out, size_t count, uint64_t seed, uint32_t kind) {
+// The seed is read from device memory so that a captured solve can be replayed with a
+// new seed without touching the graph.
+__global__ void k_normals(float* __restrict__ out, size_t count, const uint64_t* __restrict__ seed_ptr,
+                          uint32_t kind) {
+  const uint64_t seed = *seed_ptr;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
     out[e] = philox_normal(seed, kind, e);
@@ -61,14 +65,16 @@ __device__ __forceinline__ float noise_value(const NoiseRef& nr, int a, int i, i
   return acc;
 }
 
-// Slice k of every member: X rows = X_k (no spread), U rows = U_prev + W_0^i.
+// Slice k of every member: X rows = X_k (no spread), U rows = U_prev + W_0^i.  Also
+// clears the positive-definiteness flag of the solve.
 __global__ void k_init_slice0(Dims d, float* __restrict__ traj, const float* __restrict__ X0,
-                              const float* __restrict__ Uprev, NoiseRef w0) {
-  const long long NM = d.NM();
-  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                              const float* __restrict__ Uprev, NoiseRef w0, int* __restrict__ flag) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *flag = 0;
+  const int NM = (int)d.NM();
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (col >= NM) return;
-  const int i = (int)(col / d.m), x = (int)(col - (long long)i * d.m);
+  const int i = col / d.m, x = col - i * d.m;
   float v;
   if (q < d.n) {
     v = X0[(size_t)q * d.m + x];
@@ -81,11 +87,11 @@ __global__ void k_init_slice0(Dims d, float* __restrict__ traj, const float* __r
 
 // U rows of slice t: U_t^i = U_{t-1}^i (after the analysis at t-1) + W_t^i.
 __global__ void k_assemble_u(Dims d, float* __restrict__ traj, int step, NoiseRef w) {
-  const long long NM = d.NM();
-  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int NM = (int)d.NM();
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
   if (col >= NM) return;
-  const int i = (int)(col / d.m), x = (int)(col - (long long)i * d.m);
+  const int i = col / d.m, x = col - i * d.m;
   const size_t rr = (size_t)d.rr();
   const float prev = traj[((size_t)(step - 1) * rr + d.n + a) * NM + col];
   traj[((size_t)step * rr + d.n + a) * NM + col] = prev + noise_value(w, a, i, x, d.m);
@@ -94,11 +100,11 @@ __global__ void k_assemble_u(Dims d, float* __restrict__ traj, int step, NoiseRe
 // Ybar^i_t = [X_t^i + V_X^i; U_t^i + V_U^i].
 __global__ void k_observe(Dims d, const float* __restrict__ traj, int step, float* __restrict__ Y,
                           NoiseRef vx, NoiseRef vu) {
-  const long long NM = d.NM();
-  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int NM = (int)d.NM();
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (col >= NM) return;
-  const int i = (int)(col / d.m), x = (int)(col - (long long)i * d.m);
+  const int i = col / d.m, x = col - i * d.m;
   const float s = traj[((size_t)step * d.rr() + q) * NM + col];
   const float v = q < d.n ? noise_value(vx, q, i, x, d.m) : noise_value(vu, q - d.n, i, x, d.m);
   Y[(size_t)q * NM + col] = s + v;
@@ -110,7 +116,8 @@ inline dim3 row_grid(long long NM, int rows) {
 
 }  // namespace
 
-void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, uint64_t seed, uint32_t kind) {
+void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, const uint64_t* seed,
+                    uint32_t kind) {
   if (!count) return;
   size_t blocks = (count + 255) / 256;
   if (blocks > 65536) blocks = 65536;
@@ -118,9 +125,9 @@ void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, uint64_t 
 }
 
 void launch_init_slice0(hipStream_t s, Timer& t, const Dims& d, float* traj, const float* X0,
-                        const float* Uprev, NoiseRef w0) {
+                        const float* Uprev, NoiseRef w0, int* flag) {
   OIC_LAUNCH(t, KC_INIT, s, k_init_slice0, row_grid(d.NM(), d.rr()), dim3(256), 0, d, traj, X0,
-             Uprev, w0);
+             Uprev, w0, flag);
 }
 
 void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int step, NoiseRef w) {

@@ -91,6 +91,8 @@ struct oic_ctx {
   bool weights_set = false;
   float* dB = nullptr;
   float* dW[OIC_MAX_LAYERS] = {};
+  float* dWk[OIC_MAX_LAYERS] = {};     // [tap*cin + c][cout] FP32 copies for the MFMA layers
+  uint16_t* dWb[OIC_MAX_LAYERS] = {};  // [cout][tap*cin + c] BF16 copies for the BF16 rollout
   float* dBias[OIC_MAX_LAYERS] = {};
   int cmax = 2;
 
@@ -99,7 +101,7 @@ struct oic_ctx {
   float* Y = nullptr;
   float* act[2] = {nullptr, nullptr};
   float* mu_traj = nullptr;
-  float* muY = nullptr;
+  double* muY = nullptr;  // FP64 means of Ybar
   double* S = nullptr;
   double* part = nullptr;
   int max_splits = 32;
@@ -115,6 +117,14 @@ struct oic_ctx {
   float* io = nullptr;                    // staging for host-memory inputs and outputs
   size_t io_floats = 0;
   float* out_stage = nullptr;             // solve outputs before the success check
+  uint64_t* dseed = nullptr;              // device copy of the solve's seed
+  uint64_t* hseed = nullptr;              // pinned host staging for it
+
+  // replay of the per-solve kernel sequence
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  int gN = 0, gH = 0;
+  bool gSeeded = false;
 };
 
 namespace {
@@ -253,6 +263,8 @@ void free_all(oic_ctx* h) {
   f(h->dB);
   for (int k = 0; k < OIC_MAX_LAYERS; ++k) {
     f(h->dW[k]);
+    f(h->dWk[k]);
+    f(h->dWb[k]);
     f(h->dBias[k]);
   }
   f(h->traj);
@@ -272,24 +284,83 @@ void free_all(oic_ctx* h) {
   f(h->fac);
   f(h->io);
   f(h->out_stage);
+  f(h->dseed);
+  if (h->hseed) hipHostFree(h->hseed);
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
 }
 
 // Runs the CNN of Eq. (1) on `batch` fields given as strided sources, writing the
 // single output channel to `out`.
-void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out) {
+// True when the handle's rollout runs with BF16 activations: BF16 precision was
+// requested and every layer has a BF16 kernel (first 2->C, hidden C->C', last C->1).
+bool rollout_bf16(oic_ctx* h) {
   const oic_config& c = h->cfg;
   const int L = c.n_layers;
-  launch_lift(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, h->act[0]);
+  if (c.precision != OIC_PREC_BF16 || L < 2) return false;
+  if (!conv_first_supported(c.channels[1], c.l) || !conv_last_supported(c.channels[L - 1])) return false;
+  for (int k = 1; k < L - 1; ++k)
+    if (!h->dWb[k]) return false;
+  return true;
+}
+
+// Runs the CNN of Eq. (1) on `batch` fields given as strided sources, writing the
+// single output channel to `out`.  bf16 selects BF16 activations (see rollout_bf16).
+void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, bool bf16) {
+  const oic_config& c = h->cfg;
+  const int L = c.n_layers;
+  if (bf16) {
+    launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
+                      h->dBias[0], c.activation, h->act[1], true);
+    int cur = 1;
+    for (int k = 1; k < L - 1; ++k) {
+      launch_conv_mfma_bf16(h->stream, h->timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
+                            c.channels[k + 1], h->act[cur], h->dWb[k], h->dBias[k], c.activation,
+                            h->act[1 - cur]);
+      cur = 1 - cur;
+    }
+    launch_conv_last(h->stream, h->timer, batch, c.n, c.m, c.channels[L - 1], h->act[cur],
+                     h->dW[L - 1], h->dBias[L - 1], out, true);
+    return;
+  }
   int cur = 0;
-  for (int k = 0; k < L; ++k) {
+  int k0 = 0;
+  if (L > 1 && conv_first_supported(c.channels[1], c.l)) {
+    // lift fused into the first layer
+    launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
+                      h->dBias[0], c.activation, h->act[1], false);
+    cur = 1;
+    k0 = 1;
+  } else {
+    launch_lift(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, h->act[0]);
+  }
+  for (int k = k0; k < L; ++k) {
     const int cin = c.channels[k], cout = c.channels[k + 1];
     const bool last = k == L - 1;
     const int cls = k == 0 ? KC_CONV_FIRST : (last ? KC_CONV_LAST : KC_CONV_MID);
+    if (last && k > 0 && conv_last_supported(cin)) {
+      launch_conv_last(h->stream, h->timer, batch, c.n, c.m, cin, h->act[cur], h->dW[k], h->dBias[k],
+                       out, false);
+      continue;
+    }
+    if (!last && h->dWk[k]) {
+      launch_conv_mfma(h->stream, h->timer, cls, batch, c.n, c.m, cin, cout, h->act[cur], h->dWk[k],
+                       h->dBias[k], c.activation, h->act[1 - cur]);
+      cur = 1 - cur;
+      continue;
+    }
     FieldOut fo = last ? out : FieldOut{nullptr, 0, 0};
     launch_conv(h->stream, h->timer, cls, batch, c.n, c.m, cin, cout, h->act[cur], h->dW[k],
                 h->dBias[k], c.activation, last ? nullptr : h->act[1 - cur], fo);
     cur = 1 - cur;
   }
+}
+
+uint16_t host_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, sizeof(u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
 
 int copy_in(oic_ctx* h, float* dst, const float* src, size_t count) {
@@ -306,6 +377,54 @@ int copy_out(oic_ctx* h, float* dst, const float* src, size_t count) {
   else
     HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
   return OIC_OK;
+}
+
+// Every kernel of one solve, in order, on the handle's stream.  Reads only handle-owned
+// buffers (inputs and noise are copied in beforehand; the seed is in device memory),
+// so the same sequence can be captured once and replayed.
+void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
+  const oic_config& c = h->cfg;
+  const int N = d.N, H = d.H, n = c.n, m = c.m, l = c.l, rr = d.rr(), p = d.p();
+  const long long NM = d.NM();
+  hipStream_t s = h->stream;
+  float* dX0 = h->io;
+  float* dRef = dX0 + (size_t)n * m;
+  float* dUp = dRef + (size_t)(c.max_H + 1) * n * m;
+  const size_t cnt[4] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
+                         (size_t)H * N * l * m};
+  if (seeded)
+    for (int k = 0; k < 4; ++k) launch_normals(s, h->timer, h->Z[k], cnt[k], h->dseed, (uint32_t)k);
+  const float* const* Zd = h->Z;
+  // Line 4: initial ensemble (also clears the failure flag).
+  launch_init_slice0(s, h->timer, d, h->traj, dX0, dUp, noise_ref(h, Zd[0], true), h->flag);
+  for (int t = 1; t <= H; ++t) {
+    const size_t slice = (size_t)rr * NM;
+    float* prev = h->traj + (size_t)(t - 1) * slice;
+    float* cur = h->traj + (size_t)t * slice;
+    // Line 6 / Eq. (15b): X rows of slice t through the CNN, from the analysed slice t-1.
+    rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
+            FieldOut{cur, m, NM}, rollout_bf16(h));
+    launch_assemble_u(s, h->timer, d, h->traj, t,
+                      noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true));
+    // Line 9 / Eq. (12).
+    launch_observe(s, h->timer, d, h->traj, t, h->Y,
+                   noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
+                   noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true));
+    // Eq. (13a): mean of Ybar in FP64.  The trajectory rows need no mean here: the
+    // FP64-centred Ybar anomalies sum to zero, so sum_i X^i D^iT = sum_i A^i D^iT.
+    const int Ma = (t + 1) * rr;
+    launch_means_f64(s, h->timer, h->Y, p, N, m, h->muY);
+    // Eqs. (13b), (13c).
+    launch_stats(s, h->timer, d, h->traj, Ma, h->Y, h->muY, h->part, h->max_splits, h->S);
+    // Eq. (14b): gain, then line 10: analysis of every stored slice.
+    launch_chol_gain(s, h->timer, d, Ma, h->S, h->Lwork, h->part, h->K, h->flag);
+    launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m);
+  }
+  // Line 13: smoothed means of every slice.
+  launch_means(s, h->timer, h->traj, (H + 1) * rr, N, m, h->mu_traj);
+  float* sU = h->out_stage;
+  float* sX = sU + (size_t)(c.max_H + 1) * l * m;
+  launch_extract(s, h->timer, d, h->mu_traj, sU, sX, h->Uprev_new);
 }
 
 int solve_impl(oic_ctx* h, const oic_solve_args* a) {
@@ -352,52 +471,40 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   const size_t cnt[4] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
                          (size_t)H * N * l * m};
   const float* zsrc[4] = {a->Z_init, a->Z_W, a->Z_VX, a->Z_VU};
-  const float* Zd[4];
-  for (int k = 0; k < 4; ++k) {
-    if (explicit_noise) {
-      if (c.mem_mode == OIC_MEM_HOST) {
-        if ((rc = copy_in(h, h->Z[k], zsrc[k], cnt[k]))) return rc;
-        Zd[k] = h->Z[k];
-      } else {
-        Zd[k] = zsrc[k];
+  if (explicit_noise) {
+    for (int k = 0; k < 4; ++k)
+      if ((rc = copy_in(h, h->Z[k], zsrc[k], cnt[k]))) return rc;
+  } else {
+    *h->hseed = a->seed;
+    HIP_TRY(hipMemcpyAsync(h->dseed, h->hseed, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  }
+  const bool seeded = !explicit_noise;
+  if (h->use_graph && !h->timer.enabled) {
+    if (!h->gexec || h->gN != N || h->gH != H || h->gSeeded != seeded) {
+      if (h->gexec) {
+        hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
       }
-    } else {
-      launch_normals(s, h->timer, h->Z[k], cnt[k], a->seed, (uint32_t)k);
-      Zd[k] = h->Z[k];
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      enqueue_solve(h, d, seeded);
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamEndCapture(s, &g));
+      hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        h->gexec = nullptr;
+        return fail(h, OIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+      h->gN = N;
+      h->gH = H;
+      h->gSeeded = seeded;
     }
+    HIP_TRY(hipGraphLaunch(h->gexec, s));
+  } else {
+    enqueue_solve(h, d, seeded);
   }
-  HIP_TRY(hipMemsetAsync(h->flag, 0, sizeof(int), s));
-
-  // Line 4: initial ensemble.
-  launch_init_slice0(s, h->timer, d, h->traj, dX0, dUp, noise_ref(h, Zd[0], true));
-  for (int t = 1; t <= H; ++t) {
-    const size_t slice = (size_t)rr * NM;
-    float* prev = h->traj + (size_t)(t - 1) * slice;
-    float* cur = h->traj + (size_t)t * slice;
-    // Line 6 / Eq. (15b): X rows of slice t through the CNN, from the analysed slice t-1.
-    rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
-            FieldOut{cur, m, NM});
-    launch_assemble_u(s, h->timer, d, h->traj, t,
-                      noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true));
-    // Line 9 / Eq. (12).
-    launch_observe(s, h->timer, d, h->traj, t, h->Y,
-                   noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
-                   noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true));
-    // Eqs. (11), (13a): means of slices k..t and of Ybar.
-    const int Ma = (t + 1) * rr;
-    launch_means(s, h->timer, h->traj, Ma, N, m, h->mu_traj);
-    launch_means(s, h->timer, h->Y, p, N, m, h->muY);
-    // Eqs. (13b), (13c).
-    launch_stats(s, h->timer, d, h->traj, h->mu_traj, Ma, h->Y, h->muY, h->part, h->max_splits, h->S);
-    // Eq. (14b): gain, then line 10: analysis of every stored slice.
-    launch_chol_gain(s, h->timer, d, Ma, h->S, h->Lwork, h->part, h->K, h->flag);
-    launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m);
-  }
-  // Line 13: smoothed means of every slice.
-  launch_means(s, h->timer, h->traj, (H + 1) * rr, N, m, h->mu_traj);
   float* sU = h->out_stage;
   float* sX = sU + (size_t)(c.max_H + 1) * l * m;
-  launch_extract(s, h->timer, d, h->mu_traj, sU, sX, h->Uprev_new);
   int flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -425,6 +532,8 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
       (c.mem_mode != OIC_MEM_HOST && c.mem_mode != OIC_MEM_DEVICE))
     return OIC_EINVAL;
   if (c.channels[0] != 2 || c.channels[c.n_layers] != 1) return OIC_EINVAL;
+  // column indices of one trajectory row (N*m) are 32-bit in the kernels
+  if ((long long)c.max_N * c.m >= (1LL << 31) || c.n + c.l > 512) return OIC_EINVAL;
   for (int k = 1; k < c.n_layers; ++k)
     if (c.channels[k] < 1 || c.channels[k] > 128) return OIC_EINVAL;
   oic_ctx* h = new (std::nothrow) oic_ctx();
@@ -453,10 +562,10 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   rc = rc ? rc : dalloc(h, &h->act[0], N * n * m * (size_t)h->cmax);
   rc = rc ? rc : dalloc(h, &h->act[1], N * n * m * (size_t)h->cmax);
   rc = rc ? rc : dalloc(h, &h->mu_traj, Ma_max * m);
-  rc = rc ? rc : dalloc(h, &h->muY, p * m);
+  rc = rc ? rc : dalloc(h, &h->muY, p * m);  // doubles
   rc = rc ? rc : dalloc(h, &h->S, (Ma_max + p) * p);
   rc = rc ? rc : dalloc(h, &h->part, std::max((size_t)h->max_splits * (Ma_max + p) * p, Ma_max * p));
-  rc = rc ? rc : dalloc(h, &h->Lwork, p * p);
+  rc = rc ? rc : dalloc(h, &h->Lwork, 2 * p * p);
   rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
   rc = rc ? rc : dalloc(h, &h->flag, 1);
   for (int k = 0; k < 4 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));
@@ -467,6 +576,11 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   h->io_floats = n * m + Hs * n * m + l * m + N * (n + l) * m + N * n * m;
   rc = rc ? rc : dalloc(h, &h->io, h->io_floats);
   rc = rc ? rc : dalloc(h, &h->out_stage, Hs * (l + n) * m);
+  rc = rc ? rc : dalloc(h, &h->dseed, 1);
+  if (!rc && hipHostMalloc((void**)&h->hseed, sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+    h->hseed = nullptr;
+    rc = OIC_ENOMEM;
+  }
   if (!rc && hipMemsetAsync(h->Uprev, 0, l * m * sizeof(float), h->stream) != hipSuccess)
     rc = OIC_EDEVICE;
   if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = OIC_EDEVICE;
@@ -510,6 +624,28 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
     const size_t cnt = (size_t)c.channels[k + 1] * c.channels[k] * 9;
     if (!h->dW[k] && (rc = dalloc(h, &h->dW[k], cnt))) return rc;
     HIP_TRY(hipMemcpyAsync(h->dW[k], W[k], cnt * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    const int cin = c.channels[k], cout = c.channels[k + 1];
+    if (k < c.n_layers - 1 && conv_mfma_supported(cin, cout)) {
+      // re-lay out [o][c][dy][dx] -> [(dy*3+dx)*cin + c][o]
+      std::vector<float> wk(cnt);
+      for (int o = 0; o < cout; ++o)
+        for (int ci = 0; ci < cin; ++ci)
+          for (int tap = 0; tap < 9; ++tap)
+            wk[((size_t)tap * cin + ci) * cout + o] = W[k][((size_t)o * cin + ci) * 9 + tap];
+      if (!h->dWk[k] && (rc = dalloc(h, &h->dWk[k], cnt))) return rc;
+      HIP_TRY(hipMemcpy(h->dWk[k], wk.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (c.precision == OIC_PREC_BF16 && k > 0 && k < c.n_layers - 1 && conv_mfma_bf16_supported(cin, cout)) {
+      // BF16 copy, [o][c][dy][dx] -> [o][(dy*3+dx)*cin + c]
+      std::vector<uint16_t> wb(cnt);
+      for (int o = 0; o < cout; ++o)
+        for (int ci = 0; ci < cin; ++ci)
+          for (int tap = 0; tap < 9; ++tap)
+            wb[(size_t)o * 9 * cin + (size_t)tap * cin + ci] =
+                host_bf16(W[k][((size_t)o * cin + ci) * 9 + tap]);
+      if (!h->dWb[k] && (rc = dalloc(h, &h->dWb[k], cnt))) return rc;
+      HIP_TRY(hipMemcpy(h->dWb[k], wb.data(), cnt * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
     if (bias && bias[k]) {
       if (!h->dBias[k] && (rc = dalloc(h, &h->dBias[k], (size_t)c.channels[k + 1]))) return rc;
       HIP_TRY(hipMemcpyAsync(h->dBias[k], bias[k], c.channels[k + 1] * sizeof(float),
@@ -561,7 +697,9 @@ int oic_solve(oic_handle h, const float* X0, const float* reference, const float
 
 int oic_solve_ex(oic_handle h, const oic_solve_args* a) { return solve_impl(h, a); }
 
-int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, float* X_next) {
+namespace {
+int cnn_forward_impl(oic_handle h, int batch, const float* X, const float* U, float* X_next,
+                     bool fp32_only) {
   if (!h) return OIC_EINVAL;
   h->err.clear();
   const oic_config& c = h->cfg;
@@ -576,15 +714,23 @@ int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, flo
   if ((rc = copy_in(h, dX, X, batch * n * m))) return rc;
   if ((rc = copy_in(h, dU, U, batch * l * m))) return rc;
   rollout(h, batch, FieldRef{dX, (long long)(n * m), (long long)m},
-          FieldRef{dU, (long long)(l * m), (long long)m}, FieldOut{dO, (long long)(n * m), (long long)m});
+          FieldRef{dU, (long long)(l * m), (long long)m}, FieldOut{dO, (long long)(n * m), (long long)m},
+          fp32_only ? false : rollout_bf16(h));
   if ((rc = copy_out(h, X_next, dO, batch * n * m))) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->timer.harvest();
   return OIC_OK;
 }
 
+}  // namespace
+
+int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, float* X_next) {
+  return cnn_forward_impl(h, batch, X, U, X_next, false);
+}
+
 int oic_plant_step(oic_handle h, const float* X, const float* U, float* X_next) {
-  return oic_cnn_forward(h, 1, X, U, X_next);
+  // the plant stands for the real system: always the FP32 surrogate
+  return cnn_forward_impl(h, 1, X, U, X_next, true);
 }
 
 int oic_normals(oic_handle h, uint64_t seed, int kind, size_t count, float* out) {
@@ -592,7 +738,9 @@ int oic_normals(oic_handle h, uint64_t seed, int kind, size_t count, float* out)
   h->err.clear();
   if (kind < 0 || kind > 3 || !out) return fail(h, OIC_EINVAL, "bad kind or NULL output");
   if (count > noise_floats(h->cfg, kind)) return fail(h, OIC_ENOMEM, "count exceeds the noise capacity");
-  launch_normals(h->stream, h->timer, h->Z[kind], count, seed, (uint32_t)kind);
+  *h->hseed = seed;
+  HIP_TRY(hipMemcpyAsync(h->dseed, h->hseed, sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
+  launch_normals(h->stream, h->timer, h->Z[kind], count, h->dseed, (uint32_t)kind);
   int rc = copy_out(h, out, h->Z[kind], count);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -620,5 +768,16 @@ int oic_kernel_stats(oic_handle h, int id, const char** name, long long* launche
 }
 
 void* oic_stream(oic_handle h) { return h ? (void*)h->stream : nullptr; }
+
+int oic_set_graph(oic_handle h, int enable) {
+  if (!h) return OIC_EINVAL;
+  h->use_graph = enable != 0;
+  if (!h->use_graph && h->gexec) {
+    hipStreamSynchronize(h->stream);
+    hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  return OIC_OK;
+}
 
 }  // extern "C"

@@ -78,10 +78,11 @@ struct Dims {
 };
 
 // ---- kernel launchers (defined in the .hip files) ----
-void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, uint64_t seed, uint32_t kind);
+void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, const uint64_t* seed,
+                    uint32_t kind);
 
 void launch_init_slice0(hipStream_t s, Timer& t, const Dims& d, float* traj, const float* X0,
-                        const float* Uprev, NoiseRef w0);
+                        const float* Uprev, NoiseRef w0, int* flag);
 void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int step, NoiseRef w);
 void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
                     NoiseRef vx, NoiseRef vu);
@@ -101,15 +102,39 @@ void launch_conv(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int c
                  const float* in_nhwc, const float* w_oihw, const float* bias, int act,
                  float* out_nhwc, FieldOut final_out);
 
+// First layer with the lift fused (2 -> cout) and last layer (cin -> 1) on tiles.
+bool conv_first_supported(int cout, int l);
+bool conv_last_supported(int cin);
+// bf16: activations are stored as BF16 (first layer output, last layer input).
+void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
+                       const float* B, int cout, const float* w, const float* bias, int act,
+                       void* out_nhwc, bool bf16);
+void launch_conv_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
+                      const float* w, const float* bias, FieldOut fo, bool bf16);
+// Hidden layers in BF16 on MFMA.  wt holds BF16 weights as [cout][tap*cin + c].
+bool conv_mfma_bf16_supported(int cin, int cout);
+void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
+                           const void* in_nhwc, const void* wt, const float* bias, int act,
+                           void* out_nhwc);
+
+// Hidden layers on MFMA (FP32).  wk holds the weights as [tap*cin + c][cout].
+bool conv_mfma_supported(int cin, int cout);
+void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
+                      const float* in_nhwc, const float* wk, const float* bias, int act,
+                      float* out_nhwc);
+
 // Statistics and update.
 void launch_means(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, float* mean);
-void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, const float* mu_traj,
-                  int Ma, const float* Y, const float* muY, double* part, int max_splits,
-                  double* S);
+void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, double* mean);
+// S[a][b] (FP64, (Ma+p) x p): sum over columns of left row a times the FP64-centred Ybar row b;
+// left rows are the first Ma trajectory rows followed by the p rows of Ybar.
+void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, const float* Y,
+                  const double* muY, double* part, int max_splits, double* S);
 // Factor Sigma^Ybar (rows Ma..Ma+p-1 of S) in FP64 and solve K Sigma^Ybar = S[0:Ma] for the gain.
 // `scratch` holds p*Ma doubles.  flag is set to 1 when a pivot is not positive and finite.
 void launch_chol_gain(hipStream_t s, Timer& t, const Dims& d, int Ma, const double* S, double* Lwork,
                       double* scratch, float* K, int* flag);
+// Analysis of the first Ma trajectory rows (in place).
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
                    const float* Y, const float* xref_t);
 void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,

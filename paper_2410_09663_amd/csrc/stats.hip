@@ -2,10 +2,10 @@
 //
 // With the members of each row side by side (N*m columns), the pooled sums
 //   Sigma^{XY} ~ sum_i A^i D^iT  and  Sigma^Y ~ sum_i D^i D^iT
-// are row-by-row dot products over N*m columns of centred rows.  The factor
-// lambda/N of Eq. (13) is dropped: it cancels in the gain.  Products of the
-// FP32 anomalies are exact in FP64 and are accumulated in FP64; split-K partial
-// sums are reduced in a fixed order (no atomics), so results are deterministic.
+// are row-by-row dot products over N*m columns.  The factor lambda/N of Eq. (13)
+// is dropped: it cancels in the gain.  The products accumulate in FP64 and the
+// split-K partial sums are reduced in a fixed order (no atomics), so results are
+// deterministic.
 #include "oic_internal.h"
 
 namespace oic {
@@ -22,73 +22,229 @@ __global__ void k_means(const float* __restrict__ A, int rows, int N, int m, flo
   mean[idx] = (float)(s / N);
 }
 
-constexpr int TA = 32;  // rows of the left operand per tile
-constexpr int TB = 32;  // rows of the right operand (Y) per tile
-constexpr int KT = 32;  // columns per LDS stage
+// One block per row when m divides 256: thread t always sees column x = t mod m, sums
+// its members in FP64, and the 256/m partial sums of each column are added in a
+// fixed order in LDS.
+__global__ __launch_bounds__(256) void k_means_rows(const float* __restrict__ A, int N, int m,
+                                                    float* __restrict__ mean) {
+  __shared__ double part[256];
+  const int row = blockIdx.x;
+  const long long NM = (long long)N * m;
+  const float* src = A + (size_t)row * NM;
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (long long c = t; c < NM; c += 256) s += (double)src[c];
+  part[t] = s;
+  __syncthreads();
+  if (t < m) {
+    double tot = 0.0;
+    for (int g = t; g < 256; g += m) tot += part[g];
+    mean[(size_t)row * m + t] = (float)(tot / N);
+  }
+}
 
-// part[z][a][b] = sum over columns of chunk z of (L[a][c] - muL[a][c mod m]) (Y[b][c] - muY[b][c mod m]),
-// where left row a < Ma is trajectory row a and a >= Ma is Y row a - Ma.
-__global__ __launch_bounds__(256) void k_stats(Dims d, const float* __restrict__ traj,
-                                               const float* __restrict__ mu_traj, int Ma,
-                                               const float* __restrict__ Y,
-                                               const float* __restrict__ muY, long long chunk,
-                                               double* __restrict__ part) {
-  __shared__ float sA[KT][TA + 1];
-  __shared__ float sB[KT][TB + 1];
-  const long long NM = d.NM();
+typedef float f32x4m __attribute__((ext_vector_type(4)));
+
+// One block per row, float4 loads: when m is a multiple of 4 that divides 1024, thread
+// t always sees columns x = (4t mod m) .. +3; it accumulates them in FP64 over its
+// members (loads batched 8 at a time), and the 1024/m partial sums of each column
+// are added in a fixed order in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_means_rows_v4(const float* __restrict__ A, int N, int m,
+                                                       T* __restrict__ mean) {
+  __shared__ double part[256][4];
+  const int row = blockIdx.x;
+  const int NM4 = (N * m) / 4;
+  const f32x4m* src = (const f32x4m*)(A + (size_t)row * N * m);
+  const int t = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int q = t;
+  for (; q + 7 * 256 < NM4; q += 8 * 256) {
+    f32x4m v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[q + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s0 += (double)v[u][0];
+      s1 += (double)v[u][1];
+      s2 += (double)v[u][2];
+      s3 += (double)v[u][3];
+    }
+  }
+  for (; q < NM4; q += 256) {
+    const f32x4m v = src[q];
+    s0 += (double)v[0];
+    s1 += (double)v[1];
+    s2 += (double)v[2];
+    s3 += (double)v[3];
+  }
+  part[t][0] = s0;
+  part[t][1] = s1;
+  part[t][2] = s2;
+  part[t][3] = s3;
+  __syncthreads();
+  if (t < m) {
+    const int g = t / 4, j = t % 4, stride = m / 4;
+    double tot = 0.0;
+    for (int u = g; u < 256; u += stride) tot += part[u][j];
+    mean[(size_t)row * m + t] = (T)(tot / N);
+  }
+}
+
+// mean[row][x] in FP64 (same reduction order as k_means_rows).
+__global__ __launch_bounds__(256) void k_means_rows_f64(const float* __restrict__ A, int N, int m,
+                                                        double* __restrict__ mean) {
+  __shared__ double part[256];
+  const int row = blockIdx.x;
+  const long long NM = (long long)N * m;
+  const float* src = A + (size_t)row * NM;
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (long long c = t; c < NM; c += 256) s += (double)src[c];
+  part[t] = s;
+  __syncthreads();
+  if (t < m) {
+    double tot = 0.0;
+    for (int g = t; g < 256; g += m) tot += part[g];
+    mean[(size_t)row * m + t] = tot / N;
+  }
+}
+
+__global__ void k_means_f64(const float* __restrict__ A, int rows, int N, int m, double* __restrict__ mean) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)rows * m) return;
+  const int row = (int)(idx / m), x = (int)(idx - (long long)row * m);
+  const float* p = A + (size_t)row * N * m + x;
+  double s = 0.0;
+  for (int i = 0; i < N; ++i) s += (double)p[(size_t)i * m];
+  mean[idx] = s / N;
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+constexpr int MA = 64;  // left rows per tile (4 waves x 16)
+constexpr int MK = 64;  // columns per LDS stage
+
+// part[z][a][b] = sum over the columns c of chunk z of L[a][c] * D[b][c], where the
+// left row a is trajectory row a (a < Ma) or Ybar row a - Ma, and the right operand
+// D[b][c] = Ybar[b][c] - mean_i Ybar[b][c mod m] is centred in FP64.  Because the
+// FP64-centred D sums to zero over the members (to FP64 rounding), the left rows
+// need no centring: sum_i X^i D^iT = sum_i (X^i - mean) D^iT.
+//
+// FP64 matrix cores (v_mfma_f64_16x16x4_f64); a block of 4 waves owns 64 left rows
+// and NB*16 right rows; wave w computes left rows 16w..16w+15 against all NB
+// blocks.  Lane layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// element r of lane j + 16g holds D[g + 4r][j].  VEC: rows are 16-byte aligned
+// (N*m divisible by 4) and loaded as float4, one stage ahead of the compute.
+template <int NB, bool VEC>
+__global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restrict__ traj, int Ma,
+                                                    const float* __restrict__ Y,
+                                                    const double* __restrict__ muY, int chunk,
+                                                    double* __restrict__ part) {
+  constexpr int RB = NB * 16;
+  __shared__ float sA[MA][MK + 1];
+  __shared__ double sB[RB][MK + 1];
+  const int NM = (int)d.NM();
   const int m = d.m, p = d.p();
   const int Mtot = Ma + p;
-  const int a0 = blockIdx.x * TA;
-  const int b0 = blockIdx.y * TB;
-  const long long c_begin = (long long)blockIdx.z * chunk;
-  long long c_end = c_begin + chunk;
-  if (c_end > NM) c_end = NM;
+  const int a0 = blockIdx.x * MA;
+  const int b0 = blockIdx.y * RB;
+  const int c_begin = blockIdx.z * chunk;
+  const int c_end = min(c_begin + chunk, NM);
   const int tid = threadIdx.x;
-  const int ty = tid / 16, tx = tid % 16;
-  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-
-  for (long long c0 = c_begin; c0 < c_end; c0 += KT) {
-    // Load 32 x 32 tiles, centred, transposed into LDS.
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[NB];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int rloc = tid / KT + 8 * u;
-      const int kloc = tid % KT;
-      const long long c = c0 + kloc;
-      float va = 0.f, vb = 0.f;
-      if (c < c_end) {
-        const int x = (int)(c % m);
-        const int a = a0 + rloc;
-        if (a < Mtot) {
-          if (a < Ma)
-            va = traj[(size_t)a * NM + c] - mu_traj[(size_t)a * m + x];
-          else
-            va = Y[(size_t)(a - Ma) * NM + c] - muY[(size_t)(a - Ma) * m + x];
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // per-thread load slots: A tile = 64 rows x 64 cols; B tile = RB rows x 64 cols
+  constexpr int AV = MA * MK / 4 / 256;  // float4 slots per thread (4)
+  constexpr int BV = RB * MK / 4 / 256;  // (NB)
+  f32x4v ra[AV], rb[BV];
+  auto left_row = [&](int a) -> const float* {
+    return a < Ma ? traj + (size_t)a * NM : Y + (size_t)(a - Ma) * NM;
+  };
+  auto load_stage = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int a = a0 + r, c = c0 + 4 * q;
+      f32x4v v = {0.f, 0.f, 0.f, 0.f};
+      if (a < Mtot) {
+        const float* src = left_row(a);
+        if (VEC) {
+          if (c < c_end) v = *(const f32x4v*)(src + c);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = (c + j < c_end) ? src[c + j] : 0.f;
         }
-        const int b = b0 + rloc;
-        if (b < p) vb = Y[(size_t)b * NM + c] - muY[(size_t)b * m + x];
       }
-      sA[kloc][rloc] = va;
-      sB[kloc][rloc] = vb;
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int b = b0 + r, c = c0 + 4 * q;
+      f32x4v v = {0.f, 0.f, 0.f, 0.f};
+      if (b < p) {
+        const float* src = Y + (size_t)b * NM;
+        if (VEC) {
+          if (c < c_end) v = *(const f32x4v*)(src + c);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = (c + j < c_end) ? src[c + j] : 0.f;
+        }
+      }
+      rb[u] = v;
+    }
+  };
+  if (c_begin < c_end) load_stage(c_begin);
+  for (int c0 = c_begin; c0 < c_end; c0 += MK) {
+    // registers -> LDS (right operand centred in FP64)
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sA[r][4 * q + j] = ra[u][j];
+    }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int b = b0 + r, c = c0 + 4 * q;
+      int x = c % m;
+      const double* mu = muY + (size_t)(b < p ? b : 0) * m;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool live = b < p && c + j < c_end;
+        sB[r][4 * q + j] = live ? (double)rb[u][j] - mu[x] : 0.0;
+        x = (x + 1 == m) ? 0 : x + 1;
+      }
     }
     __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < KT; ++k) {
-      const double x0 = sA[k][2 * ty], x1 = sA[k][2 * ty + 1];
-      const double y0 = sB[k][2 * tx], y1 = sB[k][2 * tx + 1];
-      acc[0][0] = fma(x0, y0, acc[0][0]);
-      acc[0][1] = fma(x0, y1, acc[0][1]);
-      acc[1][0] = fma(x1, y0, acc[1][0]);
-      acc[1][1] = fma(x1, y1, acc[1][1]);
+    if (c0 + MK < c_end) load_stage(c0 + MK);  // prefetch the next stage
+#pragma unroll 4
+    for (int kk = 0; kk < MK; kk += 4) {
+      const double av = (double)sA[w * 16 + li][kk + lk];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sB[nb * 16 + li][kk + lk], acc[nb], 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = part + (size_t)blockIdx.z * Mtot * p;
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int a = a0 + 2 * ty + u, b = b0 + 2 * tx + v;
-      if (a < Mtot && b < p) out[(size_t)a * p + b] = acc[u][v];
+    for (int r = 0; r < 4; ++r) {
+      const int a = a0 + w * 16 + lk + 4 * r;
+      const int b = b0 + nb * 16 + li;
+      if (a < Mtot && b < p) out[(size_t)a * p + b] = acc[nb][r];
     }
 }
 
@@ -97,37 +253,86 @@ __global__ void k_stats_reduce(const double* __restrict__ part, int splits, long
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
   double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += part[(size_t)z * count + idx];
+  int z = 0;
+  for (; z + 8 <= splits; z += 8) {  // 8 loads in flight, summed in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(z + u) * count + idx];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; z < splits; ++z) s += part[(size_t)z * count + idx];
   S[idx] = s;
 }
 
 }  // namespace
 
+static bool means_v4_ok(int N, int m) { return m % 4 == 0 && 1024 % m == 0 && ((long long)N * m) % 4 == 0; }
+
 void launch_means(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, float* mean) {
   const long long total = (long long)rows * m;
   if (!total) return;
+  if (means_v4_ok(N, m)) {
+    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows_v4<float>, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    return;
+  }
+  if (m <= 256 && 256 % m == 0) {
+    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    return;
+  }
   OIC_LAUNCH(t, KC_MEANS, s, k_means, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, A, rows,
              N, m, mean);
 }
 
-void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, const float* mu_traj,
-                  int Ma, const float* Y, const float* muY, double* part, int max_splits,
-                  double* S) {
+void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, double* mean) {
+  const long long total = (long long)rows * m;
+  if (!total) return;
+  if (means_v4_ok(N, m)) {
+    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows_v4<double>, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    return;
+  }
+  if (m <= 256 && 256 % m == 0) {
+    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows_f64, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    return;
+  }
+  OIC_LAUNCH(t, KC_MEANS, s, k_means_f64, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, A,
+             rows, N, m, mean);
+}
+
+void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, const float* Y,
+                  const double* muY, double* part, int max_splits, double* S) {
   const int p = d.p();
   const int Mtot = Ma + p;
-  const long long NM = d.NM();
-  const int tiles = ((Mtot + TA - 1) / TA) * ((p + TB - 1) / TB);
-  // Enough split-K chunks to give the chip >= ~1024 workgroups, each chunk >= 256 columns.
-  int splits = (1024 + tiles - 1) / tiles;
-  const long long max_by_len = (NM + 255) / 256;
-  if (splits > max_by_len) splits = (int)max_by_len;
+  const int NM = (int)d.NM();
+  const int nbk = (p + 15) / 16;
+  const int NB = nbk > 8 ? 8 : nbk;  // right rows per block: NB*16 (grid.y covers the rest)
+  const int ytiles = (p + NB * 16 - 1) / (NB * 16);
+  const int tiles = ((Mtot + MA - 1) / MA) * ytiles;
+  // ~3 workgroups per CU in total, each chunk at least 4 stages of 64 columns.
+  int splits = (768 + tiles - 1) / tiles;
+  const int max_by_len = (NM + 255) / 256;
+  if (splits > max_by_len) splits = max_by_len;
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
-  long long chunk = (NM + splits - 1) / splits;
-  chunk = (chunk + KT - 1) / KT * KT;
-  splits = (int)((NM + chunk - 1) / chunk);
-  const dim3 grid((unsigned)((Mtot + TA - 1) / TA), (unsigned)((p + TB - 1) / TB), (unsigned)splits);
-  OIC_LAUNCH(t, KC_STATS, s, k_stats, grid, dim3(256), 0, d, traj, mu_traj, Ma, Y, muY, chunk, part);
+  int chunk = (NM + splits - 1) / splits;
+  chunk = (chunk + MK - 1) / MK * MK;
+  splits = (NM + chunk - 1) / chunk;
+  const dim3 grid((unsigned)((Mtot + MA - 1) / MA), (unsigned)ytiles, (unsigned)splits);
+  const bool vec = NM % 4 == 0;
+#define OIC_STATS_CASE(NBV)                                                                     \
+  case NBV:                                                                                     \
+    if (vec)                                                                                    \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, true>), grid, dim3(256), 0, d, traj, Ma, Y,  \
+                 muY, chunk, part);                                                             \
+    else                                                                                        \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, false>), grid, dim3(256), 0, d, traj, Ma, Y, \
+                 muY, chunk, part);                                                             \
+    break;
+  switch (NB) {
+    OIC_STATS_CASE(1) OIC_STATS_CASE(2) OIC_STATS_CASE(3) OIC_STATS_CASE(4)
+    OIC_STATS_CASE(5) OIC_STATS_CASE(6) OIC_STATS_CASE(7) OIC_STATS_CASE(8)
+  }
+#undef OIC_STATS_CASE
   const long long count = (long long)Mtot * p;
   OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256),
              0, part, splits, count, S);

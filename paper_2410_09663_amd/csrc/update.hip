@@ -1,77 +1,101 @@
 // Ensemble analysis over the whole stored trajectory, Eq. (14b) with Eq. (15c):
 //   Xcal^i <- Xcal^i + K (Ybar_t - Ybar^i)   for every member i and every slice k..t,
 // which is the lag update that turns the forward pass into a smoother (Eq. (7)).
-// As a matrix product: (rows x p) times (p x N*m), added in place.
+// As a matrix product: (rows x p) times (p x N*m), added in place.  The innovation
+// has mean Ybar_t - mean(Ybar^i), so the updated members' mean moves by K times that
+// (Eq. (14a)); the means are recomputed once at the end of the solve.
 #include "oic_internal.h"
 
 namespace oic {
 namespace {
 
-constexpr int UT_R = 64;  // trajectory rows per tile
-constexpr int UT_C = 64;  // columns per tile
-constexpr int UT_K = 16;  // observation rows per LDS stage
+typedef float f32x4u __attribute__((ext_vector_type(4)));
 
-// traj[a][c] += sum_b K[a][b] (Ybar[b][c mod m] - Y[b][c]),  Ybar = [X^ref_t; 0].
-__global__ __launch_bounds__(256) void k_update(Dims d, float* __restrict__ traj, int Ma,
-                                                const float* __restrict__ K,
-                                                const float* __restrict__ Y,
-                                                const float* __restrict__ xref) {
-  __shared__ float sK[UT_K][UT_R + 1];
-  __shared__ float sE[UT_K][UT_C];
-  const long long NM = d.NM();
+constexpr int UR = 64;  // trajectory rows per tile (4 waves x 16)
+constexpr int UC = 64;  // columns per tile (4 N-blocks of 16)
+constexpr int PB = 80;  // observation rows per LDS stage
+
+// traj[a][c] += sum_b K[a][b] (Ybar[b][c mod m] - Y[b][c]),  Ybar = [X^ref_t; 0],
+// on the FP32 matrix cores (v_mfma_f32_16x16x4_f32).  Wave w owns trajectory rows
+// 16w..16w+15 of the tile and all 64 columns.  The gain tile, the innovation tile and
+// the lane's own 16 trajectory values are all requested before the first LDS store.
+// Lane layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, element r of
+// lane j + 16g holds D[4g + r][j].
+__global__ __launch_bounds__(256) void k_update_mfma(Dims d, float* __restrict__ traj, int Ma,
+                                                     const float* __restrict__ K,
+                                                     const float* __restrict__ Y,
+                                                     const float* __restrict__ xref) {
+  __shared__ float sK[UR][PB + 1];
+  __shared__ float sE[PB][UC + 1];
+  const int NM = (int)d.NM();
   const int m = d.m, n = d.n, p = d.p();
-  const int r0 = blockIdx.y * UT_R;
-  const long long c0 = (long long)blockIdx.x * UT_C;
+  const int r0 = blockIdx.y * UR;
+  const int c0 = blockIdx.x * UC;
   const int tid = threadIdx.x;
-  const int ty = tid / 16, tx = tid % 16;
-  float acc[4][4] = {};
-  for (int b0 = 0; b0 < p; b0 += UT_K) {
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // the lane's trajectory values (read-modify-write), fetched first
+  float old[4][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + 256 * u;  // 0..1023
-      {  // K tile: 64 rows x 16 observation rows
-        const int rl = e / UT_K, bl = e % UT_K;
-        const int a = r0 + rl, b = b0 + bl;
-        sK[bl][rl] = (a < Ma && b < p) ? K[(size_t)a * p + b] : 0.f;
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = r0 + w * 16 + 4 * lk + r, c = c0 + nb * 16 + li;
+      old[nb][r] = (a < Ma && c < NM) ? traj[(size_t)a * NM + c] : 0.f;
+    }
+  f32x4u acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4u{0.f, 0.f, 0.f, 0.f};
+  for (int b0 = 0; b0 < p; b0 += PB) {
+    constexpr int KS = UR * PB / 256;  // 20 gain values per thread
+    constexpr int ES = PB * UC / 256;  // 20 innovation values per thread
+    float kv[KS], ev[ES];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int e = tid + 256 * u;
+      const int rl = e / PB, bl = e % PB;
+      const int a = r0 + rl, b = b0 + bl;
+      kv[u] = (a < Ma && b < p) ? K[(size_t)a * p + b] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < ES; ++u) {
+      const int e = tid + 256 * u;
+      const int bl = e / UC, cl = e % UC;
+      const int b = b0 + bl, c = c0 + cl;
+      float v = 0.f;
+      if (b < p && c < NM) {
+        const float ybar = b < n ? xref[(size_t)b * m + c % m] : 0.f;
+        v = ybar - Y[(size_t)b * NM + c];
       }
-      {  // innovation tile: 16 observation rows x 64 columns
-        const int bl = e / UT_C, cl = e % UT_C;
-        const int b = b0 + bl;
-        const long long c = c0 + cl;
-        float v = 0.f;
-        if (b < p && c < NM) {
-          const int x = (int)(c % m);
-          const float ybar = b < n ? xref[(size_t)b * m + x] : 0.f;
-          v = ybar - Y[(size_t)b * NM + c];
-        }
-        sE[bl][cl] = v;
-      }
+      ev[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int e = tid + 256 * u;
+      sK[e / PB][e % PB] = kv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < ES; ++u) {
+      const int e = tid + 256 * u;
+      sE[e / UC][e % UC] = ev[u];
     }
     __syncthreads();
+    const int kmax = min(PB, p - b0);
+    for (int ks = 0; ks < kmax; ks += 4) {
+      const float av = sK[w * 16 + li][ks + lk];
 #pragma unroll
-    for (int k = 0; k < UT_K; ++k) {
-      float kv[4], ev[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) kv[u] = sK[k][ty + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) ev[v] = sE[k][tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(kv[u], ev[v], acc[u][v]);
+      for (int nb = 0; nb < 4; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sE[ks + lk][nb * 16 + li], acc[nb], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int a = r0 + ty + 16 * u;
-    if (a >= Ma) continue;
+  for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const long long c = c0 + tx + 16 * v;
-      if (c < NM) traj[(size_t)a * NM + c] += acc[u][v];
+    for (int r = 0; r < 4; ++r) {
+      const int a = r0 + w * 16 + 4 * lk + r, c = c0 + nb * 16 + li;
+      if (a < Ma && c < NM) traj[(size_t)a * NM + c] = old[nb][r] + acc[nb][r];
     }
-  }
 }
 
 // Smoothed means of every slice -> U_out (H+1, l, m), X_out (H+1, n, m) and U_hat_k.
@@ -98,8 +122,8 @@ __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restric
 
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
                    const float* Y, const float* xref_t) {
-  const dim3 grid((unsigned)((d.NM() + UT_C - 1) / UT_C), (unsigned)((Ma + UT_R - 1) / UT_R));
-  OIC_LAUNCH(t, KC_UPDATE, s, k_update, grid, dim3(256), 0, d, traj, Ma, K, Y, xref_t);
+  const dim3 grid((unsigned)((d.NM() + UC - 1) / UC), (unsigned)((Ma + UR - 1) / UR));
+  OIC_LAUNCH(t, KC_UPDATE, s, k_update_mfma, grid, dim3(256), 0, d, traj, Ma, K, Y, xref_t);
 }
 
 void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,

@@ -88,6 +88,7 @@ def lib():
                                       ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_double)]),
             "oic_stream": (vp, [vp]),
+            "oic_set_graph": (ci, [vp, ci]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -99,7 +100,8 @@ def lib():
 
 EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
             "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_cnn_forward", "oic_plant_step",
-            "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream"]
+            "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
+            "oic_set_graph"]
 
 
 def _is_torch(x) -> bool:
@@ -272,6 +274,9 @@ class Controller:
 
     def stream(self) -> int:
         return lib().oic_stream(self._h)
+
+    def set_graph(self, enable: bool):
+        self._check(lib().oic_set_graph(self._h, 1 if enable else 0))
 
     def close(self):
         if self._h is not None:

@@ -224,3 +224,35 @@ def test_closed_loop_teacher_forced():
             Xn = c.plant_step(X, Up)
             assert relerr(Xn, enks.plant_step(X, Up, prob.B, prob.weights, p.activation)) < TOL_FP32
             X = Xn
+
+
+def test_graph_replay_matches_eager_bitwise():
+    """The captured solve replays bitwise like the kernel-by-kernel launch, picks up a
+    new seed on every replay, and is re-captured when N or H change."""
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    zero = np.zeros((p.l, p.m), np.float32)
+    with oic.controller_for(prob, max_N=48, max_H=7) as c:
+        c.set_graph(False)
+        c.set_u_prev(zero)
+        U_e, X_e = c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, 3, want_X=True)
+        c.set_graph(True)
+        outs = []
+        for seed in (3, 4, 3):
+            c.set_u_prev(zero)
+            outs.append(c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, seed, want_X=True))
+        assert np.array_equal(outs[0][0], U_e) and np.array_equal(outs[0][1], X_e)
+        assert np.array_equal(outs[2][0], U_e)
+        assert not np.array_equal(outs[1][0], U_e)
+        ref4 = oracle_solve(prob, Xref, philox.solve_noise(4, p.n, p.m, p.l, p.N, p.H))
+        assert relerr(outs[1][0], ref4.U_mean) < TOL_FP32
+        # a different shape forces a new capture; explicit noise too
+        Xref2 = wl.reference_window(p, 0, 2)
+        c.set_u_prev(zero)
+        U2, _ = c.solve(prob.X0, Xref2, prob.Q, prob.R, 40, 2, 5)
+        z2 = philox.solve_noise(5, p.n, p.m, p.l, 40, 2)
+        assert relerr(U2, oracle_solve(prob, Xref2, z2, N=40, H=2).U_mean) < TOL_FP32
+        c.set_u_prev(zero)
+        U3, _ = c.solve_ex(prob.X0, Xref2, prob.Q, prob.R, 40, 2, noise=z2)
+        assert relerr(U3, U2) < 1e-6  # device and host Philox normals agree (bitwise, up to rare 1-ulp)
