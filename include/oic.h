@@ -174,6 +174,58 @@ void* oic_stream(oic_handle h);
  * launched kernel by kernel instead.  Results are identical either way. */
 int oic_set_graph(oic_handle h, int enable);
 
+/* ---- Serving: one request loop for many independent controllers ----
+ *
+ * A server owns a set of controllers, each a handle of its own (own stream,
+ * device-resident ensemble buffers, captured solve graph, applied-control state
+ * U_prev carried from solve to solve).  Requests (one MPC solve each) are
+ * admitted continuously: a pool of max_inflight worker threads runs the oldest
+ * request whose controller is idle and whose device footprint fits the HBM
+ * budget, evicting least-recently-used idle controllers (keeping their U_prev on
+ * the host) to make room; otherwise the request waits.  Solves of different
+ * controllers overlap on the device; solves of one controller run in submission
+ * order.  Each result is the same as the controller's solve alone.  All array
+ * arguments are HOST pointers, copied before the call returns. */
+typedef struct oic_server* oic_server_handle;
+
+/* Device bytes a handle created with cfg holds (the admission footprint). */
+size_t oic_footprint_bytes(const oic_config* cfg);
+
+/* hbm_budget_bytes: device bytes the server may hold for controller buffers.
+ * max_inflight: worker threads = solves on the device at once (1..64). */
+int oic_server_create(size_t hbm_budget_bytes, int max_inflight, oic_server_handle* out);
+
+/* Stops the workers (after their current solves) and frees every controller. NULL-safe. */
+void oic_server_destroy(oic_server_handle s);
+
+/* Register a controller: cfg as for oic_create (mem_mode must be OIC_MEM_HOST;
+ * max_N, max_H and stream are ignored), surrogate as for oic_set_weights, and the
+ * fixed ensemble size N, horizon, Q and R of its solves.  Nothing is allocated on
+ * the device until its first request.  OIC_ENOMEM if its footprint exceeds the budget. */
+int oic_server_add(oic_server_handle s, const oic_config* cfg, const float* B, const float* const* W,
+                   const float* const* bias, int N, int horizon, const float* Q, const float* R,
+                   int* controller_id);
+
+/* Queue one solve for a controller: X0 (n x m) and reference ((horizon+1) x n x m)
+ * as for oic_solve, with the seeded noise stream.  *ticket identifies the result. */
+int oic_server_submit(oic_server_handle s, int controller_id, const float* X0, const float* reference,
+                      uint64_t seed, long long* ticket);
+
+/* Block until the ticket's solve has finished and copy its outputs: U_out
+ * ((horizon+1) x l x m), X_out ((horizon+1) x n x m) or NULL.  latency_ms (submit to
+ * completion) and queue_ms (submit to start) may be NULL.  Returns the solve's
+ * status; each ticket can be waited for once. */
+int oic_server_wait(oic_server_handle s, long long ticket, float* U_out, float* X_out,
+                    double* latency_ms, double* queue_ms);
+
+/* Counters: completed solves, controller admissions and evictions, device bytes
+ * held now and at peak. Any pointer may be NULL. */
+int oic_server_stats(oic_server_handle s, long long* completed, long long* admissions,
+                     long long* evictions, size_t* bytes_in_use, size_t* peak_bytes);
+
+/* Reason for the last failed oic_server_wait. */
+const char* oic_server_last_error(oic_server_handle s);
+
 #ifdef __cplusplus
 }
 #endif

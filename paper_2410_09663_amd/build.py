@@ -19,12 +19,13 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
+    "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas", "-pthread",
 ]
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
+    return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")) +
+                  glob.glob(os.path.join(PKG, "csrc", "*.cpp")))
 
 
 def build(verbose: bool = False) -> str:

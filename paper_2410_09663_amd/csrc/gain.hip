@@ -25,9 +25,13 @@ constexpr int NBK = 8;                             // panel width
 // W = L^{-1} is formed the same way by panels of rows (triangular solve of the
 // panel against its diagonal block, then a rank-8 update of the rows below), and
 // (Sigma^Y)^{-1} = W^T W.
-__device__ void chol_inverse(int p, double* A, double* W, double* __restrict__ Sinv,
-                             int* __restrict__ flag) {
+__device__ __forceinline__ void chol_inverse(int p, double* A, double* W, double* __restrict__ Sinv,
+                                             int* __restrict__ flag) {
+  // A and W use the leading dimension ld = p + 1: an odd number of doubles puts the
+  // rows read by consecutive lanes in distinct LDS banks.
+  const int ld = p + 1;
   __shared__ int bad;
+  __shared__ double rdiag[NBK];
   const int tid = threadIdx.x;
   const int ty = tid / kTX, tx = tid % kTX;
   if (tid == 0) bad = 0;
@@ -40,7 +44,7 @@ __device__ void chol_inverse(int p, double* A, double* W, double* __restrict__ S
 #pragma unroll
       for (int r = 0; r < NBK; ++r)
 #pragma unroll
-        for (int c = 0; c < NBK; ++c) a[r][c] = (r < nb && c <= r) ? A[(kb + r) * p + kb + c] : 0.0;
+        for (int c = 0; c < NBK; ++c) a[r][c] = (r < nb && c <= r) ? A[(kb + r) * ld + kb + c] : 0.0;
 #pragma unroll
       for (int k = 0; k < NBK; ++k) {
         double d = a[k][k];
@@ -60,7 +64,9 @@ __device__ void chol_inverse(int p, double* A, double* W, double* __restrict__ S
       for (int r = 0; r < NBK; ++r)
 #pragma unroll
         for (int c = 0; c < NBK; ++c)
-          if (r < nb && c <= r) A[(kb + r) * p + kb + c] = a[r][c];
+          if (r < nb && c <= r) A[(kb + r) * ld + kb + c] = a[r][c];
+#pragma unroll
+      for (int r = 0; r < NBK; ++r) rdiag[r] = 1.0 / a[r][r];
       if (!ok) bad = 1;
     }
     __syncthreads();
@@ -69,31 +75,31 @@ __device__ void chol_inverse(int p, double* A, double* W, double* __restrict__ S
     for (int i = kb + nb + tid; i < p; i += kCholThreads) {
       double x[NBK];
 #pragma unroll
-      for (int c = 0; c < NBK; ++c) x[c] = c < nb ? A[i * p + kb + c] : 0.0;
+      for (int c = 0; c < NBK; ++c) x[c] = c < nb ? A[i * ld + kb + c] : 0.0;
 #pragma unroll
       for (int c = 0; c < NBK; ++c) {
         if (c < nb) {
 #pragma unroll
-          for (int q = 0; q < c; ++q) x[c] -= x[q] * A[(kb + c) * p + kb + q];
-          x[c] /= A[(kb + c) * p + kb + c];
+          for (int q = 0; q < c; ++q) x[c] -= x[q] * A[(kb + c) * ld + kb + q];
+          x[c] *= rdiag[c];
         }
       }
 #pragma unroll
       for (int c = 0; c < NBK; ++c)
-        if (c < nb) A[i * p + kb + c] = x[c];
+        if (c < nb) A[i * ld + kb + c] = x[c];
     }
     __syncthreads();
     // trailing lower triangle: A[i][j] -= sum_c L[i][kb+c] L[j][kb+c]
     for (int i = kb + nb + ty; i < p; i += kTY) {
       double li[NBK];
 #pragma unroll
-      for (int c = 0; c < NBK; ++c) li[c] = c < nb ? A[i * p + kb + c] : 0.0;
+      for (int c = 0; c < NBK; ++c) li[c] = c < nb ? A[i * ld + kb + c] : 0.0;
       for (int j = kb + nb + tx; j <= i; j += kTX) {
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < NBK; ++c)
-          if (c < nb) acc = fma(li[c], A[j * p + kb + c], acc);
-        A[i * p + j] -= acc;
+          if (c < nb) acc = fma(li[c], A[j * ld + kb + c], acc);
+        A[i * ld + j] -= acc;
       }
     }
     __syncthreads();
@@ -103,38 +109,41 @@ __device__ void chol_inverse(int p, double* A, double* W, double* __restrict__ S
     return;
   }
   // W = L^{-1}: start from the identity, then panels of rows.
-  for (int e = tid; e < p * p; e += kCholThreads) W[e] = (e / p == e % p) ? 1.0 : 0.0;
+  for (int ii = ty; ii < p; ii += kTY)
+    for (int jj = tx; jj < p; jj += kTX) W[ii * ld + jj] = ii == jj ? 1.0 : 0.0;
   __syncthreads();
   for (int kb = 0; kb < p; kb += NBK) {
     const int nb = min(NBK, p - kb);
     const int cols = kb + nb;
+    if (tid < NBK) rdiag[tid] = tid < nb ? 1.0 / A[(kb + tid) * ld + kb + tid] : 1.0;
+    __syncthreads();
     for (int j = tid; j < cols; j += kCholThreads) {  // W[kb:kb+nb, j] = L_kk^{-1} B[kb:kb+nb, j]
       double x[NBK];
 #pragma unroll
-      for (int r = 0; r < NBK; ++r) x[r] = r < nb ? W[(kb + r) * p + j] : 0.0;
+      for (int r = 0; r < NBK; ++r) x[r] = r < nb ? W[(kb + r) * ld + j] : 0.0;
 #pragma unroll
       for (int r = 0; r < NBK; ++r) {
         if (r < nb) {
 #pragma unroll
-          for (int q = 0; q < r; ++q) x[r] -= A[(kb + r) * p + kb + q] * x[q];
-          x[r] /= A[(kb + r) * p + kb + r];
+          for (int q = 0; q < r; ++q) x[r] -= A[(kb + r) * ld + kb + q] * x[q];
+          x[r] *= rdiag[r];
         }
       }
 #pragma unroll
       for (int r = 0; r < NBK; ++r)
-        if (r < nb) W[(kb + r) * p + j] = x[r];
+        if (r < nb) W[(kb + r) * ld + j] = x[r];
     }
     __syncthreads();
     for (int i = kb + nb + ty; i < p; i += kTY) {  // B[i][j] -= sum_r L[i][kb+r] W[kb+r][j]
       double li[NBK];
 #pragma unroll
-      for (int r = 0; r < NBK; ++r) li[r] = r < nb ? A[i * p + kb + r] : 0.0;
+      for (int r = 0; r < NBK; ++r) li[r] = r < nb ? A[i * ld + kb + r] : 0.0;
       for (int j = tx; j < cols; j += kTX) {
         double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < NBK; ++r)
-          if (r < nb) acc = fma(li[r], W[(kb + r) * p + j], acc);
-        W[i * p + j] -= acc;
+          if (r < nb) acc = fma(li[r], W[(kb + r) * ld + j], acc);
+        W[i * ld + j] -= acc;
       }
     }
     __syncthreads();
@@ -143,7 +152,7 @@ __device__ void chol_inverse(int p, double* A, double* W, double* __restrict__ S
   for (int a = ty; a < p; a += kTY)
     for (int b = tx; b <= a; b += kTX) {
       double acc = 0.0;
-      for (int k = a; k < p; ++k) acc = fma(W[k * p + a], W[k * p + b], acc);
+      for (int k = a; k < p; ++k) acc = fma(W[k * ld + a], W[k * ld + b], acc);
       Sinv[a * p + b] = acc;
       Sinv[b * p + a] = acc;
     }
@@ -153,18 +162,19 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const doub
                                                                double* __restrict__ Sinv,
                                                                int* __restrict__ flag) {
   extern __shared__ double lds[];
-  for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads) lds[idx] = Syy[idx];
+  for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads) lds[(idx / p) * (p + 1) + idx % p] = Syy[idx];
   __syncthreads();
-  chol_inverse(p, lds, lds + p * p, Sinv, flag);
+  chol_inverse(p, lds, lds + p * (p + 1), Sinv, flag);
 }
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv_global(int p, const double* __restrict__ Syy,
                                                                   double* __restrict__ work,
                                                                   double* __restrict__ Sinv,
                                                                   int* __restrict__ flag) {
-  for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads) work[idx] = Syy[idx];
+  for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads)
+    work[(idx / p) * (p + 1) + idx % p] = Syy[idx];
   __syncthreads();
-  chol_inverse(p, work, work + p * p, Sinv, flag);
+  chol_inverse(p, work, work + p * (p + 1), Sinv, flag);
 }
 
 // K[a][b] = sum_c Sxy[a][c] Sinv[c][b], FP64, rounded to FP32 (any p).  Block (64, 4).
@@ -241,11 +251,11 @@ void launch_chol_gain(hipStream_t s, Timer& t, const Dims& d, int Ma, const doub
     static bool attr_set = false;
     if (!attr_set) {
       hipFuncSetAttribute((const void*)k_chol_inv_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          2 * kLdsMaxP * kLdsMaxP * (int)sizeof(double));
+                          2 * kLdsMaxP * (kLdsMaxP + 1) * (int)sizeof(double));
       attr_set = true;
     }
     OIC_LAUNCH(t, KC_CHOL, s, k_chol_inv_lds, dim3(1), dim3(kCholThreads),
-               2 * (size_t)p * p * sizeof(double), p, Syy, Sinv, flag);
+               2 * (size_t)p * (p + 1) * sizeof(double), p, Syy, Sinv, flag);
   } else {
     OIC_LAUNCH(t, KC_CHOL, s, k_chol_inv_global, dim3(1), dim3(kCholThreads), 0, p, Syy, Lwork, Sinv,
                flag);

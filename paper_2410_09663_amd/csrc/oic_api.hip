@@ -565,7 +565,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   rc = rc ? rc : dalloc(h, &h->muY, p * m);  // doubles
   rc = rc ? rc : dalloc(h, &h->S, (Ma_max + p) * p);
   rc = rc ? rc : dalloc(h, &h->part, std::max((size_t)h->max_splits * (Ma_max + p) * p, Ma_max * p));
-  rc = rc ? rc : dalloc(h, &h->Lwork, 2 * p * p);
+  rc = rc ? rc : dalloc(h, &h->Lwork, 2 * p * (p + 1));
   rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
   rc = rc ? rc : dalloc(h, &h->flag, 1);
   for (int k = 0; k < 4 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));

@@ -304,9 +304,10 @@ void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   const int p = d.p();
   const int Mtot = Ma + p;
   const int NM = (int)d.NM();
+  // right rows per block: NB*16 with NB <= 8, balanced over grid.y tiles
   const int nbk = (p + 15) / 16;
-  const int NB = nbk > 8 ? 8 : nbk;  // right rows per block: NB*16 (grid.y covers the rest)
-  const int ytiles = (p + NB * 16 - 1) / (NB * 16);
+  const int ytiles = (nbk + 7) / 8;
+  const int NB = (nbk + ytiles - 1) / ytiles;
   const int tiles = ((Mtot + MA - 1) / MA) * ytiles;
   // ~3 workgroups per CU in total, each chunk at least 4 stages of 64 columns.
   int splits = (768 + tiles - 1) / tiles;

@@ -89,6 +89,19 @@ def lib():
                                       ctypes.POINTER(ctypes.c_double)]),
             "oic_stream": (vp, [vp]),
             "oic_set_graph": (ci, [vp, ci]),
+            "oic_server_create": (ci, [cs, ci, ctypes.POINTER(vp)]),
+            "oic_server_destroy": (None, [vp]),
+            "oic_server_add": (ci, [vp, ctypes.POINTER(oic_config), vp, ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp), ci, ci, vp, vp, ctypes.POINTER(ci)]),
+            "oic_server_submit": (ci, [vp, ci, vp, vp, cu64, ctypes.POINTER(ctypes.c_longlong)]),
+            "oic_server_wait": (ci, [vp, ctypes.c_longlong, vp, vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
+            "oic_server_stats": (ci, [vp, ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+            "oic_server_last_error": (ctypes.c_char_p, [vp]),
+            "oic_footprint_bytes": (cs, [ctypes.POINTER(oic_config)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -101,7 +114,9 @@ def lib():
 EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
             "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_cnn_forward", "oic_plant_step",
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
-            "oic_set_graph"]
+            "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
+            "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
+            "oic_footprint_bytes"]
 
 
 def _is_torch(x) -> bool:
@@ -305,3 +320,101 @@ def controller_for(problem, max_N=None, max_H=None, precision=None, mem_mode=OIC
                    mem_mode=mem_mode, stream=stream)
     c.set_weights(problem.B, problem.weights)
     return c
+
+
+class Server:
+    """Request loop for many controllers (oic_server_*): host NumPy arrays in and out."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4):
+        self._s = None
+        h = ctypes.c_void_p()
+        rc = lib().oic_server_create(int(hbm_budget_bytes), int(max_inflight), ctypes.byref(h))
+        if rc != OIC_OK:
+            raise OicError(rc, "oic_server_create failed")
+        self._s = h
+        self._shapes = {}
+
+    @staticmethod
+    def config_for(problem, N: int, H: int, precision: int = None) -> oic_config:
+        p = problem.preset
+        cfg = oic_config()
+        cfg.n, cfg.m, cfg.l = p.n, p.m, p.l
+        cfg.n_layers = len(p.channels) - 1
+        for k, c in enumerate(p.channels):
+            cfg.channels[k] = c
+        cfg.activation = p.activation
+        cfg.precision = p.precision if precision is None else precision
+        cfg.mem_mode = OIC_MEM_HOST
+        cfg.max_N, cfg.max_H = N, H
+        return cfg
+
+    @staticmethod
+    def footprint(problem, N: int, H: int, precision: int = None) -> int:
+        cfg = Server.config_for(problem, N, H, precision)
+        return int(lib().oic_footprint_bytes(ctypes.byref(cfg)))
+
+    def add(self, problem, N: int, H: int, precision: int = None) -> int:
+        """Register a controller for a workloads.Problem; returns its id."""
+        p = problem.preset
+        cfg = self.config_for(problem, N, H, precision)
+        B = np.ascontiguousarray(problem.B, np.float32)
+        ws = [np.ascontiguousarray(w, np.float32) for w in problem.weights]
+        wp = (ctypes.c_void_p * len(ws))(*[w.ctypes.data for w in ws])
+        Q = np.ascontiguousarray(problem.Q, np.float32)
+        R = np.ascontiguousarray(problem.R, np.float32)
+        cid = ctypes.c_int()
+        rc = lib().oic_server_add(self._s, ctypes.byref(cfg), B.ctypes.data, wp, None, N, H,
+                                  Q.ctypes.data, R.ctypes.data, ctypes.byref(cid))
+        if rc != OIC_OK:
+            raise OicError(rc, "oic_server_add failed")
+        self._shapes[cid.value] = (p.n, p.m, p.l, H)
+        return cid.value
+
+    def submit(self, cid: int, X0, reference, seed: int) -> int:
+        n, m, l, H = self._shapes[cid]
+        X0 = np.ascontiguousarray(X0, np.float32)
+        ref = np.ascontiguousarray(reference, np.float32)
+        if X0.shape != (n, m) or ref.shape != (H + 1, n, m):
+            raise ValueError("bad X0 or reference shape")
+        t = ctypes.c_longlong()
+        rc = lib().oic_server_submit(self._s, cid, X0.ctypes.data, ref.ctypes.data, seed, ctypes.byref(t))
+        if rc != OIC_OK:
+            raise OicError(rc, "oic_server_submit failed")
+        return t.value
+
+    def wait(self, cid: int, ticket: int):
+        """Returns (U_hat, X_hat, latency_ms, queue_ms)."""
+        n, m, l, H = self._shapes[cid]
+        U = np.empty((H + 1, l, m), np.float32)
+        X = np.empty((H + 1, n, m), np.float32)
+        lat, q = ctypes.c_double(), ctypes.c_double()
+        rc = lib().oic_server_wait(self._s, ticket, U.ctypes.data, X.ctypes.data, ctypes.byref(lat),
+                                   ctypes.byref(q))
+        if rc != OIC_OK:
+            raise OicError(rc, lib().oic_server_last_error(self._s).decode())
+        return U, X, lat.value, q.value
+
+    def stats(self):
+        c, a, e = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        u, pk = ctypes.c_size_t(), ctypes.c_size_t()
+        lib().oic_server_stats(self._s, ctypes.byref(c), ctypes.byref(a), ctypes.byref(e),
+                               ctypes.byref(u), ctypes.byref(pk))
+        return {"completed": c.value, "admissions": a.value, "evictions": e.value,
+                "bytes_in_use": u.value, "peak_bytes": pk.value}
+
+    def close(self):
+        if self._s is not None:
+            lib().oic_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

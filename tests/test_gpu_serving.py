@@ -1,0 +1,74 @@
+"""Serving (continuous admission of many controllers): every request's result is the same
+when its controller runs alone and when it runs in a concurrent mix whose HBM budget
+forces evictions and re-admissions."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2410_09663_amd import oic
+from paper_2410_09663_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    base = wl.PRESETS["C1"]
+    specs = [
+        dataclasses.replace(base, name="a"),
+        dataclasses.replace(base, name="b", seed_W=11, seed_X0=12),                  # same shape, other weights
+        dataclasses.replace(wl.PRESETS["C2"], name="c", n=32, m=32, l=8, N=64, H=5, grf_length=4.0,
+                            ref_center=(16.0, 8.0)),
+        wl.small_preset(n=20, m=24, l=5, channels=(2, 16, 16, 1), N=24, H=4, name="d"),
+        dataclasses.replace(wl.PRESETS["C3"], name="e", n=32, m=32, l=8, N=32, H=3, grf_length=4.0,
+                            ref_center=(16.0, 8.0), precision=wl.PREC_BF16),
+    ]
+    return [wl.make_problem(p) for p in specs]
+
+
+def _requests(problems, steps=3):
+    reqs = []
+    for k in range(steps):
+        for cid, pr in enumerate(problems):
+            p = pr.preset
+            X0 = (pr.X0 * (1.0 + 0.1 * k)).astype(np.float32)
+            reqs.append((cid, X0, wl.reference_window(p, k), 100 * cid + k))
+    return reqs
+
+
+def test_results_identical_alone_and_in_the_mix():
+    problems = _mix()
+    reqs = _requests(problems)
+    alone = {}
+    for cid, pr in enumerate(problems):
+        with oic.Server(hbm_budget_bytes=8 << 30, max_inflight=1) as srv:
+            sid = srv.add(pr, pr.preset.N, pr.preset.H)
+            for (c, X0, ref, seed) in reqs:
+                if c == cid:
+                    alone[(c, seed)] = srv.wait(sid, srv.submit(sid, X0, ref, seed))[:2]
+    # small budget: about two controllers resident at once -> evictions and re-admissions
+    fps = [oic.Server.footprint(pr, pr.preset.N, pr.preset.H) for pr in problems]
+    budget = int(1.6 * max(fps))
+    with oic.Server(hbm_budget_bytes=budget, max_inflight=4) as srv:
+        ids = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in problems]
+        tickets = [(c, seed, srv.submit(ids[c], X0, ref, seed)) for (c, X0, ref, seed) in reqs]
+        lat = []
+        for c, seed, t in tickets:
+            U, X, ms, q = srv.wait(ids[c], t)
+            lat.append(ms)
+            Ua, Xa = alone[(c, seed)]
+            assert np.array_equal(U, Ua), (c, seed)
+            assert np.array_equal(X, Xa), (c, seed)
+        st = srv.stats()
+    print("serving stats", st, "p50 ms", np.percentile(lat, 50), flush=True)
+    assert st["completed"] == len(reqs)
+    assert st["evictions"] > 0 and st["admissions"] > len(problems)
+    assert st["peak_bytes"] <= budget
+
+
+def test_controller_larger_than_budget_is_rejected():
+    pr = wl.make_problem(wl.PRESETS["C2"])
+    with oic.Server(hbm_budget_bytes=1 << 20, max_inflight=1) as srv:
+        with pytest.raises(oic.OicError) as e:
+            srv.add(pr, pr.preset.N, pr.preset.H)
+        assert e.value.code == oic.OIC_ENOMEM
