@@ -117,7 +117,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=3)  # at least 1 (the cost needs U_{k-1})
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -137,19 +137,19 @@ def main():
     p = wl.PRESETS[args.workload]
     prec = oic.OIC_PREC_BF16 if args.precision == "bf16" else oic.OIC_PREC_FP32
     prob = wl.make_problem(p)
-    K, W = args.steps, args.warmup
+    K, W = args.steps, max(1, args.warmup)
     refs = torch.from_numpy(np.stack([wl.reference_window(p, k) for k in range(W + 2 * K + 1)])).to(dev)
     stream = torch.cuda.current_stream().cuda_stream
     ctrl = oic.controller_for(prob, precision=prec, mem_mode=oic.OIC_MEM_DEVICE, stream=stream)
     X0 = torch.from_numpy(prob.X0).to(dev)
-    Ubuf = torch.empty((p.H + 1, p.l, p.m), dtype=torch.float32, device=dev)
+    Ubufs = torch.empty((W + 2 * K, p.H + 1, p.l, p.m), dtype=torch.float32, device=dev)
     Xbuf = torch.empty((p.H + 1, p.n, p.m), dtype=torch.float32, device=dev)
 
     def step(k, X):
         # full smoother output: U_hat and X_hat of every slice (Algorithm 1, line 13)
-        ctrl.solve(X, refs[k], prob.Q, prob.R, p.N, p.H, p.noise_seed_base + k, U_out=Ubuf,
+        ctrl.solve(X, refs[k], prob.Q, prob.R, p.N, p.H, p.noise_seed_base + k, U_out=Ubufs[k],
                    X_out=Xbuf)
-        return ctrl.plant_step(X, Ubuf[0])
+        return ctrl.plant_step(X, Ubufs[k][0])
 
     X = X0
     for k in range(W):
@@ -157,13 +157,25 @@ def main():
     torch.cuda.synchronize()
     # Timed region: K closed-loop steps, each solve replayed from its captured graph.
     lat = []
+    states = [X]
     t0 = time.perf_counter()
     for k in range(W, W + K):
         ts = time.perf_counter()
         X = step(k, X)
         lat.append(time.perf_counter() - ts)
+        states.append(X)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # closed-loop tracking cost of the timed window (problem-setup stage cost, FP64 host)
+    Xs = torch.stack(states).cpu().numpy()
+    Us = Ubufs[W - 1:W + K, 0].cpu().numpy() if W > 0 else None
+    loop_cost, mse_last = 0.0, 0.0
+    for j in range(K):
+        k = W + j
+        Uk = Us[j + 1]
+        Uprev = Us[j]
+        loop_cost += oic.stage_cost(Xs[j + 1], wl.reference_at(p, k + 1), Uk, Uk - Uprev, prob.Q, prob.R)
+    mse_last = float(np.mean((Xs[-1].astype(np.float64) - wl.reference_at(p, W + K)) ** 2))
     # Per-kernel durations: the same K steps again, launched kernel by kernel with HIP
     # events around every launch on the library's stream (events cannot sit inside a
     # replayed graph); the per-class totals feed the roofline.
@@ -197,6 +209,8 @@ def main():
         "config": {"workload": workload_name(p), "n": p.n, "m": p.m, "l": p.l, "N": p.N, "H": p.H,
                    "channels": p.channels, "precision": args.precision},
         "solves_per_s": solves_per_s, "p50_ms": float(np.percentile(lat_ms, 50)),
+        "closed_loop_cost": loop_cost, "tracking_mse_last": mse_last,
+        "tracking_rmse_last": float(np.sqrt(mse_last)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "roofline": roof,
         "kernel_ms_per_solve": {c: v["total_ms"] / K for c, v in sorted(per_class.items())},

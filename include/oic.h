@@ -168,6 +168,14 @@ int oic_kernel_stats(oic_handle h, int id, const char** name, long long* launche
 /* Stream the handle orders its work on (a hipStream_t). */
 void* oic_stream(oic_handle h);
 
+/* Stage cost of the tracking objective (problem setup), in FP64 on the host:
+ *   tr[(X - Xref)^T R^{-1} (X - Xref)] + tr[U^T Q^{-1} U] + tr[dU^T Q^{-1} dU],
+ * with U^ref = 0 and Q_U = Q_dU = Q.  X, Xref: n x m; U, dU: l x m; Q: l x l; R: n x n
+ * (host pointers).  Summed over the realised steps of a closed loop this is the
+ * closed-loop tracking cost.  Errors: OIC_EINVAL (NULL, bad size, Q or R not SPD). */
+int oic_stage_cost(int n, int m, int l, const float* X, const float* Xref, const float* U,
+                   const float* dU, const float* Q, const float* R, double* cost);
+
 /* Replay the kernel sequence of a solve from a HIP graph, captured on the first
  * solve of each (N, horizon, seeded or explicit noise) and reused while those stay
  * the same.  On by default.  While per-kernel timing is enabled the sequence is

@@ -10,96 +10,206 @@
 namespace oic {
 namespace {
 
-constexpr int kCholThreads = 512;
-constexpr int kTX = 32, kTY = kCholThreads / kTX;  // 2-D thread grid for the updates
-constexpr int kLdsMaxP = 90;                       // two p x p FP64 arrays in the 160 KiB LDS
+constexpr int kCholThreads = 512;                  // 8 waves
+constexpr int kLdsMaxP = 90;                       // two p x (p+1) FP64 arrays in the 160 KiB LDS
 constexpr int NBK = 8;                             // panel width
+constexpr int kMaxPanelsLds = (kLdsMaxP + NBK - 1) / NBK;  // 12
+constexpr int kMaxPanels = 64;                              // p <= 512
 
-// Factor, invert and square the p x p SPD matrix in A (row-major; LDS or global),
-// with W (p x p, same memory kind) as workspace; writes (Sigma^Y)^{-1} to Sinv and
-// sets *flag when a pivot is not positive and finite.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// 1/sqrt(d) for d > 0: the hardware estimate refined by two Newton-Raphson steps,
+// y <- y + y (1 - d y^2) / 2, each of which doubles the number of correct bits.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  union {
+    double d;
+    int i[2];
+  } u;
+  u.d = v;
+  u.i[0] = __builtin_amdgcn_readlane(u.i[0], lane);
+  u.i[1] = __builtin_amdgcn_readlane(u.i[1], lane);
+  return u.d;
+}
+
+// D(16x16 tile at rows i0, cols j0 of M, leading dimension ld) += sum_k Aop[i][k] Bop[k][j]
+// over k = 0..K-1 on the FP64 matrix cores, where the operands are read through the
+// functors a(i, k) and b(k, j) (zero outside their ranges).  Lane layout (16x16x4 f64):
+// A[i][k] from lane i + 16g (k = 4s + g), B[k][j] from lane j + 16g, element r of lane
+// j + 16g holds D[g + 4r][j].
+template <typename FA, typename FB>
+__device__ __forceinline__ void mfma_tile_update(double* M, int ld, int rows, int cols, int i0, int j0,
+                                                 int K, FA a, FB b, double sign) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + lk + 4 * r, j = j0 + li;
+    acc[r] = (i < rows && j < cols) ? M[i * ld + j] : 0.0;
+  }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + lk;
+    const double av = (k < K) ? a(i0 + li, k) : 0.0;
+    const double bv = (k < K) ? sign * b(k, j0 + li) : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + lk + 4 * r, j = j0 + li;
+    if (i < rows && j < cols) M[i * ld + j] = acc[r];
+  }
+}
+
+// Factor, invert and square the p x p SPD matrix in A (row-major, leading dimension
+// ld = p + 1; LDS or global), with W (same shape and memory kind) as workspace; writes
+// (Sigma^Y)^{-1} to Sinv (p x p) and sets *flag when a pivot is not positive and finite.
 //
-// Blocked right-looking Cholesky with 8-wide panels: one thread factors the 8 x 8
-// diagonal block in registers, the rows below solve against it in parallel, and
-// the trailing lower triangle takes the rank-8 update; three barriers per panel.
-// W = L^{-1} is formed the same way by panels of rows (triangular solve of the
-// panel against its diagonal block, then a rank-8 update of the rows below), and
-// (Sigma^Y)^{-1} = W^T W.
+// Blocked right-looking Cholesky with 8-wide panels.  Per panel: wave 0 factors the
+// 8 x 8 diagonal block with one row per lane (pivots broadcast by readlane) and also
+// forms its inverse; the rows below become A21 L11^{-T} (eight independent dot
+// products per row); the trailing lower triangle takes the rank-8 update on the FP64
+// matrix cores.  W = L^{-1} follows by panels of rows (L11^{-1} times the panel, then
+// a rank-8 update of the rows below, on the matrix cores), and (Sigma^Y)^{-1} = W^T W
+// is one more matrix-core product.  The odd leading dimension spreads the rows read by
+// the 16 lanes of an operand fragment over distinct LDS banks.
+template <int MAXPAN>
 __device__ __forceinline__ void chol_inverse(int p, double* A, double* W, double* __restrict__ Sinv,
                                              int* __restrict__ flag) {
-  // A and W use the leading dimension ld = p + 1: an odd number of doubles puts the
-  // rows read by consecutive lanes in distinct LDS banks.
   const int ld = p + 1;
   __shared__ int bad;
-  __shared__ double rdiag[NBK];
+  __shared__ double sLinv[MAXPAN][NBK][NBK];  // inverse of every diagonal block
   const int tid = threadIdx.x;
-  const int ty = tid / kTX, tx = tid % kTX;
+  const int lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = kCholThreads / 64;
+  const int npan = (p + NBK - 1) / NBK;
   if (tid == 0) bad = 0;
+  // W = L^{-1} is built alongside the factor: it starts as the identity and takes, per
+  // panel, the same two steps as the rows below (L11^{-1} times the panel rows, then a
+  // rank-8 update of the rows below), in the same phases as the factorisation.
+  for (int e = tid; e < p * ld; e += kCholThreads) {
+    const int i = e / ld, j = e - i * ld;
+    W[e] = (i == j) ? 1.0 : 0.0;
+  }
   __syncthreads();
-  for (int kb = 0; kb < p; kb += NBK) {
+  for (int pb = 0; pb < npan; ++pb) {
+    const int kb = pb * NBK;
     const int nb = min(NBK, p - kb);
-    if (tid == 0) {  // diagonal block, in registers (no early exit: keeps the array in VGPRs)
-      double a[NBK][NBK];
-      bool ok = true;
+    if (wave == 0) {
+      // Every lane factors the whole 8 x 8 diagonal block in its own registers (no
+      // cross-lane traffic; identity rows pad a short last panel), keeping the
+      // reciprocal square roots for the block inverse.
+      double a[NBK][NBK], rs[NBK];
 #pragma unroll
       for (int r = 0; r < NBK; ++r)
 #pragma unroll
-        for (int c = 0; c < NBK; ++c) a[r][c] = (r < nb && c <= r) ? A[(kb + r) * ld + kb + c] : 0.0;
+        for (int c = 0; c < NBK; ++c)
+          a[r][c] = c > r ? 0.0 : ((r < nb) ? A[(kb + r) * ld + kb + c] : (r == c ? 1.0 : 0.0));
+      bool ok = true;
 #pragma unroll
       for (int k = 0; k < NBK; ++k) {
-        double d = a[k][k];
-        const bool live = k < nb;
-        if (live && !(d > 0.0 && isfinite(d))) ok = false;
-        if (!(d > 0.0)) d = 1.0;  // keep the arithmetic finite after a failure
-        const double sq = sqrt(d), rs = 1.0 / sq;
-        a[k][k] = live ? sq : a[k][k];
+        const double d = a[k][k];
+        if (!(d > 0.0 && isfinite(d))) ok = false;
+        rs[k] = (d > 0.0 && isfinite(d)) ? rsqrt_nr(d) : 1.0;
+        a[k][k] = d * rs[k];
 #pragma unroll
-        for (int r = k + 1; r < NBK; ++r) a[r][k] *= rs;
+        for (int r = k + 1; r < NBK; ++r) a[r][k] *= rs[k];
 #pragma unroll
         for (int c = k + 1; c < NBK; ++c)
 #pragma unroll
           for (int r = c; r < NBK; ++r) a[r][c] -= a[r][k] * a[c][k];
       }
+      // lane c < 8 forms column c of L11^{-1}: x_r = (delta_rc - sum_{q<r} L_rq x_q) / L_rr
+      if (lane < NBK) {
+        double x[NBK];
 #pragma unroll
-      for (int r = 0; r < NBK; ++r)
+        for (int r = 0; r < NBK; ++r) {
+          double v = (r == lane) ? 1.0 : 0.0;
 #pragma unroll
-        for (int c = 0; c < NBK; ++c)
-          if (r < nb && c <= r) A[(kb + r) * ld + kb + c] = a[r][c];
+          for (int q = 0; q < r; ++q) v -= a[r][q] * x[q];
+          x[r] = v * rs[r];
+        }
 #pragma unroll
-      for (int r = 0; r < NBK; ++r) rdiag[r] = 1.0 / a[r][r];
-      if (!ok) bad = 1;
+        for (int r = 0; r < NBK; ++r) sLinv[pb][r][lane] = (r >= lane) ? x[r] : 0.0;
+        if (lane < nb) {
+#pragma unroll
+          for (int c = 0; c < NBK; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int r = 0; r < NBK; ++r) v = (r == lane) ? a[r][c] : v;  // row `lane`, static indices
+            if (c <= lane) A[(kb + lane) * ld + kb + c] = v;
+          }
+        }
+      }
+      if (lane == 0 && !ok) bad = 1;
     }
     __syncthreads();
     if (bad) break;  // uniform
-    // rows below: x = a_i L_kk^{-T}
-    for (int i = kb + nb + tid; i < p; i += kCholThreads) {
-      double x[NBK];
+    const int r0 = kb + nb, rem = p - r0;
+    // rows below: L21 = A21 L11^{-T}
+    for (int i = r0 + tid; i < p; i += kCholThreads) {
+      double a21[NBK], l21[NBK];
 #pragma unroll
-      for (int c = 0; c < NBK; ++c) x[c] = c < nb ? A[i * ld + kb + c] : 0.0;
+      for (int q = 0; q < NBK; ++q) a21[q] = A[i * ld + kb + q];
 #pragma unroll
       for (int c = 0; c < NBK; ++c) {
-        if (c < nb) {
+        double v = 0.0;
 #pragma unroll
-          for (int q = 0; q < c; ++q) x[c] -= x[q] * A[(kb + c) * ld + kb + q];
-          x[c] *= rdiag[c];
-        }
+        for (int q = 0; q <= c; ++q) v = fma(a21[q], sLinv[pb][c][q], v);
+        l21[c] = v;
       }
 #pragma unroll
-      for (int c = 0; c < NBK; ++c)
-        if (c < nb) A[i * ld + kb + c] = x[c];
+      for (int c = 0; c < NBK; ++c) A[i * ld + kb + c] = l21[c];
+    }
+    const int cols = kb + nb;
+    // W[kb:kb+nb, j] = L11^{-1} B[kb:kb+nb, j] for every column j < cols
+    for (int j = tid; j < cols; j += kCholThreads) {
+      double bcol[NBK], w[NBK];
+#pragma unroll
+      for (int q = 0; q < NBK; ++q) bcol[q] = (q < nb) ? W[(kb + q) * ld + j] : 0.0;
+#pragma unroll
+      for (int r = 0; r < NBK; ++r) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q <= r; ++q) v = fma(sLinv[pb][r][q], bcol[q], v);
+        w[r] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < NBK; ++r)
+        if (r < nb) W[(kb + r) * ld + j] = w[r];
     }
     __syncthreads();
-    // trailing lower triangle: A[i][j] -= sum_c L[i][kb+c] L[j][kb+c]
-    for (int i = kb + nb + ty; i < p; i += kTY) {
-      double li[NBK];
-#pragma unroll
-      for (int c = 0; c < NBK; ++c) li[c] = c < nb ? A[i * ld + kb + c] : 0.0;
-      for (int j = kb + nb + tx; j <= i; j += kTX) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < NBK; ++c)
-          if (c < nb) acc = fma(li[c], A[j * ld + kb + c], acc);
-        A[i * ld + j] -= acc;
+    // trailing lower triangle: A22 -= L21 L21^T, and W rows below: B[i][j] -= L21[i] W[kb:, j]
+    // (i >= cols, j < cols), all as 16 x 16 tiles on the matrix cores
+    if (rem > 0) {
+      const int nt = (rem + 15) / 16;
+      const int ntri = nt * (nt + 1) / 2;
+      const int ntj = (cols + 15) / 16;
+      for (int t = wave + ntri; t < ntri + nt * ntj; t += NW) {
+        const int u = t - ntri;
+        const int ti = u / ntj, tj = u - ti * ntj;
+        mfma_tile_update(
+            W, ld, p, cols, cols + 16 * ti, 16 * tj, nb,
+            [&](int i, int k) { return i < p ? A[i * ld + kb + k] : 0.0; },
+            [&](int k, int j) { return j < cols ? W[(kb + k) * ld + j] : 0.0; }, -1.0);
+      }
+      for (int t = wave; t < ntri; t += NW) {
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        mfma_tile_update(
+            A, ld, p, p, r0 + 16 * ti, r0 + 16 * tj, NBK,
+            [&](int i, int k) { return i < p ? A[i * ld + kb + k] : 0.0; },
+            [&](int k, int j) { return j < p ? A[j * ld + kb + k] : 0.0; }, -1.0);
       }
     }
     __syncthreads();
@@ -108,54 +218,37 @@ __device__ __forceinline__ void chol_inverse(int p, double* A, double* W, double
     if (tid == 0) *flag = 1;
     return;
   }
-  // W = L^{-1}: start from the identity, then panels of rows.
-  for (int ii = ty; ii < p; ii += kTY)
-    for (int jj = tx; jj < p; jj += kTX) W[ii * ld + jj] = ii == jj ? 1.0 : 0.0;
-  __syncthreads();
-  for (int kb = 0; kb < p; kb += NBK) {
-    const int nb = min(NBK, p - kb);
-    const int cols = kb + nb;
-    if (tid < NBK) rdiag[tid] = tid < nb ? 1.0 / A[(kb + tid) * ld + kb + tid] : 1.0;
-    __syncthreads();
-    for (int j = tid; j < cols; j += kCholThreads) {  // W[kb:kb+nb, j] = L_kk^{-1} B[kb:kb+nb, j]
-      double x[NBK];
+  // (Sigma^Y)^{-1} = W^T W: lower 16 x 16 tiles, mirrored.
+  {
+    const int nt = (p + 15) / 16;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wave; t < nt * (nt + 1) / 2; t += NW) {
+      int ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      const int tj = t - ti * (ti + 1) / 2;
+      const int i0 = 16 * ti, j0 = 16 * tj;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+      const int kmin = i0;  // W is lower triangular: rows k < i0 contribute nothing
+      for (int k0 = kmin; k0 < p; k0 += 8) {
+        const int k = k0 + lk, k2 = k + 4;
+        const double av = (k < p && i0 + li < p) ? W[k * ld + i0 + li] : 0.0;
+        const double bv = (k < p && j0 + li < p) ? W[k * ld + j0 + li] : 0.0;
+        const double av2 = (k2 < p && i0 + li < p) ? W[k2 * ld + i0 + li] : 0.0;
+        const double bv2 = (k2 < p && j0 + li < p) ? W[k2 * ld + j0 + li] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av2, bv2, acc2, 0, 0, 0);
+      }
+      acc += acc2;
 #pragma unroll
-      for (int r = 0; r < NBK; ++r) x[r] = r < nb ? W[(kb + r) * ld + j] : 0.0;
-#pragma unroll
-      for (int r = 0; r < NBK; ++r) {
-        if (r < nb) {
-#pragma unroll
-          for (int q = 0; q < r; ++q) x[r] -= A[(kb + r) * ld + kb + q] * x[q];
-          x[r] *= rdiag[r];
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + lk + 4 * r, j = j0 + li;
+        if (i < p && j < p) {
+          Sinv[i * p + j] = acc[r];
+          Sinv[j * p + i] = acc[r];
         }
       }
-#pragma unroll
-      for (int r = 0; r < NBK; ++r)
-        if (r < nb) W[(kb + r) * ld + j] = x[r];
     }
-    __syncthreads();
-    for (int i = kb + nb + ty; i < p; i += kTY) {  // B[i][j] -= sum_r L[i][kb+r] W[kb+r][j]
-      double li[NBK];
-#pragma unroll
-      for (int r = 0; r < NBK; ++r) li[r] = r < nb ? A[i * ld + kb + r] : 0.0;
-      for (int j = tx; j < cols; j += kTX) {
-        double acc = 0.0;
-#pragma unroll
-        for (int r = 0; r < NBK; ++r)
-          if (r < nb) acc = fma(li[r], W[(kb + r) * ld + j], acc);
-        W[i * ld + j] -= acc;
-      }
-    }
-    __syncthreads();
   }
-  // (Sigma^Y)^{-1}[a][b] = sum_{k >= max(a,b)} W[k][a] W[k][b]
-  for (int a = ty; a < p; a += kTY)
-    for (int b = tx; b <= a; b += kTX) {
-      double acc = 0.0;
-      for (int k = a; k < p; ++k) acc = fma(W[k * ld + a], W[k * ld + b], acc);
-      Sinv[a * p + b] = acc;
-      Sinv[b * p + a] = acc;
-    }
 }
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const double* __restrict__ Syy,
@@ -164,7 +257,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const doub
   extern __shared__ double lds[];
   for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads) lds[(idx / p) * (p + 1) + idx % p] = Syy[idx];
   __syncthreads();
-  chol_inverse(p, lds, lds + p * (p + 1), Sinv, flag);
+  chol_inverse<kMaxPanelsLds>(p, lds, lds + p * (p + 1), Sinv, flag);
 }
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv_global(int p, const double* __restrict__ Syy,
@@ -174,7 +267,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_global(int p, const d
   for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads)
     work[(idx / p) * (p + 1) + idx % p] = Syy[idx];
   __syncthreads();
-  chol_inverse(p, work, work + p * (p + 1), Sinv, flag);
+  chol_inverse<kMaxPanels>(p, work, work + p * (p + 1), Sinv, flag);
 }
 
 // K[a][b] = sum_c Sxy[a][c] Sinv[c][b], FP64, rounded to FP32 (any p).  Block (64, 4).
@@ -192,7 +285,7 @@ __global__ __launch_bounds__(256) void k_gain_product(int p, int Ma, const doubl
   K[(size_t)a * p + b] = (float)s;
 }
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 
 // K = Sxy Sinv on the FP64 matrix cores.  A block of 4 waves owns 64 gain rows; wave w
 // computes rows 16w..16w+15 against every 16-column block of Sinv (staged in LDS,
@@ -242,11 +335,8 @@ __global__ __launch_bounds__(256) void k_gain_mfma(int p, int Ma, const double* 
 
 }  // namespace
 
-void launch_chol_gain(hipStream_t s, Timer& t, const Dims& d, int Ma, const double* S, double* Lwork,
-                      double* scratch, float* K, int* flag) {
-  const int p = d.p();
-  const double* Syy = S + (size_t)Ma * p;
-  double* Sinv = scratch;  // p*p
+void launch_chol(hipStream_t s, Timer& t, int p, const double* Syy, double* Lwork, double* Sinv,
+                 int* flag) {
   if (p <= kLdsMaxP) {
     static bool attr_set = false;
     if (!attr_set) {
@@ -260,17 +350,21 @@ void launch_chol_gain(hipStream_t s, Timer& t, const Dims& d, int Ma, const doub
     OIC_LAUNCH(t, KC_CHOL, s, k_chol_inv_global, dim3(1), dim3(kCholThreads), 0, p, Syy, Lwork, Sinv,
                flag);
   }
+}
+
+void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv, float* K,
+                 const int* flag) {
   const int nbk = (p + 15) / 16;
   const dim3 g((unsigned)((Ma + 63) / 64));
   switch (nbk) {
 #define OIC_GAIN_CASE(NBV) \
-  case NBV: OIC_LAUNCH(t, KC_GAIN, s, k_gain_mfma<NBV>, g, dim3(256), 0, p, Ma, S, Sinv, K, flag); return;
+  case NBV: OIC_LAUNCH(t, KC_GAIN, s, k_gain_mfma<NBV>, g, dim3(256), 0, p, Ma, Sxy, Sinv, K, flag); return;
     OIC_GAIN_CASE(1) OIC_GAIN_CASE(2) OIC_GAIN_CASE(3) OIC_GAIN_CASE(4)
     OIC_GAIN_CASE(5) OIC_GAIN_CASE(6) OIC_GAIN_CASE(7) OIC_GAIN_CASE(8)
 #undef OIC_GAIN_CASE
     default:
       OIC_LAUNCH(t, KC_GAIN, s, k_gain_product, dim3((unsigned)((Ma + 3) / 4), (unsigned)((p + 63) / 64)),
-                 dim3(64, 4), 0, p, Ma, S, Sinv, K, flag);
+                 dim3(64, 4), 0, p, Ma, Sxy, Sinv, K, flag);
   }
 }
 

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -102,7 +103,11 @@ struct oic_ctx {
   float* act[2] = {nullptr, nullptr};
   float* mu_traj = nullptr;
   double* muY = nullptr;  // FP64 means of Ybar
-  double* S = nullptr;
+  double* S = nullptr;     // Sigma^{XY} (Ma x p)
+  double* Syy = nullptr;   // Sigma^Y (p x p)
+  double* Sinv = nullptr;  // (Sigma^Y)^{-1}
+  hipStream_t side = nullptr;            // the gain solve overlaps Sigma^{XY} on this stream
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* part = nullptr;
   int max_splits = 32;
   double* Lwork = nullptr;
@@ -128,6 +133,14 @@ struct oic_ctx {
 };
 
 namespace {
+
+// Held while a solve is captured into a graph and while any handle creates or frees
+// device resources (memory, streams, events, graphs): a resource call from another
+// thread in the middle of a capture can invalidate that capture.
+std::mutex& resource_mutex() {
+  static std::mutex m;
+  return m;
+}
 
 #define HIP_TRY(expr)                                                        \
   do {                                                                       \
@@ -274,6 +287,11 @@ void free_all(oic_ctx* h) {
   f(h->mu_traj);
   f(h->muY);
   f(h->S);
+  f(h->Syy);
+  f(h->Sinv);
+  if (h->ev_fork) hipEventDestroy(h->ev_fork);
+  if (h->ev_join) hipEventDestroy(h->ev_join);
+  if (h->side) hipStreamDestroy(h->side);
   f(h->part);
   f(h->Lwork);
   f(h->K);
@@ -414,10 +432,17 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     // FP64-centred Ybar anomalies sum to zero, so sum_i X^i D^iT = sum_i A^i D^iT.
     const int Ma = (t + 1) * rr;
     launch_means_f64(s, h->timer, h->Y, p, N, m, h->muY);
-    // Eqs. (13b), (13c).
-    launch_stats(s, h->timer, d, h->traj, Ma, h->Y, h->muY, h->part, h->max_splits, h->S);
+    // Eq. (13b): Sigma^Y first; its Cholesky factor and inverse run on the side stream
+    // while Eq. (13c), Sigma^{XY}, runs here.
+    launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->max_splits, h->Syy);
+    hipEventRecord(h->ev_fork, s);
+    hipStreamWaitEvent(h->side, h->ev_fork, 0);
+    launch_chol(h->side, h->timer, p, h->Syy, h->Lwork, h->Sinv, h->flag);
+    hipEventRecord(h->ev_join, h->side);
+    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->max_splits, h->S);
+    hipStreamWaitEvent(s, h->ev_join, 0);
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
-    launch_chol_gain(s, h->timer, d, Ma, h->S, h->Lwork, h->part, h->K, h->flag);
+    launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->K, h->flag);
     launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m);
   }
   // Line 13: smoothed means of every slice.
@@ -481,6 +506,7 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   const bool seeded = !explicit_noise;
   if (h->use_graph && !h->timer.enabled) {
     if (!h->gexec || h->gN != N || h->gH != H || h->gSeeded != seeded) {
+      std::lock_guard<std::mutex> guard(resource_mutex());
       if (h->gexec) {
         hipGraphExecDestroy(h->gexec);
         h->gexec = nullptr;
@@ -524,6 +550,7 @@ extern "C" {
 
 int oic_create(const oic_config* cfg, oic_handle* out) {
   if (!cfg || !out) return OIC_EINVAL;
+  std::lock_guard<std::mutex> guard(resource_mutex());
   *out = nullptr;
   const oic_config& c = *cfg;
   if (c.n < 4 || c.m < 4 || c.l < 1 || c.l > c.n || c.n_layers < 1 || c.n_layers > OIC_MAX_LAYERS ||
@@ -566,6 +593,12 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   rc = rc ? rc : dalloc(h, &h->S, (Ma_max + p) * p);
   rc = rc ? rc : dalloc(h, &h->part, std::max((size_t)h->max_splits * (Ma_max + p) * p, Ma_max * p));
   rc = rc ? rc : dalloc(h, &h->Lwork, 2 * p * (p + 1));
+  rc = rc ? rc : dalloc(h, &h->Syy, p * p);
+  rc = rc ? rc : dalloc(h, &h->Sinv, p * p);
+  if (!rc && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) rc = OIC_EDEVICE;
+  if (!rc && (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess))
+    rc = OIC_EDEVICE;
   rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
   rc = rc ? rc : dalloc(h, &h->flag, 1);
   for (int k = 0; k < 4 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));
@@ -596,6 +629,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
 
 void oic_destroy(oic_handle h) {
   if (!h) return;
+  std::lock_guard<std::mutex> guard(resource_mutex());
   hipStreamSynchronize(h->stream);
   free_all(h);
   h->timer.destroy();
@@ -607,6 +641,7 @@ const char* oic_last_error(oic_handle h) { return h ? h->err.c_str() : "NULL han
 
 int oic_set_weights(oic_handle h, const float* B, const float* const* W, const float* const* bias) {
   if (!h) return OIC_EINVAL;
+  std::lock_guard<std::mutex> guard(resource_mutex());
   h->err.clear();
   const oic_config& c = h->cfg;
   if (!B || !W) return fail(h, OIC_EINVAL, "NULL B or W");
@@ -769,8 +804,37 @@ int oic_kernel_stats(oic_handle h, int id, const char** name, long long* launche
 
 void* oic_stream(oic_handle h) { return h ? (void*)h->stream : nullptr; }
 
+namespace {
+// sum over columns of e^T M^{-1} e with e = E - E0 (E0 may be NULL) and M = L L^T
+// (host FP64): solve L z = e, add |z|^2.
+double quad_form_inv(const std::vector<double>& L, int k, const float* E, const float* E0, int m) {
+  double total = 0.0;
+  std::vector<double> z(k);
+  for (int x = 0; x < m; ++x) {
+    for (int i = 0; i < k; ++i) {
+      double v = (double)E[(size_t)i * m + x] - (E0 ? (double)E0[(size_t)i * m + x] : 0.0);
+      for (int c = 0; c < i; ++c) v -= L[(size_t)i * k + c] * z[c];
+      z[i] = v / L[(size_t)i * k + i];
+      total += z[i] * z[i];
+    }
+  }
+  return total;
+}
+}  // namespace
+
+int oic_stage_cost(int n, int m, int l, const float* X, const float* Xref, const float* U,
+                   const float* dU, const float* Q, const float* R, double* cost) {
+  if (n < 1 || m < 1 || l < 1 || !X || !Xref || !U || !dU || !Q || !R || !cost) return OIC_EINVAL;
+  std::vector<double> Lq, Lr;
+  if (!host_cholesky(Q, l, Lq) || !host_cholesky(R, n, Lr)) return OIC_EINVAL;
+  *cost = quad_form_inv(Lr, n, X, Xref, m) + quad_form_inv(Lq, l, U, nullptr, m) +
+          quad_form_inv(Lq, l, dU, nullptr, m);
+  return OIC_OK;
+}
+
 int oic_set_graph(oic_handle h, int enable) {
   if (!h) return OIC_EINVAL;
+  std::lock_guard<std::mutex> guard(resource_mutex());
   h->use_graph = enable != 0;
   if (!h->use_graph && h->gexec) {
     hipStreamSynchronize(h->stream);

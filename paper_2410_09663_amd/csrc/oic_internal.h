@@ -126,14 +126,17 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
 // Statistics and update.
 void launch_means(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, float* mean);
 void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, double* mean);
-// S[a][b] (FP64, (Ma+p) x p): sum over columns of left row a times the FP64-centred Ybar row b;
-// left rows are the first Ma trajectory rows followed by the p rows of Ybar.
-void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, const float* Y,
-                  const double* muY, double* part, int max_splits, double* S);
-// Factor Sigma^Ybar (rows Ma..Ma+p-1 of S) in FP64 and solve K Sigma^Ybar = S[0:Ma] for the gain.
-// `scratch` holds p*Ma doubles.  flag is set to 1 when a pivot is not positive and finite.
-void launch_chol_gain(hipStream_t s, Timer& t, const Dims& d, int Ma, const double* S, double* Lwork,
-                      double* scratch, float* K, int* flag);
+// S[a][b] (FP64, (Ma+ny) x p): sum over columns of left row a times the FP64-centred Ybar
+// row b; left rows are the first Ma trajectory rows followed by the first ny rows of Ybar.
+void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
+                  const float* Y, const double* muY, double* part, int max_splits, double* S);
+// (Sigma^Y)^{-1} from the p x p Syy by an FP64 Cholesky factor (one workgroup); flag is
+// set to 1 when a pivot is not positive and finite.  Lwork holds 2 p (p+1) doubles.
+void launch_chol(hipStream_t s, Timer& t, int p, const double* Syy, double* Lwork, double* Sinv,
+                 int* flag);
+// K = Sxy Sinv (Ma x p, FP64 products, FP32 result); skipped when flag is set.
+void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv, float* K,
+                 const int* flag);
 // Analysis of the first Ma trajectory rows (in place).
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
                    const float* Y, const float* xref_t);

@@ -86,7 +86,7 @@ size_t footprint_bytes(const oic_config& c) {
   const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l;
   const size_t NM = N * m, Ma = Hs * rr;
   size_t f = 4 * (Hs * rr * NM + p * NM + 2 * N * n * m * cmax + Ma * m + Ma * p);
-  f += 8 * (p * m + (Ma + p) * p + 32 * (Ma + p) * p + 2 * p * (p + 1));
+  f += 8 * (p * m + (Ma + p) * p + 32 * (Ma + p) * p + 2 * p * (p + 1) + 2 * p * p);
   f += 4 * (N * l * m + (Hs - 1) * N * (2 * l + n) * m);                  // noise
   f += 4 * (n * m + Hs * n * m + l * m + N * (2 * n + l) * m + Hs * (l + n) * m + 3 * l * m + l * l + n * n);
   f += 64 << 10;                                                           // weights, small buffers
@@ -98,33 +98,46 @@ bool can_admit(const oic_server* s, const Controller& c) {
   if (c.h) return true;
   size_t reclaimable = 0;
   for (auto& o : s->ctrls)
-    if (o->h && !o->busy) reclaimable += o->footprint;
+    if (o->h && !o->busy && o.get() != &c) reclaimable += o->footprint;
   return s->used - reclaimable + c.footprint <= s->budget;
 }
 
+// Called with the lock held, right after the scheduling decision (same lock hold, so
+// the budget check and the reservation are atomic).  Chooses the LRU idle victims,
+// takes them and c's footprint out of the budget at once, then releases the lock for
+// the slow part (saving the victims' U_prev, freeing them, creating c's handle).
 int make_resident(oic_server* s, Controller& c, std::unique_lock<std::mutex>& lk) {
   if (c.h) return OIC_OK;
-  // evict idle least-recently-used controllers until the footprint fits
+  std::vector<std::pair<oic_handle, Controller*>> victims;
   while (s->used + c.footprint > s->budget) {
     Controller* victim = nullptr;
     for (auto& o : s->ctrls)
-      if (o->h && !o->busy && (!victim || o->last_used < victim->last_used)) victim = o.get();
-    if (!victim) return OIC_ENOMEM;
-    oic_handle vh = victim->h;
+      if (o->h && !o->busy && o.get() != &c && (!victim || o->last_used < victim->last_used))
+        victim = o.get();
+    if (!victim) {
+      for (auto& v : victims) {  // undo (cannot happen after a positive can_admit)
+        v.second->h = v.first;
+        v.second->busy = false;
+        s->used += v.second->footprint;
+        s->evictions--;
+      }
+      return OIC_ENOMEM;
+    }
+    victims.emplace_back(victim->h, victim);
     victim->h = nullptr;
-    victim->busy = true;  // keep others off it while its state is saved
-    lk.unlock();
-    victim->u_prev.resize((size_t)victim->cfg.l * victim->cfg.m);
-    oic_get_u_prev(vh, victim->u_prev.data());
-    oic_destroy(vh);
-    lk.lock();
-    victim->busy = false;
+    victim->busy = true;  // its requests wait until its state is saved
     s->used -= victim->footprint;
     s->evictions++;
   }
   s->used += c.footprint;
   if (s->used > s->peak_used) s->peak_used = s->used;
   lk.unlock();
+  for (auto& v : victims) {
+    Controller* vc = v.second;
+    vc->u_prev.resize((size_t)vc->cfg.l * vc->cfg.m);
+    oic_get_u_prev(v.first, vc->u_prev.data());
+    oic_destroy(v.first);
+  }
   oic_handle h = nullptr;
   int rc = oic_create(&c.cfg, &h);
   if (rc == OIC_OK) {
@@ -139,6 +152,7 @@ int make_resident(oic_server* s, Controller& c, std::unique_lock<std::mutex>& lk
     }
   }
   lk.lock();
+  for (auto& v : victims) v.second->busy = false;
   if (rc != OIC_OK) {
     s->used -= c.footprint;
     return rc;

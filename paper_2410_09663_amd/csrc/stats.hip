@@ -139,7 +139,7 @@ constexpr int MK = 64;  // columns per LDS stage
 // (N*m divisible by 4) and loaded as float4, one stage ahead of the compute.
 template <int NB, bool VEC>
 __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restrict__ traj, int Ma,
-                                                    const float* __restrict__ Y,
+                                                    int ny, const float* __restrict__ Y,
                                                     const double* __restrict__ muY, int chunk,
                                                     double* __restrict__ part) {
   constexpr int RB = NB * 16;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
   __shared__ double sB[RB][MK + 1];
   const int NM = (int)d.NM();
   const int m = d.m, p = d.p();
-  const int Mtot = Ma + p;
+  const int Mtot = Ma + ny;
   const int a0 = blockIdx.x * MA;
   const int b0 = blockIdx.y * RB;
   const int c_begin = blockIdx.z * chunk;
@@ -299,10 +299,10 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
              rows, N, m, mean);
 }
 
-void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, const float* Y,
-                  const double* muY, double* part, int max_splits, double* S) {
+void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
+                  const float* Y, const double* muY, double* part, int max_splits, double* S) {
   const int p = d.p();
-  const int Mtot = Ma + p;
+  const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
   // right rows per block: NB*16 with NB <= 8, balanced over grid.y tiles
   const int nbk = (p + 15) / 16;
@@ -323,11 +323,11 @@ void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 #define OIC_STATS_CASE(NBV)                                                                     \
   case NBV:                                                                                     \
     if (vec)                                                                                    \
-      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, true>), grid, dim3(256), 0, d, traj, Ma, Y,  \
-                 muY, chunk, part);                                                             \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, true>), grid, dim3(256), 0, d, traj, Ma, ny, \
+                 Y, muY, chunk, part);                                                          \
     else                                                                                        \
-      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, false>), grid, dim3(256), 0, d, traj, Ma, Y, \
-                 muY, chunk, part);                                                             \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, false>), grid, dim3(256), 0, d, traj, Ma, ny,\
+                 Y, muY, chunk, part);                                                          \
     break;
   switch (NB) {
     OIC_STATS_CASE(1) OIC_STATS_CASE(2) OIC_STATS_CASE(3) OIC_STATS_CASE(4)

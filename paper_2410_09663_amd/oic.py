@@ -102,6 +102,7 @@ def lib():
                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
             "oic_server_last_error": (ctypes.c_char_p, [vp]),
             "oic_footprint_bytes": (cs, [ctypes.POINTER(oic_config)]),
+            "oic_stage_cost": (ci, [ci, ci, ci, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -116,7 +117,7 @@ EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "o
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
             "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
             "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
-            "oic_footprint_bytes"]
+            "oic_footprint_bytes", "oic_stage_cost"]
 
 
 def _is_torch(x) -> bool:
@@ -320,6 +321,20 @@ def controller_for(problem, max_N=None, max_H=None, precision=None, mem_mode=OIC
                    mem_mode=mem_mode, stream=stream)
     c.set_weights(problem.B, problem.weights)
     return c
+
+
+def stage_cost(X, Xref, U, dU, Q, R) -> float:
+    """Stage cost of the tracking objective (oic_stage_cost), host arrays."""
+    f = lambda a: np.ascontiguousarray(a, np.float32)
+    X, Xref, U, dU, Q, R = map(f, (X, Xref, U, dU, Q, R))
+    n, m = X.shape
+    l = U.shape[0]
+    out = ctypes.c_double()
+    rc = lib().oic_stage_cost(n, m, l, X.ctypes.data, Xref.ctypes.data, U.ctypes.data, dU.ctypes.data,
+                              Q.ctypes.data, R.ctypes.data, ctypes.byref(out))
+    if rc != OIC_OK:
+        raise OicError(rc, "oic_stage_cost failed")
+    return out.value
 
 
 class Server:

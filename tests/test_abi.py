@@ -52,3 +52,23 @@ def test_host_side_validation_needs_no_device():
     cfg.activation = 7
     assert L.oic_create(ctypes.byref(cfg), ctypes.byref(h)) == oic.OIC_EINVAL
     assert L.oic_solve(None, None, None, None, None, 2, 1, 0, None, None) == oic.OIC_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(oic.LIB_PATH), reason="liboic.so not built")
+def test_stage_cost_matches_oracle_trace_form():
+    """Host-side cost of the library vs the oracle's trace form (no device call)."""
+    import numpy as np
+    from oracle import cost
+    from paper_2410_09663_amd import workloads as wl
+    rng = np.random.default_rng(4)
+    n, m, l = 6, 5, 3
+    X, Xr = rng.standard_normal((2, n, m)).astype(np.float32)
+    U, dU = rng.standard_normal((2, l, m)).astype(np.float32)
+    Q = wl.random_spd(l, 1)
+    R = wl.random_spd(n, 2)
+    got = oic.stage_cost(X, Xr, U, dU, Q, R)
+    ref = cost.stage_cost_trace(X, Xr, U, np.zeros_like(U), dU, R.astype(np.float64),
+                                Q.astype(np.float64), Q.astype(np.float64))
+    assert abs(got - ref) <= 1e-10 * abs(ref)
+    with pytest.raises(oic.OicError):
+        oic.stage_cost(X, Xr, U, dU, -Q, R)
