@@ -1,10 +1,12 @@
 // Gain of the matrix-normal Kalman update, Eq. (10a) / Eq. (14b):
 //   K = Sigma^{XY} (Sigma^Y)^{-1},
 // in FP64.  The matrix inverted is p x p with p = n + l (the rows of the virtual
-// observation).  One workgroup factors Sigma^Y = L L^T (Cholesky), inverts L in
-// place and forms (Sigma^Y)^{-1} = L^{-T} L^{-1}; a second, wide kernel multiplies
-// Sigma^{XY} by it.  For p <= 128 the factor lives in LDS; larger p work on an
-// L2-resident global copy with the same code.
+// observation).  For p <= 90 one workgroup factors Sigma^Y = L L^T (Cholesky) in LDS,
+// inverts L and forms (Sigma^Y)^{-1} = L^{-T} L^{-1}; a second, wide kernel
+// multiplies Sigma^{XY} by it.  Larger p use a blocked factorisation spread over the
+// chip and two blocked triangular solves for the gain.
+#include <algorithm>
+
 #include "oic_internal.h"
 
 namespace oic {
@@ -14,7 +16,6 @@ constexpr int kCholThreads = 512;                  // 8 waves
 constexpr int kLdsMaxP = 90;                       // two p x (p+1) FP64 arrays in the 160 KiB LDS
 constexpr int NBK = 8;                             // panel width
 constexpr int kMaxPanelsLds = (kLdsMaxP + NBK - 1) / NBK;  // 12
-constexpr int kMaxPanels = 64;                              // p <= 512
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -82,8 +83,8 @@ __device__ __forceinline__ void mfma_tile_update(double* M, int ld, int rows, in
 // a rank-8 update of the rows below, on the matrix cores), and (Sigma^Y)^{-1} = W^T W
 // is one more matrix-core product.  The odd leading dimension spreads the rows read by
 // the 16 lanes of an operand fragment over distinct LDS banks.
-template <int MAXPAN>
-__device__ __forceinline__ void chol_inverse(int p, double* A, double* W, double* __restrict__ Sinv,
+template <int MAXPAN, bool SQUARE>
+__device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double* __restrict__ Sinv,
                                              int* __restrict__ flag) {
   const int ld = p + 1;
   __shared__ int bad;
@@ -216,8 +217,9 @@ __device__ __forceinline__ void chol_inverse(int p, double* A, double* W, double
   }
   if (bad) {
     if (tid == 0) *flag = 1;
-    return;
+    return false;
   }
+  if (!SQUARE) return true;
   // (Sigma^Y)^{-1} = W^T W: lower 16 x 16 tiles, mirrored.
   {
     const int nt = (p + 15) / 16;
@@ -249,6 +251,7 @@ __device__ __forceinline__ void chol_inverse(int p, double* A, double* W, double
       }
     }
   }
+  return true;
 }
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const double* __restrict__ Syy,
@@ -257,17 +260,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const doub
   extern __shared__ double lds[];
   for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads) lds[(idx / p) * (p + 1) + idx % p] = Syy[idx];
   __syncthreads();
-  chol_inverse<kMaxPanelsLds>(p, lds, lds + p * (p + 1), Sinv, flag);
-}
-
-__global__ __launch_bounds__(kCholThreads) void k_chol_inv_global(int p, const double* __restrict__ Syy,
-                                                                  double* __restrict__ work,
-                                                                  double* __restrict__ Sinv,
-                                                                  int* __restrict__ flag) {
-  for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads)
-    work[(idx / p) * (p + 1) + idx % p] = Syy[idx];
-  __syncthreads();
-  chol_inverse<kMaxPanels>(p, work, work + p * (p + 1), Sinv, flag);
+  chol_inverse<kMaxPanelsLds, true>(p, lds, lds + p * (p + 1), Sinv, flag);
 }
 
 // K[a][b] = sum_c Sxy[a][c] Sinv[c][b], FP64, rounded to FP32 (any p).  Block (64, 4).
@@ -333,34 +326,314 @@ __global__ __launch_bounds__(256) void k_gain_mfma(int p, int Ma, const double* 
     }
 }
 
+
+// ---- Blocked factorisation for p > kLdsMaxP ----
+//
+// Right-looking blocked Cholesky with kPB-wide panels, one kernel per phase so that
+// every phase spreads over the whole chip: per panel, (1) one workgroup factors the
+// diagonal block in LDS and forms its inverse (the code above, without the final
+// product), (2) the rows below become L21 = A21 L11^{-T}, (3) the trailing lower
+// triangle takes A22 -= L21 L21^T.  The factor overwrites the lower triangle of
+// Sigma^Y in place; the inverses of the diagonal blocks go to a side buffer.  The gain
+// then follows from two blocked triangular solves per row of Sigma^{XY} (no explicit
+// inverse): z L^T = s, then k L = z, i.e. k = s L^{-T} L^{-1} = s (Sigma^Y)^{-1}.
+constexpr int kPB = 64;
+constexpr int kPBP = kPB + 1;  // padded LDS leading dimension
+
+__global__ __launch_bounds__(kCholThreads) void k_potrf_diag(int p, double* __restrict__ A, int kb,
+                                                             double* __restrict__ Linv,
+                                                             int* __restrict__ flag) {
+  extern __shared__ double lds[];  // 2 x kPB x (kPB + 1)
+  if (*flag) return;  // an earlier step failed; the solve reports it
+  const int nb = min(kPB, p - kb);
+  const int ld = nb + 1;
+  double* sA = lds;
+  double* sW = lds + nb * ld;
+  for (int e = threadIdx.x; e < nb * nb; e += kCholThreads) {
+    const int r = e / nb, c = e - r * nb;
+    sA[r * ld + c] = A[(size_t)(kb + r) * p + kb + c];
+  }
+  __syncthreads();
+  if (!chol_inverse<kPB / NBK, false>(nb, sA, sW, nullptr, flag)) return;
+  __syncthreads();
+  double* out = Linv + (size_t)(kb / kPB) * kPB * kPB;
+  for (int e = threadIdx.x; e < kPB * kPB; e += kCholThreads) {
+    const int r = e / kPB, c = e - r * kPB;
+    const bool in = r < nb && c <= r;
+    out[e] = in ? sW[r * ld + c] : 0.0;
+    if (r < nb && c < nb) A[(size_t)(kb + r) * p + kb + c] = in ? sA[r * ld + c] : 0.0;
+  }
+}
+
+// Rows r0 + 64*blockIdx.x .. +63 (r0 = kb + nb): L21 = A21 L11^{-T}.  Wave w owns 16
+// rows against the panel's four 16-column blocks.
+__global__ __launch_bounds__(256) void k_potrf_trsm(int p, double* __restrict__ A, int kb,
+                                                    const double* __restrict__ Linv,
+                                                    const int* __restrict__ flag) {
+  __shared__ double sL[kPB * kPBP];
+  __shared__ double sR[64 * kPBP];
+  if (*flag) return;
+  const int nb = min(kPB, p - kb);
+  const int i0 = kb + nb + blockIdx.x * 64;
+  const double* Li = Linv + (size_t)(kb / kPB) * kPB * kPB;
+  for (int e = threadIdx.x; e < kPB * kPB; e += 256) {
+    const int r = e / kPB, c = e - r * kPB;
+    sL[r * kPBP + c] = Li[e];
+    sR[r * kPBP + c] = (i0 + r < p && c < nb) ? A[(size_t)(i0 + r) * p + kb + c] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kPB; k0 += 4) {
+    const double av = sR[(16 * w + li) * kPBP + k0 + lk];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)  // B[k][j] = L11^{-1}[j][k]
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sL[(16 * cb + li) * kPBP + k0 + lk], acc[cb],
+                                                     0, 0, 0);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + 16 * w + lk + 4 * r, col = 16 * cb + li;
+      if (row < p && col < nb) A[(size_t)row * p + kb + col] = acc[cb][r];
+    }
+}
+
+// Trailing update of the lower triangle: 64 x 64 tile (ti, tj), ti >= tj, of the
+// rows/columns from r0 = kb + nb: A22 -= L21[ti] L21[tj]^T.
+__global__ __launch_bounds__(256) void k_potrf_syrk(int p, double* __restrict__ A, int kb,
+                                                    const int* __restrict__ flag) {
+  __shared__ double sI[64 * kPBP];
+  __shared__ double sJ[64 * kPBP];
+  if (*flag) return;
+  const int nb = min(kPB, p - kb);
+  const int r0 = kb + nb;
+  int ti = 0;
+  const int t = blockIdx.x;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
+  for (int e = threadIdx.x; e < 64 * kPB; e += 256) {
+    const int r = e / kPB, c = e - r * kPB;
+    sI[r * kPBP + c] = (i0 + r < p && c < nb) ? A[(size_t)(i0 + r) * p + kb + c] : 0.0;
+    sJ[r * kPBP + c] = (j0 + r < p && c < nb) ? A[(size_t)(j0 + r) * p + kb + c] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + 16 * w + lk + 4 * r, col = j0 + 16 * cb + li;
+      acc[cb][r] = (row < p && col < p) ? A[(size_t)row * p + col] : 0.0;
+    }
+#pragma unroll 4
+  for (int k0 = 0; k0 < kPB; k0 += 4) {
+    const double av = sI[(16 * w + li) * kPBP + k0 + lk];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, -sJ[(16 * cb + li) * kPBP + k0 + lk], acc[cb],
+                                                     0, 0, 0);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + 16 * w + lk + 4 * r, col = j0 + 16 * cb + li;
+      if (row < p && col < p) A[(size_t)row * p + col] = acc[cb][r];
+    }
+}
+
+// K rows a0 .. a0 + RB - 1 (a0 = RB*blockIdx.x) from the factor L (lower triangle of
+// A) and the diagonal-block inverses: forward z_i = (s_i - sum_{k<i} z_k L_ik^T)
+// L_ii^{-T}, then backward k_i = (z_i - sum_{j>i} k_j L_ji) L_ii^{-1}, panel by panel,
+// in FP64 on the matrix cores; the RB x p row block stays in LDS throughout and each
+// 64 x 64 block of L passes through LDS once per use.  Tiles: RB/16 row tiles x 4
+// column tiles of the current panel, spread over the 4 waves.
+template <int RB>
+__global__ __launch_bounds__(256) void k_gain_trsm(int p, int Ma, const double* __restrict__ Sxy,
+                                                   const double* __restrict__ A,
+                                                   const double* __restrict__ Linv,
+                                                   float* __restrict__ K, const int* __restrict__ flag) {
+  extern __shared__ double lds[];
+  constexpr int RT = RB / 16;       // row tiles
+  constexpr int TPW = RT * 4 / 4;   // tiles per wave
+  if (*flag) return;
+  const int npan = (p + kPB - 1) / kPB;
+  const int PP = npan * kPB + 1;    // z leading dimension
+  double* z = lds;                  // RB x PP
+  double* tmp = z + RB * PP;        // RB x kPBP
+  double* sL = tmp + RB * kPBP;     // kPB x kPBP
+  const int a0 = blockIdx.x * RB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < RB * npan * kPB; e += 256) {
+    const int r = e / (npan * kPB), c = e - r * (npan * kPB);
+    z[r * PP + c] = (a0 + r < Ma && c < p) ? Sxy[(size_t)(a0 + r) * p + c] : 0.0;
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // tile u of this wave: row tile rt = (w*TPW + u) / 4, column tile ct = (w*TPW + u) % 4
+  auto stage_block = [&](int bi, int bj) {  // sL[r][c] = L[64 bi + r][64 bj + c]
+    for (int e = tid; e < kPB * kPB; e += 256) {
+      const int r = e / kPB, c = e - r * kPB;
+      const int gr = bi * kPB + r, gc = bj * kPB + c;
+      sL[r * kPBP + c] = (gr < p && gc < p) ? A[(size_t)gr * p + gc] : 0.0;
+    }
+  };
+  auto stage_inv = [&](int bi) {
+    const double* Li = Linv + (size_t)bi * kPB * kPB;
+    for (int e = tid; e < kPB * kPB; e += 256) {
+      const int r = e / kPB, c = e - r * kPB;
+      sL[r * kPBP + c] = Li[e];
+    }
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fwd = pass == 0;
+    for (int q = 0; q < npan; ++q) {
+      const int i = fwd ? q : npan - 1 - q;
+      f64x4 acc[TPW];
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int rt = (w * TPW + u) / 4, ct = (w * TPW + u) % 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[u][r] = z[(16 * rt + lk + 4 * r) * PP + i * kPB + 16 * ct + li];
+      }
+      // the other panels' contributions: forward k < i uses L_ik^T, backward j > i uses L_ji
+      const int kb0 = fwd ? 0 : i + 1, kb1 = fwd ? i : npan;
+      for (int kbk = kb0; kbk < kb1; ++kbk) {
+        __syncthreads();
+        if (fwd)
+          stage_block(i, kbk);
+        else
+          stage_block(kbk, i);
+        __syncthreads();
+#pragma unroll 4
+        for (int k0 = 0; k0 < kPB; k0 += 4) {
+#pragma unroll
+          for (int u = 0; u < TPW; ++u) {
+            const int rt = (w * TPW + u) / 4, ct = (w * TPW + u) % 4;
+            const double av = z[(16 * rt + li) * PP + kbk * kPB + k0 + lk];
+            // forward: B[k][j] = L_ik[j][k]; backward: B[k][j] = L_ji[k][j]
+            const double bv = fwd ? sL[(16 * ct + li) * kPBP + k0 + lk] : sL[(k0 + lk) * kPBP + 16 * ct + li];
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, -bv, acc[u], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();  // every wave is done with sL and with tmp of the previous panel
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int rt = (w * TPW + u) / 4, ct = (w * TPW + u) % 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tmp[(16 * rt + lk + 4 * r) * kPBP + 16 * ct + li] = acc[u][r];
+      }
+      stage_inv(i);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < kPB; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+          const int rt = (w * TPW + u) / 4, ct = (w * TPW + u) % 4;
+          const double av = tmp[(16 * rt + li) * kPBP + k0 + lk];
+          // forward: times L_ii^{-T} (B[k][j] = Linv[j][k]); backward: times L_ii^{-1}
+          const double bv = fwd ? sL[(16 * ct + li) * kPBP + k0 + lk] : sL[(k0 + lk) * kPBP + 16 * ct + li];
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int rt = (w * TPW + u) / 4, ct = (w * TPW + u) % 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[(16 * rt + lk + 4 * r) * PP + i * kPB + 16 * ct + li] = acc[u][r];
+      }
+      __syncthreads();  // z_i is complete before any later panel reads it
+    }
+  }
+  for (int e = tid; e < RB * p; e += 256) {
+    const int r = e / p, c = e - r * p;
+    if (a0 + r < Ma) K[(size_t)(a0 + r) * p + c] = (float)z[r * PP + c];
+  }
+}
+
+size_t gain_trsm_lds(int p, int RB) {
+  const int npan = (p + kPB - 1) / kPB;
+  return sizeof(double) * ((size_t)RB * (npan * kPB + 1) + (size_t)RB * kPBP + (size_t)kPB * kPBP);
+}
+
 }  // namespace
 
-void launch_chol(hipStream_t s, Timer& t, int p, const double* Syy, double* Lwork, double* Sinv,
-                 int* flag) {
+void launch_chol(hipStream_t s, Timer& t, int p, double* Syy, double* Lwork, double* Sinv, int* flag) {
   if (p <= kLdsMaxP) {
-    static bool attr_set = false;
-    if (!attr_set) {
+    static const bool attr_set = [] {  // thread-safe one-time set-up
       hipFuncSetAttribute((const void*)k_chol_inv_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                           2 * kLdsMaxP * (kLdsMaxP + 1) * (int)sizeof(double));
-      attr_set = true;
-    }
+      return true;
+    }();
+    (void)attr_set;
     OIC_LAUNCH(t, KC_CHOL, s, k_chol_inv_lds, dim3(1), dim3(kCholThreads),
                2 * (size_t)p * (p + 1) * sizeof(double), p, Syy, Sinv, flag);
-  } else {
-    OIC_LAUNCH(t, KC_CHOL, s, k_chol_inv_global, dim3(1), dim3(kCholThreads), 0, p, Syy, Lwork, Sinv,
+    return;
+  }
+  // blocked: Syy is factored in place, the diagonal-block inverses go to Lwork
+  const size_t diag_lds = 2 * (size_t)kPB * kPBP * sizeof(double);
+  static const bool diag_attr = [&] {
+    hipFuncSetAttribute((const void*)k_potrf_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)diag_lds);
+    return true;
+  }();
+  (void)diag_attr;
+  for (int kb = 0; kb < p; kb += kPB) {
+    OIC_LAUNCH(t, KC_CHOL, s, k_potrf_diag, dim3(1), dim3(kCholThreads), diag_lds, p, Syy, kb, Lwork,
+               flag);
+    const int rem = p - kb - std::min(kPB, p - kb);
+    if (rem <= 0) break;
+    const int nt = (rem + 63) / 64;
+    OIC_LAUNCH(t, KC_CHOL, s, k_potrf_trsm, dim3((unsigned)nt), dim3(256), 0, p, Syy, kb, Lwork, flag);
+    OIC_LAUNCH(t, KC_CHOL, s, k_potrf_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, p, Syy, kb,
                flag);
   }
 }
 
-void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv, float* K,
-                 const int* flag) {
+bool chol_blocked(int p) { return p > kLdsMaxP; }
+
+void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv,
+                 const double* L, const double* Linv, float* K, const int* flag) {
+  if (p > kLdsMaxP) {
+    // rows per block: 32 while the row block and its staging fit the LDS, else 16
+    const bool big = gain_trsm_lds(p, 32) <= 160 * 1024;
+    const int RB = big ? 32 : 16;
+    const size_t bytes = gain_trsm_lds(p, RB);
+    static const bool attr_set = [] {
+      hipFuncSetAttribute((const void*)k_gain_trsm<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          160 * 1024);
+      hipFuncSetAttribute((const void*)k_gain_trsm<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          160 * 1024);
+      return true;
+    }();
+    (void)attr_set;
+    const dim3 g((unsigned)((Ma + RB - 1) / RB));
+    if (big)
+      OIC_LAUNCH(t, KC_GAIN, s, k_gain_trsm<32>, g, dim3(256), bytes, p, Ma, Sxy, L, Linv, K, flag);
+    else
+      OIC_LAUNCH(t, KC_GAIN, s, k_gain_trsm<16>, g, dim3(256), bytes, p, Ma, Sxy, L, Linv, K, flag);
+    return;
+  }
   const int nbk = (p + 15) / 16;
   const dim3 g((unsigned)((Ma + 63) / 64));
   switch (nbk) {
 #define OIC_GAIN_CASE(NBV) \
   case NBV: OIC_LAUNCH(t, KC_GAIN, s, k_gain_mfma<NBV>, g, dim3(256), 0, p, Ma, Sxy, Sinv, K, flag); return;
     OIC_GAIN_CASE(1) OIC_GAIN_CASE(2) OIC_GAIN_CASE(3) OIC_GAIN_CASE(4)
-    OIC_GAIN_CASE(5) OIC_GAIN_CASE(6) OIC_GAIN_CASE(7) OIC_GAIN_CASE(8)
+    OIC_GAIN_CASE(5) OIC_GAIN_CASE(6)
 #undef OIC_GAIN_CASE
     default:
       OIC_LAUNCH(t, KC_GAIN, s, k_gain_product, dim3((unsigned)((Ma + 3) / 4), (unsigned)((p + 63) / 64)),

@@ -312,6 +312,32 @@ void free_all(oic_ctx* h) {
 // single output channel to `out`.
 // True when the handle's rollout runs with BF16 activations: BF16 precision was
 // requested and every layer has a BF16 kernel (first 2->C, hidden C->C', last C->1).
+}  // namespace
+
+namespace oic {
+
+bool bf16_rollout_possible(const oic_config& c) {
+  const int L = c.n_layers;
+  if (c.precision != OIC_PREC_BF16 || L < 2) return false;
+  if (!conv_first_supported(c.channels[1], c.l) || !conv_last_supported(c.channels[L - 1])) return false;
+  for (int k = 1; k < L - 1; ++k)
+    if (!conv_mfma_bf16_supported(c.channels[k], c.channels[k + 1])) return false;
+  return true;
+}
+
+size_t activation_floats(const oic_config& c) {
+  size_t cmax = 2;
+  for (int k = 1; k < c.n_layers; ++k) cmax = std::max(cmax, (size_t)c.channels[k]);
+  const size_t full = (size_t)c.max_N * c.n * c.m * cmax;
+  if (!bf16_rollout_possible(c)) return full;
+  // BF16 activations for batched rollouts; FP32 only for the one-field plant step
+  return std::max((full + 1) / 2, (size_t)c.n * c.m * cmax);
+}
+
+}  // namespace oic
+
+namespace {
+
 bool rollout_bf16(oic_ctx* h) {
   const oic_config& c = h->cfg;
   const int L = c.n_layers;
@@ -442,7 +468,7 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->max_splits, h->S);
     hipStreamWaitEvent(s, h->ev_join, 0);
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
-    launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->K, h->flag);
+    launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
     launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m);
   }
   // Line 13: smoothed means of every slice.
@@ -586,8 +612,8 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   int rc = OIC_OK;
   rc = rc ? rc : dalloc(h, &h->traj, Hs * rr * NM);
   rc = rc ? rc : dalloc(h, &h->Y, p * NM);
-  rc = rc ? rc : dalloc(h, &h->act[0], N * n * m * (size_t)h->cmax);
-  rc = rc ? rc : dalloc(h, &h->act[1], N * n * m * (size_t)h->cmax);
+  rc = rc ? rc : dalloc(h, &h->act[0], activation_floats(c));
+  rc = rc ? rc : dalloc(h, &h->act[1], activation_floats(c));
   rc = rc ? rc : dalloc(h, &h->mu_traj, Ma_max * m);
   rc = rc ? rc : dalloc(h, &h->muY, p * m);  // doubles
   rc = rc ? rc : dalloc(h, &h->S, (Ma_max + p) * p);

@@ -118,6 +118,10 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
                            void* out_nhwc);
 
 // Hidden layers on MFMA (FP32).  wk holds the weights as [tap*cin + c][cout].
+// Whether a handle with this configuration runs its batched rollouts in BF16, and the
+// floats each of its two activation buffers holds.
+bool bf16_rollout_possible(const oic_config& c);
+size_t activation_floats(const oic_config& c);
 bool conv_mfma_supported(int cin, int cout);
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                       const float* in_nhwc, const float* wk, const float* bias, int act,
@@ -130,13 +134,17 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
 // row b; left rows are the first Ma trajectory rows followed by the first ny rows of Ybar.
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const double* muY, double* part, int max_splits, double* S);
-// (Sigma^Y)^{-1} from the p x p Syy by an FP64 Cholesky factor (one workgroup); flag is
-// set to 1 when a pivot is not positive and finite.  Lwork holds 2 p (p+1) doubles.
-void launch_chol(hipStream_t s, Timer& t, int p, const double* Syy, double* Lwork, double* Sinv,
-                 int* flag);
-// K = Sxy Sinv (Ma x p, FP64 products, FP32 result); skipped when flag is set.
-void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv, float* K,
-                 const int* flag);
+// FP64 Cholesky factor of the p x p Syy; flag is set to 1 when a pivot is not positive
+// and finite.  p <= 90 (one workgroup, LDS): Sinv = (Sigma^Y)^{-1}, Syy untouched.
+// p > 90 (blocked, chip-wide): Syy is overwritten by L in its lower triangle and
+// Lwork receives the inverses of its 64 x 64 diagonal blocks; Sinv is not written.
+// Lwork holds 2 p (p+1) doubles.
+void launch_chol(hipStream_t s, Timer& t, int p, double* Syy, double* Lwork, double* Sinv, int* flag);
+// K = Sxy (Sigma^Y)^{-1} (Ma x p, FP64 arithmetic, FP32 result), from Sinv for p <= 90
+// and from L (lower triangle of the factored Syy) and its diagonal-block inverses
+// (Lwork) otherwise; skipped when flag is set.
+void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv,
+                 const double* L, const double* Linv, float* K, const int* flag);
 // Analysis of the first Ma trajectory rows (in place).
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
                    const float* Y, const float* xref_t);

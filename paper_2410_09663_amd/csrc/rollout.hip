@@ -165,27 +165,30 @@ __device__ __forceinline__ void stage_halo(const bf16_t* __restrict__ in, int i,
 }
 
 // Hidden layer as an implicit GEMM on MFMA (v_mfma_f32_16x16x4_f32): rows = output
-// pixels, columns = output channels, K = 9*CIN ordered (tap, channel).  A block owns
-// TR output rows x 64 output columns of one member; wave w computes rows
-// w, w+4, ... as 16-pixel M-blocks against all COUT/16 N-blocks.  The input halo tile
-// ((TR+2) x 66 x CIN, zero-padded) and the weights Wk[tap*CIN + c][o] sit in LDS; the
-// pixel stride in LDS is CIN+1 floats so the 16 pixels of an A fragment fall in
-// distinct banks.  Lane layout (16x16x4 f32): A[i][k] from lane i + 16k, B[k][j] from
-// lane j + 16k, and element r of lane j + 16g holds D[4g + r][j].
-template <int CIN, int COUT, int TR>
+// pixels, columns = output channels, K = 9*CIN ordered (channel chunk, tap, channel).
+// A block owns TR output rows x 64 output columns of one member; wave w computes rows
+// w, w+4, ... as 16-pixel M-blocks against all COUT/16 N-blocks.  The input channels
+// are taken CCH at a time: per chunk the halo tile ((TR+2) x 66 x CCH, zero-padded)
+// and the weight rows Wk[tap*CIN + c][o] of those channels sit in LDS (so 64-channel
+// layers fit), and the accumulators carry over the chunks.  The pixel stride in LDS
+// is CCH+1 floats so the 16 pixels of an A fragment fall in distinct banks.  Lane
+// layout (16x16x4 f32): A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, and
+// element r of lane j + 16g holds D[4g + r][j].
+template <int CIN, int COUT, int TR, int CCH>
 __global__ __launch_bounds__(256) void k_conv_mfma_f32(int N, int n, int m,
                                                        const float* __restrict__ in,
                                                        const float* __restrict__ wk,
                                                        const float* __restrict__ bias, int act,
                                                        float* __restrict__ out) {
+  static_assert(CIN % CCH == 0 && CCH % 4 == 0, "channel chunks");
   constexpr int TC = 64;
   constexpr int HR = TR + 2, HC = TC + 2;
-  constexpr int CP = CIN + 1;
-  constexpr int KD = 9 * CIN;
+  constexpr int CP = CCH + 1;
+  constexpr int KC = 9 * CCH;  // K-indices per chunk
   constexpr int NB = COUT / 16;
   constexpr int RPW = TR / 4;  // output rows per wave
   __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
-  __shared__ __attribute__((aligned(16))) float s_w[KD * COUT];
+  __shared__ __attribute__((aligned(16))) float s_w[KC * COUT];
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
   int bid = blockIdx.x;
@@ -195,23 +198,6 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32(int N, int n, int m,
   const int i = bid / row_tiles;
   const int y0 = rt * TR, x0 = ct * TC;
   const int tid = threadIdx.x;
-  {
-    constexpr int WV = KD * COUT / 4;
-    constexpr int WS = (WV + 255) / 256;
-    f32x4 wv[WS];
-#pragma unroll
-    for (int u = 0; u < WS; ++u) {
-      const int e = tid + 256 * u;
-      wv[u] = e < WV ? *(const f32x4*)(wk + 4 * e) : f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    stage_halo<CIN, HR, HC, CP, 256>(in, i, n, m, y0, x0, s_in);
-#pragma unroll
-    for (int u = 0; u < WS; ++u) {
-      const int e = tid + 256 * u;
-      if (e < WV) *(f32x4*)(s_w + 4 * e) = wv[u];
-    }
-  }
-  __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   f32x4 acc[RPW][4][NB];
@@ -221,23 +207,74 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32(int N, int n, int m,
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < CIN; c0 += CCH) {
+    if (c0 > 0) __syncthreads();  // the previous chunk's reads are done
+    {
+      // weight rows (tap, c0..c0+CCH) -> s_w[(tap*CCH + cc)*COUT + o]; every global
+      // load of the thread is issued before its first LDS store
+      constexpr int WQ = CCH * COUT / 4;  // float4 per tap
+      constexpr int WV = 9 * WQ;
+      constexpr int WS = (WV + 255) / 256;
+      constexpr int Q = CCH / 4;
+      constexpr int TOTAL = HR * HC * Q;
+      constexpr int SLOTS = (TOTAL + 255) / 256;
+      f32x4 wv[WS], v[SLOTS];
+#pragma unroll
+      for (int u = 0; u < WS; ++u) {
+        const int e = tid + 256 * u;
+        const int tap = e / WQ, r = e - tap * WQ;
+        wv[u] = e < WV ? *(const f32x4*)(wk + ((size_t)tap * CIN + c0) * COUT + 4 * r)
+                       : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < SLOTS; ++u) {
+        const int e = tid + u * 256;
+        v[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (e < TOTAL) {
+          const int q = e % Q, pix = e / Q;
+          const int xx = pix % HC, yy = pix / HC;
+          const int gy = y0 + yy - 1, gx = x0 + xx - 1;
+          if (gy >= 0 && gy < n && gx >= 0 && gx < m)
+            v[u] = *(const f32x4*)(in + (((size_t)i * n + gy) * m + gx) * CIN + c0 + 4 * q);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < WS; ++u) {
+        const int e = tid + 256 * u;
+        if (e < WV) *(f32x4*)(s_w + 4 * e) = wv[u];
+      }
+#pragma unroll
+      for (int u = 0; u < SLOTS; ++u) {
+        const int e = tid + u * 256;
+        if (e < TOTAL) {
+          const int q = e % Q, pix = e / Q;
+          float* dst = s_in + pix * CP + 4 * q;
+          dst[0] = v[u][0];
+          dst[1] = v[u][1];
+          dst[2] = v[u][2];
+          dst[3] = v[u][3];
+        }
+      }
+    }
+    __syncthreads();
 #pragma unroll 2
-  for (int kb = 0; kb < KD / 4; ++kb) {
-    const int k = kb * 4 + lk;
-    const int tap = k / CIN, c = k - tap * CIN;
-    const int dy = tap / 3, dx = tap - dy * 3;
-    float b[NB];
+    for (int kb = 0; kb < KC / 4; ++kb) {
+      const int k = kb * 4 + lk;
+      const int tap = k / CCH, c = k - tap * CCH;
+      const int dy = tap / 3, dx = tap - dy * 3;
+      float b[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) b[nb] = s_w[k * COUT + nb * 16 + li];
+      for (int nb = 0; nb < NB; ++nb) b[nb] = s_w[k * COUT + nb * 16 + li];
 #pragma unroll
-    for (int rw = 0; rw < RPW; ++rw) {
-      const int ry = w + 4 * rw;
+      for (int rw = 0; rw < RPW; ++rw) {
+        const int ry = w + 4 * rw;
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const float a = s_in[((ry + dy) * HC + mb * 16 + li + dx) * CP + c];
+        for (int mb = 0; mb < 4; ++mb) {
+          const float a = s_in[((ry + dy) * HC + mb * 16 + li + dx) * CP + c];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[rw][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[rw][mb][nb], 0, 0, 0);
+          for (int nb = 0; nb < NB; ++nb)
+            acc[rw][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[rw][mb][nb], 0, 0, 0);
+        }
       }
     }
   }
@@ -612,8 +649,7 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
 }
 
 bool conv_mfma_supported(int cin, int cout) {
-  return (cin == 16 && cout == 16) || (cin == 32 && cout == 32) || (cin == 16 && cout == 32) ||
-         (cin == 32 && cout == 16);
+  return (cin == 16 || cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64);
 }
 
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
@@ -621,16 +657,22 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
                       float* out_nhwc) {
 #define OIC_CONV_CASE(CI, CO)                                                                   \
   if (cin == CI && cout == CO) {                                                                \
-    constexpr int TRV = CI <= 16 ? 8 : 4;                                                       \
+    constexpr int TRV = (CI <= 16 && CO <= 32) ? 8 : 4;                                         \
+    constexpr int CCH = CI <= 32 ? CI : 32;                                                     \
     const unsigned blocks = (unsigned)((long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64)); \
-    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, m, \
-               in_nhwc, wk, bias, act, out_nhwc);                                               \
+    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32<CI, CO, TRV, CCH>), dim3(blocks), dim3(256), 0, N, n, \
+               m, in_nhwc, wk, bias, act, out_nhwc);                                            \
     return;                                                                                     \
   }
   OIC_CONV_CASE(16, 16)
   OIC_CONV_CASE(32, 32)
   OIC_CONV_CASE(16, 32)
   OIC_CONV_CASE(32, 16)
+  OIC_CONV_CASE(64, 64)
+  OIC_CONV_CASE(16, 64)
+  OIC_CONV_CASE(64, 16)
+  OIC_CONV_CASE(32, 64)
+  OIC_CONV_CASE(64, 32)
 #undef OIC_CONV_CASE
 }
 

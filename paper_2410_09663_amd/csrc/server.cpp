@@ -26,7 +26,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/oic.h"
+#include "oic_internal.h"
 
 namespace {
 
@@ -81,11 +81,9 @@ namespace {
 
 // Device bytes oic_create allocates for cfg (mirrors its buffer list, rounded up).
 size_t footprint_bytes(const oic_config& c) {
-  size_t cmax = 2;
-  for (int k = 1; k < c.n_layers; ++k) cmax = cmax > (size_t)c.channels[k] ? cmax : (size_t)c.channels[k];
   const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l;
   const size_t NM = N * m, Ma = Hs * rr;
-  size_t f = 4 * (Hs * rr * NM + p * NM + 2 * N * n * m * cmax + Ma * m + Ma * p);
+  size_t f = 4 * (Hs * rr * NM + p * NM + 2 * oic::activation_floats(c) + Ma * m + Ma * p);
   f += 8 * (p * m + (Ma + p) * p + 32 * (Ma + p) * p + 2 * p * (p + 1) + 2 * p * p);
   f += 4 * (N * l * m + (Hs - 1) * N * (2 * l + n) * m);                  // noise
   f += 4 * (n * m + Hs * n * m + l * m + N * (2 * n + l) * m + Hs * (l + n) * m + 3 * l * m + l * l + n * n);

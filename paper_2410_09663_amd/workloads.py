@@ -73,6 +73,34 @@ PRESETS = {
 }
 
 
+# Serving mix: per controller a grid side from SERVE_GRIDS, l = side/4, N and H drawn
+# from the lists below, and the CNN of matching size.
+SERVE_GRIDS = (32, 64, 128, 256)
+SERVE_N = (64, 128, 256)
+SERVE_H = (5, 10, 20)
+SERVE_CNN = {32: ([2, 16, 16, 1], ACT_TANH), 64: ([2, 16, 16, 1], ACT_TANH),
+             128: ([2, 32, 32, 32, 1], ACT_GELU), 256: ([2, 64, 64, 64, 64, 1], ACT_GELU)}
+
+
+def serving_mix(count: int, seed: int = 7, precision: int = PREC_BF16) -> List[Preset]:
+    """`count` independent controllers drawn uniformly from the serving mix, each with its
+    own seeds for B, the weights and X0; GRF length and bump width 0.75 sqrt(n), the bump
+    drifting one column per step from (n/2, m/4); Q = 0.05 I, R = 0.005 I."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(count):
+        g = int(rng.choice(SERVE_GRIDS))
+        N = int(rng.choice(SERVE_N))
+        H = int(rng.choice(SERVE_H))
+        ch, act = SERVE_CNN[g]
+        ell = 0.75 * math.sqrt(g)
+        out.append(Preset(f"serve{c}", g, g, g // 4, list(ch), act, N, H, 0.05, 0.005, ell, "moving",
+                          ell, (g / 2.0, g / 4.0), closed_loop_steps=1, precision=precision,
+                          seed_B=10 * c + 100, seed_W=10 * c + 101, seed_X0=10 * c + 102,
+                          noise_seed_base=10 * c + 103))
+    return out
+
+
 def small_preset(n=8, m=8, l=2, channels=(2, 4, 1), activation=ACT_TANH, N=16, H=3,
                  q=0.1, r=0.01, name="tiny") -> Preset:
     """A hand-sized preset for unit tests (ragged sizes allowed)."""

@@ -53,10 +53,17 @@ def test_device_normals_match_oracle(kind, count):
         assert np.all(np.abs(got[diff].view(np.int32) - ref[diff].view(np.int32)) <= 1)
 
 
-@pytest.mark.parametrize("preset", ["C1", "C2", "tiny", "tiny_gelu", "wide"])
+@pytest.mark.parametrize("preset", ["C1", "C2", "tiny", "tiny_gelu", "wide", "deep_a", "deep_b"])
 def test_cnn_forward_matches_oracle(preset):
     if preset == "tiny":
         p = tiny()
+    elif preset == "deep_a":
+        # hidden pairs (64,64), (64,32), (32,16), (16,64): channel-chunked MFMA layers;
+        # 9 rows and 70 columns leave ragged row and column tiles
+        p = wl.small_preset(n=9, m=70, l=4, channels=(2, 64, 64, 32, 16, 64, 1),
+                            activation=wl.ACT_GELU, N=3)
+    elif preset == "deep_b":
+        p = wl.small_preset(n=13, m=66, l=5, channels=(2, 16, 32, 64, 16, 1), N=3)
     elif preset == "tiny_gelu":
         p = tiny(n=5, m=7, l=3, channels=(2, 5, 4, 1), act=wl.ACT_GELU)
     elif preset == "wide":
@@ -76,10 +83,19 @@ def test_cnn_forward_matches_oracle(preset):
     assert np.array_equal(one, got[0])
 
 
-@pytest.mark.parametrize("preset", ["C1", "tiny", "tiny_gelu", "tiny_l1", "C2"])
+@pytest.mark.parametrize("preset", ["C1", "tiny", "tiny_gelu", "tiny_l1", "C2", "p100", "p150",
+                                    "p500"])
 def test_solve_explicit_noise_matches_oracle(preset):
     if preset == "tiny":
         p = tiny()
+    elif preset == "p100":
+        # p = n + l = 100 > 90: blocked Cholesky (panels 64 + 36) and triangular-solve gain
+        p = tiny(n=80, m=6, l=20, channels=(2, 4, 1), N=40, H=2)
+    elif preset == "p150":
+        p = tiny(n=120, m=4, l=30, channels=(2, 4, 1), N=64, H=3)
+    elif preset == "p500":
+        # p = 500: eight panels, the gain's 16-row blocks
+        p = tiny(n=400, m=2, l=100, channels=(2, 4, 1), N=400, H=2)
     elif preset == "tiny_gelu":
         p = tiny(n=5, m=7, l=3, channels=(2, 5, 4, 1), act=wl.ACT_GELU, N=6, H=4)
     elif preset == "tiny_l1":
