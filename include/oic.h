@@ -51,6 +51,10 @@ extern "C" {
 
 #define OIC_PREC_FP32 0   /* rollout in FP32 */
 #define OIC_PREC_BF16 1   /* rollout in BF16 x BF16 products with FP32 accumulation */
+#define OIC_PREC_FP8 2    /* hidden layers in OCP FP8 e4m3 x e4m3 products with FP32 accumulation:
+                             weights scaled per output channel, activations per layer by their
+                             largest magnitude over the ensemble; BF16 storage between layers;
+                             hidden widths 32 or 64 in, 16, 32 or 64 out */
 
 #define OIC_MEM_HOST 0
 #define OIC_MEM_DEVICE 1

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <new>
 #include <string>
@@ -94,6 +95,9 @@ struct oic_ctx {
   float* dW[OIC_MAX_LAYERS] = {};
   float* dWk[OIC_MAX_LAYERS] = {};     // [tap*cin + c][cout] FP32 copies for the MFMA layers
   uint16_t* dWb[OIC_MAX_LAYERS] = {};  // [cout][tap*cin + c] BF16 copies for the BF16 rollout
+  uint8_t* dWq[OIC_MAX_LAYERS] = {};   // [cout][tap*cin + c, zero-padded to 128] e4m3 for FP8
+  float* dWs[OIC_MAX_LAYERS] = {};     // per-output-channel scales of dWq
+  unsigned* amax = nullptr;            // per-layer activation maxima of an FP8 rollout
   float* dBias[OIC_MAX_LAYERS] = {};
   int cmax = 2;
 
@@ -108,8 +112,8 @@ struct oic_ctx {
   double* Sinv = nullptr;  // (Sigma^Y)^{-1}
   hipStream_t side = nullptr;            // the gain solve overlaps Sigma^{XY} on this stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  double* part = nullptr;
-  int max_splits = 32;
+  double* part = nullptr;   // split-K partial sums of the statistics
+  size_t part_cap = 0;      // its size in doubles
   double* Lwork = nullptr;
   float* K = nullptr;
   int* flag = nullptr;
@@ -278,8 +282,11 @@ void free_all(oic_ctx* h) {
     f(h->dW[k]);
     f(h->dWk[k]);
     f(h->dWb[k]);
+    f(h->dWq[k]);
+    f(h->dWs[k]);
     f(h->dBias[k]);
   }
+  f(h->amax);
   f(h->traj);
   f(h->Y);
   f(h->act[0]);
@@ -308,20 +315,22 @@ void free_all(oic_ctx* h) {
   h->gexec = nullptr;
 }
 
-// Runs the CNN of Eq. (1) on `batch` fields given as strided sources, writing the
-// single output channel to `out`.
-// True when the handle's rollout runs with BF16 activations: BF16 precision was
-// requested and every layer has a BF16 kernel (first 2->C, hidden C->C', last C->1).
 }  // namespace
 
 namespace oic {
 
+// Whether a handle's batched rollouts run with BF16 activations: BF16 or FP8 precision
+// was requested and every layer has a kernel for it (first 2->C and last C->1 with
+// BF16 storage; hidden C->C' in BF16, or in FP8 for the FP8 precision).
 bool bf16_rollout_possible(const oic_config& c) {
   const int L = c.n_layers;
-  if (c.precision != OIC_PREC_BF16 || L < 2) return false;
+  if ((c.precision != OIC_PREC_BF16 && c.precision != OIC_PREC_FP8) || L < 2) return false;
   if (!conv_first_supported(c.channels[1], c.l) || !conv_last_supported(c.channels[L - 1])) return false;
-  for (int k = 1; k < L - 1; ++k)
-    if (!conv_mfma_bf16_supported(c.channels[k], c.channels[k + 1])) return false;
+  for (int k = 1; k < L - 1; ++k) {
+    const int ci = c.channels[k], co = c.channels[k + 1];
+    if (c.precision == OIC_PREC_FP8 ? !conv_mfma_fp8_supported(ci, co) : !conv_mfma_bf16_supported(ci, co))
+      return false;
+  }
   return true;
 }
 
@@ -338,33 +347,45 @@ size_t activation_floats(const oic_config& c) {
 
 namespace {
 
-bool rollout_bf16(oic_ctx* h) {
+enum RolloutMode { RM_FP32 = 0, RM_BF16 = 1, RM_FP8 = 2 };
+
+// The handle's batched rollout mode once its weights are set.
+RolloutMode rollout_mode(oic_ctx* h) {
   const oic_config& c = h->cfg;
-  const int L = c.n_layers;
-  if (c.precision != OIC_PREC_BF16 || L < 2) return false;
-  if (!conv_first_supported(c.channels[1], c.l) || !conv_last_supported(c.channels[L - 1])) return false;
-  for (int k = 1; k < L - 1; ++k)
-    if (!h->dWb[k]) return false;
-  return true;
+  if (!h->weights_set || !bf16_rollout_possible(c)) return RM_FP32;
+  return c.precision == OIC_PREC_FP8 ? RM_FP8 : RM_BF16;
 }
 
 // Runs the CNN of Eq. (1) on `batch` fields given as strided sources, writing the
-// single output channel to `out`.  bf16 selects BF16 activations (see rollout_bf16).
-void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, bool bf16) {
+// single output channel to `out`, in the given mode (the plant step always uses FP32).
+void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode) {
   const oic_config& c = h->cfg;
   const int L = c.n_layers;
-  if (bf16) {
+  if (mode != RM_FP32) {
+    const bool f8 = mode == RM_FP8;
+    // per-layer activation maxima: slot k holds the largest |x| written by layer k
+    if (f8) launch_zero_u32(h->stream, h->timer, h->amax, L);
     launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
-                      h->dBias[0], c.activation, h->act[1], true);
+                      h->dBias[0], c.activation, h->act[1], true, f8 ? h->amax : nullptr);
     int cur = 1;
     for (int k = 1; k < L - 1; ++k) {
-      launch_conv_mfma_bf16(h->stream, h->timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
-                            c.channels[k + 1], h->act[cur], h->dWb[k], h->dBias[k], c.activation,
-                            h->act[1 - cur]);
+      if (f8)
+        launch_conv_mfma_fp8(h->stream, h->timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
+                             c.channels[k + 1], h->act[cur], h->amax + (k - 1), h->dWq[k], h->dWs[k],
+                             h->dBias[k], c.activation, h->act[1 - cur], h->amax + k);
+      else
+        launch_conv_mfma_bf16(h->stream, h->timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
+                              c.channels[k + 1], h->act[cur], h->dWb[k], h->dBias[k], c.activation,
+                              h->act[1 - cur]);
       cur = 1 - cur;
     }
     launch_conv_last(h->stream, h->timer, batch, c.n, c.m, c.channels[L - 1], h->act[cur],
                      h->dW[L - 1], h->dBias[L - 1], out, true);
+    return;
+  }
+  if (rollout3_supported(L, c.channels, c.l) && h->dWk[1]) {
+    launch_rollout3(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, h->dW[0], h->dBias[0],
+                    h->dWk[1], h->dBias[1], h->dW[2], h->dBias[2], c.activation, out);
     return;
   }
   int cur = 0;
@@ -398,6 +419,31 @@ void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, bool b
                 h->dBias[k], c.activation, last ? nullptr : h->act[1 - cur], fo);
     cur = 1 - cur;
   }
+}
+
+// OCP FP8 e4m3 (bias 7, no infinities, largest finite 448) nearest to f, ties to the
+// even code, saturating beyond 448.  The finite non-negative codes 0x00..0x7E are
+// increasing in value, so the nearest is found by bisection over them.
+uint8_t host_e4m3(float f) {
+  static const std::vector<float> table = [] {
+    std::vector<float> t(127);
+    for (int c = 0; c < 127; ++c) {
+      const int e = c >> 3, mant = c & 7;
+      t[c] = e == 0 ? std::ldexp((float)mant / 8.0f, -6) : std::ldexp(1.0f + (float)mant / 8.0f, e - 7);
+    }
+    return t;
+  }();
+  const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+  const float a = std::fabs(f);
+  if (!(a < table[126])) return sign | 0x7E;  // saturate (NaN does not occur: finite weights)
+  int lo = 0, hi = 126;                       // table[lo] <= a < table[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (table[mid] <= a) lo = mid; else hi = mid;
+  }
+  const float dl = a - table[lo], dh = table[hi] - a;
+  const int c = dl < dh ? lo : (dh < dl ? hi : ((lo & 1) ? hi : lo));
+  return sign | (uint8_t)c;
 }
 
 uint16_t host_bf16(float f) {
@@ -447,7 +493,7 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     float* cur = h->traj + (size_t)t * slice;
     // Line 6 / Eq. (15b): X rows of slice t through the CNN, from the analysed slice t-1.
     rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
-            FieldOut{cur, m, NM}, rollout_bf16(h));
+            FieldOut{cur, m, NM}, rollout_mode(h));
     launch_assemble_u(s, h->timer, d, h->traj, t,
                       noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true));
     // Line 9 / Eq. (12).
@@ -460,12 +506,12 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     launch_means_f64(s, h->timer, h->Y, p, N, m, h->muY);
     // Eq. (13b): Sigma^Y first; its Cholesky factor and inverse run on the side stream
     // while Eq. (13c), Sigma^{XY}, runs here.
-    launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->max_splits, h->Syy);
+    launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->part_cap, h->Syy);
     hipEventRecord(h->ev_fork, s);
     hipStreamWaitEvent(h->side, h->ev_fork, 0);
     launch_chol(h->side, h->timer, p, h->Syy, h->Lwork, h->Sinv, h->flag);
     hipEventRecord(h->ev_join, h->side);
-    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->max_splits, h->S);
+    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S);
     hipStreamWaitEvent(s, h->ev_join, 0);
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
     launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
@@ -581,7 +627,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   const oic_config& c = *cfg;
   if (c.n < 4 || c.m < 4 || c.l < 1 || c.l > c.n || c.n_layers < 1 || c.n_layers > OIC_MAX_LAYERS ||
       c.max_N < 2 || c.max_H < 1 || (c.activation != OIC_ACT_TANH && c.activation != OIC_ACT_GELU) ||
-      (c.precision != OIC_PREC_FP32 && c.precision != OIC_PREC_BF16) ||
+      (c.precision != OIC_PREC_FP32 && c.precision != OIC_PREC_BF16 && c.precision != OIC_PREC_FP8) ||
       (c.mem_mode != OIC_MEM_HOST && c.mem_mode != OIC_MEM_DEVICE))
     return OIC_EINVAL;
   if (c.channels[0] != 2 || c.channels[c.n_layers] != 1) return OIC_EINVAL;
@@ -617,7 +663,8 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   rc = rc ? rc : dalloc(h, &h->mu_traj, Ma_max * m);
   rc = rc ? rc : dalloc(h, &h->muY, p * m);  // doubles
   rc = rc ? rc : dalloc(h, &h->S, (Ma_max + p) * p);
-  rc = rc ? rc : dalloc(h, &h->part, std::max((size_t)h->max_splits * (Ma_max + p) * p, Ma_max * p));
+  h->part_cap = std::max((size_t)32 * (Ma_max + p) * p, Ma_max * p);
+  rc = rc ? rc : dalloc(h, &h->part, h->part_cap);
   rc = rc ? rc : dalloc(h, &h->Lwork, 2 * p * (p + 1));
   rc = rc ? rc : dalloc(h, &h->Syy, p * p);
   rc = rc ? rc : dalloc(h, &h->Sinv, p * p);
@@ -627,6 +674,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
     rc = OIC_EDEVICE;
   rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
   rc = rc ? rc : dalloc(h, &h->flag, 1);
+  rc = rc ? rc : dalloc(h, &h->amax, OIC_MAX_LAYERS);
   for (int k = 0; k < 4 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));
   rc = rc ? rc : dalloc(h, &h->Uprev, l * m);
   rc = rc ? rc : dalloc(h, &h->Uprev_new, l * m);
@@ -695,6 +743,26 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
             wk[((size_t)tap * cin + ci) * cout + o] = W[k][((size_t)o * cin + ci) * 9 + tap];
       if (!h->dWk[k] && (rc = dalloc(h, &h->dWk[k], cnt))) return rc;
       HIP_TRY(hipMemcpy(h->dWk[k], wk.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (c.precision == OIC_PREC_FP8 && k > 0 && k < c.n_layers - 1 && conv_mfma_fp8_supported(cin, cout)) {
+      // e4m3 copy scaled per output channel, [o][c][dy][dx] -> [o][(dy*3+dx)*cin + c],
+      // each row zero-padded to a multiple of 128
+      const size_t kd = (size_t)9 * cin, kd128 = (kd + 127) / 128 * 128;
+      std::vector<uint8_t> wq((size_t)cout * kd128, 0);
+      std::vector<float> ws(cout);
+      for (int o = 0; o < cout; ++o) {
+        float mx = 0.f;
+        for (size_t e = 0; e < kd; ++e) mx = std::max(mx, std::fabs(W[k][(size_t)o * kd + e]));
+        ws[o] = mx > 0.f ? mx / 448.0f : 1.0f;
+        for (int ci = 0; ci < cin; ++ci)
+          for (int tap = 0; tap < 9; ++tap)
+            wq[(size_t)o * kd128 + (size_t)tap * cin + ci] =
+                host_e4m3(W[k][((size_t)o * cin + ci) * 9 + tap] / ws[o]);
+      }
+      if (!h->dWq[k] && (rc = dalloc(h, &h->dWq[k], wq.size()))) return rc;
+      if (!h->dWs[k] && (rc = dalloc(h, &h->dWs[k], (size_t)cout))) return rc;
+      HIP_TRY(hipMemcpy(h->dWq[k], wq.data(), wq.size(), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(h->dWs[k], ws.data(), cout * sizeof(float), hipMemcpyHostToDevice));
     }
     if (c.precision == OIC_PREC_BF16 && k > 0 && k < c.n_layers - 1 && conv_mfma_bf16_supported(cin, cout)) {
       // BF16 copy, [o][c][dy][dx] -> [o][(dy*3+dx)*cin + c]
@@ -776,7 +844,7 @@ int cnn_forward_impl(oic_handle h, int batch, const float* X, const float* U, fl
   if ((rc = copy_in(h, dU, U, batch * l * m))) return rc;
   rollout(h, batch, FieldRef{dX, (long long)(n * m), (long long)m},
           FieldRef{dU, (long long)(l * m), (long long)m}, FieldOut{dO, (long long)(n * m), (long long)m},
-          fp32_only ? false : rollout_bf16(h));
+          fp32_only ? RM_FP32 : rollout_mode(h));
   if ((rc = copy_out(h, X_next, dO, batch * n * m))) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->timer.harvest();

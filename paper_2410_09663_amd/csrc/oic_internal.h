@@ -108,7 +108,7 @@ bool conv_last_supported(int cin);
 // bf16: activations are stored as BF16 (first layer output, last layer input).
 void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
                        const float* B, int cout, const float* w, const float* bias, int act,
-                       void* out_nhwc, bool bf16);
+                       void* out_nhwc, bool bf16, unsigned* amax = nullptr);
 void launch_conv_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
                       const float* w, const float* bias, FieldOut fo, bool bf16);
 // Hidden layers in BF16 on MFMA.  wt holds BF16 weights as [cout][tap*cin + c].
@@ -116,6 +116,20 @@ bool conv_mfma_bf16_supported(int cin, int cout);
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                            const void* in_nhwc, const void* wt, const float* bias, int act,
                            void* out_nhwc);
+// The 2 -> 16 -> 16 -> 1 FP32 network in one kernel (hidden activations stay in LDS);
+// l <= 16.  w2k is the [tap*16 + c][o] layout of the hidden layer.
+bool rollout3_supported(int n_layers, const int* ch, int l);
+void launch_rollout3(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
+                     const float* B, const float* w1, const float* b1, const float* w2k, const float* b2,
+                     const float* w3, const float* b3, int act, FieldOut fo);
+// FP8 hidden layer: BF16 NHWC in and out, input scale from *amax_in (largest |x| of the
+// input layer), weights wq [cout][K padded to 128] e4m3 with per-channel scales ws;
+// folds the largest |output| into *amax_out.
+bool conv_mfma_fp8_supported(int cin, int cout);
+void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
+                          const void* in_nhwc, const unsigned* amax_in, const uint8_t* wq, const float* ws,
+                          const float* bias, int act, void* out_nhwc, unsigned* amax_out);
+void launch_zero_u32(hipStream_t s, Timer& t, unsigned* p, int count);
 
 // Hidden layers on MFMA (FP32).  wk holds the weights as [tap*cin + c][cout].
 // Whether a handle with this configuration runs its batched rollouts in BF16, and the
@@ -133,7 +147,7 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
 // S[a][b] (FP64, (Ma+ny) x p): sum over columns of left row a times the FP64-centred Ybar
 // row b; left rows are the first Ma trajectory rows followed by the first ny rows of Ybar.
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
-                  const float* Y, const double* muY, double* part, int max_splits, double* S);
+                  const float* Y, const double* muY, double* part, size_t part_cap, double* S);
 // FP64 Cholesky factor of the p x p Syy; flag is set to 1 when a pivot is not positive
 // and finite.  p <= 90 (one workgroup, LDS): Sinv = (Sigma^Y)^{-1}, Syy untouched.
 // p > 90 (blocked, chip-wide): Syy is overwritten by L in its lower triangle and

@@ -27,6 +27,20 @@ __device__ __forceinline__ float from_bf16(bf16_t h) { return __uint_as_float(((
 __device__ __forceinline__ void store_act(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_act(bf16_t* p, float v) { *p = to_bf16(v); }
 
+// Largest |value| written by a wave, folded into *amax (the bit pattern of a
+// non-negative float orders like the float, so an integer max is exact and the
+// result does not depend on the order of the atomics).
+__device__ __forceinline__ void amax_publish(float v, unsigned* amax) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(v));
+}
+
+__global__ void k_zero_u32(unsigned* __restrict__ p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0u;
+}
+
 // x0[i][y][x] = (X^i[y][x], sum_a B[y][a] U^i[a][x]).
 __global__ void k_lift(int N, int n, int m, int l, FieldRef X, FieldRef U,
                        const float* __restrict__ B, float* __restrict__ out) {
@@ -91,6 +105,9 @@ __global__ void k_conv_direct(int N, int n, int m, int cin, int cout,
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // Stage the HR x HC halo (rows y0-1.., columns x0-1..) of member i of an NHWC
 // [N][n][m][CIN] tensor into s_in[(yy*HC + xx)*CP + c], zero outside the field.
@@ -308,7 +325,7 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
                                                     FieldRef U, const float* __restrict__ B,
                                                     const float* __restrict__ w,
                                                     const float* __restrict__ bias, int act,
-                                                    TOUT* __restrict__ out) {
+                                                    TOUT* __restrict__ out, unsigned* __restrict__ amax) {
   constexpr int TR = 4, TC = 64, HR = TR + 2, HC = TC + 2;
   constexpr int LMAX = 64;
   __shared__ float s_x[HR * HC];
@@ -392,6 +409,7 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
     s_out[tid * (COUT + 1) + o] = activate(acc, act);
   }
   __syncthreads();
+  float vmax = 0.f;
   for (int r = 0; r < TR; ++r) {
     const int y = y0 + r;
     if (y >= n) break;
@@ -399,9 +417,12 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
     TOUT* dst = out + (((size_t)i * n + y) * m + x0) * COUT;
     for (int e = tid; e < valid * COUT; e += 256) {
       const int px = e / COUT, o = e % COUT;
-      store_act(dst + e, s_out[(r * TC + px) * (COUT + 1) + o]);
+      const float v = s_out[(r * TC + px) * (COUT + 1) + o];
+      store_act(dst + e, v);
+      vmax = fmaxf(vmax, fabsf(v));
     }
   }
+  if (amax) amax_publish(vmax, amax);
 }
 
 // Last layer (one output channel) from an LDS halo tile of the NHWC input; each
@@ -573,6 +594,345 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
   }
 }
 
+// Hidden layer in FP8 (OCP e4m3) on the gfx950 matrix cores
+// (v_mfma_scale_f32_16x16x128_f8f6f4 with unit block scales, FP32 accumulation).
+// Weights arrive quantised per output channel, wq[o][k] = W[o][k] / ws[o], with K
+// ordered (tap, channel) and zero-padded to a multiple of 128.  The BF16 input
+// activations are quantised while the halo tile is staged, x / sa with sa = (largest
+// |x| of the layer over the whole ensemble) / 448, that maximum having been folded in
+// by the kernel that wrote them.  The epilogue rescales by sa * ws[o], adds the bias,
+// applies the activation, stores BF16 and folds its own maximum into amax_out.
+// Lane layout (16x16x128): A[i][k] for k = 32g..32g+31 from lane i + 16g (bytes in
+// k order), B[k][j] likewise from lane j + 16g, element r of lane j + 16g holds
+// D[4g + r][j].  CIN is a multiple of 32, so the 32 K-indices of a lane are 32
+// consecutive channels of one tap.
+template <int CIN, int COUT, int TR>
+__global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
+                                                       const bf16_t* __restrict__ in,
+                                                       const unsigned* __restrict__ amax_in,
+                                                       const uint8_t* __restrict__ wq,
+                                                       const float* __restrict__ ws,
+                                                       const float* __restrict__ bias, int act,
+                                                       bf16_t* __restrict__ out,
+                                                       unsigned* __restrict__ amax_out) {
+  static_assert(CIN % 32 == 0, "32 channels per lane fragment");
+  constexpr int TC = 64;
+  constexpr int HR = TR + 2, HC = TC + 2;
+  constexpr int CP = CIN + 16;                      // bytes per halo pixel in LDS
+  constexpr int KD = 9 * CIN;
+  constexpr int KD128 = (KD + 127) / 128 * 128;      // zero weights past KD
+  constexpr int KDP = KD128 + 16;
+  constexpr int NB = COUT / 16;
+  constexpr int RPW = TR / 4;
+  __shared__ __attribute__((aligned(16))) uint8_t s_in[HR * HC * CP];
+  __shared__ __attribute__((aligned(16))) uint8_t s_w[COUT * KDP];
+  const int col_tiles = (m + TC - 1) / TC;
+  const int row_tiles = (n + TR - 1) / TR;
+  int bid = blockIdx.x;
+  const int ct = bid % col_tiles;
+  bid /= col_tiles;
+  const int rt = bid % row_tiles;
+  const int i = bid / row_tiles;
+  const int y0 = rt * TR, x0 = ct * TC;
+  const int tid = threadIdx.x;
+  const float amx = __uint_as_float(*amax_in);
+  const float sa = amx > 0.f ? amx * (1.0f / 448.0f) : 1.0f;
+  const float inv_sa = 1.0f / sa;
+  {
+    constexpr int WQ = KD128 / 16;  // 16-byte vectors per weight row
+    constexpr int WV = COUT * WQ;
+    constexpr int WS = (WV + 255) / 256;
+    constexpr int IQ = CIN / 8;
+    constexpr int IV = HR * HC * IQ;
+    constexpr int IS = (IV + 255) / 256;
+    u32x4 wv[WS];
+    u16x8 iv[IS];
+#pragma unroll
+    for (int u = 0; u < WS; ++u) {
+      const int e = tid + 256 * u;
+      wv[u] = e < WV ? *(const u32x4*)(wq + (size_t)16 * e) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < IS; ++u) {
+      const int e = tid + 256 * u;
+      iv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (e < IV) {
+        const int q = e % IQ, pix = e / IQ;
+        const int xx = pix % HC, yy = pix / HC;
+        const int gy = y0 + yy - 1, gx = x0 + xx - 1;
+        if (gy >= 0 && gy < n && gx >= 0 && gx < m)
+          iv[u] = *(const u16x8*)(in + (((size_t)i * n + gy) * m + gx) * CIN + 8 * q);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < WS; ++u) {
+      const int e = tid + 256 * u;
+      if (e < WV) *(u32x4*)(s_w + (e / WQ) * KDP + 16 * (e % WQ)) = wv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < IS; ++u) {
+      const int e = tid + 256 * u;
+      if (e < IV) {
+        uint32_t lo = 0u, hi = 0u;
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(from_bf16(iv[u][0]) * inv_sa, from_bf16(iv[u][1]) * inv_sa, lo, false);
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(from_bf16(iv[u][2]) * inv_sa, from_bf16(iv[u][3]) * inv_sa, lo, true);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(from_bf16(iv[u][4]) * inv_sa, from_bf16(iv[u][5]) * inv_sa, hi, false);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(from_bf16(iv[u][6]) * inv_sa, from_bf16(iv[u][7]) * inv_sa, hi, true);
+        *(u32x2*)(s_in + (e / IQ) * CP + 8 * (e % IQ)) = u32x2{lo, hi};
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f32x4 acc[RPW][4][NB];
+#pragma unroll
+  for (int rw = 0; rw < RPW; ++rw)
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int kb = 0; kb < KD128 / 128; ++kb) {
+    const int k0 = kb * 128 + 32 * lk;
+    // past KD the weights are zero; read any in-tile (finite) activations there
+    const int kk = k0 < KD ? k0 : 0;
+    const int tap = kk / CIN, c0 = kk - tap * CIN;
+    const int dy = tap / 3, dx = tap - dy * 3;
+    i32x8 b[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const uint8_t* src = s_w + (nb * 16 + li) * KDP + k0;
+      const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
+      b[nb] = i32x8{(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3], (int)v1[0], (int)v1[1], (int)v1[2],
+                    (int)v1[3]};
+    }
+#pragma unroll
+    for (int rw = 0; rw < RPW; ++rw) {
+      const int ry = w + 4 * rw;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const uint8_t* src = s_in + ((ry + dy) * HC + mb * 16 + li + dx) * CP + c0;
+        const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
+        const i32x8 a = {(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3],
+                         (int)v1[0], (int)v1[1], (int)v1[2], (int)v1[3]};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[rw][mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b[nb], acc[rw][mb][nb], 0, 0,
+                                                                             0, 127, 0, 127);
+      }
+    }
+  }
+  float vmax = 0.f;
+#pragma unroll
+  for (int rw = 0; rw < RPW; ++rw) {
+    const int y = y0 + w + 4 * rw;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int o = nb * 16 + li;
+        const float sc = sa * ws[o];
+        const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int x = x0 + mb * 16 + 4 * lk + r;
+          if (y < n && x < m) {
+            const float v = activate(fmaf(acc[rw][mb][nb][r], sc, bo), act);
+            out[(((size_t)i * n + y) * m + x) * COUT + o] = to_bf16(v);
+            vmax = fmaxf(vmax, fabsf(v));
+          }
+        }
+      }
+  }
+  amax_publish(vmax, amax_out);
+}
+
+// The whole 2 -> C -> C -> 1 network in one kernel (FP32), so that neither hidden
+// activation touches HBM.  A block owns TR x 64 output pixels of one member and
+// stages the (TR+6) x 70 input region (X, and B U formed in LDS from the staged U rows
+// and B rows); layer 1 (VALU) fills the (TR+4) x 68 region around the tile, layer 2
+// (v_mfma_f32_16x16x4_f32, implicit GEMM over the flattened (TR+2) x 66 region, 16
+// pixels per M-block) the (TR+2) x 66 region, and layer 3 (VALU) the tile itself,
+// written straight to the strided output field.  Cells of the intermediate regions
+// that fall outside the field are zero: they are the next layer's zero padding.
+// Weights: w1 [C][2][3][3], w2k [tap*C + c][o], w3 [1][C][3][3].
+template <int C>
+__global__ __launch_bounds__(512) void k_rollout3_f32(int N, int n, int m, int l, FieldRef X, FieldRef U,
+                                                      const float* __restrict__ B,
+                                                      const float* __restrict__ w1,
+                                                      const float* __restrict__ b1,
+                                                      const float* __restrict__ w2k,
+                                                      const float* __restrict__ b2,
+                                                      const float* __restrict__ w3,
+                                                      const float* __restrict__ b3, int act, FieldOut fo) {
+  static_assert(C == 16, "one 16-wide N-block in layer 2");
+  constexpr int NT = 512, TR = 8, TC = 64, LMX = 16;
+  constexpr int R0 = TR + 6, C0 = TC + 6;  // input region, origin (y0-3, x0-3)
+  constexpr int R1 = TR + 4, C1 = TC + 4;  // layer-1 region, origin (y0-2, x0-2)
+  constexpr int R2 = TR + 2, C2 = TC + 2;  // layer-2 region, origin (y0-1, x0-1)
+  constexpr int CP = C + 1;
+  constexpr int NQ2 = R2 * C2;             // layer-2 pixels
+  constexpr int MB2 = (NQ2 + 15) / 16;     // their 16-pixel M-blocks
+  __shared__ float s_x[R0 * C0];
+  __shared__ float s_bu[R0 * C0];
+  __shared__ float s_u[LMX * C0];
+  __shared__ float s_b[R0 * LMX];
+  __shared__ float s_w1[C * 19];           // 18 taps + bias per output channel
+  __shared__ __attribute__((aligned(16))) float s_w2[9 * C * C];
+  __shared__ float s_w3[9 * C + 1];
+  __shared__ __attribute__((aligned(16))) float s_l1[R1 * C1 * CP];
+  __shared__ __attribute__((aligned(16))) float s_l2[NQ2 * CP];
+  const int col_tiles = (m + TC - 1) / TC;
+  const int row_tiles = (n + TR - 1) / TR;
+  int bid = blockIdx.x;
+  const int ct = bid % col_tiles;
+  bid /= col_tiles;
+  const int rt = bid % row_tiles;
+  const int i = bid / row_tiles;
+  const int y0 = rt * TR, x0 = ct * TC;
+  const int tid = threadIdx.x;
+  {
+    constexpr int XS = (R0 * C0 + NT - 1) / NT;
+    constexpr int US = (LMX * C0 + NT - 1) / NT;
+    constexpr int W2S = (9 * C * C / 4 + NT - 1) / NT;
+    float xv[XS], uv[US], bv;
+    f32x4 wv[W2S];
+#pragma unroll
+    for (int u = 0; u < XS; ++u) {
+      const int e = tid + NT * u;
+      const int yy = e / C0, xx = e % C0;
+      const int gy = y0 + yy - 3, gx = x0 + xx - 3;
+      xv[u] = (e < R0 * C0 && gy >= 0 && gy < n && gx >= 0 && gx < m) ? X.base[i * X.si + gy * X.sy + gx]
+                                                                       : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < US; ++u) {
+      const int e = tid + NT * u;
+      const int a = e / C0, xx = e % C0;
+      const int gx = x0 + xx - 3;
+      uv[u] = (a < l && gx >= 0 && gx < m) ? U.base[i * U.si + a * U.sy + gx] : 0.f;
+    }
+    {
+      const int yy = tid / LMX, a = tid % LMX;
+      const int gy = y0 + yy - 3;
+      bv = (yy < R0 && a < l && gy >= 0 && gy < n) ? B[(size_t)gy * l + a] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < W2S; ++u) {
+      const int e = tid + NT * u;
+      wv[u] = e < 9 * C * C / 4 ? *(const f32x4*)(w2k + 4 * e) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int e = tid; e < C * 18; e += NT) s_w1[(e / 18) * 19 + e % 18] = w1[e];
+    if (tid < C) s_w1[tid * 19 + 18] = b1 ? b1[tid] : 0.f;
+    for (int e = tid; e < 9 * C; e += NT) s_w3[e] = w3[e];
+    if (tid == 0) s_w3[9 * C] = b3 ? b3[0] : 0.f;
+#pragma unroll
+    for (int u = 0; u < XS; ++u)
+      if (tid + NT * u < R0 * C0) s_x[tid + NT * u] = xv[u];
+#pragma unroll
+    for (int u = 0; u < US; ++u)
+      if (tid + NT * u < LMX * C0) s_u[tid + NT * u] = uv[u];
+    if (tid < R0 * LMX) s_b[tid] = bv;
+#pragma unroll
+    for (int u = 0; u < W2S; ++u)
+      if (tid + NT * u < 9 * C * C / 4) *(f32x4*)(s_w2 + 4 * (tid + NT * u)) = wv[u];
+  }
+  __syncthreads();
+  // lift: the B U channel over the input region (zero outside the field, as U is)
+  for (int e = tid; e < R0 * C0; e += NT) {
+    const int yy = e / C0, xx = e % C0;
+    float bu = 0.f;
+    for (int a = 0; a < l; ++a) bu = fmaf(s_b[yy * LMX + a], s_u[a * C0 + xx], bu);
+    s_bu[e] = bu;
+  }
+  __syncthreads();
+  // layer 1: every cell of the (TR+4) x 68 region, all C channels
+  for (int e = tid; e < R1 * C1; e += NT) {
+    const int r1 = e / C1, c1 = e % C1;
+    const int gy = y0 - 2 + r1, gx = x0 - 2 + c1;
+    float* dst = s_l1 + e * CP;
+    if (gy < 0 || gy >= n || gx < 0 || gx >= m) {
+#pragma unroll
+      for (int o = 0; o < C; ++o) dst[o] = 0.f;
+      continue;
+    }
+    float inx[18];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        inx[dy * 3 + dx] = s_x[(r1 + dy) * C0 + c1 + dx];
+        inx[9 + dy * 3 + dx] = s_bu[(r1 + dy) * C0 + c1 + dx];
+      }
+#pragma unroll 4
+    for (int o = 0; o < C; ++o) {
+      float acc = s_w1[o * 19 + 18];
+#pragma unroll
+      for (int q = 0; q < 18; ++q) acc = fmaf(s_w1[o * 19 + q], inx[q], acc);
+      dst[o] = activate(acc, act);
+    }
+  }
+  __syncthreads();
+  // layer 2 on the matrix cores: wave w takes M-blocks w, w + 8, ... together
+  {
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    constexpr int NW = NT / 64;
+    constexpr int MPW = (MB2 + NW - 1) / NW;
+    f32x4 acc[MPW];
+    int base[MPW];  // LDS offset of this lane's A pixel (tap (0,0)) in each M-block
+#pragma unroll
+    for (int j = 0; j < MPW; ++j) {
+      acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      int q = (w + NW * j) * 16 + li;
+      q = q < NQ2 ? q : NQ2 - 1;  // padding lanes of the last M-block read a valid pixel
+      base[j] = ((q / C2) * C1 + q % C2) * CP;
+    }
+#pragma unroll 4
+    for (int kb = 0; kb < 9 * C / 4; ++kb) {
+      const int k = kb * 4 + lk;
+      const int tap = k / C, c = k - tap * C;
+      const int off = ((tap / 3) * C1 + tap % 3) * CP + c;
+      const float b = s_w2[k * C + li];
+#pragma unroll
+      for (int j = 0; j < MPW; ++j)
+        if (w + NW * j < MB2)
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_l1[base[j] + off], b, acc[j], 0, 0, 0);
+    }
+    const float bo = b2 ? b2[li] : 0.f;
+#pragma unroll
+    for (int j = 0; j < MPW; ++j) {
+      if (w + NW * j >= MB2) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = (w + NW * j) * 16 + 4 * lk + r;
+        if (q < NQ2) {
+          const int gy = y0 - 1 + q / C2, gx = x0 - 1 + q % C2;
+          const bool in = gy >= 0 && gy < n && gx >= 0 && gx < m;
+          s_l2[q * CP + li] = in ? activate(acc[j][r] + bo, act) : 0.f;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // layer 3: one output pixel per thread, no activation after the last layer
+  {
+    const int r3 = tid / TC, c3 = tid % TC;
+    const int gy = y0 + r3, gx = x0 + c3;
+    if (gy < n && gx < m) {
+      float acc = s_w3[9 * C];
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const float* src = s_l2 + ((r3 + tap / 3) * C2 + c3 + tap % 3) * CP;
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc = fmaf(s_w3[c * 9 + tap], src[c], acc);
+      }
+      fo.base[i * fo.si + gy * fo.sy + gx] = acc;
+    }
+  }
+}
+
 }  // namespace
 
 bool conv_first_supported(int cout, int l) {
@@ -582,16 +942,16 @@ bool conv_last_supported(int cin) { return cin == 8 || cin == 16 || cin == 32 ||
 
 void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
                        const float* B, int cout, const float* w, const float* bias, int act,
-                       void* out_nhwc, bool bf16) {
+                       void* out_nhwc, bool bf16, unsigned* amax) {
   const unsigned blocks = (unsigned)((long long)N * ((n + 3) / 4) * ((m + 63) / 64));
 #define OIC_FIRST_CASE(CO)                                                                        \
   if (cout == CO) {                                                                               \
     if (bf16)                                                                                     \
       OIC_LAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, bf16_t>), dim3(blocks), dim3(256), 0, N, n, \
-                 m, l, X, U, B, w, bias, act, (bf16_t*)out_nhwc);                                 \
+                 m, l, X, U, B, w, bias, act, (bf16_t*)out_nhwc, amax);                           \
     else                                                                                          \
       OIC_LAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, float>), dim3(blocks), dim3(256), 0, N, n,  \
-                 m, l, X, U, B, w, bias, act, (float*)out_nhwc);                                  \
+                 m, l, X, U, B, w, bias, act, (float*)out_nhwc, amax);                            \
     return;                                                                                       \
   }
   OIC_FIRST_CASE(8)
@@ -646,6 +1006,46 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
   OIC_BF_CASE(32, 64)
   OIC_BF_CASE(64, 32)
 #undef OIC_BF_CASE
+}
+
+bool rollout3_supported(int n_layers, const int* ch, int l) {
+  return n_layers == 3 && ch[1] == 16 && ch[2] == 16 && l <= 16;
+}
+
+void launch_rollout3(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
+                     const float* B, const float* w1, const float* b1, const float* w2k, const float* b2,
+                     const float* w3, const float* b3, int act, FieldOut fo) {
+  const unsigned blocks = (unsigned)((long long)N * ((n + 7) / 8) * ((m + 63) / 64));
+  OIC_LAUNCH(t, KC_CONV_MID, s, k_rollout3_f32<16>, dim3(blocks), dim3(512), 0, N, n, m, l, X, U, B, w1,
+             b1, w2k, b2, w3, b3, act, fo);
+}
+
+bool conv_mfma_fp8_supported(int cin, int cout) {
+  return (cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64);
+}
+
+void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
+                          const void* in_nhwc, const unsigned* amax_in, const uint8_t* wq, const float* ws,
+                          const float* bias, int act, void* out_nhwc, unsigned* amax_out) {
+#define OIC_F8_CASE(CI, CO)                                                                        \
+  if (cin == CI && cout == CO) {                                                                   \
+    constexpr int TRV = 8;                                                                         \
+    const unsigned blocks = (unsigned)((long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64));     \
+    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_fp8<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, m,    \
+               (const bf16_t*)in_nhwc, amax_in, wq, ws, bias, act, (bf16_t*)out_nhwc, amax_out);     \
+    return;                                                                                        \
+  }
+  OIC_F8_CASE(32, 16)
+  OIC_F8_CASE(32, 32)
+  OIC_F8_CASE(32, 64)
+  OIC_F8_CASE(64, 16)
+  OIC_F8_CASE(64, 32)
+  OIC_F8_CASE(64, 64)
+#undef OIC_F8_CASE
+}
+
+void launch_zero_u32(hipStream_t s, Timer& t, unsigned* p, int count) {
+  OIC_LAUNCH(t, KC_ASSEMBLE, s, k_zero_u32, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, p, count);
 }
 
 bool conv_mfma_supported(int cin, int cout) {

@@ -300,7 +300,7 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
 }
 
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
-                  const float* Y, const double* muY, double* part, int max_splits, double* S) {
+                  const float* Y, const double* muY, double* part, size_t part_cap, double* S) {
   const int p = d.p();
   const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
@@ -309,11 +309,15 @@ void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   const int ytiles = (nbk + 7) / 8;
   const int NB = (nbk + ytiles - 1) / ytiles;
   const int tiles = ((Mtot + MA - 1) / MA) * ytiles;
-  // ~3 workgroups per CU in total, each chunk at least 4 stages of 64 columns.
-  int splits = (768 + tiles - 1) / tiles;
-  const int max_by_len = (NM + 255) / 256;
+  // Split K so that about two workgroups per CU (their LDS allows two) are in flight
+  // even for the few output tiles of the early horizon steps: a workgroup's time is set
+  // by its chunk of K, not by the size of the output.  Chunks are whole 64-column
+  // stages; the partials must fit the split buffer.
+  int splits = (512 + tiles - 1) / tiles;
+  const int max_by_len = (NM + MK - 1) / MK;
   if (splits > max_by_len) splits = max_by_len;
-  if (splits > max_splits) splits = max_splits;
+  const size_t by_cap = part_cap / ((size_t)Mtot * p);
+  if ((size_t)splits > by_cap) splits = (int)by_cap;
   if (splits < 1) splits = 1;
   int chunk = (NM + splits - 1) / splits;
   chunk = (chunk + MK - 1) / MK * MK;

@@ -25,6 +25,7 @@ OIC_ACT_TANH = 0
 OIC_ACT_GELU = 1
 OIC_PREC_FP32 = 0
 OIC_PREC_BF16 = 1
+OIC_PREC_FP8 = 2
 OIC_MEM_HOST = 0
 OIC_MEM_DEVICE = 1
 OIC_MAX_LAYERS = 8

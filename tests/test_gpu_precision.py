@@ -97,3 +97,91 @@ def test_bf16_closed_loop_tracking_cost_within_2pct(preset, steps):
     print(f"{preset} closed-loop cost fp32 {j32:.6e} bf16 {j16:.6e} rel {abs(j16 - j32) / j32:.2e}",
           flush=True)
     assert abs(j16 - j32) / j32 < 0.02
+
+
+# ---- FP8 (OCP e4m3) hidden layers: per-output-channel weight scales, per-layer
+# activation scales from the ensemble's largest magnitude, BF16 storage between layers.
+
+TOL_FP8_ROLLOUT = 6e-2  # one rollout, before any analysis: e4m3 keeps 3 mantissa bits
+
+
+def fp8_preset(n=40, l=10, channels=(2, 32, 32, 32, 1), N=64, H=5):
+    return dataclasses.replace(wl.PRESETS["C3"], name="f8", n=n, m=n, l=l, channels=list(channels),
+                               N=N, H=H, grf_length=4.0, ref_sigma=4.0, ref_center=(n / 2, n / 4),
+                               precision=wl.PREC_FP8)
+
+
+@pytest.mark.parametrize("channels", [(2, 32, 32, 32, 1), (2, 64, 64, 64, 1), (2, 32, 64, 16, 1)])
+def test_fp8_rollout_vs_oracle(channels):
+    p = fp8_preset(channels=channels)
+    prob = wl.make_problem(p)
+    rng = np.random.default_rng(0)
+    b = 8
+    X = rng.standard_normal((b, p.n, p.m)).astype(np.float32)
+    U = (0.3 * rng.standard_normal((b, p.l, p.m))).astype(np.float32)
+    with oic.controller_for(prob, max_N=b, precision=oic.OIC_PREC_FP8) as c:
+        got = c.cnn_forward(X, U)
+        plant = c.plant_step(X[0], U[0])
+    with oic.controller_for(prob, max_N=b, precision=oic.OIC_PREC_BF16) as c:
+        got16 = c.cnn_forward(X, U)
+    ref = ocnn.cnn_forward(X, U, prob.B, prob.weights, p.activation)
+    e, e16 = relerr(got, ref), relerr(got16, ref)
+    print(f"{channels} fp8 rollout relerr {e:.2e} (bf16 {e16:.2e})", flush=True)
+    assert e < TOL_FP8_ROLLOUT
+    assert e > 2 * e16  # it really ran in FP8
+    assert relerr(plant, ref[0]) < 1e-5  # the plant stays FP32
+
+
+def test_fp8_solve_vs_oracle():
+    p = fp8_preset()
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=23)
+    with oic.controller_for(prob, precision=oic.OIC_PREC_FP8) as c:
+        U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
+    ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N,
+                     p.H, z.Z_init, z.Z_W, z.Z_VX, z.Z_VU)
+    eu, ex = relerr(U, ref.U_mean), relerr(X, ref.X_mean)
+    print(f"fp8 solve: relerr U {eu:.2e} X {ex:.2e}", flush=True)
+    assert eu < TOL_BF16
+    assert ex < TOL_BF16
+
+
+def test_fp8_closed_loop_tracking_cost_within_2pct():
+    prob = wl.make_problem(fp8_preset())
+    j32 = closed_loop(prob, oic.OIC_PREC_FP32, 10)
+    j8 = closed_loop(prob, oic.OIC_PREC_FP8, 10)
+    print(f"fp8 closed-loop cost fp32 {j32:.6e} fp8 {j8:.6e} rel {abs(j8 - j32) / j32:.2e}", flush=True)
+    assert abs(j8 - j32) / j32 < 0.02
+
+
+@pytest.mark.slow
+def test_full_size_256_precisions_tracking_cost():
+    """256x256 field, 5-layer 64-channel GELU CNN, N = 512, H = 20: FP8 and BF16 against
+    the FP32 GPU path on the closed-loop tracking cost (3 steps) and on the first
+    solve's smoothed control mean (the FP64 oracle takes minutes per solve here)."""
+    p = dataclasses.replace(wl.PRESETS["C4"], closed_loop_steps=3)
+    prob = wl.make_problem(p)
+    costs, first = {}, {}
+    for prec in (oic.OIC_PREC_FP32, oic.OIC_PREC_BF16, oic.OIC_PREC_FP8):
+        X = prob.X0.copy()
+        Xs, Us = [X], []
+        with oic.controller_for(prob, precision=prec) as c:
+            for k in range(3):
+                U, _ = c.solve(X, wl.reference_window(p, k), prob.Q, prob.R, p.N, p.H, 7000 + k)
+                if k == 0:
+                    first[prec] = U
+                X = c.plant_step(X, U[0])
+                Xs.append(X)
+                Us.append(U[0])
+        Xrefs = np.stack([wl.reference_at(p, k) for k in range(4)])
+        costs[prec] = ocost.closed_loop_cost(np.stack(Xs), np.stack(Us), np.zeros((p.l, p.m)), Xrefs,
+                                             prob.R.astype(np.float64), prob.Q.astype(np.float64))
+    j32 = costs[oic.OIC_PREC_FP32]
+    for prec, name in ((oic.OIC_PREC_BF16, "bf16"), (oic.OIC_PREC_FP8, "fp8")):
+        eu = relerr(first[prec], first[oic.OIC_PREC_FP32])
+        rel = abs(costs[prec] - j32) / j32
+        print(f"256x256 {name}: U relerr vs fp32 {eu:.2e}, cost {costs[prec]:.6e} vs {j32:.6e} "
+              f"rel {rel:.2e}", flush=True)
+        assert eu < TOL_BF16
+        assert rel < 0.02
