@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"hbm": 8.0e12, "fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15}
+PEAK = {"hbm": 8.0e12, "fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15, "fp8": 5.0e15}
 
 
 def workload_name(p):
@@ -35,12 +35,16 @@ def workload_name(p):
             f"closed-loop MPC steps")
 
 
-def algorithmic_work(p, H):
+def algorithmic_work(p, H, precision="fp32", fused=False):
     """Per kernel class: (FLOP, HBM bytes) the method needs in one solve, summed over
-    the launches of that class.  FLOP counts multiply-adds as 2."""
+    the launches of that class.  FLOPs count multiply-adds as 2; bytes are the operands
+    each launch must read and write once (activations 2 B in BF16/FP8, 4 B in FP32).
+    fused: the whole network runs as one kernel (class "rollout"): only its input
+    fields and its output field move."""
     n, m, l, N = p.n, p.m, p.l, p.N
     rr = pp = n + l
     NM = N * m
+    ab = 4 if precision == "fp32" else 2
     work = {}
 
     def add(k, f, b):
@@ -50,9 +54,15 @@ def algorithmic_work(p, H):
     L = len(p.channels) - 1
     for t in range(1, H + 1):
         Ma = (t + 1) * rr
-        for k, (ci, co) in enumerate(zip(p.channels[:-1], p.channels[1:])):
-            cls = "conv_first" if k == 0 else ("conv_last" if k == L - 1 else "conv_mid")
-            add(cls, 2.0 * 9 * ci * co * n * m * N, 4.0 * n * m * N * (ci + co))
+        if fused:
+            f = sum(2.0 * 9 * ci * co * n * m * N for ci, co in zip(p.channels[:-1], p.channels[1:]))
+            add("rollout", f, 4.0 * N * m * (n + l) + 4.0 * N * n * m)
+        else:
+            for k, (ci, co) in enumerate(zip(p.channels[:-1], p.channels[1:])):
+                cls = "conv_first" if k == 0 else ("conv_last" if k == L - 1 else "conv_mid")
+                rd = 4.0 * (n + l) * m * N if k == 0 else ab * ci * n * m * N
+                wr = 4.0 * n * m * N if k == L - 1 else ab * co * n * m * N
+                add(cls, 2.0 * 9 * ci * co * n * m * N, rd + wr)
         add("stats", 2.0 * (Ma + pp) * pp * NM, 4.0 * (Ma + pp) * NM)
         add("update", 2.0 * Ma * pp * NM, 4.0 * (2 * Ma + pp) * NM)
         add("means", float(pp) * NM, 4.0 * pp * NM)
@@ -62,22 +72,59 @@ def algorithmic_work(p, H):
     return work
 
 
+MATRIX_CLASSES = ("conv_mid", "rollout", "stats", "gain", "update")
+SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last": "rollout.hip",
+             "rollout": "rollout.hip", "stats": "stats.hip", "stats_reduce": "stats.hip",
+             "means": "stats.hip", "chol": "gain.hip", "gain": "gain.hip", "update": "update.hip",
+             "noise": "noise.hip", "assemble": "noise.hip", "observe": "noise.hip", "init": "noise.hip"}
+
+
 def roofline_for(cls, flops, nbytes, ms, launches, precision):
     sec = ms * 1e-3
-    fpeak = PEAK["fp64"] if cls in ("stats", "gain", "chol") else (
-        PEAK["bf16"] if (precision == "bf16" and cls.startswith("conv")) else PEAK["fp32"])
+    if cls in ("stats", "gain", "chol"):
+        fpeak = PEAK["fp64"]
+    elif cls.startswith("conv") or cls == "rollout":
+        fpeak = {"bf16": PEAK["bf16"], "fp8": PEAK["fp8"]}.get(precision, PEAK["fp32"])
+    else:
+        fpeak = PEAK["fp32"]
     t_f = flops / fpeak
     t_b = nbytes / PEAK["hbm"]
+    common = {"traffic": measured_traffic(cls, launches), "kernel_class": cls, "launches": launches,
+              "avg_launch_us": 1e3 * ms / max(launches, 1),
+              "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
+              "algorithmic_flop_per_launch": flops / max(launches, 1)}
     if t_b > t_f:
         ach = nbytes / sec / 1e9
-        return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
-                "frac": ach / (PEAK["hbm"] / 1e9), "traffic": None, "kernel_class": cls,
-                "launches": launches, "avg_launch_us": 1e3 * ms / max(launches, 1)}
+        return dict({"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                     "frac": ach / (PEAK["hbm"] / 1e9)}, **common)
     ach = flops / sec / 1e12
-    kind = "mfma" if cls in ("conv_mid", "stats", "gain", "update") else "alu"
-    return {"bound": kind, "achieved": ach, "peak": fpeak / 1e12, "unit": "TFLOP/s",
-            "frac": ach / (fpeak / 1e12), "traffic": None, "kernel_class": cls,
-            "launches": launches, "avg_launch_us": 1e3 * ms / max(launches, 1)}
+    kind = "mfma" if cls in MATRIX_CLASSES else "alu"
+    return dict({"bound": kind, "achieved": ach, "peak": fpeak / 1e12, "unit": "TFLOP/s",
+                 "frac": ach / (fpeak / 1e12)}, **common)
+
+
+def measured_traffic(cls, launches):
+    """HBM bytes per launch of the class from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (each scaled by what the counter reads for a plain device copy of
+    known size), or None when there are none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(cls)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2410_09663_amd", "csrc", SOURCE_OF.get(cls, ""))
+    try:
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if sha != rec.get("source_sha256"):
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(p, prob, seconds_budget=25.0):
@@ -113,15 +160,105 @@ def cpu_baseline(p, prob, seconds_budget=25.0):
                       f"{el:.1f} s wall"}, first
 
 
+def serve_main(args):
+    """Serving workload: many independent controllers (grids 32^2..256^2, N 64..256, H 5..20,
+    BF16 rollout) behind one request loop with continuous admission by HBM footprint.
+    Three runs over the same request list: (1) every request submitted at once (capacity,
+    solves/s); (2) Poisson arrivals at the offered rate (default 400 solves/s, above
+    capacity: latency is queue-dominated); (3) Poisson arrivals at 70% of the measured
+    capacity.  Then the same requests in the plain FP32 single-request form (one solve at
+    a time, FP32 rollout), whose solves/s gives the speed-up."""
+    from paper_2410_09663_amd import oic
+    from paper_2410_09663_amd import workloads as wl
+
+    mix = wl.serving_mix(args.controllers)
+    probs = [wl.make_problem(p) for p in mix]
+    rng = np.random.default_rng(99)
+    ctrl_of = rng.integers(0, len(probs), args.requests)
+    step_of = np.zeros(args.requests, np.int64)
+    seen = {}
+    for r, c in enumerate(ctrl_of):
+        step_of[r] = seen.get(int(c), 0) + 1  # step 0 is the warm-up request
+        seen[int(c)] = step_of[r]
+    budget = int(args.hbm_gb * (1 << 30))
+
+    def inputs(c, k):
+        p = probs[c].preset
+        return (probs[c].X0 * (1.0 + 0.02 * k)).astype(np.float32), wl.reference_window(p, k), \
+            p.noise_seed_base + k
+
+    def run(srv, ids, rate, seed):
+        arr = np.zeros(args.requests)
+        if rate:
+            arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, args.requests))
+        t0 = time.perf_counter()
+        sub = []
+        for r in range(args.requests):
+            while time.perf_counter() - t0 < arr[r]:
+                time.sleep(min(1e-3, max(0.0, arr[r] - (time.perf_counter() - t0))))
+            c = int(ctrl_of[r])
+            X0, ref, sd = inputs(c, int(step_of[r]))
+            sub.append((c, time.perf_counter() - t0, srv.submit(ids[c], X0, ref, sd)))
+        lat, svc, done = [], [], []
+        for c, ts, t in sub:
+            _, _, ms, q = srv.wait(ids[c], t)
+            lat.append(ms)
+            svc.append(ms - q)
+            done.append(ts + 1e-3 * ms)
+        span = max(done)
+        return {"solves_per_s": args.requests / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "service_p50_ms": float(np.percentile(svc, 50)),
+                "service_p99_ms": float(np.percentile(svc, 99)), "makespan_s": span}
+
+    def warm(srv, ids):
+        for c in range(len(probs)):
+            X0, ref, sd = inputs(c, 0)
+            srv.wait(ids[c], srv.submit(ids[c], X0, ref, sd))
+
+    out = {"metric": "solves/s (served mix)", "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": f"serving: {args.controllers} controllers, grids "
+                                  f"{list(wl.SERVE_GRIDS)}, N {list(wl.SERVE_N)}, H {list(wl.SERVE_H)}, "
+                                  f"BF16 rollout, FP64 gain; {args.requests} requests",
+                      "hbm_budget_gb": args.hbm_gb, "max_inflight": args.inflight}}
+    with oic.Server(budget, max_inflight=args.inflight) as srv:
+        ids = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in probs]
+        warm(srv, ids)
+        cap = run(srv, ids, None, 0)
+        offered = run(srv, ids, args.rate, 1)
+        sustain_rate = 0.7 * cap["solves_per_s"]
+        sustained = run(srv, ids, sustain_rate, 2)
+        st = srv.stats()
+    out.update({"value": cap["solves_per_s"], "capacity": cap,
+                "offered": dict(offered, rate=args.rate),
+                "sustainable": dict(sustained, rate=sustain_rate), "server": st})
+    if not args.no_fp32_baseline:
+        with oic.Server(budget, max_inflight=1) as srv:
+            ids = [srv.add(pr, pr.preset.N, pr.preset.H, precision=wl.PREC_FP32) for pr in probs]
+            warm(srv, ids)
+            single = run(srv, ids, None, 0)
+        out["fp32_single_request"] = single
+        out["speedup_solves_per_s"] = cap["solves_per_s"] / single["solves_per_s"]
+        out["p99_ms_fp32_single_service"] = single["service_p99_ms"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)  # at least 1 (the cost needs U_{k-1})
     ap.add_argument("--workload", default="C2")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
+    # serving workload (--workload C5)
+    ap.add_argument("--controllers", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--rate", type=float, default=400.0)
+    ap.add_argument("--hbm-gb", type=float, default=200.0)
+    ap.add_argument("--inflight", type=int, default=8)
+    ap.add_argument("--no-fp32-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -133,9 +270,12 @@ def main():
     from paper_2410_09663_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "C5":
+        serve_main(args)
+        return
     dev = torch.device("cuda:0")
     p = wl.PRESETS[args.workload]
-    prec = oic.OIC_PREC_BF16 if args.precision == "bf16" else oic.OIC_PREC_FP32
+    prec = {"fp32": oic.OIC_PREC_FP32, "bf16": oic.OIC_PREC_BF16, "fp8": oic.OIC_PREC_FP8}[args.precision]
     prob = wl.make_problem(p)
     K, W = args.steps, max(1, args.warmup)
     refs = torch.from_numpy(np.stack([wl.reference_window(p, k) for k in range(W + 2 * K + 1)])).to(dev)
@@ -186,7 +326,7 @@ def main():
     stats = ctrl.kernel_stats()
     ctrl.timing(False)
 
-    work = algorithmic_work(p, p.H)
+    work = algorithmic_work(p, p.H, args.precision, fused="rollout" in stats and stats["rollout"][0] > 0)
     per_class = {}
     for cls, (cnt, ms) in stats.items():
         if cnt == 0:
@@ -205,7 +345,7 @@ def main():
         "metric": "member-steps/s", "value": p.N * p.H * solves_per_s, "unit": "member-steps/s",
         "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * el / K,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec == oic.OIC_PREC_FP32 else "bf16", "data": "synthetic",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8-e4m3"}[args.precision], "data": "synthetic",
         "config": {"workload": workload_name(p), "n": p.n, "m": p.m, "l": p.l, "N": p.N, "H": p.H,
                    "channels": p.channels, "precision": args.precision},
         "solves_per_s": solves_per_s, "p50_ms": float(np.percentile(lat_ms, 50)),

@@ -29,7 +29,7 @@ namespace oic {
 
 const char* const kKernelClassNames[KC_COUNT] = {
     "noise", "init", "lift", "conv_first", "conv_mid", "conv_last", "assemble", "observe",
-    "means", "stats", "stats_reduce", "chol", "gain", "update", "extract"};
+    "means", "stats", "stats_reduce", "chol", "gain", "update", "extract", "rollout"};
 
 void Timer::reset() {
   cursor = 0;

@@ -38,6 +38,7 @@ enum KernelClass {
   KC_GAIN,
   KC_UPDATE,
   KC_EXTRACT,
+  KC_ROLLOUT,  // a whole network in one kernel
   KC_COUNT
 };
 

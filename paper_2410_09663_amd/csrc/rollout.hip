@@ -1016,7 +1016,7 @@ void launch_rollout3(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldR
                      const float* B, const float* w1, const float* b1, const float* w2k, const float* b2,
                      const float* w3, const float* b3, int act, FieldOut fo) {
   const unsigned blocks = (unsigned)((long long)N * ((n + 7) / 8) * ((m + 63) / 64));
-  OIC_LAUNCH(t, KC_CONV_MID, s, k_rollout3_f32<16>, dim3(blocks), dim3(512), 0, N, n, m, l, X, U, B, w1,
+  OIC_LAUNCH(t, KC_ROLLOUT, s, k_rollout3_f32<16>, dim3(blocks), dim3(512), 0, N, n, m, l, X, U, B, w1,
              b1, w2k, b2, w3, b3, act, fo);
 }
 
