@@ -200,7 +200,9 @@ def serve_main(args):
             X0, ref, sd = inputs(c, int(step_of[r]))
             sub.append((c, time.perf_counter() - t0, srv.submit(ids[c], X0, ref, sd)))
         lat, svc, done = [], [], []
-        for c, ts, t in sub:
+        for j, (c, ts, t) in enumerate(sub):
+            if j % 50 == 0:
+                print(f"[serve] {j}/{len(sub)} results", file=sys.stderr, flush=True)
             _, _, ms, q = srv.wait(ids[c], t)
             lat.append(ms)
             svc.append(ms - q)
@@ -211,7 +213,10 @@ def serve_main(args):
                 "service_p99_ms": float(np.percentile(svc, 99)), "makespan_s": span}
 
     def warm(srv, ids):
+        print(f"[serve] warm-up: one request per controller ({len(probs)})", file=sys.stderr, flush=True)
         for c in range(len(probs)):
+            if c % 25 == 0:
+                print(f"[serve] warm-up {c}/{len(probs)}", file=sys.stderr, flush=True)
             X0, ref, sd = inputs(c, 0)
             srv.wait(ids[c], srv.submit(ids[c], X0, ref, sd))
 
@@ -259,6 +264,9 @@ def main():
     ap.add_argument("--hbm-gb", type=float, default=200.0)
     ap.add_argument("--inflight", type=int, default=8)
     ap.add_argument("--no-fp32-baseline", action="store_true")
+    # a plain 256 MiB device-to-device copy, three times: the reference that scales the
+    # FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 --pmc run into HBM bytes
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -270,6 +278,15 @@ def main():
     from paper_2410_09663_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        x = torch.ones(64 << 20, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": x.numel() * 4, "copies": 3}), flush=True)
+        return
     if args.workload == "C5":
         serve_main(args)
         return

@@ -421,10 +421,9 @@ void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
   }
 }
 
-// OCP FP8 e4m3 (bias 7, no infinities, largest finite 448) nearest to f, ties to the
-// even code, saturating beyond 448.  The finite non-negative codes 0x00..0x7E are
-// increasing in value, so the nearest is found by bisection over them.
-uint8_t host_e4m3(float f) {
+// OCP FP8 e4m3: bias 7, no infinities, largest finite 448.  The finite non-negative
+// codes 0x00..0x7E are increasing in value.
+const std::vector<float>& e4m3_table() {
   static const std::vector<float> table = [] {
     std::vector<float> t(127);
     for (int c = 0; c < 127; ++c) {
@@ -433,6 +432,18 @@ uint8_t host_e4m3(float f) {
     }
     return t;
   }();
+  return table;
+}
+
+float e4m3_value(uint8_t c) {
+  const float v = e4m3_table()[c & 0x7F];
+  return (c & 0x80) ? -v : v;
+}
+
+// The e4m3 code nearest to f, ties to the even code, saturating beyond 448 (found by
+// bisection over the increasing codes).
+uint8_t host_e4m3(float f) {
+  const std::vector<float>& table = e4m3_table();
   const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
   const float a = std::fabs(f);
   if (!(a < table[126])) return sign | 0x7E;  // saturate (NaN does not occur: finite weights)
@@ -754,10 +765,18 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
         float mx = 0.f;
         for (size_t e = 0; e < kd; ++e) mx = std::max(mx, std::fabs(W[k][(size_t)o * kd + e]));
         ws[o] = mx > 0.f ? mx / 448.0f : 1.0f;
-        for (int ci = 0; ci < cin; ++ci)
-          for (int tap = 0; tap < 9; ++tap)
-            wq[(size_t)o * kd128 + (size_t)tap * cin + ci] =
-                host_e4m3(W[k][((size_t)o * cin + ci) * 9 + tap] / ws[o]);
+        // Rounding error carried from tap to tap of each (o, c) kernel, so that the 9
+        // rounded taps keep the exact sum up to the last rounding: on a locally smooth
+        // input the layer's output then sees almost none of the weight rounding.
+        for (int ci = 0; ci < cin; ++ci) {
+          float carry = 0.f;
+          for (int tap = 0; tap < 9; ++tap) {
+            const float target = W[k][((size_t)o * cin + ci) * 9 + tap] / ws[o] + carry;
+            const uint8_t q = host_e4m3(target);
+            carry = target - e4m3_value(q);
+            wq[(size_t)o * kd128 + (size_t)tap * cin + ci] = q;
+          }
+        }
       }
       if (!h->dWq[k] && (rc = dalloc(h, &h->dWq[k], wq.size()))) return rc;
       if (!h->dWs[k] && (rc = dalloc(h, &h->dWs[k], (size_t)cout))) return rc;

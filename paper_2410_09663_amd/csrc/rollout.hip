@@ -11,9 +11,35 @@
 namespace oic {
 namespace {
 
+// tanh from the hardware exp2 and reciprocal: tanh|x| = 1 - 2 / (exp(2|x|) + 1) for
+// |x| >= 1/8, and its odd Taylor series to x^7 below (truncation < 2e-9 there, where
+// the closed form would lose relative accuracy to cancellation).  Absolute error a few
+// 1e-8, relative error below 1e-6 everywhere.
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float a = fabsf(x);
+  const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);  // exp(2a) = 2^(2a log2 e)
+  float big = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+  big = a > 44.0f ? 1.0f : big;
+  const float a2 = a * a;
+  const float small = a * fmaf(a2, fmaf(a2, fmaf(a2, -17.0f / 315.0f, 2.0f / 15.0f), -1.0f / 3.0f), 1.0f);
+  return copysignf(a < 0.125f ? small : big, x);
+}
+
+// erf by Abramowitz & Stegun 7.1.26 (Hastings' rational approximation), absolute error
+// below 1.5e-7: erf|x| = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p|x|).
+__device__ __forceinline__ float fast_erf(float x) {
+  const float a = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+               0.254829592f);
+  const float ex = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);  // exp(-a^2)
+  return copysignf(1.0f - poly * ex, x);
+}
+
 __device__ __forceinline__ float activate(float v, int act) {
-  if (act == OIC_ACT_TANH) return tanhf(v);
-  return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));  // exact GELU
+  if (act == OIC_ACT_TANH) return fast_tanh(v);
+  return 0.5f * v * (1.0f + fast_erf(v * 0.70710678118654752f));  // GELU, erf form
 }
 
 // BF16 storage: round to nearest even (activations are finite), and back by shifting.
@@ -751,7 +777,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
 // The whole 2 -> C -> C -> 1 network in one kernel (FP32), so that neither hidden
 // activation touches HBM.  A block owns TR x 64 output pixels of one member and
 // stages the (TR+6) x 70 input region (X, and B U formed in LDS from the staged U rows
-// and B rows); layer 1 (VALU) fills the (TR+4) x 68 region around the tile, layer 2
+// and B rows); layer 1 (matrix cores, K = 2 x 9) fills the (TR+4) x 68 region around
+// the tile, layer 2
 // (v_mfma_f32_16x16x4_f32, implicit GEMM over the flattened (TR+2) x 66 region, 16
 // pixels per M-block) the (TR+2) x 66 region, and layer 3 (VALU) the tile itself,
 // written straight to the strided output field.  Cells of the intermediate regions
@@ -778,9 +805,8 @@ __global__ __launch_bounds__(512) void k_rollout3_f32(int N, int n, int m, int l
   __shared__ float s_bu[R0 * C0];
   __shared__ float s_u[LMX * C0];
   __shared__ float s_b[R0 * LMX];
-  __shared__ float s_w1[C * 19];           // 18 taps + bias per output channel
+  __shared__ float s_w1[20 * C];           // [k = ch*9 + tap, zero-padded to 20][o]
   __shared__ __attribute__((aligned(16))) float s_w2[9 * C * C];
-  __shared__ float s_w3[9 * C + 1];
   __shared__ __attribute__((aligned(16))) float s_l1[R1 * C1 * CP];
   __shared__ __attribute__((aligned(16))) float s_l2[NQ2 * CP];
   const int col_tiles = (m + TC - 1) / TC;
@@ -823,10 +849,10 @@ __global__ __launch_bounds__(512) void k_rollout3_f32(int N, int n, int m, int l
       const int e = tid + NT * u;
       wv[u] = e < 9 * C * C / 4 ? *(const f32x4*)(w2k + 4 * e) : f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    for (int e = tid; e < C * 18; e += NT) s_w1[(e / 18) * 19 + e % 18] = w1[e];
-    if (tid < C) s_w1[tid * 19 + 18] = b1 ? b1[tid] : 0.f;
-    for (int e = tid; e < 9 * C; e += NT) s_w3[e] = w3[e];
-    if (tid == 0) s_w3[9 * C] = b3 ? b3[0] : 0.f;
+    for (int e = tid; e < 20 * C; e += NT) {
+      const int k = e / C, o = e % C;
+      s_w1[e] = k < 18 ? w1[o * 18 + k] : 0.f;
+    }
 #pragma unroll
     for (int u = 0; u < XS; ++u)
       if (tid + NT * u < R0 * C0) s_x[tid + NT * u] = xv[u];
@@ -847,38 +873,54 @@ __global__ __launch_bounds__(512) void k_rollout3_f32(int N, int n, int m, int l
     s_bu[e] = bu;
   }
   __syncthreads();
-  // layer 1: every cell of the (TR+4) x 68 region, all C channels
-  for (int e = tid; e < R1 * C1; e += NT) {
-    const int r1 = e / C1, c1 = e % C1;
-    const int gy = y0 - 2 + r1, gx = x0 - 2 + c1;
-    float* dst = s_l1 + e * CP;
-    if (gy < 0 || gy >= n || gx < 0 || gx >= m) {
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int NW = NT / 64;
+  // layer 1 on the matrix cores: the (TR+4) x 68 region flattened into 16-pixel
+  // M-blocks, K = (channel, tap) = 18 padded to 20 with zero weights
+  {
+    constexpr int NQ1 = R1 * C1;
+    constexpr int MB1 = (NQ1 + 15) / 16;
+    constexpr int MPW1 = (MB1 + NW - 1) / NW;
+    f32x4 acc[MPW1];
+    int base[MPW1];  // input-region offset of this lane's pixel (tap (0,0))
 #pragma unroll
-      for (int o = 0; o < C; ++o) dst[o] = 0.f;
-      continue;
+    for (int j = 0; j < MPW1; ++j) {
+      acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      int q = (w + NW * j) * 16 + li;
+      q = q < NQ1 ? q : NQ1 - 1;
+      base[j] = (q / C1) * C0 + q % C1;
     }
-    float inx[18];
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+    for (int kb = 0; kb < 5; ++kb) {
+      const int k = kb * 4 + lk;
+      const int kk = k < 18 ? k : 0;  // past 18 the weights are zero
+      const float* src = kk < 9 ? s_x : s_bu;
+      const int tap = kk % 9;
+      const int off = (tap / 3) * C0 + tap % 3;
+      const float b = s_w1[k * C + li];
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        inx[dy * 3 + dx] = s_x[(r1 + dy) * C0 + c1 + dx];
-        inx[9 + dy * 3 + dx] = s_bu[(r1 + dy) * C0 + c1 + dx];
+      for (int j = 0; j < MPW1; ++j)
+        if (w + NW * j < MB1) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[base[j] + off], b, acc[j], 0, 0, 0);
+    }
+    const float bo = b1 ? b1[li] : 0.f;
+#pragma unroll
+    for (int j = 0; j < MPW1; ++j) {
+      if (w + NW * j >= MB1) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = (w + NW * j) * 16 + 4 * lk + r;
+        if (q < NQ1) {
+          const int gy = y0 - 2 + q / C1, gx = x0 - 2 + q % C1;
+          const bool in = gy >= 0 && gy < n && gx >= 0 && gx < m;
+          s_l1[q * CP + li] = in ? activate(acc[j][r] + bo, act) : 0.f;
+        }
       }
-#pragma unroll 4
-    for (int o = 0; o < C; ++o) {
-      float acc = s_w1[o * 19 + 18];
-#pragma unroll
-      for (int q = 0; q < 18; ++q) acc = fmaf(s_w1[o * 19 + q], inx[q], acc);
-      dst[o] = activate(acc, act);
     }
   }
   __syncthreads();
   // layer 2 on the matrix cores: wave w takes M-blocks w, w + 8, ... together
   {
-    const int lane = tid & 63, w = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    constexpr int NW = NT / 64;
     constexpr int MPW = (MB2 + NW - 1) / NW;
     f32x4 acc[MPW];
     int base[MPW];  // LDS offset of this lane's A pixel (tap (0,0)) in each M-block
@@ -921,12 +963,14 @@ __global__ __launch_bounds__(512) void k_rollout3_f32(int N, int n, int m, int l
     const int r3 = tid / TC, c3 = tid % TC;
     const int gy = y0 + r3, gx = x0 + c3;
     if (gy < n && gx < m) {
-      float acc = s_w3[9 * C];
+      // the weights are the same for every lane: read straight from memory (uniform
+      // loads), leaving the LDS to the activations
+      float acc = b3 ? b3[0] : 0.f;
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const float* src = s_l2 + ((r3 + tap / 3) * C2 + c3 + tap % 3) * CP;
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc = fmaf(s_w3[c * 9 + tap], src[c], acc);
+        for (int c = 0; c < C; ++c) acc = fmaf(w3[c * 9 + tap], src[c], acc);
       }
       fo.base[i * fo.si + gy * fo.sy + gx] = acc;
     }

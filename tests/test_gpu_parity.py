@@ -62,7 +62,7 @@ def test_cnn_forward_matches_oracle(preset):
         # 2-16-16-1 runs as one fused kernel; ragged row (13 = 8 + 5) and column (70) tiles
         p = wl.small_preset(n=13, m=70, l=5, channels=(2, 16, 16, 1), activation=wl.ACT_GELU, N=3)
     elif preset == "fused3_l16":
-        p = wl.small_preset(n=9, m=20, l=16, channels=(2, 16, 16, 1), N=4)
+        p = wl.small_preset(n=17, m=20, l=16, channels=(2, 16, 16, 1), N=4)
     elif preset == "deep_a":
         # hidden pairs (64,64), (64,32), (32,16), (16,64): channel-chunked MFMA layers;
         # 9 rows and 70 columns leave ragged row and column tiles
@@ -98,10 +98,10 @@ def test_solve_explicit_noise_matches_oracle(preset):
         # p = n + l = 100 > 90: blocked Cholesky (panels 64 + 36) and triangular-solve gain
         p = tiny(n=80, m=6, l=20, channels=(2, 4, 1), N=40, H=2)
     elif preset == "p150":
-        p = tiny(n=120, m=4, l=30, channels=(2, 4, 1), N=64, H=3)
+        p = tiny(n=120, m=8, l=30, channels=(2, 4, 1), N=64, H=3)
     elif preset == "p500":
         # p = 500: eight panels, the gain's 16-row blocks
-        p = tiny(n=400, m=2, l=100, channels=(2, 4, 1), N=400, H=2)
+        p = tiny(n=400, m=4, l=100, channels=(2, 4, 1), N=400, H=2)
     elif preset == "tiny_gelu":
         p = tiny(n=5, m=7, l=3, channels=(2, 5, 4, 1), act=wl.ACT_GELU, N=6, H=4)
     elif preset == "tiny_l1":
