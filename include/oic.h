@@ -145,6 +145,18 @@ typedef struct {
 
 int oic_solve_ex(oic_handle h, const oic_solve_args* a);
 
+/* oic_solve_ex plus the optional covariance outputs of Algorithm 1 (lines 8 and 11):
+ * for every horizon step t = 1..horizon, the pooled covariance of all stored
+ * trajectory rows, Sigma = (lambda / N) sum_i A^i A^iT with lambda = 1/tr(Psi) = 1/m
+ * and A^i the member's anomaly, before the analysis of step t (Eqs. (15d)-(15f)) in
+ * prior_cov and after it (Eq. (14c)) in post_cov.  Step t's block is Ma_t x Ma_t
+ * row-major FP64 with Ma_t = (t+1)(n+l): slices k..k+t, each its n X rows then its l
+ * U rows (the Delta U rows are not carried).  The blocks follow one another for
+ * t = 1..horizon, sum_t Ma_t^2 doubles in each output, in host or device memory per
+ * mem_mode.  The first call allocates the covariance buffers; the solve runs kernel by
+ * kernel (not from a captured graph).  Results otherwise identical to oic_solve_ex. */
+int oic_solve_cov(oic_handle h, const oic_solve_args* a, double* prior_cov, double* post_cov);
+
 /* The surrogate alone, Eq. (1), on `batch` independent fields:
  * X: batch x n x m, U: batch x l x m, X_next: batch x n x m (memory per
  * mem_mode).  batch <= max_N.  Runs the same rollout kernels a solve runs. */

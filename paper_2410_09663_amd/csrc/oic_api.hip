@@ -129,6 +129,15 @@ struct oic_ctx {
   uint64_t* dseed = nullptr;              // device copy of the solve's seed
   uint64_t* hseed = nullptr;              // pinned host staging for it
 
+  // optional covariance outputs (Eqs. (14c), (15d)-(15f)): per horizon step the pooled
+  // covariance of all stored trajectory rows before and after the analysis
+  bool want_cov = false;
+  double* cov_prior = nullptr;
+  double* cov_post = nullptr;
+  size_t cov_cap = 0;       // doubles in each of cov_prior / cov_post
+  double* mu64 = nullptr;   // FP64 means of the trajectory rows
+  size_t mu64_cap = 0;
+
   // replay of the per-solve kernel sequence
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
@@ -309,6 +318,9 @@ void free_all(oic_ctx* h) {
   f(h->fac);
   f(h->io);
   f(h->out_stage);
+  f(h->cov_prior);
+  f(h->cov_post);
+  f(h->mu64);
   f(h->dseed);
   if (h->hseed) hipHostFree(h->hseed);
   if (h->gexec) hipGraphExecDestroy(h->gexec);
@@ -435,11 +447,6 @@ const std::vector<float>& e4m3_table() {
   return table;
 }
 
-float e4m3_value(uint8_t c) {
-  const float v = e4m3_table()[c & 0x7F];
-  return (c & 0x80) ? -v : v;
-}
-
 // The e4m3 code nearest to f, ties to the even code, saturating beyond 448 (found by
 // bisection over the increasing codes).
 uint8_t host_e4m3(float f) {
@@ -483,6 +490,22 @@ int copy_out(oic_ctx* h, float* dst, const float* src, size_t count) {
 // Every kernel of one solve, in order, on the handle's stream.  Reads only handle-owned
 // buffers (inputs and noise are copied in beforehand; the seed is in device memory),
 // so the same sequence can be captured once and replayed.
+// Offset (in doubles) of horizon step t's block in the covariance outputs: the blocks
+// of steps 1..t-1, each ((s+1) rr)^2.
+size_t cov_offset(int rr, int t) {
+  size_t off = 0;
+  for (int s = 1; s < t; ++s) off += (size_t)((s + 1) * rr) * ((s + 1) * rr);
+  return off;
+}
+
+// out (Ma x Ma) = (lambda / N) sum_i A^i A^iT over the first Ma trajectory rows, with
+// lambda = 1 / tr(Psi) = 1 / m, anomalies taken about the FP64 ensemble means.
+void enqueue_cov(oic_ctx* h, const Dims& d, int Ma, double* out) {
+  launch_means_f64(h->stream, h->timer, h->traj, Ma, d.N, d.m, h->mu64);
+  launch_cross(h->stream, h->timer, d, h->traj, Ma, 0, h->Y, h->traj, Ma, h->mu64, h->part, h->part_cap, out,
+               1.0 / ((double)d.m * d.N));
+}
+
 void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
   const oic_config& c = h->cfg;
   const int N = d.N, H = d.H, n = c.n, m = c.m, l = c.l, rr = d.rr(), p = d.p();
@@ -507,6 +530,8 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
             FieldOut{cur, m, NM}, rollout_mode(h));
     launch_assemble_u(s, h->timer, d, h->traj, t,
                       noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true));
+    // Line 8 / Eqs. (15d)-(15f): covariance of the forecast trajectory (optional)
+    if (h->want_cov) enqueue_cov(h, d, (t + 1) * rr, h->cov_prior + cov_offset(rr, t));
     // Line 9 / Eq. (12).
     launch_observe(s, h->timer, d, h->traj, t, h->Y,
                    noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
@@ -527,6 +552,8 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
     launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
     launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m);
+    // Line 11 / Eq. (14c): covariance after the analysis (optional)
+    if (h->want_cov) enqueue_cov(h, d, Ma, h->cov_post + cov_offset(rr, t));
   }
   // Line 13: smoothed means of every slice.
   launch_means(s, h->timer, h->traj, (H + 1) * rr, N, m, h->mu_traj);
@@ -587,7 +614,7 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
     HIP_TRY(hipMemcpyAsync(h->dseed, h->hseed, sizeof(uint64_t), hipMemcpyHostToDevice, s));
   }
   const bool seeded = !explicit_noise;
-  if (h->use_graph && !h->timer.enabled) {
+  if (h->use_graph && !h->timer.enabled && !h->want_cov) {
     if (!h->gexec || h->gN != N || h->gH != H || h->gSeeded != seeded) {
       std::lock_guard<std::mutex> guard(resource_mutex());
       if (h->gexec) {
@@ -765,18 +792,10 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
         float mx = 0.f;
         for (size_t e = 0; e < kd; ++e) mx = std::max(mx, std::fabs(W[k][(size_t)o * kd + e]));
         ws[o] = mx > 0.f ? mx / 448.0f : 1.0f;
-        // Rounding error carried from tap to tap of each (o, c) kernel, so that the 9
-        // rounded taps keep the exact sum up to the last rounding: on a locally smooth
-        // input the layer's output then sees almost none of the weight rounding.
-        for (int ci = 0; ci < cin; ++ci) {
-          float carry = 0.f;
-          for (int tap = 0; tap < 9; ++tap) {
-            const float target = W[k][((size_t)o * cin + ci) * 9 + tap] / ws[o] + carry;
-            const uint8_t q = host_e4m3(target);
-            carry = target - e4m3_value(q);
-            wq[(size_t)o * kd128 + (size_t)tap * cin + ci] = q;
-          }
-        }
+        for (int ci = 0; ci < cin; ++ci)
+          for (int tap = 0; tap < 9; ++tap)
+            wq[(size_t)o * kd128 + (size_t)tap * cin + ci] =
+                host_e4m3(W[k][((size_t)o * cin + ci) * 9 + tap] / ws[o]);
       }
       if (!h->dWq[k] && (rc = dalloc(h, &h->dWq[k], wq.size()))) return rc;
       if (!h->dWs[k] && (rc = dalloc(h, &h->dWs[k], (size_t)cout))) return rc;
@@ -844,6 +863,59 @@ int oic_solve(oic_handle h, const float* X0, const float* reference, const float
 }
 
 int oic_solve_ex(oic_handle h, const oic_solve_args* a) { return solve_impl(h, a); }
+
+int oic_solve_cov(oic_handle h, const oic_solve_args* a, double* prior_cov, double* post_cov) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  if (!a) return fail(h, OIC_EINVAL, "NULL argument block");
+  if (!prior_cov || !post_cov) return fail(h, OIC_EINVAL, "NULL covariance output");
+  const oic_config& c = h->cfg;
+  const int H = a->horizon;
+  if (H < 1 || H > c.max_H) return solve_impl(h, a);  // reports the error
+  const size_t rr = (size_t)c.n + c.l;
+  const size_t need = cov_offset((int)rr, H + 1);
+  const size_t ma = (size_t)(H + 1) * rr;
+  int rc;
+  // buffers on first use (this entry point allocates; the solve itself does not)
+  std::unique_lock<std::mutex> guard(resource_mutex());
+  if (h->cov_cap < need) {
+    if (h->cov_prior) hipFree(h->cov_prior);
+    if (h->cov_post) hipFree(h->cov_post);
+    h->cov_prior = h->cov_post = nullptr;
+    h->cov_cap = 0;
+    if ((rc = dalloc(h, &h->cov_prior, need)) || (rc = dalloc(h, &h->cov_post, need))) return rc;
+    h->cov_cap = need;
+  }
+  if (h->mu64_cap < ma * c.m) {
+    if (h->mu64) hipFree(h->mu64);
+    h->mu64 = nullptr;
+    h->mu64_cap = 0;
+    if ((rc = dalloc(h, &h->mu64, ma * c.m))) return rc;
+    h->mu64_cap = ma * c.m;
+  }
+  if (h->part_cap < ma * ma) {  // one split of the largest covariance must fit
+    double* bigger = nullptr;     // the old buffer stays in place if this fails
+    if ((rc = dalloc(h, &bigger, ma * ma))) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    hipFree(h->part);
+    h->part = bigger;
+    h->part_cap = ma * ma;
+    if (h->gexec) {  // a captured solve refers to the old buffer
+      hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+  }
+  guard.unlock();
+  h->want_cov = true;
+  rc = solve_impl(h, a);
+  h->want_cov = false;
+  if (rc) return rc;
+  const hipMemcpyKind kind = c.mem_mode == OIC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  HIP_TRY(hipMemcpyAsync(prior_cov, h->cov_prior, need * sizeof(double), kind, h->stream));
+  HIP_TRY(hipMemcpyAsync(post_cov, h->cov_post, need * sizeof(double), kind, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return OIC_OK;
+}
 
 namespace {
 int cnn_forward_impl(oic_handle h, int batch, const float* X, const float* U, float* X_next,

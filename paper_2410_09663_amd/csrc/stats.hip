@@ -128,7 +128,9 @@ constexpr int MK = 64;  // columns per LDS stage
 
 // part[z][a][b] = sum over the columns c of chunk z of L[a][c] * D[b][c], where the
 // left row a is trajectory row a (a < Ma) or Ybar row a - Ma, and the right operand
-// D[b][c] = Ybar[b][c] - mean_i Ybar[b][c mod m] is centred in FP64.  Because the
+// D[b][c] = R[b][c] - mean_i R[b][c mod m] is centred in FP64 (R = Ybar for the
+// statistics of Eq. (13); R = trajectory rows for the covariances of Eqs. (14c),
+// (15d)-(15f)).  Because the
 // FP64-centred D sums to zero over the members (to FP64 rounding), the left rows
 // need no centring: sum_i X^i D^iT = sum_i (X^i - mean) D^iT.
 //
@@ -140,13 +142,15 @@ constexpr int MK = 64;  // columns per LDS stage
 template <int NB, bool VEC>
 __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restrict__ traj, int Ma,
                                                     int ny, const float* __restrict__ Y,
+                                                    const float* __restrict__ R, int p,
                                                     const double* __restrict__ muY, int chunk,
                                                     double* __restrict__ part) {
+  // right operand: the p rows of R (Ybar for the statistics), centred by muY
   constexpr int RB = NB * 16;
   __shared__ float sA[MA][MK + 1];
   __shared__ double sB[RB][MK + 1];
   const int NM = (int)d.NM();
-  const int m = d.m, p = d.p();
+  const int m = d.m;
   const int Mtot = Ma + ny;
   const int a0 = blockIdx.x * MA;
   const int b0 = blockIdx.y * RB;
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
       const int b = b0 + r, c = c0 + 4 * q;
       f32x4v v = {0.f, 0.f, 0.f, 0.f};
       if (b < p) {
-        const float* src = Y + (size_t)b * NM;
+        const float* src = R + (size_t)b * NM;
         if (VEC) {
           if (c < c_end) v = *(const f32x4v*)(src + c);
         } else {
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
 }
 
 __global__ void k_stats_reduce(const double* __restrict__ part, int splits, long long count,
-                               double* __restrict__ S) {
+                               double scale, double* __restrict__ S) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
   double s = 0.0;
@@ -262,7 +266,7 @@ __global__ void k_stats_reduce(const double* __restrict__ part, int splits, long
     for (int u = 0; u < 8; ++u) s += v[u];
   }
   for (; z < splits; ++z) s += part[(size_t)z * count + idx];
-  S[idx] = s;
+  S[idx] = scale * s;
 }
 
 }  // namespace
@@ -299,9 +303,9 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
              rows, N, m, mean);
 }
 
-void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
-                  const float* Y, const double* muY, double* part, size_t part_cap, double* S) {
-  const int p = d.p();
+void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
+                  const float* Y, const float* R, int p, const double* muR, double* part, size_t part_cap,
+                  double* S, double scale) {
   const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
   // right rows per block: NB*16 with NB <= 8, balanced over grid.y tiles
@@ -328,10 +332,10 @@ void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   case NBV:                                                                                     \
     if (vec)                                                                                    \
       OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, true>), grid, dim3(256), 0, d, traj, Ma, ny, \
-                 Y, muY, chunk, part);                                                          \
+                 Y, R, p, muR, chunk, part);                                                    \
     else                                                                                        \
       OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, false>), grid, dim3(256), 0, d, traj, Ma, ny,\
-                 Y, muY, chunk, part);                                                          \
+                 Y, R, p, muR, chunk, part);                                                    \
     break;
   switch (NB) {
     OIC_STATS_CASE(1) OIC_STATS_CASE(2) OIC_STATS_CASE(3) OIC_STATS_CASE(4)
@@ -340,7 +344,12 @@ void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 #undef OIC_STATS_CASE
   const long long count = (long long)Mtot * p;
   OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256),
-             0, part, splits, count, S);
+             0, part, splits, count, scale, S);
+}
+
+void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
+                  const float* Y, const double* muY, double* part, size_t part_cap, double* S) {
+  launch_cross(s, t, d, traj, Ma, ny, Y, Y, d.p(), muY, part, part_cap, S, 1.0);
 }
 
 }  // namespace oic

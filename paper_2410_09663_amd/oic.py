@@ -80,6 +80,7 @@ def lib():
             "oic_get_u_prev": (ci, [vp, vp]),
             "oic_solve": (ci, [vp, vp, vp, vp, vp, ci, ci, cu64, vp, vp]),
             "oic_solve_ex": (ci, [vp, ctypes.POINTER(oic_solve_args)]),
+            "oic_solve_cov": (ci, [vp, ctypes.POINTER(oic_solve_args), vp, vp]),
             "oic_cnn_forward": (ci, [vp, ci, vp, vp, vp]),
             "oic_plant_step": (ci, [vp, vp, vp, vp]),
             "oic_normals": (ci, [vp, cu64, ci, cs, vp]),
@@ -114,7 +115,7 @@ def lib():
 
 
 EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
-            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_cnn_forward", "oic_plant_step",
+            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_cnn_forward", "oic_plant_step",
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
             "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
             "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
@@ -253,6 +254,49 @@ class Controller:
         a.X_out = self._ptr(X_out, (H + 1, self.n, self.m), True) if want_X else None
         self._check(lib().oic_solve_ex(self._h, ctypes.byref(a)))
         return U_out, X_out
+
+    def solve_cov(self, X0, reference, Q, R, N: int, H: int, seed: int = 0, U_prev=None, noise=None):
+        """oic_solve_cov: returns (U_hat, X_hat, prior, post), where prior[t-1] and post[t-1]
+        are the (t+1)(n+l) x (t+1)(n+l) pooled trajectory covariances before and after the
+        analysis of horizon step t (FP64)."""
+        Q = self._host(Q, (self.l, self.l))
+        R = self._host(R, (self.n, self.n))
+        a = oic_solve_args()
+        a.X0 = self._ptr(X0, (self.n, self.m))
+        a.reference = self._ptr(reference, (H + 1, self.n, self.m))
+        a.Q, a.R = Q.ctypes.data, R.ctypes.data
+        a.N, a.horizon, a.seed = N, H, seed
+        a.U_prev = self._ptr(U_prev, (self.l, self.m))
+        if noise is not None:
+            z = (noise.Z_init, noise.Z_W, noise.Z_VX, noise.Z_VU) if hasattr(noise, "Z_init") else noise
+            a.Z_init = self._ptr(z[0], (N, self.l, self.m))
+            a.Z_W = self._ptr(z[1], (H, N, self.l, self.m))
+            a.Z_VX = self._ptr(z[2], (H, N, self.n, self.m))
+            a.Z_VU = self._ptr(z[3], (H, N, self.l, self.m))
+        U_out = self._new((H + 1, self.l, self.m))
+        X_out = self._new((H + 1, self.n, self.m))
+        a.U_out = self._ptr(U_out, U_out.shape, True)
+        a.X_out = self._ptr(X_out, X_out.shape, True)
+        rr = self.n + self.l
+        sizes = [((t + 1) * rr) ** 2 for t in range(1, H + 1)]
+        if self.mem_mode == OIC_MEM_DEVICE:
+            import torch
+            prior = torch.empty(sum(sizes), dtype=torch.float64, device="cuda")
+            post = torch.empty(sum(sizes), dtype=torch.float64, device="cuda")
+            pp, qp = prior.data_ptr(), post.data_ptr()
+        else:
+            prior = np.empty(sum(sizes), np.float64)
+            post = np.empty(sum(sizes), np.float64)
+            pp, qp = prior.ctypes.data, post.ctypes.data
+        self._check(lib().oic_solve_cov(self._h, ctypes.byref(a), pp, qp))
+        def split(buf):
+            out, off = [], 0
+            for t, sz in enumerate(sizes, start=1):
+                ma = (t + 1) * rr
+                out.append(buf[off:off + sz].reshape(ma, ma))
+                off += sz
+            return out
+        return U_out, X_out, split(prior), split(post)
 
     def cnn_forward(self, X, U):
         b = X.shape[0]

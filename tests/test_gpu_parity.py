@@ -278,3 +278,28 @@ def test_graph_replay_matches_eager_bitwise():
         c.set_u_prev(zero)
         U3, _ = c.solve_ex(prob.X0, Xref2, prob.Q, prob.R, 40, 2, noise=z2)
         assert relerr(U3, U2) < 1e-6  # device and host Philox normals agree (bitwise, up to rare 1-ulp)
+
+
+@pytest.mark.parametrize("preset", ["tiny", "C1"])
+def test_covariance_outputs_match_oracle(preset):
+    """Optional outputs of Algorithm 1 (lines 8 and 11): the pooled covariance of the
+    stored trajectory before (Eqs. 15d-15f) and after (Eq. 14c) every analysis, against
+    the oracle's (whose slices also carry the Delta U rows, dropped here)."""
+    p = tiny() if preset == "tiny" else wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=5)
+    with oic.controller_for(prob) as c:
+        U, X, prior, post = c.solve_cov(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
+        U2, X2 = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
+    assert np.array_equal(U, U2) and np.array_equal(X, X2)  # the covariances change nothing
+    ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N,
+                     p.H, z.Z_init, z.Z_W, z.Z_VX, z.Z_VU, want_cov=True)
+    rows = p.n + 2 * p.l
+    for t in range(1, p.H + 1):
+        keep = np.concatenate([s * rows + np.arange(p.n + p.l) for s in range(t + 1)])
+        for got, want in ((prior[t - 1], ref.prior_cov[t - 1]), (post[t - 1], ref.post_cov[t - 1])):
+            want = want[np.ix_(keep, keep)]
+            assert got.shape == want.shape
+            assert relerr(got, want) < TOL_FP32, (t, relerr(got, want))
+            assert np.allclose(got, got.T, rtol=0, atol=1e-12 * np.abs(got).max())
