@@ -289,9 +289,10 @@ def test_covariance_outputs_match_oracle(preset):
     prob = wl.make_problem(p)
     Xref = wl.reference_window(p, 0)
     z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=5)
+    Up = np.zeros((p.l, p.m), np.float32)  # both solves start from the same U_prev
     with oic.controller_for(prob) as c:
-        U, X, prior, post = c.solve_cov(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
-        U2, X2 = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
+        U, X, prior, post = c.solve_cov(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, U_prev=Up, noise=z)
+        U2, X2 = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, U_prev=Up, noise=z)
     assert np.array_equal(U, U2) and np.array_equal(X, X2)  # the covariances change nothing
     ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N,
                      p.H, z.Z_init, z.Z_W, z.Z_VX, z.Z_VU, want_cov=True)
