@@ -358,7 +358,8 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   __shared__ float s_bu[HR * HC];
   __shared__ float s_u[LMAX * HC];
   __shared__ float s_b[HR * LMAX];
-  __shared__ float s_w[COUT * 18 + COUT];
+  __shared__ float s_w[20 * COUT];  // [k = channel*9 + tap, zero-padded to 20][o]
+  __shared__ float s_bias[COUT];
   __shared__ float s_out[TR * TC * (COUT + 1)];
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
@@ -396,8 +397,11 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
       const int gy = y0 + yy - 1;
       bv[u] = (yy < HR && a < l && gy >= 0 && gy < n) ? B[(size_t)gy * l + a] : 0.f;
     }
-    for (int e = tid; e < COUT * 18; e += 256) s_w[e] = w[e];
-    if (tid < COUT) s_w[COUT * 18 + tid] = bias ? bias[tid] : 0.f;
+    for (int e = tid; e < 20 * COUT; e += 256) {
+      const int kk = e / COUT, o = e % COUT;
+      s_w[e] = kk < 18 ? w[o * 18 + kk] : 0.f;
+    }
+    if (tid < COUT) s_bias[tid] = bias ? bias[tid] : 0.f;
 #pragma unroll
     for (int u = 0; u < XS; ++u)
       if (tid + 256 * u < HR * HC) s_x[tid + 256 * u] = xv[u];
@@ -416,23 +420,49 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
     s_bu[e] = bu;
   }
   __syncthreads();
-  const int ty = tid / TC, tx = tid % TC;
-  float inx[18];
+  // 256 pixels x COUT channels x K = 18 (two channels x 9 taps, padded to 20) on the
+  // matrix cores: wave w owns pixel blocks 4w..4w+3 (16 pixels each, one output row)
+  {
+    constexpr int NB = (COUT + 15) / 16;  // COUT = 8 uses half of one N-block
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    f32x4 acc[4][NB];
 #pragma unroll
-  for (int dy = 0; dy < 3; ++dy)
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      inx[dy * 3 + dx] = s_x[(ty + dy) * HC + tx + dx];
-      inx[9 + dy * 3 + dx] = s_bu[(ty + dy) * HC + tx + dx];
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 5; ++kb) {
+      const int kq = kb * 4 + lk;
+      const int kk = kq < 18 ? kq : 0;  // past 18 the weights are zero
+      const float* src = kk < 9 ? s_x : s_bu;
+      const int tap = kk % 9;
+      const int off = (tap / 3) * HC + tap % 3;
+      float b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[nb] = nb * 16 + li < COUT ? s_w[kq * COUT + nb * 16 + li] : 0.f;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const int px = (4 * w + mb) * 16 + li;  // pixel (px / 64, px % 64) of the tile
+        const float a = src[(px / TC) * HC + px % TC + off];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[mb][nb], 0, 0, 0);
+      }
     }
-#pragma unroll 4
-  for (int o = 0; o < COUT; ++o) {
-    float acc = s_w[COUT * 18 + o];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc = fmaf(s_w[o * 18 + q], inx[q], acc);          // channel X
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc = fmaf(s_w[o * 18 + 9 + q], inx[9 + q], acc);  // channel B U
-    s_out[tid * (COUT + 1) + o] = activate(acc, act);
+      for (int nb = 0; nb < NB; ++nb) {
+        const int o = nb * 16 + li;
+        if (o >= COUT) continue;
+        const float bo = s_bias[o];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int px = (4 * w + mb) * 16 + 4 * lk + r;
+          s_out[px * (COUT + 1) + o] = activate(acc[mb][nb][r] + bo, act);
+        }
+      }
   }
   __syncthreads();
   float vmax = 0.f;
