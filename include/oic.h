@@ -198,6 +198,17 @@ int oic_stage_cost(int n, int m, int l, const float* X, const float* Xref, const
  * launched kernel by kernel instead.  Results are identical either way. */
 int oic_set_graph(oic_handle h, int enable);
 
+/* Right transformation of the control (the extension after Table 1 of the paper):
+ * when the system's actual input u_t has q < m columns, the method runs on
+ * U_t = u_t T with a q x m matrix T of full row rank, and the smoothed control is
+ * mapped back by least squares, u_hat = U_hat T^T (T T^T)^{-1}.  Host pointers,
+ * row-major FP32, FP64 arithmetic inside; no GPU work.
+ * oic_columns_expand:  U (l x m) = u (l x q) T (q x m).
+ * oic_columns_project: u (l x q) = U (l x m) T^T (T T^T)^{-1}; OIC_ENOTSPD when T T^T is
+ * not positive definite (T lacks full row rank), OIC_EINVAL for bad sizes (q > m). */
+int oic_columns_expand(int l, int q, int m, const float* u, const float* T, float* U);
+int oic_columns_project(int l, int m, int q, const float* U, const float* T, float* u);
+
 /* ---- Serving: one request loop for many independent controllers ----
  *
  * A server owns a set of controllers, each a handle of its own (own stream,

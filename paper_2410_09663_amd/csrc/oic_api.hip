@@ -1017,6 +1017,56 @@ int oic_stage_cost(int n, int m, int l, const float* X, const float* Xref, const
   return OIC_OK;
 }
 
+int oic_columns_expand(int l, int q, int m, const float* u, const float* T, float* U) {
+  if (l < 1 || q < 1 || m < 1 || !u || !T || !U) return OIC_EINVAL;
+  for (int a = 0; a < l; ++a)
+    for (int c = 0; c < m; ++c) {
+      double s = 0.0;
+      for (int j = 0; j < q; ++j) s += (double)u[(size_t)a * q + j] * T[(size_t)j * m + c];
+      U[(size_t)a * m + c] = (float)s;
+    }
+  return OIC_OK;
+}
+
+int oic_columns_project(int l, int m, int q, const float* U, const float* T, float* u) {
+  if (l < 1 || q < 1 || m < 1 || q > m || !U || !T || !u) return OIC_EINVAL;
+  // G = T T^T (q x q, SPD when T has full row rank), then u^T = G^{-1} T U^T column by
+  // column with the Cholesky factor of G, all in FP64
+  std::vector<double> L((size_t)q * q, 0.0);  // Cholesky factor of G, built row by row
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double g = 0.0;
+      for (int c = 0; c < m; ++c) g += (double)T[(size_t)i * m + c] * T[(size_t)j * m + c];
+      for (int k = 0; k < j; ++k) g -= L[(size_t)i * q + k] * L[(size_t)j * q + k];
+      if (i == j) {
+        if (!(g > 0.0) || !std::isfinite(g)) return OIC_ENOTSPD;
+        L[(size_t)i * q + i] = std::sqrt(g);
+      } else {
+        L[(size_t)i * q + j] = g / L[(size_t)j * q + j];
+      }
+    }
+  std::vector<double> y(q);
+  for (int a = 0; a < l; ++a) {
+    for (int i = 0; i < q; ++i) {  // rhs_i = (U T^T)[a][i]
+      double s = 0.0;
+      for (int c = 0; c < m; ++c) s += (double)U[(size_t)a * m + c] * T[(size_t)i * m + c];
+      y[i] = s;
+    }
+    for (int i = 0; i < q; ++i) {  // L z = rhs
+      double v = y[i];
+      for (int j = 0; j < i; ++j) v -= L[(size_t)i * q + j] * y[j];
+      y[i] = v / L[(size_t)i * q + i];
+    }
+    for (int i = q - 1; i >= 0; --i) {  // L^T x = z
+      double v = y[i];
+      for (int j = i + 1; j < q; ++j) v -= L[(size_t)j * q + i] * y[j];
+      y[i] = v / L[(size_t)i * q + i];
+    }
+    for (int i = 0; i < q; ++i) u[(size_t)a * q + i] = (float)y[i];
+  }
+  return OIC_OK;
+}
+
 int oic_set_graph(oic_handle h, int enable) {
   if (!h) return OIC_EINVAL;
   std::lock_guard<std::mutex> guard(resource_mutex());

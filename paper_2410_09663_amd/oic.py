@@ -81,6 +81,8 @@ def lib():
             "oic_solve": (ci, [vp, vp, vp, vp, vp, ci, ci, cu64, vp, vp]),
             "oic_solve_ex": (ci, [vp, ctypes.POINTER(oic_solve_args)]),
             "oic_solve_cov": (ci, [vp, ctypes.POINTER(oic_solve_args), vp, vp]),
+            "oic_columns_expand": (ci, [ci, ci, ci, vp, vp, vp]),
+            "oic_columns_project": (ci, [ci, ci, ci, vp, vp, vp]),
             "oic_cnn_forward": (ci, [vp, ci, vp, vp, vp]),
             "oic_plant_step": (ci, [vp, vp, vp, vp]),
             "oic_normals": (ci, [vp, cu64, ci, cs, vp]),
@@ -115,7 +117,7 @@ def lib():
 
 
 EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
-            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_cnn_forward", "oic_plant_step",
+            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_columns_expand", "oic_columns_project", "oic_cnn_forward", "oic_plant_step",
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
             "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
             "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
@@ -380,6 +382,36 @@ def stage_cost(X, Xref, U, dU, Q, R) -> float:
     if rc != OIC_OK:
         raise OicError(rc, "oic_stage_cost failed")
     return out.value
+
+
+def columns_expand(u, T):
+    """U = u T (oic_columns_expand): u (l, q), T (q, m) -> (l, m) float32."""
+    u = np.ascontiguousarray(u, np.float32)
+    T = np.ascontiguousarray(T, np.float32)
+    l, q = u.shape
+    m = T.shape[1]
+    if T.shape[0] != q:
+        raise ValueError("T must be q x m")
+    U = np.empty((l, m), np.float32)
+    rc = lib().oic_columns_expand(l, q, m, u.ctypes.data, T.ctypes.data, U.ctypes.data)
+    if rc != OIC_OK:
+        raise OicError(rc, "oic_columns_expand failed")
+    return U
+
+
+def columns_project(U, T):
+    """u = U T^T (T T^T)^{-1} (oic_columns_project): U (l, m), T (q, m) -> (l, q) float32."""
+    U = np.ascontiguousarray(U, np.float32)
+    T = np.ascontiguousarray(T, np.float32)
+    l, m = U.shape
+    q = T.shape[0]
+    if T.shape[1] != m:
+        raise ValueError("T must be q x m")
+    u = np.empty((l, q), np.float32)
+    rc = lib().oic_columns_project(l, m, q, U.ctypes.data, T.ctypes.data, u.ctypes.data)
+    if rc != OIC_OK:
+        raise OicError(rc, "oic_columns_project failed")
+    return u
 
 
 class Server:

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2410_09663_amd import oic
@@ -72,3 +73,22 @@ def test_stage_cost_matches_oracle_trace_form():
     assert abs(got - ref) <= 1e-10 * abs(ref)
     with pytest.raises(oic.OicError):
         oic.stage_cost(X, Xr, U, dU, -Q, R)
+
+
+def test_column_transform_matches_oracle():
+    """oic_columns_expand / oic_columns_project (host functions) against the oracle's
+    U = u T and u = U T^T (T T^T)^{-1}, including the repeat-the-column T = [1 ... 1]."""
+    from oracle import transform as tr
+    rng = np.random.default_rng(4)
+    for (l, q, m) in ((3, 1, 8), (4, 2, 16), (2, 5, 5)):
+        T = (np.ones((1, m)) if q == 1 else rng.standard_normal((q, m))).astype(np.float32)
+        u = rng.standard_normal((l, q)).astype(np.float32)
+        U = oic.columns_expand(u, T)
+        assert np.allclose(U, tr.expand(u, T), rtol=1e-6, atol=1e-6)
+        U2 = rng.standard_normal((l, m)).astype(np.float32)
+        got = oic.columns_project(U2, T)
+        want = tr.project(U2, T)
+        assert np.linalg.norm(got - want) <= 1e-6 * np.linalg.norm(want)
+    # rank-deficient T: T T^T singular
+    with pytest.raises(oic.OicError):
+        oic.columns_project(np.ones((2, 4), np.float32), np.ones((2, 4), np.float32))
