@@ -43,6 +43,33 @@ class SolveResult:
     prior_cov: List[np.ndarray]  # Sigma^X_{t|t-1} (Eq. 15f, line 8) per step, if requested
 
 
+@dataclasses.dataclass
+class Constraint:
+    """A constraint g(Xbar_t, Ubar_t) <= 0 observed through a barrier (section on
+    extensions after Table 1): z_t = phi(g) + eps_t with the softplus barrier
+    phi(x) = ln(1 + exp(beta x)) / alpha and eps_t ~ N(0, rz), appended to Ybar_t as one
+    more row whose actual value is 0.  Reading: g is applied column by column, as the
+    linear form g_c = aX . X[:, c] + aU . U[:, c] - b on the forecast (noise-free) state
+    and control, so the extra row has the m columns of every other row; a scalar g of
+    the whole matrix corresponds to repeating one value over the columns."""
+
+    aX: np.ndarray  # (n,)
+    aU: np.ndarray  # (l,)
+    b: float
+    alpha: float
+    beta: float
+    rz: float
+
+    def g(self, X, U):
+        """Per-column constraint values of (.., n, m) states and (.., l, m) controls."""
+        return (np.einsum("r,...rm->...m", np.asarray(self.aX, np.float64), X)
+                + np.einsum("a,...am->...m", np.asarray(self.aU, np.float64), U) - self.b)
+
+    def barrier(self, x):
+        """Softplus barrier ln(1 + e^{beta x}) / alpha, evaluated without overflow."""
+        return np.logaddexp(0.0, self.beta * np.asarray(x, np.float64)) / self.alpha
+
+
 def _chol_lower(a: np.ndarray) -> np.ndarray:
     return np.linalg.cholesky(np.asarray(a, dtype=np.float64))
 
@@ -72,11 +99,13 @@ def analysis(Xcal, Y, Ybar_t):
 
 
 def solve(B, weights, act, X0, Xref, QU, QdU, R, N, H, Z_init, Z_W, Z_VX, Z_VU,
-          U_prev=None, Uref=None, biases=None, want_cov=False) -> SolveResult:
+          U_prev=None, Uref=None, biases=None, want_cov=False, constraint=None,
+          Z_VZ=None) -> SolveResult:
     """One MPC solve at time k (Algorithm 1, lines 4-13).
 
     Shapes: B (n,l); X0 (n,m); Xref (H+1,n,m) = X^ref_t for t=k..k+H; QU, QdU (l,l);
     R (n,n); Z_init (N,l,m); Z_W, Z_VU (H,N,l,m); Z_VX (H,N,n,m) standard normals.
+    constraint: an optional Constraint, observed with the standard normals Z_VZ (H,N,1,m).
     """
     X0 = np.asarray(X0, dtype=np.float64)
     n, m = X0.shape
@@ -114,6 +143,11 @@ def solve(B, weights, act, X0, Xref, QU, QdU, R, N, H, Z_init, Z_W, Z_VX, Z_VU,
         VU = np.matmul(L_U, np.asarray(Z_VU[t - 1], dtype=np.float64))
         Y = np.concatenate([traj[:, t, :n] + VX, traj[:, t, n:n + l] + VU], axis=1)  # (N, p, m)
         Ybar_t = np.concatenate([Xref[t], Uref], axis=0)  # (p, m)
+        if constraint is not None:  # the barrier observation z_t, actual value 0
+            g = constraint.g(traj[:, t, :n], traj[:, t, n:n + l])  # (N, m)
+            z = constraint.barrier(g) + np.sqrt(constraint.rz) * np.asarray(Z_VZ[t - 1], np.float64)[:, 0]
+            Y = np.concatenate([Y, z[:, None, :]], axis=1)
+            Ybar_t = np.concatenate([Ybar_t, np.zeros((1, m))], axis=0)
         if want_cov:  # Line 8, Eqs. (15d)-(15f): the block matrix equals the pooled covariance
             Ap = Xcal - Xcal.mean(axis=0)
             priors.append((1.0 / (m * N)) * np.einsum("iam,ibm->ab", Ap, Ap))
