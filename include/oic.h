@@ -111,7 +111,8 @@ int oic_get_u_prev(oic_handle h, float* U_prev);
  *   seed:      key of the Philox4x32-10 stream the noise is drawn from: the
  *              normal with C-order index e in the (H, N, rows, m) array of noise
  *              kind c (0: initial control spread, shape (N, l, m); 1: W_t; 2: V_X,t;
- *              3: V_U,t) uses counter (e mod 2^32, e div 2^32, c, 0) and key
+ *              3: V_U,t; 4: the constraint row's eps_t, shape (H, N, 1, m), drawn only
+ *              when a constraint is set) uses counter (e mod 2^32, e div 2^32, c, 0) and key
  *              (seed mod 2^32, seed div 2^32); two 53-bit uniforms feed the
  *              Box-Muller cosine branch in FP64, rounded to FP32.
  *   U_out:     (horizon+1) x l x m, the smoothed control means U_hat_{k..k+H}.
@@ -141,6 +142,7 @@ typedef struct {
   const float* Z_VU;
   float* U_out;
   float* X_out;
+  const float* Z_VZ;  /* H x N x m: noise of the constraint row (only with oic_set_constraint) */
 } oic_solve_args;
 
 int oic_solve_ex(oic_handle h, const oic_solve_args* a);
@@ -197,6 +199,19 @@ int oic_stage_cost(int n, int m, int l, const float* X, const float* Xref, const
  * the same.  On by default.  While per-kernel timing is enabled the sequence is
  * launched kernel by kernel instead.  Results are identical either way. */
 int oic_set_graph(oic_handle h, int enable);
+
+/* A constraint observed through a barrier (the extension after Table 1 of the
+ * paper): z_t = phi(g) + eps_t, phi(x) = ln(1 + exp(beta x)) / alpha, eps_t ~ N(0, rz),
+ * is appended to Ybar_t as one more row whose actual value is 0, so that the
+ * smoother steers away from g > 0.  The constraint is applied column by column as
+ * the linear form g_c = aX . X_t[:, c] + aU . U_t[:, c] - b on each member's forecast
+ * state and control (aX: n values, aU: l values, host pointers, copied).  Passing
+ * aX = aU = NULL removes it.  alpha, beta, rz > 0.  With a constraint set, explicit-
+ * noise solves also take Z_VZ (standard normals, H x N x m, index t-1 for step t);
+ * seeded solves draw them as kind 4 of the stream (see oic_normals).  Needs
+ * (N-1) m >= n + l + 1 and n + l + 1 <= 512. */
+int oic_set_constraint(oic_handle h, const float* aX, const float* aU, float b, float alpha, float beta,
+                       float rz);
 
 /* Right transformation of the control (the extension after Table 1 of the paper):
  * when the system's actual input u_t has q < m columns, the method runs on

@@ -110,6 +110,23 @@ __global__ void k_observe(Dims d, const float* __restrict__ traj, int step, floa
   Y[(size_t)q * NM + col] = s + v;
 }
 
+// The constraint row of Ybar for every member and column (one thread per column).
+__global__ void k_constraint_row(Dims d, const float* __restrict__ traj, int step, float* __restrict__ Y,
+                                 const float* __restrict__ aX, const float* __restrict__ aU, float b,
+                                 float alpha, float beta, float sqrt_rz, const float* __restrict__ Zvz) {
+  const int NM = (int)d.NM();
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= NM) return;
+  const float* slice = traj + (size_t)step * d.rr() * NM + col;
+  float g = -b;
+  for (int r = 0; r < d.n; ++r) g = fmaf(aX[r], slice[(size_t)r * NM], g);
+  for (int a = 0; a < d.l; ++a) g = fmaf(aU[a], slice[(size_t)(d.n + a) * NM], g);
+  // softplus without overflow: max(x, 0) + log1p(exp(-|x|))
+  const float x = beta * g;
+  const float sp = fmaxf(x, 0.f) + log1pf(expf(-fabsf(x)));
+  Y[(size_t)(d.n + d.l) * NM + col] = sp / alpha + sqrt_rz * Zvz[col];
+}
+
 inline dim3 row_grid(long long NM, int rows) {
   return dim3((unsigned)((NM + 255) / 256), (unsigned)rows);
 }
@@ -136,8 +153,16 @@ void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int 
 
 void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
                     NoiseRef vx, NoiseRef vu) {
-  OIC_LAUNCH(t, KC_OBSERVE, s, k_observe, row_grid(d.NM(), d.p()), dim3(256), 0, d, traj, step, Y,
+  OIC_LAUNCH(t, KC_OBSERVE, s, k_observe, row_grid(d.NM(), d.n + d.l), dim3(256), 0, d, traj, step, Y,
              vx, vu);
+}
+
+void launch_constraint_row(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
+                           const float* aX, const float* aU, float b, float alpha, float beta,
+                           float sqrt_rz, const float* Zvz) {
+  const long long NM = d.NM();
+  OIC_LAUNCH(t, KC_OBSERVE, s, k_constraint_row, dim3((unsigned)((NM + 255) / 256)), dim3(256), 0, d, traj,
+             step, Y, aX, aU, b, alpha, beta, sqrt_rz, Zvz);
 }
 
 }  // namespace oic

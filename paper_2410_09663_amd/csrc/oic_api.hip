@@ -117,7 +117,11 @@ struct oic_ctx {
   double* Lwork = nullptr;
   float* K = nullptr;
   int* flag = nullptr;
-  float* Z[4] = {};  // 0 init (N,l,m); 1 W (H,N,l,m); 2 V_X (H,N,n,m); 3 V_U (H,N,l,m)
+  float* Z[5] = {};  // 0 init (N,l,m); 1 W (H,N,l,m); 2 V_X (H,N,n,m); 3 V_U (H,N,l,m); 4 eps (H,N,m)
+  // barrier-observed constraint (one extra row of Ybar), off unless set
+  bool con_on = false;
+  float* con_a = nullptr;  // [aX (n)][aU (l)]
+  float con_b = 0.f, con_alpha = 1.f, con_beta = 1.f, con_rz = 1.f;
   float* Uprev = nullptr;
   float* Uprev_new = nullptr;
   float* fac = nullptr;  // [Q factor (l*l)][R factor (n*n)]
@@ -181,6 +185,7 @@ size_t noise_floats(const oic_config& c, int kind) {
     case 0: return N * c.l * m;
     case 1: return H * N * c.l * m;
     case 2: return H * N * c.n * m;
+    case 4: return H * N * m;
     default: return H * N * c.l * m;
   }
 }
@@ -312,7 +317,8 @@ void free_all(oic_ctx* h) {
   f(h->Lwork);
   f(h->K);
   f(h->flag);
-  for (int k = 0; k < 4; ++k) f(h->Z[k]);
+  for (int k = 0; k < 5; ++k) f(h->Z[k]);
+  f(h->con_a);
   f(h->Uprev);
   f(h->Uprev_new);
   f(h->fac);
@@ -353,6 +359,22 @@ size_t activation_floats(const oic_config& c) {
   if (!bf16_rollout_possible(c)) return full;
   // BF16 activations for batched rollouts; FP32 only for the one-field plant step
   return std::max((full + 1) / 2, (size_t)c.n * c.m * cmax);
+}
+
+// Device bytes oic_create allocates for c (plus the weights oic_set_weights adds),
+// buffer by buffer as in oic_create.
+size_t handle_bytes(const oic_config& c) {
+  const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l + 1;
+  const size_t NM = N * m, Ma = Hs * rr;
+  size_t floats = Hs * rr * NM + p * NM + 2 * activation_floats(c) + Ma * m + Ma * p;
+  for (int k = 0; k < 5; ++k) floats += noise_floats(c, k);
+  floats += (n + l) + 2 * l * m + l * l + n * n;                                  // con_a, U_prev, factors
+  floats += n * m + Hs * n * m + l * m + N * (n + l) * m + N * n * m + Hs * (l + n) * m;  // staging
+  size_t doubles = p * m + (Ma + p) * p + std::max(32 * (Ma + p) * p, Ma * p) + 2 * p * (p + 1) + 2 * p * p;
+  size_t weights = n * l * 4;
+  for (int k = 0; k < c.n_layers; ++k)  // FP32, MFMA-layout FP32, BF16 and FP8 copies at most
+    weights += (size_t)c.channels[k + 1] * c.channels[k] * 9 * 11 + (size_t)c.channels[k + 1] * 8;
+  return 4 * floats + 8 * doubles + weights + 4096;
 }
 
 }  // namespace oic
@@ -514,10 +536,10 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
   float* dX0 = h->io;
   float* dRef = dX0 + (size_t)n * m;
   float* dUp = dRef + (size_t)(c.max_H + 1) * n * m;
-  const size_t cnt[4] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
-                         (size_t)H * N * l * m};
+  const size_t cnt[5] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
+                         (size_t)H * N * l * m, (size_t)H * N * m};
   if (seeded)
-    for (int k = 0; k < 4; ++k) launch_normals(s, h->timer, h->Z[k], cnt[k], h->dseed, (uint32_t)k);
+    for (int k = 0; k < 4 + d.nc; ++k) launch_normals(s, h->timer, h->Z[k], cnt[k], h->dseed, (uint32_t)k);
   const float* const* Zd = h->Z;
   // Line 4: initial ensemble (also clears the failure flag).
   launch_init_slice0(s, h->timer, d, h->traj, dX0, dUp, noise_ref(h, Zd[0], true), h->flag);
@@ -536,6 +558,10 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     launch_observe(s, h->timer, d, h->traj, t, h->Y,
                    noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
                    noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true));
+    // the barrier observation of the constraint, if one is set (actual value 0)
+    if (d.nc)
+      launch_constraint_row(s, h->timer, d, h->traj, t, h->Y, h->con_a, h->con_a + n, h->con_b, h->con_alpha,
+                            h->con_beta, std::sqrt(h->con_rz), Zd[4] + (size_t)(t - 1) * N * m);
     // Eq. (13a): mean of Ybar in FP64.  The trajectory rows need no mean here: the
     // FP64-centred Ybar anomalies sum to zero, so sum_i X^i D^iT = sum_i A^i D^iT.
     const int Ma = (t + 1) * rr;
@@ -573,12 +599,14 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   if (H < 1) return fail(h, OIC_EINVAL, "horizon must be at least 1");
   if (N > c.max_N || H > c.max_H)
     return fail(h, OIC_ENOMEM, "N or horizon exceeds the capacity the handle was created with");
-  if ((long long)(N - 1) * c.m < c.n + c.l)
-    return fail(h, OIC_EINVAL, "(N-1)*m < n+l: Sigma^Ybar cannot be positive definite");
+  if ((long long)(N - 1) * c.m < c.n + c.l + (h->con_on ? 1 : 0))
+    return fail(h, OIC_EINVAL, "(N-1)*m is below the observation rows: Sigma^Ybar cannot be positive definite");
   if (!a->X0 || !a->reference || !a->U_out) return fail(h, OIC_EINVAL, "NULL X0, reference or U_out");
   const bool explicit_noise = a->Z_init || a->Z_W || a->Z_VX || a->Z_VU;
   if (explicit_noise && !(a->Z_init && a->Z_W && a->Z_VX && a->Z_VU))
     return fail(h, OIC_EINVAL, "noise arrays must be all NULL or all non-NULL");
+  if (explicit_noise && h->con_on && !a->Z_VZ)
+    return fail(h, OIC_EINVAL, "a constraint is set: explicit noise needs Z_VZ too");
   if (c.mem_mode == OIC_MEM_HOST) {
     if (!finite_all(a->X0, (size_t)c.n * c.m) ||
         !finite_all(a->reference, (size_t)(H + 1) * c.n * c.m))
@@ -588,8 +616,8 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   if (rc) return rc;
 
   Dims d{c.n, c.m, c.l, N, H};
-  const int n = c.n, m = c.m, l = c.l, rr = d.rr(), p = d.p();
-  const long long NM = d.NM();
+  d.nc = h->con_on ? 1 : 0;
+  const int n = c.n, m = c.m, l = c.l;
   hipStream_t s = h->stream;
 
   // Inputs into device memory.
@@ -603,11 +631,11 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   } else {
     HIP_TRY(hipMemcpyAsync(dUp, h->Uprev, (size_t)l * m * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
-  const size_t cnt[4] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
-                         (size_t)H * N * l * m};
-  const float* zsrc[4] = {a->Z_init, a->Z_W, a->Z_VX, a->Z_VU};
+  const size_t cnt[5] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
+                         (size_t)H * N * l * m, (size_t)H * N * m};
+  const float* zsrc[5] = {a->Z_init, a->Z_W, a->Z_VX, a->Z_VU, a->Z_VZ};
   if (explicit_noise) {
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4 + d.nc; ++k)
       if ((rc = copy_in(h, h->Z[k], zsrc[k], cnt[k]))) return rc;
   } else {
     *h->hseed = a->seed;
@@ -690,7 +718,8 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
     h->own_stream = true;
   }
   for (int k = 1; k < c.n_layers; ++k) h->cmax = std::max(h->cmax, c.channels[k]);
-  const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l;
+  // observation rows: n + l, plus one if a constraint is set later
+  const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l + 1;
   const size_t NM = N * m;
   const size_t Ma_max = Hs * rr;
   int rc = OIC_OK;
@@ -713,7 +742,8 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
   rc = rc ? rc : dalloc(h, &h->flag, 1);
   rc = rc ? rc : dalloc(h, &h->amax, OIC_MAX_LAYERS);
-  for (int k = 0; k < 4 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));
+  for (int k = 0; k < 5 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));
+  rc = rc ? rc : dalloc(h, &h->con_a, n + l);
   rc = rc ? rc : dalloc(h, &h->Uprev, l * m);
   rc = rc ? rc : dalloc(h, &h->Uprev_new, l * m);
   rc = rc ? rc : dalloc(h, &h->fac, l * l + n * n);
@@ -956,7 +986,7 @@ int oic_plant_step(oic_handle h, const float* X, const float* U, float* X_next) 
 int oic_normals(oic_handle h, uint64_t seed, int kind, size_t count, float* out) {
   if (!h) return OIC_EINVAL;
   h->err.clear();
-  if (kind < 0 || kind > 3 || !out) return fail(h, OIC_EINVAL, "bad kind or NULL output");
+  if (kind < 0 || kind > 4 || !out) return fail(h, OIC_EINVAL, "bad kind or NULL output");
   if (count > noise_floats(h->cfg, kind)) return fail(h, OIC_ENOMEM, "count exceeds the noise capacity");
   *h->hseed = seed;
   HIP_TRY(hipMemcpyAsync(h->dseed, h->hseed, sizeof(uint64_t), hipMemcpyHostToDevice, h->stream));
@@ -1014,6 +1044,38 @@ int oic_stage_cost(int n, int m, int l, const float* X, const float* Xref, const
   if (!host_cholesky(Q, l, Lq) || !host_cholesky(R, n, Lr)) return OIC_EINVAL;
   *cost = quad_form_inv(Lr, n, X, Xref, m) + quad_form_inv(Lq, l, U, nullptr, m) +
           quad_form_inv(Lq, l, dU, nullptr, m);
+  return OIC_OK;
+}
+
+int oic_set_constraint(oic_handle h, const float* aX, const float* aU, float b, float alpha, float beta,
+                       float rz) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  const oic_config& c = h->cfg;
+  bool on = aX || aU;
+  if (on) {
+    if (!aX || !aU) return fail(h, OIC_EINVAL, "aX and aU must both be given (or both NULL)");
+    if (!(alpha > 0.f) || !(beta > 0.f) || !(rz > 0.f) || !std::isfinite(b) || !std::isfinite(alpha) ||
+        !std::isfinite(beta) || !std::isfinite(rz))
+      return fail(h, OIC_EINVAL, "alpha, beta and rz must be positive and finite, b finite");
+    if (!finite_all(aX, c.n) || !finite_all(aU, c.l)) return fail(h, OIC_EINVAL, "non-finite aX or aU");
+    if (c.n + c.l + 1 > 512) return fail(h, OIC_EINVAL, "n + l + 1 observation rows exceed 512");
+  }
+  std::lock_guard<std::mutex> guard(resource_mutex());
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (on) {
+    HIP_TRY(hipMemcpy(h->con_a, aX, c.n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->con_a + c.n, aU, c.l * sizeof(float), hipMemcpyHostToDevice));
+    h->con_b = b;
+    h->con_alpha = alpha;
+    h->con_beta = beta;
+    h->con_rz = rz;
+  }
+  h->con_on = on;
+  if (h->gexec) {  // the captured solve has the old observation rows and parameters
+    hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
   return OIC_OK;
 }
 

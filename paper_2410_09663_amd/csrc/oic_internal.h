@@ -73,8 +73,9 @@ struct NoiseRef {
 
 struct Dims {
   int n, m, l, N, H;
+  int nc = 0;  // barrier-observed constraint rows appended to Ybar (0 or 1)
   __host__ __device__ int rr() const { return n + l; }
-  __host__ __device__ int p() const { return n + l; }
+  __host__ __device__ int p() const { return n + l + nc; }
   __host__ __device__ long long NM() const { return (long long)N * m; }
 };
 
@@ -87,6 +88,12 @@ void launch_init_slice0(hipStream_t s, Timer& t, const Dims& d, float* traj, con
 void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int step, NoiseRef w);
 void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
                     NoiseRef vx, NoiseRef vu);
+// Row n + l of Ybar: the barrier observation z = ln(1 + exp(beta g)) / alpha + sqrt(rz) eps
+// of the per-column constraint g = aX . X_t[:, c] + aU . U_t[:, c] - b of every member
+// (slice `step` of the trajectory, before the observation noise); eps from Zvz (N x m).
+void launch_constraint_row(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
+                           const float* aX, const float* aU, float b, float alpha, float beta,
+                           float sqrt_rz, const float* Zvz);
 
 // Rollout.  Field element (i, y, x) of a strided source sits at base + i*si + y*sy + x.
 struct FieldRef {
@@ -137,6 +144,8 @@ void launch_zero_u32(hipStream_t s, Timer& t, unsigned* p, int count);
 // floats each of its two activation buffers holds.
 bool bf16_rollout_possible(const oic_config& c);
 size_t activation_floats(const oic_config& c);
+// Device bytes a handle created with c holds (the serving admission footprint).
+size_t handle_bytes(const oic_config& c);
 bool conv_mfma_supported(int cin, int cout);
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                       const float* in_nhwc, const float* wk, const float* bias, int act,

@@ -80,16 +80,7 @@ struct oic_server {
 namespace {
 
 // Device bytes oic_create allocates for cfg (mirrors its buffer list, rounded up).
-size_t footprint_bytes(const oic_config& c) {
-  const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l;
-  const size_t NM = N * m, Ma = Hs * rr;
-  size_t f = 4 * (Hs * rr * NM + p * NM + 2 * oic::activation_floats(c) + Ma * m + Ma * p);
-  f += 8 * (p * m + (Ma + p) * p + 32 * (Ma + p) * p + 2 * p * (p + 1) + 2 * p * p);
-  f += 4 * (N * l * m + (Hs - 1) * N * (2 * l + n) * m);                  // noise
-  f += 4 * (n * m + Hs * n * m + l * m + N * (2 * n + l) * m + Hs * (l + n) * m + 3 * l * m + l * l + n * n);
-  f += 64 << 10;                                                           // weights, small buffers
-  return f;
-}
+size_t footprint_bytes(const oic_config& c) { return oic::handle_bytes(c); }
 
 // Whether c's buffers are resident or can be, after evicting idle resident controllers.
 bool can_admit(const oic_server* s, const Controller& c) {

@@ -56,7 +56,8 @@ class oic_solve_args(ctypes.Structure):
                 ("R", ctypes.c_void_p), ("N", ctypes.c_int), ("horizon", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("U_prev", ctypes.c_void_p),
                 ("Z_init", ctypes.c_void_p), ("Z_W", ctypes.c_void_p), ("Z_VX", ctypes.c_void_p),
-                ("Z_VU", ctypes.c_void_p), ("U_out", ctypes.c_void_p), ("X_out", ctypes.c_void_p)]
+                ("Z_VU", ctypes.c_void_p), ("U_out", ctypes.c_void_p), ("X_out", ctypes.c_void_p),
+                ("Z_VZ", ctypes.c_void_p)]
 
 
 _lib = None
@@ -82,6 +83,8 @@ def lib():
             "oic_solve_ex": (ci, [vp, ctypes.POINTER(oic_solve_args)]),
             "oic_solve_cov": (ci, [vp, ctypes.POINTER(oic_solve_args), vp, vp]),
             "oic_columns_expand": (ci, [ci, ci, ci, vp, vp, vp]),
+            "oic_set_constraint": (ci, [vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float]),
             "oic_columns_project": (ci, [ci, ci, ci, vp, vp, vp]),
             "oic_cnn_forward": (ci, [vp, ci, vp, vp, vp]),
             "oic_plant_step": (ci, [vp, vp, vp, vp]),
@@ -117,7 +120,7 @@ def lib():
 
 
 EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
-            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_columns_expand", "oic_columns_project", "oic_cnn_forward", "oic_plant_step",
+            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_columns_expand", "oic_columns_project", "oic_set_constraint", "oic_cnn_forward", "oic_plant_step",
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
             "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
             "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
@@ -233,7 +236,7 @@ class Controller:
         return U_out, X_out
 
     def solve_ex(self, X0, reference, Q, R, N: int, H: int, seed: int = 0, U_prev=None,
-                 noise=None, want_X: bool = True):
+                 noise=None, want_X: bool = True, Z_VZ=None):
         """Solve with explicit noise (a workloads.Noise or a 4-tuple) or, if noise is None,
         the seeded stream.  Returns (U_hat, X_hat)."""
         Q = self._host(Q, (self.l, self.l))
@@ -250,6 +253,8 @@ class Controller:
             a.Z_W = self._ptr(z[1], (H, N, self.l, self.m))
             a.Z_VX = self._ptr(z[2], (H, N, self.n, self.m))
             a.Z_VU = self._ptr(z[3], (H, N, self.l, self.m))
+        if Z_VZ is not None:
+            a.Z_VZ = self._ptr(Z_VZ, (H, N, 1, self.m))
         U_out = self._new((H + 1, self.l, self.m))
         X_out = self._new((H + 1, self.n, self.m)) if want_X else None
         a.U_out = self._ptr(U_out, U_out.shape, True)
@@ -257,7 +262,8 @@ class Controller:
         self._check(lib().oic_solve_ex(self._h, ctypes.byref(a)))
         return U_out, X_out
 
-    def solve_cov(self, X0, reference, Q, R, N: int, H: int, seed: int = 0, U_prev=None, noise=None):
+    def solve_cov(self, X0, reference, Q, R, N: int, H: int, seed: int = 0, U_prev=None, noise=None,
+                  Z_VZ=None):
         """oic_solve_cov: returns (U_hat, X_hat, prior, post), where prior[t-1] and post[t-1]
         are the (t+1)(n+l) x (t+1)(n+l) pooled trajectory covariances before and after the
         analysis of horizon step t (FP64)."""
@@ -275,6 +281,8 @@ class Controller:
             a.Z_W = self._ptr(z[1], (H, N, self.l, self.m))
             a.Z_VX = self._ptr(z[2], (H, N, self.n, self.m))
             a.Z_VU = self._ptr(z[3], (H, N, self.l, self.m))
+        if Z_VZ is not None:
+            a.Z_VZ = self._ptr(Z_VZ, (H, N, 1, self.m))
         U_out = self._new((H + 1, self.l, self.m))
         X_out = self._new((H + 1, self.n, self.m))
         a.U_out = self._ptr(U_out, U_out.shape, True)
@@ -299,6 +307,16 @@ class Controller:
                 off += sz
             return out
         return U_out, X_out, split(prior), split(post)
+
+    def set_constraint(self, aX=None, aU=None, b=0.0, alpha=1.0, beta=1.0, rz=1.0):
+        """oic_set_constraint: g_c = aX . X[:, c] + aU . U[:, c] - b <= 0 observed through
+        the softplus barrier with noise variance rz; no arguments removes it."""
+        if aX is None and aU is None:
+            self._check(lib().oic_set_constraint(self._h, None, None, 0.0, 1.0, 1.0, 1.0))
+            return
+        ax = np.ascontiguousarray(aX, np.float32).reshape(self.n)
+        au = np.ascontiguousarray(aU, np.float32).reshape(self.l)
+        self._check(lib().oic_set_constraint(self._h, ax.ctypes.data, au.ctypes.data, b, alpha, beta, rz))
 
     def cnn_forward(self, X, U):
         b = X.shape[0]

@@ -304,3 +304,54 @@ def test_covariance_outputs_match_oracle(preset):
             assert got.shape == want.shape
             assert relerr(got, want) < TOL_FP32, (t, relerr(got, want))
             assert np.allclose(got, got.T, rtol=0, atol=1e-12 * np.abs(got).max())
+
+
+def _constraint(p, rng):
+    c = enks.Constraint(aX=rng.standard_normal(p.n).astype(np.float32) / p.n,
+                        aU=np.full(p.l, 1.0 / p.l, np.float32), b=float(np.float32(0.05)),
+                        alpha=float(np.float32(2.0)), beta=float(np.float32(8.0)),
+                        rz=float(np.float32(1e-3)))
+    return c
+
+
+@pytest.mark.parametrize("preset", ["tiny", "C1"])
+def test_constrained_solve_matches_oracle(preset):
+    """The barrier-observed constraint as one more row of Ybar (explicit noise), against
+    the oracle; then removing it gives the unconstrained solve again."""
+    p = tiny(N=12) if preset == "tiny" else wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    rng = np.random.default_rng(31)
+    con = _constraint(p, rng)
+    Xref = wl.reference_window(p, 0)
+    z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=13)
+    zz = rng.standard_normal((p.H, p.N, 1, p.m)).astype(np.float32)
+    Up = np.zeros((p.l, p.m), np.float32)
+    with oic.controller_for(prob) as c:
+        c.set_constraint(con.aX, con.aU, con.b, con.alpha, con.beta, con.rz)
+        U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, U_prev=Up, noise=z, Z_VZ=zz)
+        c.set_constraint()
+        U0, _ = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, U_prev=Up, noise=z)
+    ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N, p.H,
+                     z.Z_init, z.Z_W, z.Z_VX, z.Z_VU, constraint=con, Z_VZ=zz)
+    ref0 = oracle_solve(prob, Xref, (z.Z_init, z.Z_W, z.Z_VX, z.Z_VU), U_prev=Up)
+    eu, ex = relerr(U, ref.U_mean), relerr(X, ref.X_mean)
+    print(f"{preset} constrained: relerr U {eu:.2e} X {ex:.2e}", flush=True)
+    assert eu < TOL_FP32 and ex < TOL_FP32
+    assert relerr(U0, ref0.U_mean) < TOL_FP32
+    assert relerr(ref.U_mean, ref0.U_mean) > 1e-3  # the constraint did change the solve
+
+
+def test_constrained_seeded_solve_uses_noise_kind_4():
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    con = _constraint(p, np.random.default_rng(32))
+    Xref = wl.reference_window(p, 0)
+    seed = 77
+    with oic.controller_for(prob) as c:
+        c.set_constraint(con.aX, con.aU, con.b, con.alpha, con.beta, con.rz)
+        U, _ = c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, seed)
+    z = philox.solve_noise(seed, p.n, p.m, p.l, p.N, p.H)
+    zz = philox.normals(seed, 4, (p.H, p.N, 1, p.m))
+    ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N, p.H,
+                     *z, constraint=con, Z_VZ=zz)
+    assert relerr(U, ref.U_mean) < TOL_FP32
