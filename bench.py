@@ -35,12 +35,10 @@ def workload_name(p):
             f"closed-loop MPC steps")
 
 
-def algorithmic_work(p, H, precision="fp32", fused=False):
+def algorithmic_work(p, H, precision="fp32"):
     """Per kernel class: (FLOP, HBM bytes) the method needs in one solve, summed over
     the launches of that class.  FLOPs count multiply-adds as 2; bytes are the operands
-    each launch must read and write once (activations 2 B in BF16/FP8, 4 B in FP32).
-    fused: the whole network runs as one kernel (class "rollout"): only its input
-    fields and its output field move."""
+    each launch must read and write once (activations 2 B in BF16/FP8, 4 B in FP32)."""
     n, m, l, N = p.n, p.m, p.l, p.N
     rr = pp = n + l
     NM = N * m
@@ -54,15 +52,11 @@ def algorithmic_work(p, H, precision="fp32", fused=False):
     L = len(p.channels) - 1
     for t in range(1, H + 1):
         Ma = (t + 1) * rr
-        if fused:
-            f = sum(2.0 * 9 * ci * co * n * m * N for ci, co in zip(p.channels[:-1], p.channels[1:]))
-            add("rollout", f, 4.0 * N * m * (n + l) + 4.0 * N * n * m)
-        else:
-            for k, (ci, co) in enumerate(zip(p.channels[:-1], p.channels[1:])):
-                cls = "conv_first" if k == 0 else ("conv_last" if k == L - 1 else "conv_mid")
-                rd = 4.0 * (n + l) * m * N if k == 0 else ab * ci * n * m * N
-                wr = 4.0 * n * m * N if k == L - 1 else ab * co * n * m * N
-                add(cls, 2.0 * 9 * ci * co * n * m * N, rd + wr)
+        for k, (ci, co) in enumerate(zip(p.channels[:-1], p.channels[1:])):
+            cls = "conv_first" if k == 0 else ("conv_last" if k == L - 1 else "conv_mid")
+            rd = 4.0 * (n + l) * m * N if k == 0 else ab * ci * n * m * N
+            wr = 4.0 * n * m * N if k == L - 1 else ab * co * n * m * N
+            add(cls, 2.0 * 9 * ci * co * n * m * N, rd + wr)
         add("stats", 2.0 * (Ma + pp) * pp * NM, 4.0 * (Ma + pp) * NM)
         add("update", 2.0 * Ma * pp * NM, 4.0 * (2 * Ma + pp) * NM)
         add("means", float(pp) * NM, 4.0 * pp * NM)
@@ -72,9 +66,9 @@ def algorithmic_work(p, H, precision="fp32", fused=False):
     return work
 
 
-MATRIX_CLASSES = ("conv_mid", "rollout", "stats", "gain", "update")
+MATRIX_CLASSES = ("conv_first", "conv_mid", "stats", "gain", "update")
 SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last": "rollout.hip",
-             "rollout": "rollout.hip", "stats": "stats.hip", "stats_reduce": "stats.hip",
+             "stats": "stats.hip", "stats_reduce": "stats.hip",
              "means": "stats.hip", "chol": "gain.hip", "gain": "gain.hip", "update": "update.hip",
              "noise": "noise.hip", "assemble": "noise.hip", "observe": "noise.hip", "init": "noise.hip"}
 
@@ -83,7 +77,7 @@ def roofline_for(cls, flops, nbytes, ms, launches, precision):
     sec = ms * 1e-3
     if cls in ("stats", "gain", "chol"):
         fpeak = PEAK["fp64"]
-    elif cls.startswith("conv") or cls == "rollout":
+    elif cls.startswith("conv"):
         fpeak = {"bf16": PEAK["bf16"], "fp8": PEAK["fp8"]}.get(precision, PEAK["fp32"])
     else:
         fpeak = PEAK["fp32"]
@@ -343,7 +337,7 @@ def main():
     stats = ctrl.kernel_stats()
     ctrl.timing(False)
 
-    work = algorithmic_work(p, p.H, args.precision, fused="rollout" in stats and stats["rollout"][0] > 0)
+    work = algorithmic_work(p, p.H, args.precision)
     per_class = {}
     for cls, (cnt, ms) in stats.items():
         if cnt == 0:

@@ -29,7 +29,7 @@ namespace oic {
 
 const char* const kKernelClassNames[KC_COUNT] = {
     "noise", "init", "lift", "conv_first", "conv_mid", "conv_last", "assemble", "observe",
-    "means", "stats", "stats_reduce", "chol", "gain", "update", "extract", "rollout"};
+    "means", "stats", "stats_reduce", "chol", "gain", "update", "extract"};
 
 void Timer::reset() {
   cursor = 0;
@@ -415,11 +415,6 @@ void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
     }
     launch_conv_last(h->stream, h->timer, batch, c.n, c.m, c.channels[L - 1], h->act[cur],
                      h->dW[L - 1], h->dBias[L - 1], out, true);
-    return;
-  }
-  if (rollout3_supported(L, c.channels, c.l) && h->dWk[1]) {
-    launch_rollout3(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, h->dW[0], h->dBias[0],
-                    h->dWk[1], h->dBias[1], h->dW[2], h->dBias[2], c.activation, out);
     return;
   }
   int cur = 0;

@@ -38,7 +38,6 @@ enum KernelClass {
   KC_GAIN,
   KC_UPDATE,
   KC_EXTRACT,
-  KC_ROLLOUT,  // a whole network in one kernel
   KC_COUNT
 };
 
@@ -124,12 +123,6 @@ bool conv_mfma_bf16_supported(int cin, int cout);
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                            const void* in_nhwc, const void* wt, const float* bias, int act,
                            void* out_nhwc);
-// The 2 -> 16 -> 16 -> 1 FP32 network in one kernel (hidden activations stay in LDS);
-// l <= 16.  w2k is the [tap*16 + c][o] layout of the hidden layer.
-bool rollout3_supported(int n_layers, const int* ch, int l);
-void launch_rollout3(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
-                     const float* B, const float* w1, const float* b1, const float* w2k, const float* b2,
-                     const float* w3, const float* b3, int act, FieldOut fo);
 // FP8 hidden layer: BF16 NHWC in and out, input scale from *amax_in (largest |x| of the
 // input layer), weights wq [cout][K padded to 128] e4m3 with per-channel scales ws;
 // folds the largest |output| into *amax_out.

@@ -804,209 +804,6 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
   amax_publish(vmax, amax_out);
 }
 
-// The whole 2 -> C -> C -> 1 network in one kernel (FP32), so that neither hidden
-// activation touches HBM.  A block owns TR x 64 output pixels of one member and
-// stages the (TR+6) x 70 input region (X, and B U formed in LDS from the staged U rows
-// and B rows); layer 1 (matrix cores, K = 2 x 9) fills the (TR+4) x 68 region around
-// the tile, layer 2
-// (v_mfma_f32_16x16x4_f32, implicit GEMM over the flattened (TR+2) x 66 region, 16
-// pixels per M-block) the (TR+2) x 66 region, and layer 3 (VALU) the tile itself,
-// written straight to the strided output field.  Cells of the intermediate regions
-// that fall outside the field are zero: they are the next layer's zero padding.
-// Weights: w1 [C][2][3][3], w2k [tap*C + c][o], w3 [1][C][3][3].
-template <int C>
-__global__ __launch_bounds__(512) void k_rollout3_f32(int N, int n, int m, int l, FieldRef X, FieldRef U,
-                                                      const float* __restrict__ B,
-                                                      const float* __restrict__ w1,
-                                                      const float* __restrict__ b1,
-                                                      const float* __restrict__ w2k,
-                                                      const float* __restrict__ b2,
-                                                      const float* __restrict__ w3,
-                                                      const float* __restrict__ b3, int act, FieldOut fo) {
-  static_assert(C == 16, "one 16-wide N-block in layer 2");
-  constexpr int NT = 512, TR = 8, TC = 64, LMX = 16;
-  constexpr int R0 = TR + 6, C0 = TC + 6;  // input region, origin (y0-3, x0-3)
-  constexpr int R1 = TR + 4, C1 = TC + 4;  // layer-1 region, origin (y0-2, x0-2)
-  constexpr int R2 = TR + 2, C2 = TC + 2;  // layer-2 region, origin (y0-1, x0-1)
-  constexpr int CP = C + 1;
-  constexpr int NQ2 = R2 * C2;             // layer-2 pixels
-  constexpr int MB2 = (NQ2 + 15) / 16;     // their 16-pixel M-blocks
-  __shared__ float s_x[R0 * C0];
-  __shared__ float s_bu[R0 * C0];
-  __shared__ float s_u[LMX * C0];
-  __shared__ float s_b[R0 * LMX];
-  __shared__ float s_w1[20 * C];           // [k = ch*9 + tap, zero-padded to 20][o]
-  __shared__ __attribute__((aligned(16))) float s_w2[9 * C * C];
-  __shared__ __attribute__((aligned(16))) float s_l1[R1 * C1 * CP];
-  __shared__ __attribute__((aligned(16))) float s_l2[NQ2 * CP];
-  const int col_tiles = (m + TC - 1) / TC;
-  const int row_tiles = (n + TR - 1) / TR;
-  int bid = blockIdx.x;
-  const int ct = bid % col_tiles;
-  bid /= col_tiles;
-  const int rt = bid % row_tiles;
-  const int i = bid / row_tiles;
-  const int y0 = rt * TR, x0 = ct * TC;
-  const int tid = threadIdx.x;
-  {
-    constexpr int XS = (R0 * C0 + NT - 1) / NT;
-    constexpr int US = (LMX * C0 + NT - 1) / NT;
-    constexpr int W2S = (9 * C * C / 4 + NT - 1) / NT;
-    float xv[XS], uv[US], bv;
-    f32x4 wv[W2S];
-#pragma unroll
-    for (int u = 0; u < XS; ++u) {
-      const int e = tid + NT * u;
-      const int yy = e / C0, xx = e % C0;
-      const int gy = y0 + yy - 3, gx = x0 + xx - 3;
-      xv[u] = (e < R0 * C0 && gy >= 0 && gy < n && gx >= 0 && gx < m) ? X.base[i * X.si + gy * X.sy + gx]
-                                                                       : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < US; ++u) {
-      const int e = tid + NT * u;
-      const int a = e / C0, xx = e % C0;
-      const int gx = x0 + xx - 3;
-      uv[u] = (a < l && gx >= 0 && gx < m) ? U.base[i * U.si + a * U.sy + gx] : 0.f;
-    }
-    {
-      const int yy = tid / LMX, a = tid % LMX;
-      const int gy = y0 + yy - 3;
-      bv = (yy < R0 && a < l && gy >= 0 && gy < n) ? B[(size_t)gy * l + a] : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < W2S; ++u) {
-      const int e = tid + NT * u;
-      wv[u] = e < 9 * C * C / 4 ? *(const f32x4*)(w2k + 4 * e) : f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int e = tid; e < 20 * C; e += NT) {
-      const int k = e / C, o = e % C;
-      s_w1[e] = k < 18 ? w1[o * 18 + k] : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < XS; ++u)
-      if (tid + NT * u < R0 * C0) s_x[tid + NT * u] = xv[u];
-#pragma unroll
-    for (int u = 0; u < US; ++u)
-      if (tid + NT * u < LMX * C0) s_u[tid + NT * u] = uv[u];
-    if (tid < R0 * LMX) s_b[tid] = bv;
-#pragma unroll
-    for (int u = 0; u < W2S; ++u)
-      if (tid + NT * u < 9 * C * C / 4) *(f32x4*)(s_w2 + 4 * (tid + NT * u)) = wv[u];
-  }
-  __syncthreads();
-  // lift: the B U channel over the input region (zero outside the field, as U is)
-  for (int e = tid; e < R0 * C0; e += NT) {
-    const int yy = e / C0, xx = e % C0;
-    float bu = 0.f;
-    for (int a = 0; a < l; ++a) bu = fmaf(s_b[yy * LMX + a], s_u[a * C0 + xx], bu);
-    s_bu[e] = bu;
-  }
-  __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  constexpr int NW = NT / 64;
-  // layer 1 on the matrix cores: the (TR+4) x 68 region flattened into 16-pixel
-  // M-blocks, K = (channel, tap) = 18 padded to 20 with zero weights
-  {
-    constexpr int NQ1 = R1 * C1;
-    constexpr int MB1 = (NQ1 + 15) / 16;
-    constexpr int MPW1 = (MB1 + NW - 1) / NW;
-    f32x4 acc[MPW1];
-    int base[MPW1];  // input-region offset of this lane's pixel (tap (0,0))
-#pragma unroll
-    for (int j = 0; j < MPW1; ++j) {
-      acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-      int q = (w + NW * j) * 16 + li;
-      q = q < NQ1 ? q : NQ1 - 1;
-      base[j] = (q / C1) * C0 + q % C1;
-    }
-#pragma unroll
-    for (int kb = 0; kb < 5; ++kb) {
-      const int k = kb * 4 + lk;
-      const int kk = k < 18 ? k : 0;  // past 18 the weights are zero
-      const float* src = kk < 9 ? s_x : s_bu;
-      const int tap = kk % 9;
-      const int off = (tap / 3) * C0 + tap % 3;
-      const float b = s_w1[k * C + li];
-#pragma unroll
-      for (int j = 0; j < MPW1; ++j)
-        if (w + NW * j < MB1) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(src[base[j] + off], b, acc[j], 0, 0, 0);
-    }
-    const float bo = b1 ? b1[li] : 0.f;
-#pragma unroll
-    for (int j = 0; j < MPW1; ++j) {
-      if (w + NW * j >= MB1) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = (w + NW * j) * 16 + 4 * lk + r;
-        if (q < NQ1) {
-          const int gy = y0 - 2 + q / C1, gx = x0 - 2 + q % C1;
-          const bool in = gy >= 0 && gy < n && gx >= 0 && gx < m;
-          s_l1[q * CP + li] = in ? activate(acc[j][r] + bo, act) : 0.f;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // layer 2 on the matrix cores: wave w takes M-blocks w, w + 8, ... together
-  {
-    constexpr int MPW = (MB2 + NW - 1) / NW;
-    f32x4 acc[MPW];
-    int base[MPW];  // LDS offset of this lane's A pixel (tap (0,0)) in each M-block
-#pragma unroll
-    for (int j = 0; j < MPW; ++j) {
-      acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-      int q = (w + NW * j) * 16 + li;
-      q = q < NQ2 ? q : NQ2 - 1;  // padding lanes of the last M-block read a valid pixel
-      base[j] = ((q / C2) * C1 + q % C2) * CP;
-    }
-#pragma unroll 4
-    for (int kb = 0; kb < 9 * C / 4; ++kb) {
-      const int k = kb * 4 + lk;
-      const int tap = k / C, c = k - tap * C;
-      const int off = ((tap / 3) * C1 + tap % 3) * CP + c;
-      const float b = s_w2[k * C + li];
-#pragma unroll
-      for (int j = 0; j < MPW; ++j)
-        if (w + NW * j < MB2)
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_l1[base[j] + off], b, acc[j], 0, 0, 0);
-    }
-    const float bo = b2 ? b2[li] : 0.f;
-#pragma unroll
-    for (int j = 0; j < MPW; ++j) {
-      if (w + NW * j >= MB2) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = (w + NW * j) * 16 + 4 * lk + r;
-        if (q < NQ2) {
-          const int gy = y0 - 1 + q / C2, gx = x0 - 1 + q % C2;
-          const bool in = gy >= 0 && gy < n && gx >= 0 && gx < m;
-          s_l2[q * CP + li] = in ? activate(acc[j][r] + bo, act) : 0.f;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // layer 3: one output pixel per thread, no activation after the last layer
-  {
-    const int r3 = tid / TC, c3 = tid % TC;
-    const int gy = y0 + r3, gx = x0 + c3;
-    if (gy < n && gx < m) {
-      // the weights are the same for every lane: read straight from memory (uniform
-      // loads), leaving the LDS to the activations
-      float acc = b3 ? b3[0] : 0.f;
-#pragma unroll
-      for (int tap = 0; tap < 9; ++tap) {
-        const float* src = s_l2 + ((r3 + tap / 3) * C2 + c3 + tap % 3) * CP;
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc = fmaf(w3[c * 9 + tap], src[c], acc);
-      }
-      fo.base[i * fo.si + gy * fo.sy + gx] = acc;
-    }
-  }
-}
-
 }  // namespace
 
 bool conv_first_supported(int cout, int l) {
@@ -1080,18 +877,6 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
   OIC_BF_CASE(32, 64)
   OIC_BF_CASE(64, 32)
 #undef OIC_BF_CASE
-}
-
-bool rollout3_supported(int n_layers, const int* ch, int l) {
-  return n_layers == 3 && ch[1] == 16 && ch[2] == 16 && l <= 16;
-}
-
-void launch_rollout3(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
-                     const float* B, const float* w1, const float* b1, const float* w2k, const float* b2,
-                     const float* w3, const float* b3, int act, FieldOut fo) {
-  const unsigned blocks = (unsigned)((long long)N * ((n + 7) / 8) * ((m + 63) / 64));
-  OIC_LAUNCH(t, KC_ROLLOUT, s, k_rollout3_f32<16>, dim3(blocks), dim3(512), 0, N, n, m, l, X, U, B, w1,
-             b1, w2k, b2, w3, b3, act, fo);
 }
 
 bool conv_mfma_fp8_supported(int cin, int cout) {

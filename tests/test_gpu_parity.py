@@ -54,14 +54,14 @@ def test_device_normals_match_oracle(kind, count):
 
 
 @pytest.mark.parametrize("preset", ["C1", "C2", "tiny", "tiny_gelu", "wide", "deep_a", "deep_b",
-                                    "fused3", "fused3_l16"])
+                                    "c16_ragged", "c16_l16"])
 def test_cnn_forward_matches_oracle(preset):
     if preset == "tiny":
         p = tiny()
-    elif preset == "fused3":
-        # 2-16-16-1 runs as one fused kernel; ragged row (13 = 8 + 5) and column (70) tiles
+    elif preset == "c16_ragged":
+        # 2-16-16-1 with ragged row (13) and column (70 = 64 + 6) tiles
         p = wl.small_preset(n=13, m=70, l=5, channels=(2, 16, 16, 1), activation=wl.ACT_GELU, N=3)
-    elif preset == "fused3_l16":
+    elif preset == "c16_l16":
         p = wl.small_preset(n=17, m=20, l=16, channels=(2, 16, 16, 1), N=4)
     elif preset == "deep_a":
         # hidden pairs (64,64), (64,32), (32,16), (16,64): channel-chunked MFMA layers;
