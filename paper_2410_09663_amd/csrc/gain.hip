@@ -102,59 +102,63 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
     W[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int pb = 0; pb < npan; ++pb) {
+  // Factor the pb-th 8 x 8 diagonal block (wave 0 only; every update it receives is done).
+  auto factor_diag = [&](int pb) {
     const int kb = pb * NBK;
     const int nb = min(NBK, p - kb);
-    if (wave == 0) {
-      // Every lane factors the whole 8 x 8 diagonal block in its own registers (no
-      // cross-lane traffic; identity rows pad a short last panel), keeping the
-      // reciprocal square roots for the block inverse.
-      double a[NBK][NBK], rs[NBK];
+    // Every lane factors the whole 8 x 8 diagonal block in its own registers (no
+    // cross-lane traffic; identity rows pad a short last panel), keeping the
+    // reciprocal square roots for the block inverse.
+    double a[NBK][NBK], rs[NBK];
 #pragma unroll
-      for (int r = 0; r < NBK; ++r)
+    for (int r = 0; r < NBK; ++r)
 #pragma unroll
-        for (int c = 0; c < NBK; ++c)
-          a[r][c] = c > r ? 0.0 : ((r < nb) ? A[(kb + r) * ld + kb + c] : (r == c ? 1.0 : 0.0));
-      bool ok = true;
+      for (int c = 0; c < NBK; ++c)
+        a[r][c] = c > r ? 0.0 : ((r < nb) ? A[(kb + r) * ld + kb + c] : (r == c ? 1.0 : 0.0));
+    bool ok = true;
 #pragma unroll
-      for (int k = 0; k < NBK; ++k) {
-        const double d = a[k][k];
-        if (!(d > 0.0 && isfinite(d))) ok = false;
-        rs[k] = (d > 0.0 && isfinite(d)) ? rsqrt_nr(d) : 1.0;
-        a[k][k] = d * rs[k];
+    for (int k = 0; k < NBK; ++k) {
+      const double d = a[k][k];
+      if (!(d > 0.0 && isfinite(d))) ok = false;
+      rs[k] = (d > 0.0 && isfinite(d)) ? rsqrt_nr(d) : 1.0;
+      a[k][k] = d * rs[k];
 #pragma unroll
-        for (int r = k + 1; r < NBK; ++r) a[r][k] *= rs[k];
+      for (int r = k + 1; r < NBK; ++r) a[r][k] *= rs[k];
 #pragma unroll
-        for (int c = k + 1; c < NBK; ++c)
+      for (int c = k + 1; c < NBK; ++c)
 #pragma unroll
-          for (int r = c; r < NBK; ++r) a[r][c] -= a[r][k] * a[c][k];
-      }
-      // lane c < 8 forms column c of L11^{-1}: x_r = (delta_rc - sum_{q<r} L_rq x_q) / L_rr
-      if (lane < NBK) {
-        double x[NBK];
-#pragma unroll
-        for (int r = 0; r < NBK; ++r) {
-          double v = (r == lane) ? 1.0 : 0.0;
-#pragma unroll
-          for (int q = 0; q < r; ++q) v -= a[r][q] * x[q];
-          x[r] = v * rs[r];
-        }
-#pragma unroll
-        for (int r = 0; r < NBK; ++r) sLinv[pb][r][lane] = (r >= lane) ? x[r] : 0.0;
-        if (lane < nb) {
-#pragma unroll
-          for (int c = 0; c < NBK; ++c) {
-            double v = 0.0;
-#pragma unroll
-            for (int r = 0; r < NBK; ++r) v = (r == lane) ? a[r][c] : v;  // row `lane`, static indices
-            if (c <= lane) A[(kb + lane) * ld + kb + c] = v;
-          }
-        }
-      }
-      if (lane == 0 && !ok) bad = 1;
+        for (int r = c; r < NBK; ++r) a[r][c] -= a[r][k] * a[c][k];
     }
-    __syncthreads();
+    // lane c < 8 forms column c of L11^{-1}: x_r = (delta_rc - sum_{q<r} L_rq x_q) / L_rr
+    if (lane < NBK) {
+      double x[NBK];
+#pragma unroll
+      for (int r = 0; r < NBK; ++r) {
+        double v = (r == lane) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < r; ++q) v -= a[r][q] * x[q];
+        x[r] = v * rs[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NBK; ++r) sLinv[pb][r][lane] = (r >= lane) ? x[r] : 0.0;
+      if (lane < nb) {
+#pragma unroll
+        for (int c = 0; c < NBK; ++c) {
+          double v = 0.0;
+#pragma unroll
+          for (int r = 0; r < NBK; ++r) v = (r == lane) ? a[r][c] : v;  // row `lane`, static indices
+          if (c <= lane) A[(kb + lane) * ld + kb + c] = v;
+        }
+      }
+    }
+    if (lane == 0 && !ok) bad = 1;
+  };
+  if (wave == 0) factor_diag(0);
+  __syncthreads();
+  for (int pb = 0; pb < npan; ++pb) {
     if (bad) break;  // uniform
+    const int kb = pb * NBK;
+    const int nb = min(NBK, p - kb);
     const int r0 = kb + nb, rem = p - r0;
     // rows below: L21 = A21 L11^{-T}
     for (int i = r0 + tid; i < p; i += kCholThreads) {
@@ -190,20 +194,14 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
     }
     __syncthreads();
     // trailing lower triangle: A22 -= L21 L21^T, and W rows below: B[i][j] -= L21[i] W[kb:, j]
-    // (i >= cols, j < cols), all as 16 x 16 tiles on the matrix cores
+    // (i >= cols, j < cols), as 16 x 16 tiles on the matrix cores.  Look-ahead: wave 0
+    // takes the tile holding the next diagonal block first and then factors that block,
+    // while the other waves update the remaining tiles.
     if (rem > 0) {
       const int nt = (rem + 15) / 16;
       const int ntri = nt * (nt + 1) / 2;
       const int ntj = (cols + 15) / 16;
-      for (int t = wave + ntri; t < ntri + nt * ntj; t += NW) {
-        const int u = t - ntri;
-        const int ti = u / ntj, tj = u - ti * ntj;
-        mfma_tile_update(
-            W, ld, p, cols, cols + 16 * ti, 16 * tj, nb,
-            [&](int i, int k) { return i < p ? A[i * ld + kb + k] : 0.0; },
-            [&](int k, int j) { return j < cols ? W[(kb + k) * ld + j] : 0.0; }, -1.0);
-      }
-      for (int t = wave; t < ntri; t += NW) {
+      auto a22_tile = [&](int t) {
         int ti = 0;
         while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
         const int tj = t - ti * (ti + 1) / 2;
@@ -211,6 +209,23 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
             A, ld, p, p, r0 + 16 * ti, r0 + 16 * tj, NBK,
             [&](int i, int k) { return i < p ? A[i * ld + kb + k] : 0.0; },
             [&](int k, int j) { return j < p ? A[j * ld + kb + k] : 0.0; }, -1.0);
+      };
+      if (wave == 0) {
+        a22_tile(0);
+        factor_diag(pb + 1);
+      } else {
+        for (int t = wave; t < ntri + nt * ntj; t += NW - 1) {
+          if (t < ntri) {
+            a22_tile(t);
+          } else {
+            const int u = t - ntri;
+            const int ti = u / ntj, tj = u - ti * ntj;
+            mfma_tile_update(
+                W, ld, p, cols, cols + 16 * ti, 16 * tj, nb,
+                [&](int i, int k) { return i < p ? A[i * ld + kb + k] : 0.0; },
+                [&](int k, int j) { return j < cols ? W[(kb + k) * ld + j] : 0.0; }, -1.0);
+          }
+        }
       }
     }
     __syncthreads();
