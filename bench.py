@@ -73,7 +73,7 @@ SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last"
              "noise": "noise.hip", "assemble": "noise.hip", "observe": "noise.hip", "init": "noise.hip"}
 
 
-def roofline_for(cls, flops, nbytes, ms, launches, precision):
+def roofline_for(cls, flops, nbytes, ms, launches, precision, tag=None):
     sec = ms * 1e-3
     if cls in ("stats", "gain", "chol"):
         fpeak = PEAK["fp64"]
@@ -83,7 +83,7 @@ def roofline_for(cls, flops, nbytes, ms, launches, precision):
         fpeak = PEAK["fp32"]
     t_f = flops / fpeak
     t_b = nbytes / PEAK["hbm"]
-    common = {"traffic": measured_traffic(cls, launches), "kernel_class": cls, "launches": launches,
+    common = {"traffic": measured_traffic(cls, tag), "kernel_class": cls, "launches": launches,
               "avg_launch_us": 1e3 * ms / max(launches, 1),
               "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
               "algorithmic_flop_per_launch": flops / max(launches, 1)}
@@ -97,10 +97,11 @@ def roofline_for(cls, flops, nbytes, ms, launches, precision):
                  "frac": ach / (fpeak / 1e12)}, **common)
 
 
-def measured_traffic(cls, launches):
+def measured_traffic(cls, tag):
     """HBM bytes per launch of the class from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes (each scaled by what the counter reads for a plain device copy of
-    known size), or None when there are none or the kernel source changed since."""
+    WRITE_SIZE passes of the same workload (each scaled by what the counter reads for a
+    plain device copy of known size), or None when there are none, they were taken on
+    another workload, or the kernel source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -108,7 +109,7 @@ def measured_traffic(cls, launches):
             rec = json.load(f).get(cls)
     except (OSError, ValueError):
         return None
-    if not rec:
+    if not rec or rec.get("workload") != tag:
         return None
     src = os.path.join(ROOT, "paper_2410_09663_amd", "csrc", SOURCE_OF.get(cls, ""))
     try:
@@ -346,7 +347,8 @@ def main():
         per_class[cls] = {"launches": cnt, "total_ms": ms, "flop": f * K, "bytes": b * K}
     dom = max(per_class, key=lambda c: per_class[c]["total_ms"])
     d = per_class[dom]
-    roof = roofline_for(dom, d["flop"], d["bytes"], d["total_ms"], d["launches"], args.precision)
+    roof = roofline_for(dom, d["flop"], d["bytes"], d["total_ms"], d["launches"], args.precision,
+                        f"{args.workload}_{args.precision}")
     roof["measured"] = ("HIP events around each launch on the library stream, over the same "
                         "number of steps launched kernel by kernel right after the timed region")
 
