@@ -112,7 +112,6 @@ struct oic_ctx {
   double* Sinv = nullptr;  // (Sigma^Y)^{-1}
   hipStream_t side = nullptr;            // the gain solve overlaps Sigma^{XY} on this stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipEvent_t ev_lag_fork = nullptr, ev_lag_done = nullptr;  // the lagged-slice analysis runs there too
   double* part = nullptr;   // split-K partial sums of the statistics
   size_t part_cap = 0;      // its size in doubles
   double* Lwork = nullptr;
@@ -313,8 +312,6 @@ void free_all(oic_ctx* h) {
   f(h->Sinv);
   if (h->ev_fork) hipEventDestroy(h->ev_fork);
   if (h->ev_join) hipEventDestroy(h->ev_join);
-  if (h->ev_lag_fork) hipEventDestroy(h->ev_lag_fork);
-  if (h->ev_lag_done) hipEventDestroy(h->ev_lag_done);
   if (h->side) hipStreamDestroy(h->side);
   f(h->part);
   f(h->Lwork);
@@ -539,9 +536,6 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
   if (seeded)
     for (int k = 0; k < 4 + d.nc; ++k) launch_normals(s, h->timer, h->Z[k], cnt[k], h->dseed, (uint32_t)k);
   const float* const* Zd = h->Z;
-  // With the covariance outputs every slice must be analysed before the next step's
-  // forecast covariance, so the lagged slices are then analysed in line.
-  const bool split = !h->want_cov;
   // Line 4: initial ensemble (also clears the failure flag).
   launch_init_slice0(s, h->timer, d, h->traj, dX0, dUp, noise_ref(h, Zd[0], true), h->flag);
   for (int t = 1; t <= H; ++t) {
@@ -555,9 +549,7 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
                       noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true));
     // Line 8 / Eqs. (15d)-(15f): covariance of the forecast trajectory (optional)
     if (h->want_cov) enqueue_cov(h, d, (t + 1) * rr, h->cov_prior + cov_offset(rr, t));
-    // Line 9 / Eq. (12); the previous step's lagged-slice analysis (side stream) reads
-    // Ybar until it is done.
-    if (split && t > 1) hipStreamWaitEvent(s, h->ev_lag_done, 0);
+    // Line 9 / Eq. (12).
     launch_observe(s, h->timer, d, h->traj, t, h->Y,
                    noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
                    noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true));
@@ -578,25 +570,12 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     hipEventRecord(h->ev_join, h->side);
     launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S);
     hipStreamWaitEvent(s, h->ev_join, 0);
-    // Eq. (14b): gain, then line 10: analysis of every stored slice.  Only the newest
-    // slice (the last rr rows) feeds the next rollout: it is analysed here, and the
-    // lagged slices on the side stream, overlapping the next step's rollout.
-    const int a0 = split ? Ma - rr : 0;
-    launch_gain(s, h->timer, p, Ma - a0, h->S + (size_t)a0 * p, h->Sinv, h->Syy, h->Lwork,
-                h->K + (size_t)a0 * p, h->flag);
-    launch_update(s, h->timer, d, h->traj + (size_t)a0 * NM, Ma - a0, h->K + (size_t)a0 * p, h->Y,
-                  dRef + (size_t)t * n * m);
-    if (split) {
-      hipEventRecord(h->ev_lag_fork, s);
-      hipStreamWaitEvent(h->side, h->ev_lag_fork, 0);
-      launch_gain(h->side, h->timer, p, a0, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
-      launch_update(h->side, h->timer, d, h->traj, a0, h->K, h->Y, dRef + (size_t)t * n * m);
-      hipEventRecord(h->ev_lag_done, h->side);
-    }
+    // Eq. (14b): gain, then line 10: analysis of every stored slice.
+    launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
+    launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m);
     // Line 11 / Eq. (14c): covariance after the analysis (optional)
     if (h->want_cov) enqueue_cov(h, d, Ma, h->cov_post + cov_offset(rr, t));
   }
-  if (split) hipStreamWaitEvent(s, h->ev_lag_done, 0);
   // Line 13: smoothed means of every slice.
   launch_means(s, h->timer, h->traj, (H + 1) * rr, N, m, h->mu_traj);
   float* sU = h->out_stage;
@@ -753,9 +732,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   rc = rc ? rc : dalloc(h, &h->Sinv, p * p);
   if (!rc && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) rc = OIC_EDEVICE;
   if (!rc && (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&h->ev_lag_fork, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&h->ev_lag_done, hipEventDisableTiming) != hipSuccess))
+              hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess))
     rc = OIC_EDEVICE;
   rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
   rc = rc ? rc : dalloc(h, &h->flag, 1);

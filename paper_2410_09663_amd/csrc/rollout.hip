@@ -544,8 +544,12 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
   constexpr int KDP = KD32 + 8;
   constexpr int NB = COUT / 16;
   constexpr int RPW = TR / 4;
-  __shared__ __attribute__((aligned(16))) bf16_t s_in[HR * HC * CP];
-  __shared__ __attribute__((aligned(16))) bf16_t s_w[COUT * KDP];
+  // halo tile and weights, and after the MFMA loop the output tile, share one buffer
+  constexpr int OP = COUT + 8;
+  constexpr int LDS_IN = HR * HC * CP + COUT * KDP, LDS_OUT = TR * 64 * OP;
+  __shared__ __attribute__((aligned(16))) bf16_t s_buf[LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT];
+  bf16_t* const s_in = s_buf;
+  bf16_t* const s_w = s_buf + HR * HC * CP;
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
   int bid = blockIdx.x;
@@ -630,10 +634,14 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
       }
     }
   }
+  // Epilogue through LDS: every lane writes its activated outputs into the tile
+  // [pixel][channel] (BF16, rows padded by 8), then the tile leaves as 16-byte rows of
+  // 8 channels, so the NHWC stores are full vector stores instead of 2-byte ones.
+  __syncthreads();  // every wave is done with the halo tile and the weights
+  bf16_t* const s_out = s_buf;
 #pragma unroll
   for (int rw = 0; rw < RPW; ++rw) {
-    const int y = y0 + w + 4 * rw;
-    if (y >= n) continue;
+    const int ty = w + 4 * rw;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
@@ -642,11 +650,18 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
         const float bo = bias ? bias[o] : 0.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int x = x0 + mb * 16 + 4 * lk + r;
-          if (x < m)
-            out[(((size_t)i * n + y) * m + x) * COUT + o] = to_bf16(activate(acc[rw][mb][nb][r] + bo, act));
+          const int tx = mb * 16 + 4 * lk + r;
+          s_out[(ty * TC + tx) * OP + o] = to_bf16(activate(acc[rw][mb][nb][r] + bo, act));
         }
       }
+  }
+  __syncthreads();
+  constexpr int QV = COUT / 8;  // 16-byte vectors per pixel
+  for (int e = tid; e < TR * TC * QV; e += 256) {
+    const int px = e / QV, q = e - px * QV;
+    const int y = y0 + px / TC, x = x0 + px % TC;
+    if (y < n && x < m)
+      *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
   }
 }
 
@@ -680,8 +695,13 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
   constexpr int KDP = KD128 + 16;
   constexpr int NB = COUT / 16;
   constexpr int RPW = TR / 4;
-  __shared__ __attribute__((aligned(16))) uint8_t s_in[HR * HC * CP];
-  __shared__ __attribute__((aligned(16))) uint8_t s_w[COUT * KDP];
+  // halo tile and weights (bytes), and after the MFMA loop the BF16 output tile, share
+  // one buffer
+  constexpr int OP = COUT + 8;
+  constexpr int LDS_IN = HR * HC * CP + COUT * KDP, LDS_OUT = TR * 64 * OP * 2;
+  __shared__ __attribute__((aligned(16))) uint8_t s_buf[LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT];
+  uint8_t* const s_in = s_buf;
+  uint8_t* const s_w = s_buf + HR * HC * CP;
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
   int bid = blockIdx.x;
@@ -779,10 +799,15 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
       }
     }
   }
+  // Epilogue through LDS, as in the BF16 kernel: activated outputs into the BF16 tile
+  // [pixel][channel], then 16-byte NHWC stores; the largest |output| of the valid pixels
+  // goes to amax_out.
+  __syncthreads();  // every wave is done with the halo tile and the weights
+  bf16_t* const s_out = reinterpret_cast<bf16_t*>(s_buf);
   float vmax = 0.f;
 #pragma unroll
   for (int rw = 0; rw < RPW; ++rw) {
-    const int y = y0 + w + 4 * rw;
+    const int ty = w + 4 * rw;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
@@ -792,14 +817,20 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
         const float bo = bias ? bias[o] : 0.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int x = x0 + mb * 16 + 4 * lk + r;
-          if (y < n && x < m) {
-            const float v = activate(fmaf(acc[rw][mb][nb][r], sc, bo), act);
-            out[(((size_t)i * n + y) * m + x) * COUT + o] = to_bf16(v);
-            vmax = fmaxf(vmax, fabsf(v));
-          }
+          const int tx = mb * 16 + 4 * lk + r;
+          const float v = activate(fmaf(acc[rw][mb][nb][r], sc, bo), act);
+          s_out[(ty * TC + tx) * OP + o] = to_bf16(v);
+          if (y0 + ty < n && x0 + tx < m) vmax = fmaxf(vmax, fabsf(v));
         }
       }
+  }
+  __syncthreads();
+  constexpr int QV = COUT / 8;
+  for (int e = tid; e < TR * TC * QV; e += 256) {
+    const int px = e / QV, q = e - px * QV;
+    const int y = y0 + px / TC, x = x0 + px % TC;
+    if (y < n && x < m)
+      *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
   }
   amax_publish(vmax, amax_out);
 }
