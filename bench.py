@@ -251,6 +251,7 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch each solve kernel by kernel")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     # serving workload (--workload C5)
     ap.add_argument("--controllers", type=int, default=200)
@@ -293,6 +294,8 @@ def main():
     refs = torch.from_numpy(np.stack([wl.reference_window(p, k) for k in range(W + 2 * K + 1)])).to(dev)
     stream = torch.cuda.current_stream().cuda_stream
     ctrl = oic.controller_for(prob, precision=prec, mem_mode=oic.OIC_MEM_DEVICE, stream=stream)
+    if args.no_graph:
+        ctrl.set_graph(False)
     X0 = torch.from_numpy(prob.X0).to(dev)
     Ubufs = torch.empty((W + 2 * K, p.H + 1, p.l, p.m), dtype=torch.float32, device=dev)
     Xbuf = torch.empty((p.H + 1, p.n, p.m), dtype=torch.float32, device=dev)
@@ -307,7 +310,8 @@ def main():
     for k in range(W):
         X = step(k, X)
     torch.cuda.synchronize()
-    # Timed region: K closed-loop steps, each solve replayed from its captured graph.
+    # Timed region: K closed-loop steps, each solve replayed from its captured graph (or
+    # launched kernel by kernel with --no-graph).
     lat = []
     states = [X]
     t0 = time.perf_counter()
