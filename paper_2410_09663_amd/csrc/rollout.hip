@@ -341,6 +341,129 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32(int N, int n, int m,
   }
 }
 
+// The same layer for CIN <= 32 (one channel chunk) as a persistent kernel: a block
+// keeps the weights in LDS and walks over tiles tile, tile + gridDim.x, ...; the next
+// tile's halo is loaded into registers while the current one is on the matrix cores,
+// so the global-load latency of a tile hides behind the previous tile's MFMAs.
+template <int CIN, int COUT, int TR>
+__global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
+                                                        const float* __restrict__ in,
+                                                        const float* __restrict__ wk,
+                                                        const float* __restrict__ bias, int act,
+                                                        float* __restrict__ out) {
+  constexpr int TC = 64;
+  constexpr int HR = TR + 2, HC = TC + 2;
+  constexpr int CP = CIN + 1;
+  constexpr int KD = 9 * CIN;
+  constexpr int NB = COUT / 16;
+  constexpr int RPW = TR / 4;
+  constexpr int Q = CIN / 4;
+  constexpr int TOTAL = HR * HC * Q;
+  constexpr int SLOTS = (TOTAL + 255) / 256;
+  __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
+  __shared__ __attribute__((aligned(16))) float s_w[KD * COUT];
+  const int col_tiles = (m + TC - 1) / TC;
+  const int row_tiles = (n + TR - 1) / TR;
+  const int tiles = N * row_tiles * col_tiles;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  {
+    constexpr int WV = KD * COUT / 4;
+    constexpr int WS = (WV + 255) / 256;
+#pragma unroll
+    for (int u = 0; u < WS; ++u) {
+      const int e = tid + 256 * u;
+      if (e < WV) *(f32x4*)(s_w + 4 * e) = *(const f32x4*)(wk + 4 * e);
+    }
+  }
+  f32x4 v[SLOTS];
+  auto load_halo = [&](int tile) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int e = tid + u * 256;
+      v[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (e < TOTAL) {
+        const int q = e % Q, pix = e / Q;
+        const int xx = pix % HC, yy = pix / HC;
+        const int gy = y0 + yy - 1, gx = x0 + xx - 1;
+        if (gy >= 0 && gy < n && gx >= 0 && gx < m)
+          v[u] = *(const f32x4*)(in + (((size_t)i * n + gy) * m + gx) * CIN + 4 * q);
+      }
+    }
+  };
+  int tile = blockIdx.x;
+  if (tile < tiles) load_halo(tile);
+  for (; tile < tiles; tile += gridDim.x) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+    __syncthreads();  // the previous tile's MFMAs are done with s_in (and s_w is staged)
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int e = tid + u * 256;
+      if (e < TOTAL) {
+        const int q = e % Q, pix = e / Q;
+        float* dst = s_in + pix * CP + 4 * q;
+        dst[0] = v[u][0];
+        dst[1] = v[u][1];
+        dst[2] = v[u][2];
+        dst[3] = v[u][3];
+      }
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < tiles) load_halo(tile + gridDim.x);  // in flight meanwhile
+    f32x4 acc[RPW][4][NB];
+#pragma unroll
+    for (int rw = 0; rw < RPW; ++rw)
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kb = 0; kb < KD / 4; ++kb) {
+      const int k = kb * 4 + lk;
+      const int tap = k / CIN, c = k - tap * CIN;
+      const int dy = tap / 3, dx = tap - dy * 3;
+      float b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[nb] = s_w[k * COUT + nb * 16 + li];
+#pragma unroll
+      for (int rw = 0; rw < RPW; ++rw) {
+        const int ry = w + 4 * rw;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const float a = s_in[((ry + dy) * HC + mb * 16 + li + dx) * CP + c];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[rw][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[rw][mb][nb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int rw = 0; rw < RPW; ++rw) {
+      const int y = y0 + w + 4 * rw;
+      if (y >= n) continue;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int o = nb * 16 + li;
+          const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int x = x0 + mb * 16 + 4 * lk + r;
+            if (x < m)
+              out[(((size_t)i * n + y) * m + x) * COUT + o] = activate(acc[rw][mb][nb][r] + bo, act);
+          }
+        }
+    }
+  }
+}
+
 // First layer with the lift fused: the block stages the 6 x 66 halo of X, the l rows
 // of U over the same columns and the 6 rows of B in LDS (all loads issued before the
 // stores), forms B U per halo cell from LDS, computes 4 x 64 output pixels x COUT
@@ -949,9 +1072,15 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
   if (cin == CI && cout == CO) {                                                                \
     constexpr int TRV = (CI <= 16 && CO <= 32) ? 8 : 4;                                         \
     constexpr int CCH = CI <= 32 ? CI : 32;                                                     \
-    const unsigned blocks = (unsigned)((long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64)); \
-    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32<CI, CO, TRV, CCH>), dim3(blocks), dim3(256), 0, N, n, \
-               m, in_nhwc, wk, bias, act, out_nhwc);                                            \
+    const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
+    if constexpr (CCH == CI) {  /* persistent: about two workgroups per CU */                   \
+      const unsigned blocks = (unsigned)(tiles < 512 ? tiles : 512);                            \
+      OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32p<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, \
+                 m, in_nhwc, wk, bias, act, out_nhwc);                                          \
+    } else {                                                                                    \
+      OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32<CI, CO, TRV, CCH>), dim3((unsigned)tiles), dim3(256), \
+                 0, N, n, m, in_nhwc, wk, bias, act, out_nhwc);                                 \
+    }                                                                                           \
     return;                                                                                     \
   }
   OIC_CONV_CASE(16, 16)
