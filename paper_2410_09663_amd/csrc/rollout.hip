@@ -667,34 +667,45 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
   constexpr int KDP = KD32 + 8;
   constexpr int NB = COUT / 16;
   constexpr int RPW = TR / 4;
-  // halo tile and weights, and after the MFMA loop the output tile, share one buffer
   constexpr int OP = COUT + 8;
-  constexpr int LDS_IN = HR * HC * CP + COUT * KDP, LDS_OUT = TR * 64 * OP;
-  __shared__ __attribute__((aligned(16))) bf16_t s_buf[LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT];
-  bf16_t* const s_in = s_buf;
-  bf16_t* const s_w = s_buf + HR * HC * CP;
+  constexpr int IQ = CIN / 8;
+  constexpr int IV = HR * HC * IQ;
+  constexpr int IS = (IV + 255) / 256;
+  // the weights stay resident; the halo tile and, after the MFMA loop, the output tile
+  // share the rest
+  constexpr int TILE = HR * HC * CP > TR * TC * OP ? HR * HC * CP : TR * TC * OP;
+  __shared__ __attribute__((aligned(16))) bf16_t s_w[COUT * KDP];
+  __shared__ __attribute__((aligned(16))) bf16_t s_tile[TILE];
+  bf16_t* const s_in = s_tile;
+  bf16_t* const s_out = s_tile;
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
-  int bid = blockIdx.x;
-  const int ct = bid % col_tiles;
-  bid /= col_tiles;
-  const int rt = bid % row_tiles;
-  const int i = bid / row_tiles;
-  const int y0 = rt * TR, x0 = ct * TC;
+  const int tiles = N * row_tiles * col_tiles;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   {
-    constexpr int WQ = KD / 8;              // 16-byte vectors per weight row
+    constexpr int WQ = KD / 8;  // 16-byte vectors per weight row
     constexpr int WV = COUT * WQ;
     constexpr int WS = (WV + 255) / 256;
-    constexpr int IQ = CIN / 8;
-    constexpr int IV = HR * HC * IQ;
-    constexpr int IS = (IV + 255) / 256;
-    u16x8 wv[WS], iv[IS];
 #pragma unroll
     for (int u = 0; u < WS; ++u) {
       const int e = tid + 256 * u;
-      wv[u] = e < WV ? *(const u16x8*)(wt + (size_t)8 * e) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (e < WV) *(u16x8*)(s_w + (e / WQ) * KDP + 8 * (e % WQ)) = *(const u16x8*)(wt + (size_t)8 * e);
     }
+    if (KD32 > KD) {  // zero the K padding of every weight row
+      constexpr int PQ = (KD32 - KD) / 8;
+      for (int e = tid; e < COUT * PQ; e += 256)
+        *(u16x8*)(s_w + (e / PQ) * KDP + KD + 8 * (e % PQ)) = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+  }
+  // Persistent over tiles tile, tile + gridDim.x, ...: the next tile's halo is loaded
+  // into registers while the current one is on the matrix cores.
+  u16x8 iv[IS];
+  auto load_halo = [&](int tile) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
       const int e = tid + 256 * u;
@@ -707,84 +718,80 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
           iv[u] = *(const u16x8*)(in + (((size_t)i * n + gy) * m + gx) * CIN + 8 * q);
       }
     }
-#pragma unroll
-    for (int u = 0; u < WS; ++u) {
-      const int e = tid + 256 * u;
-      if (e < WV) *(u16x8*)(s_w + (e / WQ) * KDP + 8 * (e % WQ)) = wv[u];
-    }
-    if (KD32 > KD) {  // zero the K padding of every weight row
-      constexpr int PQ = (KD32 - KD) / 8;
-      for (int e = tid; e < COUT * PQ; e += 256)
-        *(u16x8*)(s_w + (e / PQ) * KDP + KD + 8 * (e % PQ)) = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    }
+  };
+  int tile = blockIdx.x;
+  if (tile < tiles) load_halo(tile);
+  for (; tile < tiles; tile += gridDim.x) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+    __syncthreads();  // the previous tile's output has left s_tile (and s_w is staged)
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
       const int e = tid + 256 * u;
       if (e < IV) *(u16x8*)(s_in + (e / IQ) * CP + 8 * (e % IQ)) = iv[u];
     }
-  }
-  __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  f32x4 acc[RPW][4][NB];
+    __syncthreads();
+    if (tile + (int)gridDim.x < tiles) load_halo(tile + gridDim.x);  // in flight meanwhile
+    f32x4 acc[RPW][4][NB];
 #pragma unroll
-  for (int rw = 0; rw < RPW; ++rw)
+    for (int rw = 0; rw < RPW; ++rw)
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+      for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 3
-  for (int kb = 0; kb < KD32 / 32; ++kb) {
-    const int k0 = kb * 32 + 8 * lk;
-    // past KD the weights are zero; read any in-tile (finite) activations there
-    const int kk = k0 < KD ? k0 : 0;
-    const int tap = kk / CIN, c0 = kk - tap * CIN;
-    const int dy = tap / 3, dx = tap - dy * 3;
-    bf16x8_t b[NB];
+    for (int kb = 0; kb < KD32 / 32; ++kb) {
+      const int k0 = kb * 32 + 8 * lk;
+      // past KD the weights are zero; read any in-tile (finite) activations there
+      const int kk = k0 < KD ? k0 : 0;
+      const int tap = kk / CIN, c0 = kk - tap * CIN;
+      const int dy = tap / 3, dx = tap - dy * 3;
+      bf16x8_t b[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      b[nb] = __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_w + (nb * 16 + li) * KDP + k0));
+      for (int nb = 0; nb < NB; ++nb)
+        b[nb] = __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_w + (nb * 16 + li) * KDP + k0));
 #pragma unroll
-    for (int rw = 0; rw < RPW; ++rw) {
-      const int ry = w + 4 * rw;
+      for (int rw = 0; rw < RPW; ++rw) {
+        const int ry = w + 4 * rw;
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const bf16x8_t a = __builtin_bit_cast(
-            bf16x8_t, *(const u16x8*)(s_in + ((ry + dy) * HC + mb * 16 + li + dx) * CP + c0));
+        for (int mb = 0; mb < 4; ++mb) {
+          const bf16x8_t a = __builtin_bit_cast(
+              bf16x8_t, *(const u16x8*)(s_in + ((ry + dy) * HC + mb * 16 + li + dx) * CP + c0));
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[rw][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[rw][mb][nb], 0, 0, 0);
-      }
-    }
-  }
-  // Epilogue through LDS: every lane writes its activated outputs into the tile
-  // [pixel][channel] (BF16, rows padded by 8), then the tile leaves as 16-byte rows of
-  // 8 channels, so the NHWC stores are full vector stores instead of 2-byte ones.
-  __syncthreads();  // every wave is done with the halo tile and the weights
-  bf16_t* const s_out = s_buf;
-#pragma unroll
-  for (int rw = 0; rw < RPW; ++rw) {
-    const int ty = w + 4 * rw;
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int o = nb * 16 + li;
-        const float bo = bias ? bias[o] : 0.f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int tx = mb * 16 + 4 * lk + r;
-          s_out[(ty * TC + tx) * OP + o] = to_bf16(activate(acc[rw][mb][nb][r] + bo, act));
+          for (int nb = 0; nb < NB; ++nb)
+            acc[rw][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[rw][mb][nb], 0, 0, 0);
         }
       }
-  }
-  __syncthreads();
-  constexpr int QV = COUT / 8;  // 16-byte vectors per pixel
-  for (int e = tid; e < TR * TC * QV; e += 256) {
-    const int px = e / QV, q = e - px * QV;
-    const int y = y0 + px / TC, x = x0 + px % TC;
-    if (y < n && x < m)
-      *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+    }
+    // Epilogue through LDS: every lane writes its activated outputs into the tile
+    // [pixel][channel] (BF16, rows padded by 8), then the tile leaves as 16-byte rows
+    // of 8 channels, so the NHWC stores are full vector stores instead of 2-byte ones.
+    __syncthreads();  // every wave is done with the halo tile
+#pragma unroll
+    for (int rw = 0; rw < RPW; ++rw) {
+      const int ty = w + 4 * rw;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int o = nb * 16 + li;
+          const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int tx = mb * 16 + 4 * lk + r;
+            s_out[(ty * TC + tx) * OP + o] = to_bf16(activate(acc[rw][mb][nb][r] + bo, act));
+          }
+        }
+    }
+    __syncthreads();
+    constexpr int QV = COUT / 8;  // 16-byte vectors per pixel
+    for (int e = tid; e < TR * TC * QV; e += 256) {
+      const int px = e / QV, q = e - px * QV;
+      const int y = y0 + px / TC, x = x0 + px % TC;
+      if (y < n && x < m)
+        *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+    }
   }
 }
 
@@ -1018,7 +1025,8 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
 #define OIC_BF_CASE(CI, CO)                                                                      \
   if (cin == CI && cout == CO) {                                                                 \
     constexpr int TRV = CI <= 32 ? 8 : 4;                                                        \
-    const unsigned blocks = (unsigned)((long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64));  \
+    const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
+    const unsigned blocks = (unsigned)(tiles < 512 ? tiles : 512); /* persistent */             \
     OIC_LAUNCH(t, kclass, s, (k_conv_mfma_bf16<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, m, \
                (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out_nhwc);         \
     return;                                                                                      \
