@@ -107,9 +107,9 @@ def test_bf16_closed_loop_tracking_cost_within_2pct(preset, steps):
 # reach the 2e-2 / 2% bars that BF16 meets.  These tests pin the FP8 path to the error
 # bands it does reach (regression guards), each with the measured value beside it.
 
-TOL_FP8_ROLLOUT = 9e-2   # three FP8 layers, white-noise inputs: measured 6.0e-2 .. 7.3e-2
-TOL_FP8_U = 3.5e-2       # smoothed control mean, 40x40 solve: measured 2.5e-2
-TOL_FP8_COST = 6e-2      # closed-loop tracking cost, 10 steps: measured 3.7e-2 .. 3.9e-2
+TOL_FP8_ROLLOUT = 9e-2   # three FP8 layers, white-noise inputs: measured 6.5e-2 .. 7.5e-2
+TOL_FP8_U = 3.5e-2       # smoothed control mean, 40x40 solve: measured 2.6e-2
+TOL_FP8_COST = 6e-2      # closed-loop tracking cost, 10 steps: measured 3.7e-2
 
 
 def fp8_preset(n=40, l=10, channels=(2, 32, 32, 32, 1), N=64, H=5):
@@ -167,7 +167,8 @@ def test_full_size_256_precisions_tracking_cost():
     """256x256 field, 5-layer 64-channel GELU CNN, N = 512, H = 20: BF16 and FP8 against
     the FP32 GPU path on the closed-loop tracking cost (3 steps) and on the first
     solve's smoothed control mean (the FP64 oracle takes minutes per solve here).
-    Measured: BF16 U 1.0e-2, cost 1.4e-3; FP8 U 1.7e-1 (above the 2e-2 bar), cost 1.5e-2."""
+    Measured: BF16 U 1.0e-2, cost 1.4e-3; FP8 U 1.7e-1 (above the 2e-2 bar), cost 1.5e-2
+    (within the 2% bar)."""
     p = dataclasses.replace(wl.PRESETS["C4"], closed_loop_steps=3)
     prob = wl.make_problem(p)
     costs, first = {}, {}
@@ -186,7 +187,7 @@ def test_full_size_256_precisions_tracking_cost():
         costs[prec] = ocost.closed_loop_cost(np.stack(Xs), np.stack(Us), np.zeros((p.l, p.m)), Xrefs,
                                              prob.R.astype(np.float64), prob.Q.astype(np.float64))
     j32 = costs[oic.OIC_PREC_FP32]
-    bars = {oic.OIC_PREC_BF16: ("bf16", TOL_BF16, 0.02), oic.OIC_PREC_FP8: ("fp8", 0.25, 0.03)}
+    bars = {oic.OIC_PREC_BF16: ("bf16", TOL_BF16, 0.02), oic.OIC_PREC_FP8: ("fp8", 0.25, 0.02)}
     for prec, (name, tol_u, tol_cost) in bars.items():
         eu = relerr(first[prec], first[oic.OIC_PREC_FP32])
         rel = abs(costs[prec] - j32) / j32
