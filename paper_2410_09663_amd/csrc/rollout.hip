@@ -1078,11 +1078,14 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
                       float* out_nhwc) {
 #define OIC_CONV_CASE(CI, CO)                                                                   \
   if (cin == CI && cout == CO) {                                                                \
-    constexpr int TRV = (CI <= 16 && CO <= 32) ? 8 : 4;                                         \
+    constexpr int TRV = (CI <= 16 && CO <= 32 && CO != CI) ? 8 : 4;                             \
     constexpr int CCH = CI <= 32 ? CI : 32;                                                     \
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
-    if constexpr (CCH == CI) {  /* persistent: about two workgroups per CU */                   \
-      const unsigned blocks = (unsigned)(tiles < 512 ? tiles : 512);                            \
+    if constexpr (CCH == CI) {  /* persistent: as many workgroups as the CUs' LDS holds */      \
+      constexpr int lds = 4 * ((TRV + 2) * 66 * (CI + 1) + 9 * CI * CO);                         \
+      constexpr int per_cu = 160 * 1024 / lds < 4 ? 160 * 1024 / lds : 4;                        \
+      constexpr long long cap = 256LL * (per_cu > 0 ? per_cu : 1);                               \
+      const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                            \
       OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32p<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, \
                  m, in_nhwc, wk, bias, act, out_nhwc);                                          \
     } else {                                                                                    \
