@@ -98,6 +98,91 @@ __global__ __launch_bounds__(256) void k_update_mfma(Dims d, float* __restrict__
     }
 }
 
+// The same update for p <= PB as a persistent kernel over row tiles: block (x, y) owns
+// columns 64x .. 64x + 63 and row tiles y, y + gridDim.y, ...  The innovation tile is
+// formed in LDS once per block; the gain rows and the trajectory values of the next row
+// tile are loaded into registers while the current tile is on the matrix cores.
+__global__ __launch_bounds__(256) void k_update_rows(Dims d, float* __restrict__ traj, int Ma,
+                                                     const float* __restrict__ K,
+                                                     const float* __restrict__ Y,
+                                                     const float* __restrict__ xref) {
+  __shared__ float sK[UR][PB + 1];
+  __shared__ float sE[PB][UC + 1];
+  const int NM = (int)d.NM();
+  const int m = d.m, n = d.n, p = d.p();
+  const int c0 = blockIdx.x * UC;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row_tiles = (Ma + UR - 1) / UR;
+  constexpr int KS = UR * PB / 256;  // 20 gain values per thread
+  constexpr int ES = PB * UC / 256;  // 20 innovation values per thread
+#pragma unroll
+  for (int u = 0; u < ES; ++u) {
+    const int e = tid + 256 * u;
+    const int b = e / UC, cl = e % UC;
+    const int c = c0 + cl;
+    float v = 0.f;
+    if (b < p && c < NM) {
+      const float ybar = b < n ? xref[(size_t)b * m + c % m] : 0.f;
+      v = ybar - Y[(size_t)b * NM + c];
+    }
+    sE[b][cl] = v;
+  }
+  float kv[KS], old[4][4];
+  auto load_rows = [&](int rt) {
+    const int r0 = rt * UR;
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int e = tid + 256 * u;
+      const int rl = e / PB, b = e % PB;
+      const int a = r0 + rl;
+      kv[u] = (a < Ma && b < p) ? K[(size_t)a * p + b] : 0.f;
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = r0 + w * 16 + 4 * lk + r, c = c0 + nb * 16 + li;
+        old[nb][r] = (a < Ma && c < NM) ? traj[(size_t)a * NM + c] : 0.f;
+      }
+  };
+  int rt = blockIdx.y;
+  if (rt < row_tiles) load_rows(rt);
+  for (; rt < row_tiles; rt += gridDim.y) {
+    const int r0 = rt * UR;
+    __syncthreads();  // the previous tile's products are done with sK (and sE is complete)
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int e = tid + 256 * u;
+      sK[e / PB][e % PB] = kv[u];
+    }
+    float cur[4][4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cur[nb][r] = old[nb][r];
+    __syncthreads();
+    if (rt + (int)gridDim.y < row_tiles) load_rows(rt + gridDim.y);  // in flight meanwhile
+    f32x4u acc[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4u{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < p; ks += 4) {
+      const float av = sK[w * 16 + li][ks + lk];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sE[ks + lk][nb * 16 + li], acc[nb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = r0 + w * 16 + 4 * lk + r, c = c0 + nb * 16 + li;
+        if (a < Ma && c < NM) traj[(size_t)a * NM + c] = cur[nb][r] + acc[nb][r];
+      }
+  }
+}
+
 // Smoothed means of every slice -> U_out (H+1, l, m), X_out (H+1, n, m) and U_hat_k.
 __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restrict__ Uout,
                           float* __restrict__ Xout, float* __restrict__ Uprev) {
@@ -122,8 +207,18 @@ __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restric
 
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
                    const float* Y, const float* xref_t) {
-  const dim3 grid((unsigned)((d.NM() + UC - 1) / UC), (unsigned)((Ma + UR - 1) / UR));
-  OIC_LAUNCH(t, KC_UPDATE, s, k_update_mfma, grid, dim3(256), 0, d, traj, Ma, K, Y, xref_t);
+  const unsigned col_tiles = (unsigned)((d.NM() + UC - 1) / UC);
+  const unsigned row_tiles = (unsigned)((Ma + UR - 1) / UR);
+  if (d.p() <= PB) {
+    // about two workgroups per CU (the register budget allows two) on 256 CUs
+    const unsigned want = (512 + col_tiles - 1) / col_tiles;
+    const unsigned groups = row_tiles < want ? row_tiles : want;
+    OIC_LAUNCH(t, KC_UPDATE, s, k_update_rows, dim3(col_tiles, groups), dim3(256), 0, d, traj, Ma, K, Y,
+               xref_t);
+    return;
+  }
+  OIC_LAUNCH(t, KC_UPDATE, s, k_update_mfma, dim3(col_tiles, row_tiles), dim3(256), 0, d, traj, Ma, K, Y,
+             xref_t);
 }
 
 void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,
