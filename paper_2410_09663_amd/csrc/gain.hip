@@ -273,7 +273,21 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const doub
                                                                double* __restrict__ Sinv,
                                                                int* __restrict__ flag) {
   extern __shared__ double lds[];
-  for (int idx = threadIdx.x; idx < p * p; idx += kCholThreads) lds[(idx / p) * (p + 1) + idx % p] = Syy[idx];
+  {
+    // every load of Sigma^Y in flight at once (p * p <= kLoadSlots * kCholThreads), then into LDS
+    constexpr int kLoadSlots = (kLdsMaxP * kLdsMaxP + kCholThreads - 1) / kCholThreads;
+    double v[kLoadSlots];
+#pragma unroll
+    for (int u = 0; u < kLoadSlots; ++u) {
+      const int idx = threadIdx.x + kCholThreads * u;
+      v[u] = idx < p * p ? Syy[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadSlots; ++u) {
+      const int idx = threadIdx.x + kCholThreads * u;
+      if (idx < p * p) lds[(idx / p) * (p + 1) + idx % p] = v[u];
+    }
+  }
   __syncthreads();
   chol_inverse<kMaxPanelsLds, true>(p, lds, lds + p * (p + 1), Sinv, flag);
 }
@@ -306,9 +320,21 @@ __global__ __launch_bounds__(256) void k_gain_mfma(int p, int Ma, const double* 
   constexpr int P16 = NB * 16;
   __shared__ double sS[P16 * (P16 + 1)];
   if (*flag) return;
-  for (int e = threadIdx.x; e < P16 * P16; e += 256) {
-    const int r = e / P16, c = e % P16;
-    sS[r * (P16 + 1) + c] = (r < p && c < p) ? Sinv[r * p + c] : 0.0;
+  {
+    // every load of the inverse in flight at once, then into LDS
+    constexpr int SV = P16 * P16 / 256;
+    double v[SV];
+#pragma unroll
+    for (int u = 0; u < SV; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int r = e / P16, c = e % P16;
+      v[u] = (r < p && c < p) ? Sinv[r * p + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SV; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      sS[(e / P16) * (P16 + 1) + e % P16] = v[u];
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

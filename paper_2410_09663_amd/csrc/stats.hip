@@ -252,21 +252,37 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
     }
 }
 
-__global__ void k_stats_reduce(const double* __restrict__ part, int splits, long long count,
-                               double scale, double* __restrict__ S) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
+// S[idx] = scale * sum_z part[z][idx].  Block (64, RG): lane x owns output idx, and the
+// RG threads of a column sum interleaved subsets of the splits (z = y, y + RG, ...), which
+// are then added in the order y = 0, 1, ..., RG - 1: a fixed order, so the result is
+// the same on every run.
+constexpr int RG = 8;
+__global__ __launch_bounds__(64 * RG) void k_stats_reduce(const double* __restrict__ part, int splits,
+                                                          long long count, double scale,
+                                                          double* __restrict__ S) {
+  __shared__ double sub[RG][64];
+  const long long idx = (long long)blockIdx.x * 64 + threadIdx.x;
+  const int y = threadIdx.y;
   double s = 0.0;
-  int z = 0;
-  for (; z + 8 <= splits; z += 8) {  // 8 loads in flight, summed in order
-    double v[8];
+  if (idx < count) {
+    int z = y;
+    for (; z + 3 * RG < splits; z += 4 * RG) {  // four loads in flight, summed in order
+      double v[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(z + u) * count + idx];
+      for (int u = 0; u < 4; ++u) v[u] = part[(size_t)(z + u * RG) * count + idx];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+      for (int u = 0; u < 4; ++u) s += v[u];
+    }
+    for (; z < splits; z += RG) s += part[(size_t)z * count + idx];
   }
-  for (; z < splits; ++z) s += part[(size_t)z * count + idx];
-  S[idx] = scale * s;
+  sub[y][threadIdx.x] = s;
+  __syncthreads();
+  if (y == 0 && idx < count) {
+    double tot = sub[0][threadIdx.x];
+#pragma unroll
+    for (int g = 1; g < RG; ++g) tot += sub[g][threadIdx.x];
+    S[idx] = scale * tot;
+  }
 }
 
 }  // namespace
@@ -343,8 +359,8 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   }
 #undef OIC_STATS_CASE
   const long long count = (long long)Mtot * p;
-  OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256),
-             0, part, splits, count, scale, S);
+  OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 63) / 64)), dim3(64, RG), 0,
+             part, splits, count, scale, S);
 }
 
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
