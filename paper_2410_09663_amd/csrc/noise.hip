@@ -3,6 +3,7 @@
 //  - the initial ensemble (Algorithm 1, line 4);
 //  - the control part of the forecast, U_t = U_{t-1} + W_t (Eq. (4), Eq. (15b));
 //  - the perturbed virtual observations Ybar^i = H Xbar^i + Vbar^i (Eq. (12)).
+#include "noise_value.h"
 #include "oic_internal.h"
 
 namespace oic {
@@ -53,16 +54,6 @@ __global__ void k_normals(float* __restrict__ out, size_t count, const uint64_t*
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
     out[e] = philox_normal(seed, kind, e);
-}
-
-// Row factor times the normals: (L Z^i)[a][x] for member i, or diag[a] Z^i[a][x].
-__device__ __forceinline__ float noise_value(const NoiseRef& nr, int a, int i, int x, int m) {
-  const float* z = nr.Z + ((size_t)i * nr.rows) * m + x;
-  if (nr.diag) return nr.diag[a] * z[(size_t)a * m];
-  float acc = 0.f;
-  const float* Lrow = nr.L + (size_t)a * nr.rows;
-  for (int b = 0; b <= a; ++b) acc = fmaf(Lrow[b], z[(size_t)b * m], acc);
-  return acc;
 }
 
 // Slice k of every member: X rows = X_k (no spread), U rows = U_prev + W_0^i.  Also

@@ -392,7 +392,10 @@ RolloutMode rollout_mode(oic_ctx* h) {
 
 // Runs the CNN of Eq. (1) on `batch` fields given as strided sources, writing the
 // single output channel to `out`, in the given mode (the plant step always uses FP32).
-void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode) {
+// With `obs`, the first and last layers also write the side outputs it names when both
+// layers run as the tiled kernels; returns whether they did.
+bool rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode,
+             const ObserveArgs* obs = nullptr) {
   const oic_config& c = h->cfg;
   const int L = c.n_layers;
   if (mode != RM_FP32) {
@@ -400,7 +403,7 @@ void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
     // per-layer activation maxima: slot k holds the largest |x| written by layer k
     if (f8) launch_zero_u32(h->stream, h->timer, h->amax, L);
     launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
-                      h->dBias[0], c.activation, h->act[1], true, f8 ? h->amax : nullptr);
+                      h->dBias[0], c.activation, h->act[1], true, f8 ? h->amax : nullptr, obs);
     int cur = 1;
     for (int k = 1; k < L - 1; ++k) {
       if (f8)
@@ -414,15 +417,18 @@ void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
       cur = 1 - cur;
     }
     launch_conv_last(h->stream, h->timer, batch, c.n, c.m, c.channels[L - 1], h->act[cur],
-                     h->dW[L - 1], h->dBias[L - 1], out, true);
-    return;
+                     h->dW[L - 1], h->dBias[L - 1], out, true, obs);
+    return obs != nullptr;
   }
+  // side outputs only when both the first and the last layer are the tiled kernels
+  const bool tiled = L > 1 && conv_first_supported(c.channels[1], c.l) && conv_last_supported(c.channels[L - 1]);
+  const ObserveArgs* o = tiled ? obs : nullptr;
   int cur = 0;
   int k0 = 0;
   if (L > 1 && conv_first_supported(c.channels[1], c.l)) {
     // lift fused into the first layer
     launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
-                      h->dBias[0], c.activation, h->act[1], false);
+                      h->dBias[0], c.activation, h->act[1], false, nullptr, o);
     cur = 1;
     k0 = 1;
   } else {
@@ -434,7 +440,7 @@ void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
     const int cls = k == 0 ? KC_CONV_FIRST : (last ? KC_CONV_LAST : KC_CONV_MID);
     if (last && k > 0 && conv_last_supported(cin)) {
       launch_conv_last(h->stream, h->timer, batch, c.n, c.m, cin, h->act[cur], h->dW[k], h->dBias[k],
-                       out, false);
+                       out, false, o);
       continue;
     }
     if (!last && h->dWk[k]) {
@@ -448,6 +454,7 @@ void rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
                 h->dBias[k], c.activation, last ? nullptr : h->act[1 - cur], fo);
     cur = 1 - cur;
   }
+  return o != nullptr;
 }
 
 // OCP FP8 e4m3: bias 7, no infinities, largest finite 448.  The finite non-negative
@@ -548,16 +555,19 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     float* prev = h->traj + (size_t)(t - 1) * slice;
     float* cur = h->traj + (size_t)t * slice;
     // Line 6 / Eq. (15b): X rows of slice t through the CNN, from the analysed slice t-1.
-    rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
-            FieldOut{cur, m, NM}, rollout_mode(h));
-    launch_assemble_u(s, h->timer, d, h->traj, t,
-                      noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true));
+    // Eq. (4) for the U rows of slice t and line 9 / Eq. (12) ride along with the rollout's
+    // first and last layers where those are the tiled kernels.
+    const ObserveArgs oa{cur + (size_t)n * NM, h->Y, NM, noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true),
+                         noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
+                         noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true)};
+    const bool observed = rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
+                                  FieldOut{cur, m, NM}, rollout_mode(h), &oa);
+    if (!observed) {
+      launch_assemble_u(s, h->timer, d, h->traj, t, oa.w);
+      launch_observe(s, h->timer, d, h->traj, t, h->Y, oa.vx, oa.vu);
+    }
     // Line 8 / Eqs. (15d)-(15f): covariance of the forecast trajectory (optional)
     if (h->want_cov) enqueue_cov(h, d, (t + 1) * rr, h->cov_prior + cov_offset(rr, t));
-    // Line 9 / Eq. (12).
-    launch_observe(s, h->timer, d, h->traj, t, h->Y,
-                   noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
-                   noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true));
     // the barrier observation of the constraint, if one is set (actual value 0)
     if (d.nc)
       launch_constraint_row(s, h->timer, d, h->traj, t, h->Y, h->con_a, h->con_a + n, h->con_b, h->con_alpha,

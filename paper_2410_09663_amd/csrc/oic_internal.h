@@ -95,6 +95,17 @@ void launch_constraint_row(hipStream_t s, Timer& t, const Dims& d, const float* 
                            float sqrt_rz, const float* Zvz);
 
 // Rollout.  Field element (i, y, x) of a strided source sits at base + i*si + y*sy + x.
+// Side outputs of a solve's rollout (null pointers: none).  The first layer, which
+// reads U_{t-1}, also writes the U rows of the new slice, U_t = U_{t-1} + W_t (Eq. (4)),
+// and their observation rows of Ybar; the last layer writes the X rows of Ybar next to
+// the new states (Eq. (12)).  U_cur and Y are row-major with row stride NM, member i's
+// columns at i*m ..
+struct ObserveArgs {
+  float* U_cur;
+  float* Y;
+  long long NM;
+  NoiseRef w, vx, vu;
+};
 struct FieldRef {
   const float* base;
   long long si, sy;
@@ -115,9 +126,11 @@ bool conv_last_supported(int cin);
 // bf16: activations are stored as BF16 (first layer output, last layer input).
 void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
                        const float* B, int cout, const float* w, const float* bias, int act,
-                       void* out_nhwc, bool bf16, unsigned* amax = nullptr);
+                       void* out_nhwc, bool bf16, unsigned* amax = nullptr,
+                       const ObserveArgs* obs = nullptr);
 void launch_conv_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
-                      const float* w, const float* bias, FieldOut fo, bool bf16);
+                      const float* w, const float* bias, FieldOut fo, bool bf16,
+                      const ObserveArgs* obs = nullptr);
 // Hidden layers in BF16 on MFMA.  wt holds BF16 weights as [cout][tap*cin + c].
 bool conv_mfma_bf16_supported(int cin, int cout);
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,

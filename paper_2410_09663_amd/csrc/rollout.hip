@@ -6,6 +6,7 @@
 // builds the two input channels straight from the trajectory buffer; the last
 // layer writes its single channel straight back into the trajectory (or any
 // strided field), so no extra pass touches the next state.
+#include "noise_value.h"
 #include "oic_internal.h"
 
 namespace oic {
@@ -474,7 +475,8 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
                                                     FieldRef U, const float* __restrict__ B,
                                                     const float* __restrict__ w,
                                                     const float* __restrict__ bias, int act,
-                                                    TOUT* __restrict__ out, unsigned* __restrict__ amax) {
+                                                    TOUT* __restrict__ out, unsigned* __restrict__ amax,
+                                                    ObserveArgs obs) {
   constexpr int TR = 4, TC = 64, HR = TR + 2, HC = TC + 2;
   constexpr int LMAX = 64;
   __shared__ float s_x[HR * HC];
@@ -520,11 +522,19 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
       const int gy = y0 + yy - 1;
       bv[u] = (yy < HR && a < l && gy >= 0 && gy < n) ? B[(size_t)gy * l + a] : 0.f;
     }
-    for (int e = tid; e < 20 * COUT; e += 256) {
+    constexpr int WS = (20 * COUT + 255) / 256;
+    float wv[WS];
+#pragma unroll
+    for (int u = 0; u < WS; ++u) {
+      const int e = tid + 256 * u;
       const int kk = e / COUT, o = e % COUT;
-      s_w[e] = kk < 18 ? w[o * 18 + kk] : 0.f;
+      wv[u] = (e < 20 * COUT && kk < 18) ? w[o * 18 + kk] : 0.f;
     }
-    if (tid < COUT) s_bias[tid] = bias ? bias[tid] : 0.f;
+    const float bias_v = (tid < COUT && bias) ? bias[tid] : 0.f;
+#pragma unroll
+    for (int u = 0; u < WS; ++u)
+      if (tid + 256 * u < 20 * COUT) s_w[tid + 256 * u] = wv[u];
+    if (tid < COUT) s_bias[tid] = bias_v;
 #pragma unroll
     for (int u = 0; u < XS; ++u)
       if (tid + 256 * u < HR * HC) s_x[tid + 256 * u] = xv[u];
@@ -541,6 +551,18 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
     float bu = 0.f;
     for (int a = 0; a < l; ++a) bu = fmaf(s_b[yy * LMAX + a], s_u[a * HC + xx], bu);
     s_bu[e] = bu;
+  }
+  // the U rows of the new slice and their observations, once per column tile (row tile 0)
+  if (obs.Y && y0 == 0) {
+    for (int e = tid; e < l * TC; e += 256) {
+      const int a = e / TC, xx = e % TC, x = x0 + xx;
+      if (x < m) {
+        const long long col = (long long)i * m + x;
+        const float u = s_u[a * HC + xx + 1] + noise_value(obs.w, a, i, x, m);
+        obs.U_cur[a * obs.NM + col] = u;
+        obs.Y[(n + a) * obs.NM + col] = u + noise_value(obs.vu, a, i, x, m);
+      }
+    }
   }
   __syncthreads();
   // 256 pixels x COUT channels x K = 18 (two channels x 9 taps, padded to 20) on the
@@ -610,7 +632,8 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
 template <int CIN, typename TIN>
 __global__ __launch_bounds__(256) void k_conv_last(int N, int n, int m, const TIN* __restrict__ in,
                                                    const float* __restrict__ w,
-                                                   const float* __restrict__ bias, FieldOut fo) {
+                                                   const float* __restrict__ bias, FieldOut fo,
+                                                   ObserveArgs obs) {
   constexpr int TR = 4, TC = 64, HR = TR + 2, HC = TC + 2, CP = CIN + 1;
   __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
   __shared__ float s_w[9 * CIN];
@@ -623,12 +646,17 @@ __global__ __launch_bounds__(256) void k_conv_last(int N, int n, int m, const TI
   const int i = bid / row_tiles;
   const int y0 = rt * TR, x0 = ct * TC;
   const int tid = threadIdx.x;
-  // weights [0][c][dy][dx] -> s_w[tap * CIN + c]
-  for (int e = tid; e < 9 * CIN; e += 256) {
-    const int c = e / 9, tap = e % 9;
-    s_w[tap * CIN + c] = w[e];
-  }
+  // weights [0][c][dy][dx] -> s_w[tap * CIN + c], requested before the halo
+  constexpr int WS = (9 * CIN + 255) / 256;
+  float wv[WS];
+#pragma unroll
+  for (int u = 0; u < WS; ++u) wv[u] = tid + 256 * u < 9 * CIN ? w[tid + 256 * u] : 0.f;
   stage_halo<CIN, HR, HC, CP, 256>(in, i, n, m, y0, x0, s_in);
+#pragma unroll
+  for (int u = 0; u < WS; ++u) {
+    const int e = tid + 256 * u;
+    if (e < 9 * CIN) s_w[(e % 9) * CIN + e / 9] = wv[u];
+  }
   __syncthreads();
   const int ty = tid / TC, tx = tid % TC;
   const int y = y0 + ty, x = x0 + tx;
@@ -640,7 +668,10 @@ __global__ __launch_bounds__(256) void k_conv_last(int N, int n, int m, const TI
 #pragma unroll 8
     for (int c = 0; c < CIN; ++c) acc = fmaf(s_w[tap * CIN + c], src[c], acc);
   }
-  if (y < n && x < m) fo.base[i * fo.si + y * fo.sy + x] = acc;
+  if (y < n && x < m) {
+    fo.base[i * fo.si + y * fo.sy + x] = acc;
+    if (obs.Y) obs.Y[y * obs.NM + (long long)i * m + x] = acc + noise_value(obs.vx, y, i, x, m);
+  }
 }
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -974,16 +1005,17 @@ bool conv_last_supported(int cin) { return cin == 8 || cin == 16 || cin == 32 ||
 
 void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
                        const float* B, int cout, const float* w, const float* bias, int act,
-                       void* out_nhwc, bool bf16, unsigned* amax) {
+                       void* out_nhwc, bool bf16, unsigned* amax, const ObserveArgs* obs) {
   const unsigned blocks = (unsigned)((long long)N * ((n + 3) / 4) * ((m + 63) / 64));
+  const ObserveArgs oa = obs ? *obs : ObserveArgs{};
 #define OIC_FIRST_CASE(CO)                                                                        \
   if (cout == CO) {                                                                               \
     if (bf16)                                                                                     \
       OIC_LAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, bf16_t>), dim3(blocks), dim3(256), 0, N, n, \
-                 m, l, X, U, B, w, bias, act, (bf16_t*)out_nhwc, amax);                           \
+                 m, l, X, U, B, w, bias, act, (bf16_t*)out_nhwc, amax, oa);                       \
     else                                                                                          \
       OIC_LAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, float>), dim3(blocks), dim3(256), 0, N, n,  \
-                 m, l, X, U, B, w, bias, act, (float*)out_nhwc, amax);                            \
+                 m, l, X, U, B, w, bias, act, (float*)out_nhwc, amax, oa);                        \
     return;                                                                                       \
   }
   OIC_FIRST_CASE(8)
@@ -994,16 +1026,17 @@ void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, Fiel
 }
 
 void launch_conv_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
-                      const float* w, const float* bias, FieldOut fo, bool bf16) {
+                      const float* w, const float* bias, FieldOut fo, bool bf16, const ObserveArgs* obs) {
   const unsigned blocks = (unsigned)((long long)N * ((n + 3) / 4) * ((m + 63) / 64));
+  const ObserveArgs oa = obs ? *obs : ObserveArgs{};
 #define OIC_LAST_CASE(CI)                                                                         \
   if (cin == CI) {                                                                                \
     if (bf16)                                                                                     \
       OIC_LAUNCH(t, KC_CONV_LAST, s, (k_conv_last<CI, bf16_t>), dim3(blocks), dim3(256), 0, N, n, m, \
-                 (const bf16_t*)in_nhwc, w, bias, fo);                                            \
+                 (const bf16_t*)in_nhwc, w, bias, fo, oa);                                        \
     else                                                                                          \
       OIC_LAUNCH(t, KC_CONV_LAST, s, (k_conv_last<CI, float>), dim3(blocks), dim3(256), 0, N, n, m,  \
-                 (const float*)in_nhwc, w, bias, fo);                                             \
+                 (const float*)in_nhwc, w, bias, fo, oa);                                         \
     return;                                                                                       \
   }
   OIC_LAST_CASE(8)
