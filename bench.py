@@ -355,6 +355,20 @@ def main():
                         f"{args.workload}_{args.precision}")
     roof["measured"] = ("HIP events around each launch on the library stream, over the same "
                         "number of steps launched kernel by kernel right after the timed region")
+    # every class that does matrix work, and the two figures the method's targets name:
+    # the whole rollout against the MFMA peak of its precision, the update against HBM
+    by_class = {}
+    for cls in ("conv_first", "conv_mid", "conv_last", "stats", "gain", "update"):
+        if cls in per_class and per_class[cls]["flop"] > 0:
+            c = per_class[cls]
+            r = roofline_for(cls, c["flop"], c["bytes"], c["total_ms"], c["launches"], args.precision)
+            by_class[cls] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_launch_us")}
+    conv = [per_class[c] for c in ("conv_first", "conv_mid", "conv_last") if c in per_class]
+    conv_s = sum(c["total_ms"] for c in conv) * 1e-3
+    mfma_peak = {"bf16": PEAK["bf16"], "fp8": PEAK["fp8"]}.get(args.precision, PEAK["fp32"])
+    rollout_frac = sum(c["flop"] for c in conv) / conv_s / mfma_peak if conv_s > 0 else None
+    upd = per_class.get("update")
+    update_frac = upd["bytes"] / (upd["total_ms"] * 1e-3) / PEAK["hbm"] if upd else None
 
     lat_ms = np.array(lat) * 1e3
     solves_per_s = K / el
@@ -370,6 +384,9 @@ def main():
         "tracking_rmse_last": float(np.sqrt(mse_last)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "roofline": roof,
+        "roofline_by_class": by_class,
+        "rollout_mfma_frac": rollout_frac,
+        "update_hbm_frac": update_frac,
         "kernel_ms_per_solve": {c: v["total_ms"] / K for c, v in sorted(per_class.items())},
     }
     if not args.no_cpu_baseline:

@@ -90,10 +90,10 @@ __global__ void k_assemble_u(Dims d, float* __restrict__ traj, int step, NoiseRe
 
 // Ybar^i_t = [X_t^i + V_X^i; U_t^i + V_U^i].
 __global__ void k_observe(Dims d, const float* __restrict__ traj, int step, float* __restrict__ Y,
-                          NoiseRef vx, NoiseRef vu) {
+                          NoiseRef vx, NoiseRef vu, int row0) {
   const int NM = (int)d.NM();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
+  const int q = row0 + (int)blockIdx.y;
   if (col >= NM) return;
   const int i = col / d.m, x = col - i * d.m;
   const float s = traj[((size_t)step * d.rr() + q) * NM + col];
@@ -143,9 +143,10 @@ void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int 
 }
 
 void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
-                    NoiseRef vx, NoiseRef vu) {
-  OIC_LAUNCH(t, KC_OBSERVE, s, k_observe, row_grid(d.NM(), d.n + d.l), dim3(256), 0, d, traj, step, Y,
-             vx, vu);
+                    NoiseRef vx, NoiseRef vu, int row0, int row1) {
+  if (row1 <= row0) return;
+  OIC_LAUNCH(t, KC_OBSERVE, s, k_observe, row_grid(d.NM(), row1 - row0), dim3(256), 0, d, traj, step, Y,
+             vx, vu, row0);
 }
 
 void launch_constraint_row(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,

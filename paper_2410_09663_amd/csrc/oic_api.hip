@@ -392,10 +392,11 @@ RolloutMode rollout_mode(oic_ctx* h) {
 
 // Runs the CNN of Eq. (1) on `batch` fields given as strided sources, writing the
 // single output channel to `out`, in the given mode (the plant step always uses FP32).
-// With `obs`, the first and last layers also write the side outputs it names when both
-// layers run as the tiled kernels; returns whether they did.
-bool rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode,
-             const ObserveArgs* obs = nullptr) {
+// With `obs`, the first and last layers also write the side outputs it names where they
+// run as the tiled kernels; returns ROLL_X_OBSERVED | ROLL_U_ASSEMBLED for what was written.
+enum { ROLL_X_OBSERVED = 1, ROLL_U_ASSEMBLED = 2 };
+int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode,
+            const ObserveArgs* obs = nullptr) {
   const oic_config& c = h->cfg;
   const int L = c.n_layers;
   if (mode != RM_FP32) {
@@ -418,17 +419,16 @@ bool rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
     }
     launch_conv_last(h->stream, h->timer, batch, c.n, c.m, c.channels[L - 1], h->act[cur],
                      h->dW[L - 1], h->dBias[L - 1], out, true, obs);
-    return obs != nullptr;
+    return obs ? ROLL_X_OBSERVED | (obs->U_cur ? ROLL_U_ASSEMBLED : 0) : 0;
   }
-  // side outputs only when both the first and the last layer are the tiled kernels
-  const bool tiled = L > 1 && conv_first_supported(c.channels[1], c.l) && conv_last_supported(c.channels[L - 1]);
-  const ObserveArgs* o = tiled ? obs : nullptr;
+  int done = 0;
   int cur = 0;
   int k0 = 0;
   if (L > 1 && conv_first_supported(c.channels[1], c.l)) {
     // lift fused into the first layer
     launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
-                      h->dBias[0], c.activation, h->act[1], false, nullptr, o);
+                      h->dBias[0], c.activation, h->act[1], false, nullptr, obs);
+    if (obs && obs->U_cur) done |= ROLL_U_ASSEMBLED;
     cur = 1;
     k0 = 1;
   } else {
@@ -440,7 +440,8 @@ bool rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
     const int cls = k == 0 ? KC_CONV_FIRST : (last ? KC_CONV_LAST : KC_CONV_MID);
     if (last && k > 0 && conv_last_supported(cin)) {
       launch_conv_last(h->stream, h->timer, batch, c.n, c.m, cin, h->act[cur], h->dW[k], h->dBias[k],
-                       out, false, o);
+                       out, false, obs);
+      if (obs) done |= ROLL_X_OBSERVED;
       continue;
     }
     if (!last && h->dWk[k]) {
@@ -454,7 +455,7 @@ bool rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollou
                 h->dBias[k], c.activation, last ? nullptr : h->act[1 - cur], fo);
     cur = 1 - cur;
   }
-  return o != nullptr;
+  return done;
 }
 
 // OCP FP8 e4m3: bias 7, no infinities, largest finite 448.  The finite non-negative
@@ -555,17 +556,20 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     float* prev = h->traj + (size_t)(t - 1) * slice;
     float* cur = h->traj + (size_t)t * slice;
     // Line 6 / Eq. (15b): X rows of slice t through the CNN, from the analysed slice t-1.
-    // Eq. (4) for the U rows of slice t and line 9 / Eq. (12) ride along with the rollout's
-    // first and last layers where those are the tiled kernels.
-    const ObserveArgs oa{cur + (size_t)n * NM, h->Y, NM, noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true),
+    // Line 9 / Eq. (12) for the X rows rides along with the rollout's last layer; Eq. (4)
+    // for the U rows of slice t (and their rows of Ybar) with its first layer while the
+    // slice is small: for l*N*m above 2^17 the extra noise loads and stores in every
+    // first-layer workgroup cost more than the separate launch saves.
+    const bool small = (long long)l * NM <= (1LL << 17);
+    const ObserveArgs oa{small ? cur + (size_t)n * NM : nullptr, h->Y, NM,
+                         noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true),
                          noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
                          noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true)};
-    const bool observed = rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
-                                  FieldOut{cur, m, NM}, rollout_mode(h), &oa);
-    if (!observed) {
-      launch_assemble_u(s, h->timer, d, h->traj, t, oa.w);
-      launch_observe(s, h->timer, d, h->traj, t, h->Y, oa.vx, oa.vu);
-    }
+    const int done = rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
+                             FieldOut{cur, m, NM}, rollout_mode(h), &oa);
+    if (!(done & ROLL_U_ASSEMBLED)) launch_assemble_u(s, h->timer, d, h->traj, t, oa.w);
+    launch_observe(s, h->timer, d, h->traj, t, h->Y, oa.vx, oa.vu, (done & ROLL_X_OBSERVED) ? n : 0,
+                   (done & ROLL_U_ASSEMBLED) ? n : n + l);
     // Line 8 / Eqs. (15d)-(15f): covariance of the forecast trajectory (optional)
     if (h->want_cov) enqueue_cov(h, d, (t + 1) * rr, h->cov_prior + cov_offset(rr, t));
     // the barrier observation of the constraint, if one is set (actual value 0)

@@ -85,8 +85,9 @@ void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, const uin
 void launch_init_slice0(hipStream_t s, Timer& t, const Dims& d, float* traj, const float* X0,
                         const float* Uprev, NoiseRef w0, int* flag);
 void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int step, NoiseRef w);
+// observation rows row0 .. row1 - 1 of Ybar (X rows below n, U rows from n on)
 void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
-                    NoiseRef vx, NoiseRef vu);
+                    NoiseRef vx, NoiseRef vu, int row0, int row1);
 // Row n + l of Ybar: the barrier observation z = ln(1 + exp(beta g)) / alpha + sqrt(rz) eps
 // of the per-column constraint g = aX . X_t[:, c] + aU . U_t[:, c] - b of every member
 // (slice `step` of the trajectory, before the observation noise); eps from Zvz (N x m).
@@ -95,10 +96,10 @@ void launch_constraint_row(hipStream_t s, Timer& t, const Dims& d, const float* 
                            float sqrt_rz, const float* Zvz);
 
 // Rollout.  Field element (i, y, x) of a strided source sits at base + i*si + y*sy + x.
-// Side outputs of a solve's rollout (null pointers: none).  The first layer, which
+// Side outputs of a solve's rollout (null pointers: none).  The last layer writes the X
+// rows of Ybar next to the new states (Eq. (12)); with U_cur set, the first layer, which
 // reads U_{t-1}, also writes the U rows of the new slice, U_t = U_{t-1} + W_t (Eq. (4)),
-// and their observation rows of Ybar; the last layer writes the X rows of Ybar next to
-// the new states (Eq. (12)).  U_cur and Y are row-major with row stride NM, member i's
+// and their rows of Ybar.  U_cur and Y are row-major with row stride NM, member i's
 // columns at i*m ..
 struct ObserveArgs {
   float* U_cur;

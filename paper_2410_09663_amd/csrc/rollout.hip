@@ -495,6 +495,14 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   const int i = bid / row_tiles;
   const int y0 = rt * TR, x0 = ct * TC;
   const int tid = threadIdx.x;
+  const int a0 = (rt * l) / row_tiles, a1 = ((rt + 1) * l) / row_tiles;
+  const int ne = obs.U_cur ? (a1 - a0) * TC : 0;
+  float pw = 0.f, pv = 0.f;
+  if (tid < ne && x0 + tid % TC < m) {
+    const int a = a0 + tid / TC, x = x0 + tid % TC;
+    pw = noise_value(obs.w, a, i, x, m);
+    pv = noise_value(obs.vu, a, i, x, m);
+  }
   {
     // X halo: 396 cells; U rows: l x 66; B rows: 6 x l  (l <= 64)
     constexpr int XS = (HR * HC + 255) / 256;
@@ -553,15 +561,15 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
     s_bu[e] = bu;
   }
   // the U rows of the new slice and their observations, once per column tile (row tile 0)
-  if (obs.Y && y0 == 0) {
-    for (int e = tid; e < l * TC; e += 256) {
-      const int a = e / TC, xx = e % TC, x = x0 + xx;
-      if (x < m) {
-        const long long col = (long long)i * m + x;
-        const float u = s_u[a * HC + xx + 1] + noise_value(obs.w, a, i, x, m);
-        obs.U_cur[a * obs.NM + col] = u;
-        obs.Y[(n + a) * obs.NM + col] = u + noise_value(obs.vu, a, i, x, m);
-      }
+  // the U rows of the new slice and their observations: the l rows of this column tile
+  // are shared out over its row tiles; the first 256 noise pairs were requested with the halo
+  for (int e = tid; e < ne; e += 256) {
+    const int a = a0 + e / TC, xx = e % TC, x = x0 + xx;
+    if (x < m) {
+      const long long col = (long long)i * m + x;
+      const float u = s_u[a * HC + xx + 1] + (e < 256 ? pw : noise_value(obs.w, a, i, x, m));
+      obs.U_cur[a * obs.NM + col] = u;
+      obs.Y[(n + a) * obs.NM + col] = u + (e < 256 ? pv : noise_value(obs.vu, a, i, x, m));
     }
   }
   __syncthreads();
