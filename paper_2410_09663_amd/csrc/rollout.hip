@@ -174,6 +174,13 @@ __device__ __forceinline__ void stage_halo(const float* __restrict__ in, int i, 
 }
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+// Eight BF16 activations from floats as one 16-byte store (p 16-byte aligned).
+__device__ __forceinline__ void store_vec16(bf16_t* p, const float* v) {
+  u16x8 h;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) h[q] = to_bf16(v[q]);
+  *(u16x8*)p = h;
+}
 
 // The same staging for a BF16 NHWC input, widened to FP32 in LDS (16-byte loads of
 // 8 channels).
@@ -485,7 +492,11 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   __shared__ float s_b[HR * LMAX];
   __shared__ float s_w[20 * COUT];  // [k = channel*9 + tap, zero-padded to 20][o]
   __shared__ float s_bias[COUT];
-  __shared__ float s_out[TR * TC * (COUT + 1)];
+  // BF16 output leaves as 16-byte stores, so each pixel's channels stay 16-byte aligned in
+  // LDS; FP32 output keeps the odd stride (fewer bank conflicts, measured faster)
+  constexpr bool VEC = sizeof(TOUT) == 2;
+  constexpr int OPAD = VEC ? COUT + 4 : COUT + 1;
+  __shared__ __attribute__((aligned(16))) float s_out[TR * TC * OPAD];
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
   int bid = blockIdx.x;
@@ -613,22 +624,42 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int px = (4 * w + mb) * 16 + 4 * lk + r;
-          s_out[px * (COUT + 1) + o] = activate(acc[mb][nb][r] + bo, act);
+          s_out[px * OPAD + o] = activate(acc[mb][nb][r] + bo, act);
         }
       }
   }
   __syncthreads();
+  constexpr int V = VEC ? 8 : 1;  // channels per store
+  static_assert(COUT % V == 0, "a pixel's channels split into whole 16-byte vectors");
   float vmax = 0.f;
   for (int r = 0; r < TR; ++r) {
     const int y = y0 + r;
     if (y >= n) break;
     const int valid = min(TC, m - x0);
     TOUT* dst = out + (((size_t)i * n + y) * m + x0) * COUT;
-    for (int e = tid; e < valid * COUT; e += 256) {
-      const int px = e / COUT, o = e % COUT;
-      const float v = s_out[(r * TC + px) * (COUT + 1) + o];
-      store_act(dst + e, v);
-      vmax = fmaxf(vmax, fabsf(v));
+    if constexpr (!VEC) {
+      for (int e = tid; e < valid * COUT; e += 256) {
+        const float v = s_out[(r * TC + e / COUT) * OPAD + e % COUT];
+        store_act(dst + e, v);
+        vmax = fmaxf(vmax, fabsf(v));
+      }
+    } else {
+      for (int e = tid; e < valid * COUT / V; e += 256) {
+        const int px = (e * V) / COUT, o = (e * V) % COUT;
+        const float* src = s_out + (r * TC + px) * OPAD + o;  // 16-byte aligned: OPAD, o multiples of 4
+        float v[V];
+#pragma unroll
+        for (int q = 0; q < V; q += 4) {
+          const f32x4 f = *(const f32x4*)(src + q);
+          v[q] = f[0];
+          v[q + 1] = f[1];
+          v[q + 2] = f[2];
+          v[q + 3] = f[3];
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q) vmax = fmaxf(vmax, fabsf(v[q]));
+        store_vec16(dst + e * V, v);
+      }
     }
   }
   if (amax) amax_publish(vmax, amax);
