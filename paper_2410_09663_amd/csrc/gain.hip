@@ -42,6 +42,26 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return u.d;
 }
 
+// store(e, load(e)) for e = 0 .. count - 1 across the NT threads of a block, sixteen
+// loads per thread in flight before their stores (global -> LDS staging without one
+// memory latency per element).
+template <int NT, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int count, Load load, Store store) {
+  for (int base = 0; base < count; base += NT * 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + (int)threadIdx.x + NT * u;
+      v[u] = e < count ? load(e) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + (int)threadIdx.x + NT * u;
+      if (e < count) store(e, v[u]);
+    }
+  }
+}
+
 // D(16x16 tile at rows i0, cols j0 of M, leading dimension ld) += sum_k Aop[i][k] Bop[k][j]
 // over k = 0..K-1 on the FP64 matrix cores, where the operands are read through the
 // functors a(i, k) and b(k, j) (zero outside their ranges).  Lane layout (16x16x4 f64):
@@ -390,10 +410,9 @@ __global__ __launch_bounds__(kCholThreads) void k_potrf_diag(int p, double* __re
   const int ld = nb + 1;
   double* sA = lds;
   double* sW = lds + nb * ld;
-  for (int e = threadIdx.x; e < nb * nb; e += kCholThreads) {
-    const int r = e / nb, c = e - r * nb;
-    sA[r * ld + c] = A[(size_t)(kb + r) * p + kb + c];
-  }
+  staged_copy<kCholThreads>(
+      nb * nb, [&](int e) { return A[(size_t)(kb + e / nb) * p + kb + e % nb]; },
+      [&](int e, double v) { sA[(e / nb) * ld + e % nb] = v; });
   __syncthreads();
   if (!chol_inverse<kPB / NBK, false>(nb, sA, sW, nullptr, flag)) return;
   __syncthreads();
@@ -417,11 +436,15 @@ __global__ __launch_bounds__(256) void k_potrf_trsm(int p, double* __restrict__ 
   const int nb = min(kPB, p - kb);
   const int i0 = kb + nb + blockIdx.x * 64;
   const double* Li = Linv + (size_t)(kb / kPB) * kPB * kPB;
-  for (int e = threadIdx.x; e < kPB * kPB; e += 256) {
-    const int r = e / kPB, c = e - r * kPB;
-    sL[r * kPBP + c] = Li[e];
-    sR[r * kPBP + c] = (i0 + r < p && c < nb) ? A[(size_t)(i0 + r) * p + kb + c] : 0.0;
-  }
+  staged_copy<256>(
+      kPB * kPB, [&](int e) { return Li[e]; }, [&](int e, double v) { sL[(e / kPB) * kPBP + e % kPB] = v; });
+  staged_copy<256>(
+      kPB * kPB,
+      [&](int e) {
+        const int r = e / kPB, c = e - r * kPB;
+        return (i0 + r < p && c < nb) ? A[(size_t)(i0 + r) * p + kb + c] : 0.0;
+      },
+      [&](int e, double v) { sR[(e / kPB) * kPBP + e % kPB] = v; });
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -459,11 +482,20 @@ __global__ __launch_bounds__(256) void k_potrf_syrk(int p, double* __restrict__ 
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
   const int tj = t - ti * (ti + 1) / 2;
   const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
-  for (int e = threadIdx.x; e < 64 * kPB; e += 256) {
-    const int r = e / kPB, c = e - r * kPB;
-    sI[r * kPBP + c] = (i0 + r < p && c < nb) ? A[(size_t)(i0 + r) * p + kb + c] : 0.0;
-    sJ[r * kPBP + c] = (j0 + r < p && c < nb) ? A[(size_t)(j0 + r) * p + kb + c] : 0.0;
-  }
+  staged_copy<256>(
+      64 * kPB,
+      [&](int e) {
+        const int r = e / kPB, c = e - r * kPB;
+        return (i0 + r < p && c < nb) ? A[(size_t)(i0 + r) * p + kb + c] : 0.0;
+      },
+      [&](int e, double v) { sI[(e / kPB) * kPBP + e % kPB] = v; });
+  staged_copy<256>(
+      64 * kPB,
+      [&](int e) {
+        const int r = e / kPB, c = e - r * kPB;
+        return (j0 + r < p && c < nb) ? A[(size_t)(j0 + r) * p + kb + c] : 0.0;
+      },
+      [&](int e, double v) { sJ[(e / kPB) * kPBP + e % kPB] = v; });
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -514,27 +546,30 @@ __global__ __launch_bounds__(256) void k_gain_trsm(int p, int Ma, const double* 
   double* sL = tmp + RB * kPBP;     // kPB x kPBP
   const int a0 = blockIdx.x * RB;
   const int tid = threadIdx.x;
-  for (int e = tid; e < RB * npan * kPB; e += 256) {
-    const int r = e / (npan * kPB), c = e - r * (npan * kPB);
-    z[r * PP + c] = (a0 + r < Ma && c < p) ? Sxy[(size_t)(a0 + r) * p + c] : 0.0;
-  }
+  staged_copy<256>(
+      RB * npan * kPB,
+      [&](int e) {
+        const int r = e / (npan * kPB), c = e - r * (npan * kPB);
+        return (a0 + r < Ma && c < p) ? Sxy[(size_t)(a0 + r) * p + c] : 0.0;
+      },
+      [&](int e, double v) { z[(e / (npan * kPB)) * PP + e % (npan * kPB)] = v; });
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   // tile u of this wave: row tile rt = (w*TPW + u) / 4, column tile ct = (w*TPW + u) % 4
   auto stage_block = [&](int bi, int bj) {  // sL[r][c] = L[64 bi + r][64 bj + c]
-    for (int e = tid; e < kPB * kPB; e += 256) {
-      const int r = e / kPB, c = e - r * kPB;
-      const int gr = bi * kPB + r, gc = bj * kPB + c;
-      sL[r * kPBP + c] = (gr < p && gc < p) ? A[(size_t)gr * p + gc] : 0.0;
-    }
+    staged_copy<256>(
+        kPB * kPB,
+        [&](int e) {
+          const int gr = bi * kPB + e / kPB, gc = bj * kPB + e % kPB;
+          return (gr < p && gc < p) ? A[(size_t)gr * p + gc] : 0.0;
+        },
+        [&](int e, double v) { sL[(e / kPB) * kPBP + e % kPB] = v; });
   };
   auto stage_inv = [&](int bi) {
     const double* Li = Linv + (size_t)bi * kPB * kPB;
-    for (int e = tid; e < kPB * kPB; e += 256) {
-      const int r = e / kPB, c = e - r * kPB;
-      sL[r * kPBP + c] = Li[e];
-    }
+    staged_copy<256>(
+        kPB * kPB, [&](int e) { return Li[e]; }, [&](int e, double v) { sL[(e / kPB) * kPBP + e % kPB] = v; });
   };
   for (int pass = 0; pass < 2; ++pass) {
     const bool fwd = pass == 0;
