@@ -3,6 +3,8 @@
 //  - the initial ensemble (Algorithm 1, line 4);
 //  - the control part of the forecast, U_t = U_{t-1} + W_t (Eq. (4), Eq. (15b));
 //  - the perturbed virtual observations Ybar^i = H Xbar^i + Vbar^i (Eq. (12)).
+#include <algorithm>
+
 #include "noise_value.h"
 #include "oic_internal.h"
 
@@ -101,6 +103,19 @@ __global__ void k_observe(Dims d, const float* __restrict__ traj, int step, floa
   Y[(size_t)q * NM + col] = s + v;
 }
 
+// Up to three device-to-device copies in one launch, skipped entirely when *guard is
+// non-zero (guard may be NULL); with seed_dst set, thread 0 also stores the seed.
+__global__ void k_copy_jobs(CopyJob j0, CopyJob j1, CopyJob j2, const int* __restrict__ guard,
+                            uint64_t seed, uint64_t* __restrict__ seed_dst) {
+  if (guard && *guard) return;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (seed_dst && t == 0) *seed_dst = seed;
+  for (long long e = t; e < j0.count; e += stride) j0.dst[e] = j0.src[e];
+  for (long long e = t; e < j1.count; e += stride) j1.dst[e] = j1.src[e];
+  for (long long e = t; e < j2.count; e += stride) j2.dst[e] = j2.src[e];
+}
+
 // The constraint row of Ybar for every member and column (one thread per column).
 __global__ void k_constraint_row(Dims d, const float* __restrict__ traj, int step, float* __restrict__ Y,
                                  const float* __restrict__ aX, const float* __restrict__ aU, float b,
@@ -147,6 +162,18 @@ void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, i
   if (row1 <= row0) return;
   OIC_LAUNCH(t, KC_OBSERVE, s, k_observe, row_grid(d.NM(), row1 - row0), dim3(256), 0, d, traj, step, Y,
              vx, vu, row0);
+}
+
+void launch_copy_jobs(hipStream_t s, Timer& t, const CopyJob* jobs, int count, const int* guard, uint64_t seed,
+                      uint64_t* seed_dst) {
+  CopyJob j[3] = {};
+  long long most = 1;
+  for (int k = 0; k < count && k < 3; ++k) {
+    j[k] = jobs[k];
+    most = std::max(most, j[k].count);
+  }
+  const unsigned blocks = (unsigned)std::min<long long>((most + 255) / 256, 256);
+  OIC_LAUNCH(t, KC_COPY, s, k_copy_jobs, dim3(blocks), dim3(256), 0, j[0], j[1], j[2], guard, seed, seed_dst);
 }
 
 void launch_constraint_row(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,

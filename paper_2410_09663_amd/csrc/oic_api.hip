@@ -29,7 +29,7 @@ namespace oic {
 
 const char* const kKernelClassNames[KC_COUNT] = {
     "noise", "init", "lift", "conv_first", "conv_mid", "conv_last", "assemble", "observe",
-    "means", "stats", "stats_reduce", "chol", "gain", "update", "extract"};
+    "means", "stats", "stats_reduce", "chol", "gain", "update", "extract", "copy"};
 
 void Timer::reset() {
   cursor = 0;
@@ -638,12 +638,21 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   float* dX0 = h->io;
   float* dRef = dX0 + (size_t)n * m;
   float* dUp = dRef + (size_t)(c.max_H + 1) * n * m;
-  if ((rc = copy_in(h, dX0, a->X0, (size_t)n * m))) return rc;
-  if ((rc = copy_in(h, dRef, a->reference, (size_t)(H + 1) * n * m))) return rc;
-  if (a->U_prev) {
-    if ((rc = copy_in(h, dUp, a->U_prev, (size_t)l * m))) return rc;
+  const bool dev = c.mem_mode == OIC_MEM_DEVICE;
+  if (dev) {
+    // device pointers: X0, the reference window, U_prev and the seed in one launch
+    const CopyJob in[3] = {{a->X0, dX0, (long long)n * m},
+                           {a->reference, dRef, (long long)(H + 1) * n * m},
+                           {a->U_prev ? a->U_prev : h->Uprev, dUp, (long long)l * m}};
+    launch_copy_jobs(s, h->timer, in, 3, nullptr, a->seed, explicit_noise ? nullptr : h->dseed);
   } else {
-    HIP_TRY(hipMemcpyAsync(dUp, h->Uprev, (size_t)l * m * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if ((rc = copy_in(h, dX0, a->X0, (size_t)n * m))) return rc;
+    if ((rc = copy_in(h, dRef, a->reference, (size_t)(H + 1) * n * m))) return rc;
+    if (a->U_prev) {
+      if ((rc = copy_in(h, dUp, a->U_prev, (size_t)l * m))) return rc;
+    } else {
+      HIP_TRY(hipMemcpyAsync(dUp, h->Uprev, (size_t)l * m * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
   }
   const size_t cnt[5] = {(size_t)N * l * m, (size_t)H * N * l * m, (size_t)H * N * n * m,
                          (size_t)H * N * l * m, (size_t)H * N * m};
@@ -651,7 +660,7 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   if (explicit_noise) {
     for (int k = 0; k < 4 + d.nc; ++k)
       if ((rc = copy_in(h, h->Z[k], zsrc[k], cnt[k]))) return rc;
-  } else {
+  } else if (!dev) {
     *h->hseed = a->seed;
     HIP_TRY(hipMemcpyAsync(h->dseed, h->hseed, sizeof(uint64_t), hipMemcpyHostToDevice, s));
   }
@@ -683,16 +692,25 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   }
   float* sU = h->out_stage;
   float* sX = sU + (size_t)(c.max_H + 1) * l * m;
+  if (dev) {
+    // outputs and the carried U_prev in one launch, which does nothing if the solve failed
+    const CopyJob out[3] = {{sU, a->U_out, (long long)(H + 1) * l * m},
+                            {sX, a->X_out, a->X_out ? (long long)(H + 1) * n * m : 0},
+                            {h->Uprev_new, h->Uprev, (long long)l * m}};
+    launch_copy_jobs(s, h->timer, out, 3, h->flag, 0, nullptr);
+  }
   int flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   h->timer.harvest();
   if (flag) return fail(h, OIC_ENOTSPD, "Sigma^Ybar is not positive definite at some horizon step");
-  if ((rc = copy_out(h, a->U_out, sU, (size_t)(H + 1) * l * m))) return rc;
-  if (a->X_out && (rc = copy_out(h, a->X_out, sX, (size_t)(H + 1) * n * m))) return rc;
-  HIP_TRY(hipMemcpyAsync(h->Uprev, h->Uprev_new, (size_t)l * m * sizeof(float),
-                         hipMemcpyDeviceToDevice, s));
-  if (c.mem_mode == OIC_MEM_HOST) HIP_TRY(hipStreamSynchronize(s));
+  if (!dev) {
+    if ((rc = copy_out(h, a->U_out, sU, (size_t)(H + 1) * l * m))) return rc;
+    if (a->X_out && (rc = copy_out(h, a->X_out, sX, (size_t)(H + 1) * n * m))) return rc;
+    HIP_TRY(hipMemcpyAsync(h->Uprev, h->Uprev_new, (size_t)l * m * sizeof(float),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   return OIC_OK;
 }
 
@@ -981,6 +999,18 @@ int cnn_forward_impl(oic_handle h, int batch, const float* X, const float* U, fl
   if (batch < 1 || batch > c.max_N) return fail(h, OIC_EINVAL, "batch must be in 1..max_N");
   if (!X || !U || !X_next) return fail(h, OIC_EINVAL, "NULL pointer");
   const size_t n = c.n, m = c.m, l = c.l;
+  if (c.mem_mode == OIC_MEM_DEVICE) {
+    // device pointers go straight to the kernels (X_next may alias X: the first layer has
+    // read all of X before the last layer writes)
+    rollout(h, batch, FieldRef{X, (long long)(n * m), (long long)m}, FieldRef{U, (long long)(l * m), (long long)m},
+            FieldOut{X_next, (long long)(n * m), (long long)m}, fp32_only ? RM_FP32 : rollout_mode(h));
+    // on a private stream the caller cannot order against the work: finish it here
+    if (h->own_stream || h->timer.enabled) {
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      h->timer.harvest();
+    }
+    return OIC_OK;
+  }
   float* dX = h->io + n * m + (size_t)(c.max_H + 1) * n * m + l * m;
   float* dU = dX + (size_t)c.max_N * n * m;
   float* dO = dU + (size_t)c.max_N * l * m;

@@ -38,6 +38,7 @@ enum KernelClass {
   KC_GAIN,
   KC_UPDATE,
   KC_EXTRACT,
+  KC_COPY,
   KC_COUNT
 };
 
@@ -107,6 +108,16 @@ struct ObserveArgs {
   long long NM;
   NoiseRef w, vx, vu;
 };
+// One device-to-device copy of `count` floats (count 0: nothing).
+struct CopyJob {
+  const float* src;
+  float* dst;
+  long long count;
+};
+// Up to three copies in one kernel, all skipped when *guard != 0 (guard NULL: always
+// done); with seed_dst set the seed is stored there too.
+void launch_copy_jobs(hipStream_t s, Timer& t, const CopyJob* jobs, int count, const int* guard, uint64_t seed,
+                      uint64_t* seed_dst);
 struct FieldRef {
   const float* base;
   long long si, sy;
