@@ -236,9 +236,9 @@ class Controller:
         return U_out, X_out
 
     def solve_ex(self, X0, reference, Q, R, N: int, H: int, seed: int = 0, U_prev=None,
-                 noise=None, want_X: bool = True, Z_VZ=None):
+                 noise=None, want_X: bool = True, Z_VZ=None, U_out=None, X_out=None):
         """Solve with explicit noise (a workloads.Noise or a 4-tuple) or, if noise is None,
-        the seeded stream.  Returns (U_hat, X_hat)."""
+        the seeded stream.  Returns (U_hat, X_hat), written into U_out / X_out if given."""
         Q = self._host(Q, (self.l, self.l))
         R = self._host(R, (self.n, self.n))
         a = oic_solve_args()
@@ -255,10 +255,11 @@ class Controller:
             a.Z_VU = self._ptr(z[3], (H, N, self.l, self.m))
         if Z_VZ is not None:
             a.Z_VZ = self._ptr(Z_VZ, (H, N, 1, self.m))
-        U_out = self._new((H + 1, self.l, self.m))
-        X_out = self._new((H + 1, self.n, self.m)) if want_X else None
-        a.U_out = self._ptr(U_out, U_out.shape, True)
-        a.X_out = self._ptr(X_out, (H + 1, self.n, self.m), True) if want_X else None
+        U_out = self._new((H + 1, self.l, self.m)) if U_out is None else U_out
+        if want_X and X_out is None:
+            X_out = self._new((H + 1, self.n, self.m))
+        a.U_out = self._ptr(U_out, (H + 1, self.l, self.m), True)
+        a.X_out = self._ptr(X_out, (H + 1, self.n, self.m), True) if X_out is not None else None
         self._check(lib().oic_solve_ex(self._h, ctypes.byref(a)))
         return U_out, X_out
 

@@ -226,6 +226,59 @@ def test_error_paths_leave_outputs_untouched():
         assert np.all(np.isfinite(U))
 
 
+def test_device_mode_failed_solve_leaves_outputs_untouched():
+    """Device memory mode: a solve whose Sigma^Ybar is not positive definite reports
+    OIC_ENOTSPD and writes neither the caller's output buffers nor the carried U_prev."""
+    import torch
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    with oic.controller_for(prob, mem_mode=oic.OIC_MEM_DEVICE, stream=stream) as c:
+        c.solve(dev(prob.X0), dev(Xref), prob.Q, prob.R, p.N, p.H, seed=2)  # U_prev now non-zero
+        before = c.get_u_prev().clone()
+        U_out = torch.full((p.H + 1, p.l, p.m), 7.0, device="cuda")
+        X_out = torch.full((p.H + 1, p.n, p.m), -3.0, device="cuda")
+        z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, 0)
+        zero = tuple(torch.zeros_like(dev(a)) for a in (z.Z_init, z.Z_W, z.Z_VX, z.Z_VU))
+        with pytest.raises(oic.OicError) as e:
+            c.solve_ex(dev(prob.X0), dev(Xref), prob.Q, prob.R, p.N, p.H, noise=zero, U_out=U_out, X_out=X_out)
+        assert e.value.code == oic.OIC_ENOTSPD
+        torch.cuda.synchronize()
+        assert bool(torch.all(U_out == 7.0)) and bool(torch.all(X_out == -3.0))
+        assert torch.equal(c.get_u_prev(), before)
+        # and a good solve afterwards writes them
+        U, X = c.solve_ex(dev(prob.X0), dev(Xref), prob.Q, prob.R, p.N, p.H, noise=tuple(dev(a) for a in (
+            z.Z_init, z.Z_W, z.Z_VX, z.Z_VU)), U_out=U_out, X_out=X_out)
+        torch.cuda.synchronize()
+        assert bool(torch.all(torch.isfinite(U_out))) and not bool(torch.all(U_out == 7.0))
+
+
+@pytest.mark.parametrize("preset", ["C2", "tiny"])
+@pytest.mark.parametrize("own_stream", [False, True])
+def test_device_mode_forward_matches_host_mode_bitwise(preset, own_stream):
+    """The forward in device memory mode reads and writes the caller's buffers directly
+    (tiled and generic layer paths; on the caller's stream and on a private one)."""
+    import torch
+    p = tiny() if preset == "tiny" else wl.PRESETS[preset]
+    prob = wl.make_problem(p)
+    rng = np.random.default_rng(4)
+    b = 3
+    X = rng.standard_normal((b, p.n, p.m)).astype(np.float32)
+    U = rng.standard_normal((b, p.l, p.m)).astype(np.float32)
+    with oic.controller_for(prob) as c:
+        ref = c.cnn_forward(X, U)
+        ref_plant = c.plant_step(X[0], U[0])
+    kw = {} if own_stream else {"stream": torch.cuda.current_stream().cuda_stream}
+    with oic.controller_for(prob, mem_mode=oic.OIC_MEM_DEVICE, **kw) as c:
+        got = c.cnn_forward(torch.from_numpy(X).cuda(), torch.from_numpy(U).cuda())
+        got_plant = c.plant_step(torch.from_numpy(X[0]).cuda(), torch.from_numpy(U[0]).cuda())
+        torch.cuda.synchronize()
+        got, got_plant = got.cpu().numpy(), got_plant.cpu().numpy()
+    assert np.array_equal(ref, got) and np.array_equal(ref_plant, got_plant)
+
+
 def test_closed_loop_teacher_forced():
     """Three closed-loop steps of C2-shaped dynamics at C1 size: at each step the
     oracle solves from the library's own state X_k and applied U_{k-1}."""
