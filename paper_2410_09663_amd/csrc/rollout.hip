@@ -492,9 +492,11 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   __shared__ float s_b[HR * LMAX];
   __shared__ float s_w[20 * COUT];  // [k = channel*9 + tap, zero-padded to 20][o]
   __shared__ float s_bias[COUT];
-  // BF16 output leaves as 16-byte stores, so each pixel's channels stay 16-byte aligned in
-  // LDS; FP32 output keeps the odd stride (fewer bank conflicts, measured faster)
-  constexpr bool VEC = sizeof(TOUT) == 2;
+  // BF16 output with up to 32 channels leaves as 16-byte stores, so each pixel's channels
+  // stay 16-byte aligned in LDS; FP32 output and 64 channels keep the odd stride and
+  // scalar stores (measured faster there: 128x128 C=32 3.2 -> 2.7 ms per solve with
+  // vectors, 256x256 C=64 141 -> 171 ms)
+  constexpr bool VEC = sizeof(TOUT) == 2 && COUT <= 32;
   constexpr int OPAD = VEC ? COUT + 4 : COUT + 1;
   __shared__ __attribute__((aligned(16))) float s_out[TR * TC * OPAD];
   const int col_tiles = (m + TC - 1) / TC;
