@@ -174,14 +174,16 @@ void launch_means(hipStream_t s, Timer& t, const float* A, int rows, int N, int 
 void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, double* mean);
 // S[a][b] (FP64, (Ma+ny) x p): sum over columns of left row a times the FP64-centred Ybar
 // row b; left rows are the first Ma trajectory rows followed by the first ny rows of Ybar.
+// f32: the products on the FP32 matrix cores (right operand rounded to FP32 after
+// centring, FP32 sums over at most 256 columns, FP64 beyond), for the mixed-precision modes.
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
-                  const float* Y, const double* muY, double* part, size_t part_cap, double* S);
+                  const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32 = false);
 // The same sums against an arbitrary right operand, times scale: S[a][b] = scale *
 // sum_c L[a][c] (R[b][c] - muR[b][c mod m]) for the nr rows of R (row length N*m), S
 // with leading dimension nr.  part_cap must hold at least (Ma + ny) * nr doubles.
 void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const float* R, int nr, const double* muR, double* part, size_t part_cap,
-                  double* S, double scale);
+                  double* S, double scale, bool f32 = false);
 // FP64 Cholesky factor of the p x p Syy; flag is set to 1 when a pivot is not positive
 // and finite.  p <= 90 (one workgroup, LDS): Sinv = (Sigma^Y)^{-1}, Syy untouched.
 // p > 90 (blocked, chip-wide): Syy is overwritten by L in its lower triangle and

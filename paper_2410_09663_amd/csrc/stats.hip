@@ -252,6 +252,134 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
     }
 }
 
+// The same products for the mixed-precision modes on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32, twice the FP64 rate): the right operand is centred in FP64 and
+// rounded to FP32, products accumulate in FP32 over at most four 64-column stages and are
+// then folded into FP64 registers, and the split partials are summed in FP64 as before.
+// Lane layout (16x16x4 f32): A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// element r of lane j + 16g holds D[4g + r][j].
+template <int NB, bool VEC>
+__global__ __launch_bounds__(256) void k_stats_mfma32(Dims d, const float* __restrict__ traj, int Ma,
+                                                      int ny, const float* __restrict__ Y,
+                                                      const float* __restrict__ R, int p,
+                                                      const double* __restrict__ muY, int chunk,
+                                                      double* __restrict__ part) {
+  constexpr int RB = NB * 16;
+  __shared__ float sA[MA][MK + 1];
+  __shared__ float sB[RB][MK + 1];
+  const int NM = (int)d.NM();
+  const int m = d.m;
+  const int Mtot = Ma + ny;
+  const int a0 = blockIdx.x * MA;
+  const int b0 = blockIdx.y * RB;
+  const int c_begin = blockIdx.z * chunk;
+  const int c_end = min(c_begin + chunk, NM);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f32x4v acc[NB];
+  f64x4 tot[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    tot[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  constexpr int AV = MA * MK / 4 / 256;
+  constexpr int BV = RB * MK / 4 / 256;
+  f32x4v ra[AV], rb[BV];
+  auto left_row = [&](int a) -> const float* {
+    return a < Ma ? traj + (size_t)a * NM : Y + (size_t)(a - Ma) * NM;
+  };
+  auto load_stage = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int a = a0 + r, c = c0 + 4 * q;
+      f32x4v v = {0.f, 0.f, 0.f, 0.f};
+      if (a < Mtot) {
+        const float* src = left_row(a);
+        if (VEC) {
+          if (c < c_end) v = *(const f32x4v*)(src + c);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = (c + j < c_end) ? src[c + j] : 0.f;
+        }
+      }
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int b = b0 + r, c = c0 + 4 * q;
+      f32x4v v = {0.f, 0.f, 0.f, 0.f};
+      if (b < p) {
+        const float* src = R + (size_t)b * NM;
+        if (VEC) {
+          if (c < c_end) v = *(const f32x4v*)(src + c);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = (c + j < c_end) ? src[c + j] : 0.f;
+        }
+      }
+      rb[u] = v;
+    }
+  };
+  if (c_begin < c_end) load_stage(c_begin);
+  int stage = 0;
+  for (int c0 = c_begin; c0 < c_end; c0 += MK, ++stage) {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sA[r][4 * q + j] = ra[u][j];
+    }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int b = b0 + r, c = c0 + 4 * q;
+      int x = c % m;
+      const double* mu = muY + (size_t)(b < p ? b : 0) * m;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool live = b < p && c + j < c_end;
+        sB[r][4 * q + j] = live ? (float)((double)rb[u][j] - mu[x]) : 0.f;
+        x = (x + 1 == m) ? 0 : x + 1;
+      }
+    }
+    __syncthreads();
+    if (c0 + MK < c_end) load_stage(c0 + MK);  // prefetch the next stage
+#pragma unroll 4
+    for (int kk = 0; kk < MK; kk += 4) {
+      const float av = sA[w * 16 + li][kk + lk];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sB[nb * 16 + li][kk + lk], acc[nb], 0, 0, 0);
+    }
+    if ((stage & 3) == 3) {  // fold the FP32 sums of the last four stages into FP64
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[nb][r] += (double)acc[nb][r];
+        acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)blockIdx.z * Mtot * p;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = a0 + w * 16 + 4 * lk + r;
+      const int b = b0 + nb * 16 + li;
+      if (a < Mtot && b < p) out[(size_t)a * p + b] = tot[nb][r] + (double)acc[nb][r];
+    }
+}
+
 // S[idx] = scale * sum_z part[z][idx].  Block (64, RG): lane x owns output idx, and the
 // RG threads of a column sum interleaved subsets of the splits (z = y, y + RG, ...), which
 // are then added in the order y = 0, 1, ..., RG - 1: a fixed order, so the result is
@@ -321,7 +449,7 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
 
 void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const float* R, int p, const double* muR, double* part, size_t part_cap,
-                  double* S, double scale) {
+                  double* S, double scale, bool f32) {
   const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
   // right rows per block: NB*16 with NB <= 8, balanced over grid.y tiles
@@ -346,7 +474,13 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   const bool vec = NM % 4 == 0;
 #define OIC_STATS_CASE(NBV)                                                                     \
   case NBV:                                                                                     \
-    if (vec)                                                                                    \
+    if (f32 && vec)                                                                             \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma32<NBV, true>), grid, dim3(256), 0, d, traj, Ma,   \
+                 ny, Y, R, p, muR, chunk, part);                                                \
+    else if (f32)                                                                               \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma32<NBV, false>), grid, dim3(256), 0, d, traj, Ma,  \
+                 ny, Y, R, p, muR, chunk, part);                                                \
+    else if (vec)                                                                               \
       OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, true>), grid, dim3(256), 0, d, traj, Ma, ny, \
                  Y, R, p, muR, chunk, part);                                                    \
     else                                                                                        \
@@ -364,8 +498,8 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 }
 
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
-                  const float* Y, const double* muY, double* part, size_t part_cap, double* S) {
-  launch_cross(s, t, d, traj, Ma, ny, Y, Y, d.p(), muY, part, part_cap, S, 1.0);
+                  const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32) {
+  launch_cross(s, t, d, traj, Ma, ny, Y, Y, d.p(), muY, part, part_cap, S, 1.0, f32);
 }
 
 }  // namespace oic
