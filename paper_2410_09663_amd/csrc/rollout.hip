@@ -725,8 +725,8 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 // Row strides in LDS are padded by 8 elements so the 16 lanes of a fragment hit
 // distinct banks.  Lane layout (16x16x32): A[i][k] for k = 8g..8g+7 from lane i + 16g,
 // B[k][j] for k = 8g..8g+7 from lane j + 16g, element r of lane j + 16g holds D[4g + r][j].
-template <int CIN, int COUT, int TR>
-__global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
+template <int CIN, int COUT, int TR, int WG>
+__global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m,
                                                         const bf16_t* __restrict__ in,
                                                         const bf16_t* __restrict__ wt,
                                                         const float* __restrict__ bias, int act,
@@ -742,7 +742,10 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
   constexpr int OP = COUT + 8;
   constexpr int IQ = CIN / 8;
   constexpr int IV = HR * HC * IQ;
-  constexpr int IS = (IV + 255) / 256;
+  constexpr int NT = 256 * WG;       // WG groups of 4 waves split the output channels
+  constexpr int NBW = NB / WG;       // N-blocks per wave
+  static_assert(NB % WG == 0, "whole N-blocks per wave group");
+  constexpr int IS = (IV + NT - 1) / NT;
   // the weights stay resident; the halo tile and, after the MFMA loop, the output tile
   // share the rest
   constexpr int TILE = HR * HC * CP > TR * TC * OP ? HR * HC * CP : TR * TC * OP;
@@ -754,20 +757,20 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
   const int row_tiles = (n + TR - 1) / TR;
   const int tiles = N * row_tiles * col_tiles;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
+  const int lane = tid & 63, w = (tid >> 6) & 3, ng = tid >> 8;
   const int li = lane & 15, lk = lane >> 4;
   {
     constexpr int WQ = KD / 8;  // 16-byte vectors per weight row
     constexpr int WV = COUT * WQ;
-    constexpr int WS = (WV + 255) / 256;
+    constexpr int WS = (WV + NT - 1) / NT;
 #pragma unroll
     for (int u = 0; u < WS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       if (e < WV) *(u16x8*)(s_w + (e / WQ) * KDP + 8 * (e % WQ)) = *(const u16x8*)(wt + (size_t)8 * e);
     }
     if (KD32 > KD) {  // zero the K padding of every weight row
       constexpr int PQ = (KD32 - KD) / 8;
-      for (int e = tid; e < COUT * PQ; e += 256)
+      for (int e = tid; e < COUT * PQ; e += NT)
         *(u16x8*)(s_w + (e / PQ) * KDP + KD + 8 * (e % PQ)) = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
     }
   }
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
     const int y0 = rt * TR, x0 = ct * TC;
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       iv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
       if (e < IV) {
         const int q = e % IQ, pix = e / IQ;
@@ -800,18 +803,18 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
     __syncthreads();  // the previous tile's output has left s_tile (and s_w is staged)
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       if (e < IV) *(u16x8*)(s_in + (e / IQ) * CP + 8 * (e % IQ)) = iv[u];
     }
     __syncthreads();
     if (tile + (int)gridDim.x < tiles) load_halo(tile + gridDim.x);  // in flight meanwhile
-    f32x4 acc[RPW][4][NB];
+    f32x4 acc[RPW][4][NBW];
 #pragma unroll
     for (int rw = 0; rw < RPW; ++rw)
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < NBW; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 3
     for (int kb = 0; kb < KD32 / 32; ++kb) {
       const int k0 = kb * 32 + 8 * lk;
@@ -819,10 +822,10 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
       const int kk = k0 < KD ? k0 : 0;
       const int tap = kk / CIN, c0 = kk - tap * CIN;
       const int dy = tap / 3, dx = tap - dy * 3;
-      bf16x8_t b[NB];
+      bf16x8_t b[NBW];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        b[nb] = __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_w + (nb * 16 + li) * KDP + k0));
+      for (int nb = 0; nb < NBW; ++nb)
+        b[nb] = __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_w + ((ng * NBW + nb) * 16 + li) * KDP + k0));
 #pragma unroll
       for (int rw = 0; rw < RPW; ++rw) {
         const int ry = w + 4 * rw;
@@ -831,7 +834,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
           const bf16x8_t a = __builtin_bit_cast(
               bf16x8_t, *(const u16x8*)(s_in + ((ry + dy) * HC + mb * 16 + li + dx) * CP + c0));
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
+          for (int nb = 0; nb < NBW; ++nb)
             acc[rw][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[rw][mb][nb], 0, 0, 0);
         }
       }
@@ -846,8 +849,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int o = nb * 16 + li;
+        for (int nb = 0; nb < NBW; ++nb) {
+          const int o = (ng * NBW + nb) * 16 + li;
           const float bo = bias ? bias[o] : 0.f;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -858,7 +861,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_bf16(int N, int n, int m,
     }
     __syncthreads();
     constexpr int QV = COUT / 8;  // 16-byte vectors per pixel
-    for (int e = tid; e < TR * TC * QV; e += 256) {
+    for (int e = tid; e < TR * TC * QV; e += NT) {
       const int px = e / QV, q = e - px * QV;
       const int y = y0 + px / TC, x = x0 + px % TC;
       if (y < n && x < m)
@@ -1093,15 +1096,38 @@ bool conv_mfma_bf16_supported(int cin, int cout) {
          (cin == 64 && cout == 32);
 }
 
+// Workgroups of `Kernel` (threads per workgroup as given) that one CU holds at once.
+template <auto Kernel>
+int resident_per_cu(int threads) {
+  static const int nb = [threads] {
+    int b = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, Kernel, threads, 0) != hipSuccess || b < 1) b = 1;
+    return b;
+  }();
+  return nb;
+}
+
+#ifndef BF_WG_WIDE
+#define BF_WG_WIDE 2
+#endif
+#ifndef BF_WG_32
+#define BF_WG_32 2
+#endif
+
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                            const void* in_nhwc, const void* wt, const float* bias, int act,
                            void* out_nhwc) {
+  // pairs with 64 channels hold one workgroup per CU (their weights fill most of the LDS):
+  // there two groups of four waves split the output channels of each tile
 #define OIC_BF_CASE(CI, CO)                                                                      \
   if (cin == CI && cout == CO) {                                                                 \
     constexpr int TRV = CI <= 32 ? 8 : 4;                                                        \
+    constexpr int WG = (CI == 64 || CO == 64) ? BF_WG_WIDE : (CO >= 32 ? BF_WG_32 : 1);          \
+    constexpr auto kern = k_conv_mfma_bf16<CI, CO, TRV, WG>;                                     \
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
-    const unsigned blocks = (unsigned)(tiles < 512 ? tiles : 512); /* persistent */             \
-    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_bf16<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, m, \
+    const long long cap = 256LL * resident_per_cu<kern>(256 * WG); /* persistent */             \
+    const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                               \
+    OIC_LAUNCH(t, kclass, s, kern, dim3(blocks), dim3(256 * WG), 0, N, n, m,                     \
                (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out_nhwc);         \
     return;                                                                                      \
   }
