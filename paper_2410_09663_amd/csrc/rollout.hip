@@ -882,8 +882,8 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
 // k order), B[k][j] likewise from lane j + 16g, element r of lane j + 16g holds
 // D[4g + r][j].  CIN is a multiple of 32, so the 32 K-indices of a lane are 32
 // consecutive channels of one tap.
-template <int CIN, int COUT, int TR>
-__global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
+template <int CIN, int COUT, int TR, int WG>
+__global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
                                                        const bf16_t* __restrict__ in,
                                                        const unsigned* __restrict__ amax_in,
                                                        const uint8_t* __restrict__ wq,
@@ -900,6 +900,9 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
   constexpr int KDP = KD128 + 16;
   constexpr int NB = COUT / 16;
   constexpr int RPW = TR / 4;
+  constexpr int NT = 256 * WG;  // WG groups of 4 waves split the output channels
+  constexpr int NBW = NB / WG;
+  static_assert(NB % WG == 0, "whole N-blocks per wave group");
   // halo tile and weights (bytes), and after the MFMA loop the BF16 output tile, share
   // one buffer
   constexpr int OP = COUT + 8;
@@ -922,20 +925,20 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
   {
     constexpr int WQ = KD128 / 16;  // 16-byte vectors per weight row
     constexpr int WV = COUT * WQ;
-    constexpr int WS = (WV + 255) / 256;
+    constexpr int WS = (WV + NT - 1) / NT;
     constexpr int IQ = CIN / 8;
     constexpr int IV = HR * HC * IQ;
-    constexpr int IS = (IV + 255) / 256;
+    constexpr int IS = (IV + NT - 1) / NT;
     u32x4 wv[WS];
     u16x8 iv[IS];
 #pragma unroll
     for (int u = 0; u < WS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       wv[u] = e < WV ? *(const u32x4*)(wq + (size_t)16 * e) : u32x4{0u, 0u, 0u, 0u};
     }
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       iv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
       if (e < IV) {
         const int q = e % IQ, pix = e / IQ;
@@ -947,12 +950,12 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
     }
 #pragma unroll
     for (int u = 0; u < WS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       if (e < WV) *(u32x4*)(s_w + (e / WQ) * KDP + 16 * (e % WQ)) = wv[u];
     }
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       if (e < IV) {
         uint32_t lo = 0u, hi = 0u;
         lo = __builtin_amdgcn_cvt_pk_fp8_f32(from_bf16(iv[u][0]) * inv_sa, from_bf16(iv[u][1]) * inv_sa, lo, false);
@@ -964,15 +967,15 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
     }
   }
   __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
+  const int lane = tid & 63, w = (tid >> 6) & 3, ng = tid >> 8;
   const int li = lane & 15, lk = lane >> 4;
-  f32x4 acc[RPW][4][NB];
+  f32x4 acc[RPW][4][NBW];
 #pragma unroll
   for (int rw = 0; rw < RPW; ++rw)
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int nb = 0; nb < NBW; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
   for (int kb = 0; kb < KD128 / 128; ++kb) {
     const int k0 = kb * 128 + 32 * lk;
@@ -980,10 +983,10 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
     const int kk = k0 < KD ? k0 : 0;
     const int tap = kk / CIN, c0 = kk - tap * CIN;
     const int dy = tap / 3, dx = tap - dy * 3;
-    i32x8 b[NB];
+    i32x8 b[NBW];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const uint8_t* src = s_w + (nb * 16 + li) * KDP + k0;
+    for (int nb = 0; nb < NBW; ++nb) {
+      const uint8_t* src = s_w + ((ng * NBW + nb) * 16 + li) * KDP + k0;
       const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
       b[nb] = i32x8{(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3], (int)v1[0], (int)v1[1], (int)v1[2],
                     (int)v1[3]};
@@ -998,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
         const i32x8 a = {(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3],
                          (int)v1[0], (int)v1[1], (int)v1[2], (int)v1[3]};
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NBW; ++nb)
           acc[rw][mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b[nb], acc[rw][mb][nb], 0, 0,
                                                                              0, 127, 0, 127);
       }
@@ -1016,8 +1019,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int o = nb * 16 + li;
+      for (int nb = 0; nb < NBW; ++nb) {
+        const int o = (ng * NBW + nb) * 16 + li;
         const float sc = sa * ws[o];
         const float bo = bias ? bias[o] : 0.f;
 #pragma unroll
@@ -1031,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_fp8(int N, int n, int m,
   }
   __syncthreads();
   constexpr int QV = COUT / 8;
-  for (int e = tid; e < TR * TC * QV; e += 256) {
+  for (int e = tid; e < TR * TC * QV; e += NT) {
     const int px = e / QV, q = e - px * QV;
     const int y = y0 + px / TC, x = x0 + px % TC;
     if (y < n && x < m)
@@ -1145,15 +1148,22 @@ bool conv_mfma_fp8_supported(int cin, int cout) {
   return (cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64);
 }
 
+#ifndef FP8_WG
+#define FP8_WG 1
+#endif
+
 void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                           const void* in_nhwc, const unsigned* amax_in, const uint8_t* wq, const float* ws,
                           const float* bias, int act, void* out_nhwc, unsigned* amax_out) {
+  // FP8_WG groups of four waves may split each tile's output channels; one group measured
+  // fastest here (256x256: 330 ms per solve against 421 with two)
 #define OIC_F8_CASE(CI, CO)                                                                        \
   if (cin == CI && cout == CO) {                                                                   \
     constexpr int TRV = 8;                                                                         \
+    constexpr int WG = CO >= 32 ? FP8_WG : 1;                                                      \
     const unsigned blocks = (unsigned)((long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64));     \
-    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_fp8<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, m,    \
-               (const bf16_t*)in_nhwc, amax_in, wq, ws, bias, act, (bf16_t*)out_nhwc, amax_out);     \
+    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_fp8<CI, CO, TRV, WG>), dim3(blocks), dim3(256 * WG), 0, N, n, \
+               m, (const bf16_t*)in_nhwc, amax_in, wq, ws, bias, act, (bf16_t*)out_nhwc, amax_out);  \
     return;                                                                                        \
   }
   OIC_F8_CASE(32, 16)
