@@ -884,13 +884,13 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
 // consecutive channels of one tap.
 template <int CIN, int COUT, int TR, int WG>
 __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
-                                                       const bf16_t* __restrict__ in,
-                                                       const unsigned* __restrict__ amax_in,
-                                                       const uint8_t* __restrict__ wq,
-                                                       const float* __restrict__ ws,
-                                                       const float* __restrict__ bias, int act,
-                                                       bf16_t* __restrict__ out,
-                                                       unsigned* __restrict__ amax_out) {
+                                                            const bf16_t* __restrict__ in,
+                                                            const unsigned* __restrict__ amax_in,
+                                                            const uint8_t* __restrict__ wq,
+                                                            const float* __restrict__ ws,
+                                                            const float* __restrict__ bias, int act,
+                                                            bf16_t* __restrict__ out,
+                                                            unsigned* __restrict__ amax_out) {
   static_assert(CIN % 32 == 0, "32 channels per lane fragment");
   constexpr int TC = 64;
   constexpr int HR = TR + 2, HC = TC + 2;
@@ -903,22 +903,23 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
   constexpr int NT = 256 * WG;  // WG groups of 4 waves split the output channels
   constexpr int NBW = NB / WG;
   static_assert(NB % WG == 0, "whole N-blocks per wave group");
-  // halo tile and weights (bytes), and after the MFMA loop the BF16 output tile, share
-  // one buffer
   constexpr int OP = COUT + 8;
-  constexpr int LDS_IN = HR * HC * CP + COUT * KDP, LDS_OUT = TR * 64 * OP * 2;
-  __shared__ __attribute__((aligned(16))) uint8_t s_buf[LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT];
-  uint8_t* const s_in = s_buf;
-  uint8_t* const s_w = s_buf + HR * HC * CP;
+  constexpr int IQ = CIN / 8;
+  constexpr int IV = HR * HC * IQ;
+  constexpr int IS = (IV + NT - 1) / NT;
+  // the weights stay resident; the FP8 halo tile and, after the MFMA loop, the BF16
+  // output tile share the rest
+  constexpr int LDS_IN = HR * HC * CP, LDS_OUT = TR * TC * OP * 2;
+  __shared__ __attribute__((aligned(16))) uint8_t s_w[COUT * KDP];
+  __shared__ __attribute__((aligned(16))) uint8_t s_tile[LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT];
+  uint8_t* const s_in = s_tile;
+  bf16_t* const s_out = reinterpret_cast<bf16_t*>(s_tile);
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
-  int bid = blockIdx.x;
-  const int ct = bid % col_tiles;
-  bid /= col_tiles;
-  const int rt = bid % row_tiles;
-  const int i = bid / row_tiles;
-  const int y0 = rt * TR, x0 = ct * TC;
+  const int tiles = N * row_tiles * col_tiles;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, w = (tid >> 6) & 3, ng = tid >> 8;
+  const int li = lane & 15, lk = lane >> 4;
   const float amx = __uint_as_float(*amax_in);
   const float sa = amx > 0.f ? amx * (1.0f / 448.0f) : 1.0f;
   const float inv_sa = 1.0f / sa;
@@ -926,16 +927,19 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
     constexpr int WQ = KD128 / 16;  // 16-byte vectors per weight row
     constexpr int WV = COUT * WQ;
     constexpr int WS = (WV + NT - 1) / NT;
-    constexpr int IQ = CIN / 8;
-    constexpr int IV = HR * HC * IQ;
-    constexpr int IS = (IV + NT - 1) / NT;
-    u32x4 wv[WS];
-    u16x8 iv[IS];
 #pragma unroll
     for (int u = 0; u < WS; ++u) {
       const int e = tid + NT * u;
-      wv[u] = e < WV ? *(const u32x4*)(wq + (size_t)16 * e) : u32x4{0u, 0u, 0u, 0u};
+      if (e < WV) *(u32x4*)(s_w + (e / WQ) * KDP + 16 * (e % WQ)) = *(const u32x4*)(wq + (size_t)16 * e);
     }
+  }
+  // Persistent over tiles tile, tile + gridDim.x, ...: the next tile's BF16 halo is loaded
+  // into registers while the current one is on the matrix cores.
+  u16x8 iv[IS];
+  auto load_halo = [&](int tile) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
       const int e = tid + NT * u;
@@ -948,11 +952,16 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
           iv[u] = *(const u16x8*)(in + (((size_t)i * n + gy) * m + gx) * CIN + 8 * q);
       }
     }
-#pragma unroll
-    for (int u = 0; u < WS; ++u) {
-      const int e = tid + NT * u;
-      if (e < WV) *(u32x4*)(s_w + (e / WQ) * KDP + 16 * (e % WQ)) = wv[u];
-    }
+  };
+  float vmax = 0.f;
+  int tile = blockIdx.x;
+  if (tile < tiles) load_halo(tile);
+  for (; tile < tiles; tile += gridDim.x) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+    __syncthreads();  // the previous tile's output has left s_tile (and s_w is staged)
+    // quantise the halo to e4m3 (x / sa) on its way into LDS
 #pragma unroll
     for (int u = 0; u < IS; ++u) {
       const int e = tid + NT * u;
@@ -965,80 +974,77 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
         *(u32x2*)(s_in + (e / IQ) * CP + 8 * (e % IQ)) = u32x2{lo, hi};
       }
     }
-  }
-  __syncthreads();
-  const int lane = tid & 63, w = (tid >> 6) & 3, ng = tid >> 8;
-  const int li = lane & 15, lk = lane >> 4;
-  f32x4 acc[RPW][4][NBW];
+    __syncthreads();
+    if (tile + (int)gridDim.x < tiles) load_halo(tile + gridDim.x);  // in flight meanwhile
+    f32x4 acc[RPW][4][NBW];
 #pragma unroll
-  for (int rw = 0; rw < RPW; ++rw)
+    for (int rw = 0; rw < RPW; ++rw)
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+      for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < NBW; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-  for (int kb = 0; kb < KD128 / 128; ++kb) {
-    const int k0 = kb * 128 + 32 * lk;
-    // past KD the weights are zero; read any in-tile (finite) activations there
-    const int kk = k0 < KD ? k0 : 0;
-    const int tap = kk / CIN, c0 = kk - tap * CIN;
-    const int dy = tap / 3, dx = tap - dy * 3;
-    i32x8 b[NBW];
-#pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) {
-      const uint8_t* src = s_w + ((ng * NBW + nb) * 16 + li) * KDP + k0;
-      const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
-      b[nb] = i32x8{(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3], (int)v1[0], (int)v1[1], (int)v1[2],
-                    (int)v1[3]};
-    }
-#pragma unroll
-    for (int rw = 0; rw < RPW; ++rw) {
-      const int ry = w + 4 * rw;
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const uint8_t* src = s_in + ((ry + dy) * HC + mb * 16 + li + dx) * CP + c0;
-        const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
-        const i32x8 a = {(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3],
-                         (int)v1[0], (int)v1[1], (int)v1[2], (int)v1[3]};
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb)
-          acc[rw][mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b[nb], acc[rw][mb][nb], 0, 0,
-                                                                             0, 127, 0, 127);
-      }
-    }
-  }
-  // Epilogue through LDS, as in the BF16 kernel: activated outputs into the BF16 tile
-  // [pixel][channel], then 16-byte NHWC stores; the largest |output| of the valid pixels
-  // goes to amax_out.
-  __syncthreads();  // every wave is done with the halo tile and the weights
-  bf16_t* const s_out = reinterpret_cast<bf16_t*>(s_buf);
-  float vmax = 0.f;
-#pragma unroll
-  for (int rw = 0; rw < RPW; ++rw) {
-    const int ty = w + 4 * rw;
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int kb = 0; kb < KD128 / 128; ++kb) {
+      const int k0 = kb * 128 + 32 * lk;
+      // past KD the weights are zero; read any in-tile (finite) activations there
+      const int kk = k0 < KD ? k0 : 0;
+      const int tap = kk / CIN, c0 = kk - tap * CIN;
+      const int dy = tap / 3, dx = tap - dy * 3;
+      i32x8 b[NBW];
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) {
-        const int o = (ng * NBW + nb) * 16 + li;
-        const float sc = sa * ws[o];
-        const float bo = bias ? bias[o] : 0.f;
+        const uint8_t* src = s_w + ((ng * NBW + nb) * 16 + li) * KDP + k0;
+        const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
+        b[nb] = i32x8{(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3], (int)v1[0], (int)v1[1], (int)v1[2],
+                      (int)v1[3]};
+      }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int tx = mb * 16 + 4 * lk + r;
-          const float v = activate(fmaf(acc[rw][mb][nb][r], sc, bo), act);
-          s_out[(ty * TC + tx) * OP + o] = to_bf16(v);
-          if (y0 + ty < n && x0 + tx < m) vmax = fmaxf(vmax, fabsf(v));
+      for (int rw = 0; rw < RPW; ++rw) {
+        const int ry = w + 4 * rw;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const uint8_t* src = s_in + ((ry + dy) * HC + mb * 16 + li + dx) * CP + c0;
+          const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
+          const i32x8 a = {(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3],
+                           (int)v1[0], (int)v1[1], (int)v1[2], (int)v1[3]};
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb)
+            acc[rw][mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b[nb], acc[rw][mb][nb], 0, 0,
+                                                                               0, 127, 0, 127);
         }
       }
-  }
-  __syncthreads();
-  constexpr int QV = COUT / 8;
-  for (int e = tid; e < TR * TC * QV; e += NT) {
-    const int px = e / QV, q = e - px * QV;
-    const int y = y0 + px / TC, x = x0 + px % TC;
-    if (y < n && x < m)
-      *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+    }
+    // Epilogue through LDS, as in the BF16 kernel: activated outputs into the BF16 tile
+    // [pixel][channel], then 16-byte NHWC stores; the largest |output| of the valid
+    // pixels goes to amax_out once the block is done.
+    __syncthreads();  // every wave is done with the halo tile
+#pragma unroll
+    for (int rw = 0; rw < RPW; ++rw) {
+      const int ty = w + 4 * rw;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+          const int o = (ng * NBW + nb) * 16 + li;
+          const float sc = sa * ws[o];
+          const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int tx = mb * 16 + 4 * lk + r;
+            const float v = activate(fmaf(acc[rw][mb][nb][r], sc, bo), act);
+            s_out[(ty * TC + tx) * OP + o] = to_bf16(v);
+            if (y0 + ty < n && x0 + tx < m) vmax = fmaxf(vmax, fabsf(v));
+          }
+        }
+    }
+    __syncthreads();
+    constexpr int QV = COUT / 8;
+    for (int e = tid; e < TR * TC * QV; e += NT) {
+      const int px = e / QV, q = e - px * QV;
+      const int y = y0 + px / TC, x = x0 + px % TC;
+      if (y < n && x < m)
+        *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+    }
   }
   amax_publish(vmax, amax_out);
 }
@@ -1149,21 +1155,25 @@ bool conv_mfma_fp8_supported(int cin, int cout) {
 }
 
 #ifndef FP8_WG
-#define FP8_WG 1
+#define FP8_WG 2
 #endif
 
 void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                           const void* in_nhwc, const unsigned* amax_in, const uint8_t* wq, const float* ws,
                           const float* bias, int act, void* out_nhwc, unsigned* amax_out) {
-  // FP8_WG groups of four waves may split each tile's output channels; one group measured
-  // fastest here (256x256: 330 ms per solve against 421 with two)
+  // 32+ output channels: two groups of four waves split each tile's output channels
+  // (persistent kernel, 256x256: 330 ms per solve non-persistent, 301 persistent with
+  // one group, 222 with two)
 #define OIC_F8_CASE(CI, CO)                                                                        \
   if (cin == CI && cout == CO) {                                                                   \
     constexpr int TRV = 8;                                                                         \
     constexpr int WG = CO >= 32 ? FP8_WG : 1;                                                      \
-    const unsigned blocks = (unsigned)((long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64));     \
-    OIC_LAUNCH(t, kclass, s, (k_conv_mfma_fp8<CI, CO, TRV, WG>), dim3(blocks), dim3(256 * WG), 0, N, n, \
-               m, (const bf16_t*)in_nhwc, amax_in, wq, ws, bias, act, (bf16_t*)out_nhwc, amax_out);  \
+    constexpr auto kern = k_conv_mfma_fp8<CI, CO, TRV, WG>;                                        \
+    const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);               \
+    const long long cap = 256LL * resident_per_cu<kern>(256 * WG); /* persistent */               \
+    const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                                 \
+    OIC_LAUNCH(t, kclass, s, kern, dim3(blocks), dim3(256 * WG), 0, N, n, m, (const bf16_t*)in_nhwc, \
+               amax_in, wq, ws, bias, act, (bf16_t*)out_nhwc, amax_out);                           \
     return;                                                                                        \
   }
   OIC_F8_CASE(32, 16)
