@@ -14,6 +14,9 @@ typedef float f32x4u __attribute__((ext_vector_type(4)));
 constexpr int UR = 64;  // trajectory rows per tile (4 waves x 16)
 constexpr int UC = 64;  // columns per tile (4 N-blocks of 16)
 constexpr int PB = 80;  // observation rows per LDS stage
+#ifndef UPD_WR
+#define UPD_WR 8
+#endif
 
 // traj[a][c] += sum_b K[a][b] (Ybar[b][c mod m] - Y[b][c]),  Ybar = [X^ref_t; 0],
 // on the FP32 matrix cores (v_mfma_f32_16x16x4_f32).  Wave w owns trajectory rows
@@ -21,15 +24,17 @@ constexpr int PB = 80;  // observation rows per LDS stage
 // the lane's own 16 trajectory values are all requested before the first LDS store.
 // Lane layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, element r of
 // lane j + 16g holds D[4g + r][j].
-__global__ __launch_bounds__(256) void k_update_mfma(Dims d, float* __restrict__ traj, int Ma,
+template <int WR>  // waves along the rows: tiles of 16 WR rows x 64 columns
+__global__ __launch_bounds__(64 * WR) void k_update_mfma(Dims d, float* __restrict__ traj, int Ma,
                                                      const float* __restrict__ K,
                                                      const float* __restrict__ Y,
                                                      const float* __restrict__ xref) {
-  __shared__ float sK[UR][PB + 1];
+  constexpr int NT = 64 * WR, TR_ = 16 * WR;
+  __shared__ float sK[TR_][PB + 1];
   __shared__ float sE[PB][UC + 1];
   const int NM = (int)d.NM();
   const int m = d.m, n = d.n, p = d.p();
-  const int r0 = blockIdx.y * UR;
+  const int r0 = blockIdx.y * TR_;
   const int c0 = blockIdx.x * UC;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -47,19 +52,19 @@ __global__ __launch_bounds__(256) void k_update_mfma(Dims d, float* __restrict__
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4u{0.f, 0.f, 0.f, 0.f};
   for (int b0 = 0; b0 < p; b0 += PB) {
-    constexpr int KS = UR * PB / 256;  // 20 gain values per thread
-    constexpr int ES = PB * UC / 256;  // 20 innovation values per thread
+    constexpr int KS = TR_ * PB / NT;  // 20 gain values per thread
+    constexpr int ES = PB * UC / NT;   // 20 innovation values per thread (10 with 8 waves)
     float kv[KS], ev[ES];
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int rl = e / PB, bl = e % PB;
       const int a = r0 + rl, b = b0 + bl;
       kv[u] = (a < Ma && b < p) ? K[(size_t)a * p + b] : 0.f;
     }
 #pragma unroll
     for (int u = 0; u < ES; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int bl = e / UC, cl = e % UC;
       const int b = b0 + bl, c = c0 + cl;
       float v = 0.f;
@@ -71,12 +76,12 @@ __global__ __launch_bounds__(256) void k_update_mfma(Dims d, float* __restrict__
     }
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       sK[e / PB][e % PB] = kv[u];
     }
 #pragma unroll
     for (int u = 0; u < ES; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       sE[e / UC][e % UC] = ev[u];
     }
     __syncthreads();
@@ -217,8 +222,10 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
                xref_t);
     return;
   }
-  OIC_LAUNCH(t, KC_UPDATE, s, k_update_mfma, dim3(col_tiles, row_tiles), dim3(256), 0, d, traj, Ma, K, Y,
-             xref_t);
+  constexpr int WR = UPD_WR;
+  const unsigned tall_tiles = (unsigned)((Ma + 16 * WR - 1) / (16 * WR));
+  OIC_LAUNCH(t, KC_UPDATE, s, k_update_mfma<WR>, dim3(col_tiles, tall_tiles), dim3(64 * WR), 0, d, traj, Ma, K,
+             Y, xref_t);
 }
 
 void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,
