@@ -353,8 +353,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32(int N, int n, int m,
 // keeps the weights in LDS and walks over tiles tile, tile + gridDim.x, ...; the next
 // tile's halo is loaded into registers while the current one is on the matrix cores,
 // so the global-load latency of a tile hides behind the previous tile's MFMAs.
-template <int CIN, int COUT, int TR>
-__global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
+template <int CIN, int COUT, int TR, int WGM>
+__global__ __launch_bounds__(256 * WGM) void k_conv_mfma_f32p(int N, int n, int m,
                                                         const float* __restrict__ in,
                                                         const float* __restrict__ wk,
                                                         const float* __restrict__ bias, int act,
@@ -364,10 +364,12 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
   constexpr int CP = CIN + 1;
   constexpr int KD = 9 * CIN;
   constexpr int NB = COUT / 16;
-  constexpr int RPW = TR / 4;
+  constexpr int NW = 4 * WGM, NT = 64 * NW;  // waves: one output row each per pass
+  static_assert(TR % NW == 0, "whole rows per wave");
+  constexpr int RPW = TR / NW;
   constexpr int Q = CIN / 4;
   constexpr int TOTAL = HR * HC * Q;
-  constexpr int SLOTS = (TOTAL + 255) / 256;
+  constexpr int SLOTS = (TOTAL + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
   __shared__ __attribute__((aligned(16))) float s_w[KD * COUT];
   const int col_tiles = (m + TC - 1) / TC;
@@ -378,10 +380,10 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
   const int li = lane & 15, lk = lane >> 4;
   {
     constexpr int WV = KD * COUT / 4;
-    constexpr int WS = (WV + 255) / 256;
+    constexpr int WS = (WV + NT - 1) / NT;
 #pragma unroll
     for (int u = 0; u < WS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       if (e < WV) *(f32x4*)(s_w + 4 * e) = *(const f32x4*)(wk + 4 * e);
     }
   }
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
     const int y0 = rt * TR, x0 = ct * TC;
 #pragma unroll
     for (int u = 0; u < SLOTS; ++u) {
-      const int e = tid + u * 256;
+      const int e = tid + u * NT;
       v[u] = f32x4{0.f, 0.f, 0.f, 0.f};
       if (e < TOTAL) {
         const int q = e % Q, pix = e / Q;
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
     __syncthreads();  // the previous tile's MFMAs are done with s_in (and s_w is staged)
 #pragma unroll
     for (int u = 0; u < SLOTS; ++u) {
-      const int e = tid + u * 256;
+      const int e = tid + u * NT;
       if (e < TOTAL) {
         const int q = e % Q, pix = e / Q;
         float* dst = s_in + pix * CP + 4 * q;
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
       for (int nb = 0; nb < NB; ++nb) b[nb] = s_w[k * COUT + nb * 16 + li];
 #pragma unroll
       for (int rw = 0; rw < RPW; ++rw) {
-        const int ry = w + 4 * rw;
+        const int ry = w + NW * rw;
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           const float a = s_in[((ry + dy) * HC + mb * 16 + li + dx) * CP + c];
@@ -453,7 +455,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma_f32p(int N, int n, int m,
     }
 #pragma unroll
     for (int rw = 0; rw < RPW; ++rw) {
-      const int y = y0 + w + 4 * rw;
+      const int y = y0 + w + NW * rw;
       if (y >= n) continue;
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
@@ -1193,21 +1195,26 @@ bool conv_mfma_supported(int cin, int cout) {
   return (cin == 16 || cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64);
 }
 
+#ifndef F32_W8
+#define F32_W8 1
+#endif
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                       const float* in_nhwc, const float* wk, const float* bias, int act,
                       float* out_nhwc) {
 #define OIC_CONV_CASE(CI, CO)                                                                   \
   if (cin == CI && cout == CO) {                                                                \
-    constexpr int TRV = (CI <= 16 && CO <= 32 && CO != CI) ? 8 : 4;                             \
+    constexpr bool W8 = CI == 16 && CO == 16 && F32_W8;  /* 8 waves, one row each */            \
+    constexpr int TRV = W8 ? 8 : ((CI <= 16 && CO <= 32 && CO != CI) ? 8 : 4);                 \
+    constexpr int WGM = W8 ? 2 : 1;                                                             \
     constexpr int CCH = CI <= 32 ? CI : 32;                                                     \
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
     if constexpr (CCH == CI) {  /* persistent: as many workgroups as the CUs' LDS holds */      \
       constexpr int lds = 4 * ((TRV + 2) * 66 * (CI + 1) + 9 * CI * CO);                         \
-      constexpr int per_cu = 160 * 1024 / lds < 4 ? 160 * 1024 / lds : 4;                        \
+      constexpr int per_cu = 160 * 1024 / lds < 4 / WGM ? 160 * 1024 / lds : 4 / WGM;            \
       constexpr long long cap = 256LL * (per_cu > 0 ? per_cu : 1);                               \
       const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                            \
-      OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32p<CI, CO, TRV>), dim3(blocks), dim3(256), 0, N, n, \
-                 m, in_nhwc, wk, bias, act, out_nhwc);                                          \
+      OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32p<CI, CO, TRV, WGM>), dim3(blocks), dim3(256 * WGM), \
+                 0, N, n, m, in_nhwc, wk, bias, act, out_nhwc);                                 \
     } else {                                                                                    \
       OIC_LAUNCH(t, kclass, s, (k_conv_mfma_f32<CI, CO, TRV, CCH>), dim3((unsigned)tiles), dim3(256), \
                  0, N, n, m, in_nhwc, wk, bias, act, out_nhwc);                                 \

@@ -11,9 +11,11 @@ namespace {
 
 typedef float f32x4u __attribute__((ext_vector_type(4)));
 
-constexpr int UR = 64;  // trajectory rows per tile (4 waves x 16)
 constexpr int UC = 64;  // columns per tile (4 N-blocks of 16)
 constexpr int PB = 80;  // observation rows per LDS stage
+#ifndef UPD_ROWS_WR
+#define UPD_ROWS_WR 8
+#endif
 #ifndef UPD_WR
 #define UPD_WR 8
 #endif
@@ -107,11 +109,13 @@ __global__ __launch_bounds__(64 * WR) void k_update_mfma(Dims d, float* __restri
 // columns 64x .. 64x + 63 and row tiles y, y + gridDim.y, ...  The innovation tile is
 // formed in LDS once per block; the gain rows and the trajectory values of the next row
 // tile are loaded into registers while the current tile is on the matrix cores.
-__global__ __launch_bounds__(256) void k_update_rows(Dims d, float* __restrict__ traj, int Ma,
+template <int WR>  // waves along the rows: tiles of 16 WR rows
+__global__ __launch_bounds__(64 * WR) void k_update_rows(Dims d, float* __restrict__ traj, int Ma,
                                                      const float* __restrict__ K,
                                                      const float* __restrict__ Y,
                                                      const float* __restrict__ xref) {
-  __shared__ float sK[UR][PB + 1];
+  constexpr int NT = 64 * WR, TR_ = 16 * WR;
+  __shared__ float sK[TR_][PB + 1];
   __shared__ float sE[PB][UC + 1];
   const int NM = (int)d.NM();
   const int m = d.m, n = d.n, p = d.p();
@@ -119,12 +123,12 @@ __global__ __launch_bounds__(256) void k_update_rows(Dims d, float* __restrict__
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int row_tiles = (Ma + UR - 1) / UR;
-  constexpr int KS = UR * PB / 256;  // 20 gain values per thread
-  constexpr int ES = PB * UC / 256;  // 20 innovation values per thread
+  const int row_tiles = (Ma + TR_ - 1) / TR_;
+  constexpr int KS = TR_ * PB / NT;  // 20 gain values per thread
+  constexpr int ES = PB * UC / NT;   // innovation values per thread
 #pragma unroll
   for (int u = 0; u < ES; ++u) {
-    const int e = tid + 256 * u;
+    const int e = tid + NT * u;
     const int b = e / UC, cl = e % UC;
     const int c = c0 + cl;
     float v = 0.f;
@@ -136,10 +140,10 @@ __global__ __launch_bounds__(256) void k_update_rows(Dims d, float* __restrict__
   }
   float kv[KS], old[4][4];
   auto load_rows = [&](int rt) {
-    const int r0 = rt * UR;
+    const int r0 = rt * TR_;
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int rl = e / PB, b = e % PB;
       const int a = r0 + rl;
       kv[u] = (a < Ma && b < p) ? K[(size_t)a * p + b] : 0.f;
@@ -155,11 +159,11 @@ __global__ __launch_bounds__(256) void k_update_rows(Dims d, float* __restrict__
   int rt = blockIdx.y;
   if (rt < row_tiles) load_rows(rt);
   for (; rt < row_tiles; rt += gridDim.y) {
-    const int r0 = rt * UR;
+    const int r0 = rt * TR_;
     __syncthreads();  // the previous tile's products are done with sK (and sE is complete)
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       sK[e / PB][e % PB] = kv[u];
     }
     float cur[4][4];
@@ -213,12 +217,13 @@ __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restric
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
                    const float* Y, const float* xref_t) {
   const unsigned col_tiles = (unsigned)((d.NM() + UC - 1) / UC);
-  const unsigned row_tiles = (unsigned)((Ma + UR - 1) / UR);
   if (d.p() <= PB) {
+    constexpr int WR = UPD_ROWS_WR;
+    const unsigned row_tiles = (unsigned)((Ma + 16 * WR - 1) / (16 * WR));
     // about two workgroups per CU (the register budget allows two) on 256 CUs
     const unsigned want = (512 + col_tiles - 1) / col_tiles;
     const unsigned groups = row_tiles < want ? row_tiles : want;
-    OIC_LAUNCH(t, KC_UPDATE, s, k_update_rows, dim3(col_tiles, groups), dim3(256), 0, d, traj, Ma, K, Y,
+    OIC_LAUNCH(t, KC_UPDATE, s, k_update_rows<WR>, dim3(col_tiles, groups), dim3(64 * WR), 0, d, traj, Ma, K, Y,
                xref_t);
     return;
   }
