@@ -123,7 +123,11 @@ __global__ void k_means_f64(const float* __restrict__ A, int rows, int N, int m,
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
-constexpr int MA = 64;  // left rows per tile (4 waves x 16)
+// Left operands with at least this many rows use 8-wave blocks (128 left rows sharing
+// each staged right tile; the right tile is then loaded once per 128 rows, not 64).
+#ifndef STATS_TALL
+#define STATS_TALL 256
+#endif
 constexpr int MK = 64;  // columns per LDS stage
 
 // part[z][a][b] = sum over the columns c of chunk z of L[a][c] * D[b][c], where the
@@ -134,25 +138,26 @@ constexpr int MK = 64;  // columns per LDS stage
 // FP64-centred D sums to zero over the members (to FP64 rounding), the left rows
 // need no centring: sum_i X^i D^iT = sum_i (X^i - mean) D^iT.
 //
-// FP64 matrix cores (v_mfma_f64_16x16x4_f64); a block of 4 waves owns 64 left rows
+// FP64 matrix cores (v_mfma_f64_16x16x4_f64); a block of WL waves owns 16*WL left rows
 // and NB*16 right rows; wave w computes left rows 16w..16w+15 against all NB
 // blocks.  Lane layout: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
 // element r of lane j + 16g holds D[g + 4r][j].  VEC: rows are 16-byte aligned
 // (N*m divisible by 4) and loaded as float4, one stage ahead of the compute.
-template <int NB, bool VEC>
-__global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restrict__ traj, int Ma,
+template <int NB, bool VEC, int WL>  // WL waves, 16 left rows each
+__global__ __launch_bounds__(64 * WL) void k_stats_mfma(Dims d, const float* __restrict__ traj, int Ma,
                                                     int ny, const float* __restrict__ Y,
                                                     const float* __restrict__ R, int p,
                                                     const double* __restrict__ muY, int chunk,
                                                     double* __restrict__ part) {
   // right operand: the p rows of R (Ybar for the statistics), centred by muY
   constexpr int RB = NB * 16;
-  __shared__ float sA[MA][MK + 1];
+  constexpr int MA_ = 16 * WL, NT = 64 * WL;
+  __shared__ float sA[MA_][MK + 1];
   __shared__ double sB[RB][MK + 1];
   const int NM = (int)d.NM();
   const int m = d.m;
   const int Mtot = Ma + ny;
-  const int a0 = blockIdx.x * MA;
+  const int a0 = blockIdx.x * MA_;
   const int b0 = blockIdx.y * RB;
   const int c_begin = blockIdx.z * chunk;
   const int c_end = min(c_begin + chunk, NM);
@@ -163,9 +168,10 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  // per-thread load slots: A tile = 64 rows x 64 cols; B tile = RB rows x 64 cols
-  constexpr int AV = MA * MK / 4 / 256;  // float4 slots per thread (4)
-  constexpr int BV = RB * MK / 4 / 256;  // (NB)
+  // per-thread load slots: A tile = MA_ rows x 64 cols; B tile = RB rows x 64 cols
+  constexpr int AV = MA_ * MK / 4 / NT;  // float4 slots per thread (4)
+  constexpr int BQ = RB * MK / 4;  // float4 slots of the right tile
+  constexpr int BV = (BQ + NT - 1) / NT;  // (last slot guarded when NT does not divide BQ)
   f32x4v ra[AV], rb[BV];
   auto left_row = [&](int a) -> const float* {
     return a < Ma ? traj + (size_t)a * NM : Y + (size_t)(a - Ma) * NM;
@@ -173,7 +179,7 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
   auto load_stage = [&](int c0) {
 #pragma unroll
     for (int u = 0; u < AV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int r = e / (MK / 4), q = e % (MK / 4);
       const int a = a0 + r, c = c0 + 4 * q;
       f32x4v v = {0.f, 0.f, 0.f, 0.f};
@@ -190,11 +196,11 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
     }
 #pragma unroll
     for (int u = 0; u < BV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int r = e / (MK / 4), q = e % (MK / 4);
       const int b = b0 + r, c = c0 + 4 * q;
       f32x4v v = {0.f, 0.f, 0.f, 0.f};
-      if (b < p) {
+      if (e < BQ && b < p) {
         const float* src = R + (size_t)b * NM;
         if (VEC) {
           if (c < c_end) v = *(const f32x4v*)(src + c);
@@ -211,14 +217,15 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
     // registers -> LDS (right operand centred in FP64)
 #pragma unroll
     for (int u = 0; u < AV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int r = e / (MK / 4), q = e % (MK / 4);
 #pragma unroll
       for (int j = 0; j < 4; ++j) sA[r][4 * q + j] = ra[u][j];
     }
 #pragma unroll
     for (int u = 0; u < BV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
+      if (e >= BQ) continue;
       const int r = e / (MK / 4), q = e % (MK / 4);
       const int b = b0 + r, c = c0 + 4 * q;
       int x = c % m;
@@ -258,19 +265,20 @@ __global__ __launch_bounds__(256) void k_stats_mfma(Dims d, const float* __restr
 // then folded into FP64 registers, and the split partials are summed in FP64 as before.
 // Lane layout (16x16x4 f32): A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
 // element r of lane j + 16g holds D[4g + r][j].
-template <int NB, bool VEC>
-__global__ __launch_bounds__(256) void k_stats_mfma32(Dims d, const float* __restrict__ traj, int Ma,
+template <int NB, bool VEC, int WL>  // WL waves, 16 left rows each
+__global__ __launch_bounds__(64 * WL) void k_stats_mfma32(Dims d, const float* __restrict__ traj, int Ma,
                                                       int ny, const float* __restrict__ Y,
                                                       const float* __restrict__ R, int p,
                                                       const double* __restrict__ muY, int chunk,
                                                       double* __restrict__ part) {
   constexpr int RB = NB * 16;
-  __shared__ float sA[MA][MK + 1];
+  constexpr int MA_ = 16 * WL, NT = 64 * WL;
+  __shared__ float sA[MA_][MK + 1];
   __shared__ float sB[RB][MK + 1];
   const int NM = (int)d.NM();
   const int m = d.m;
   const int Mtot = Ma + ny;
-  const int a0 = blockIdx.x * MA;
+  const int a0 = blockIdx.x * MA_;
   const int b0 = blockIdx.y * RB;
   const int c_begin = blockIdx.z * chunk;
   const int c_end = min(c_begin + chunk, NM);
@@ -284,8 +292,9 @@ __global__ __launch_bounds__(256) void k_stats_mfma32(Dims d, const float* __res
     acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
     tot[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  constexpr int AV = MA * MK / 4 / 256;
-  constexpr int BV = RB * MK / 4 / 256;
+  constexpr int AV = MA_ * MK / 4 / NT;
+  constexpr int BQ = RB * MK / 4;  // float4 slots of the right tile
+  constexpr int BV = (BQ + NT - 1) / NT;
   f32x4v ra[AV], rb[BV];
   auto left_row = [&](int a) -> const float* {
     return a < Ma ? traj + (size_t)a * NM : Y + (size_t)(a - Ma) * NM;
@@ -293,7 +302,7 @@ __global__ __launch_bounds__(256) void k_stats_mfma32(Dims d, const float* __res
   auto load_stage = [&](int c0) {
 #pragma unroll
     for (int u = 0; u < AV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int r = e / (MK / 4), q = e % (MK / 4);
       const int a = a0 + r, c = c0 + 4 * q;
       f32x4v v = {0.f, 0.f, 0.f, 0.f};
@@ -310,11 +319,11 @@ __global__ __launch_bounds__(256) void k_stats_mfma32(Dims d, const float* __res
     }
 #pragma unroll
     for (int u = 0; u < BV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int r = e / (MK / 4), q = e % (MK / 4);
       const int b = b0 + r, c = c0 + 4 * q;
       f32x4v v = {0.f, 0.f, 0.f, 0.f};
-      if (b < p) {
+      if (e < BQ && b < p) {
         const float* src = R + (size_t)b * NM;
         if (VEC) {
           if (c < c_end) v = *(const f32x4v*)(src + c);
@@ -331,14 +340,15 @@ __global__ __launch_bounds__(256) void k_stats_mfma32(Dims d, const float* __res
   for (int c0 = c_begin; c0 < c_end; c0 += MK, ++stage) {
 #pragma unroll
     for (int u = 0; u < AV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
       const int r = e / (MK / 4), q = e % (MK / 4);
 #pragma unroll
       for (int j = 0; j < 4; ++j) sA[r][4 * q + j] = ra[u][j];
     }
 #pragma unroll
     for (int u = 0; u < BV; ++u) {
-      const int e = tid + 256 * u;
+      const int e = tid + NT * u;
+      if (e >= BQ) continue;
       const int r = e / (MK / 4), q = e % (MK / 4);
       const int b = b0 + r, c = c0 + 4 * q;
       int x = c % m;
@@ -456,12 +466,16 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   const int nbk = (p + 15) / 16;
   const int ytiles = (nbk + 7) / 8;
   const int NB = (nbk + ytiles - 1) / ytiles;
-  const int tiles = ((Mtot + MA - 1) / MA) * ytiles;
+  // eight waves (128 left rows) share each staged right tile once the left side is tall
+  const bool tall = Mtot >= STATS_TALL;
+  const int ma = tall ? 128 : 64;
+  const int tiles = ((Mtot + ma - 1) / ma) * ytiles;
   // Split K so that about two workgroups per CU (their LDS allows two) are in flight
   // even for the few output tiles of the early horizon steps: a workgroup's time is set
   // by its chunk of K, not by the size of the output.  Chunks are whole 64-column
   // stages; the partials must fit the split buffer.
-  int splits = (512 + tiles - 1) / tiles;
+  const int target = tall ? 256 : 512;  // the same number of waves in flight either way
+  int splits = (target + tiles - 1) / tiles;
   const int max_by_len = (NM + MK - 1) / MK;
   if (splits > max_by_len) splits = max_by_len;
   const size_t by_cap = part_cap / ((size_t)Mtot * p);
@@ -470,28 +484,37 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   int chunk = (NM + splits - 1) / splits;
   chunk = (chunk + MK - 1) / MK * MK;
   splits = (NM + chunk - 1) / chunk;
-  const dim3 grid((unsigned)((Mtot + MA - 1) / MA), (unsigned)ytiles, (unsigned)splits);
+  const dim3 grid((unsigned)((Mtot + ma - 1) / ma), (unsigned)ytiles, (unsigned)splits);
   const bool vec = NM % 4 == 0;
+#define OIC_STATS_LAUNCH(KERN, NBV, WLV)                                                        \
+  OIC_LAUNCH(t, KC_STATS, s, (KERN<NBV, true, WLV>), grid, dim3(64 * WLV), 0, d, traj, Ma, ny, Y, R, p, \
+             muR, chunk, part)
+#define OIC_STATS_LAUNCH_NV(KERN, NBV, WLV)                                                     \
+  OIC_LAUNCH(t, KC_STATS, s, (KERN<NBV, false, WLV>), grid, dim3(64 * WLV), 0, d, traj, Ma, ny, Y, R, \
+             p, muR, chunk, part)
 #define OIC_STATS_CASE(NBV)                                                                     \
   case NBV:                                                                                     \
-    if (f32 && vec)                                                                             \
-      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma32<NBV, true>), grid, dim3(256), 0, d, traj, Ma,   \
-                 ny, Y, R, p, muR, chunk, part);                                                \
-    else if (f32)                                                                               \
-      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma32<NBV, false>), grid, dim3(256), 0, d, traj, Ma,  \
-                 ny, Y, R, p, muR, chunk, part);                                                \
-    else if (vec)                                                                               \
-      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, true>), grid, dim3(256), 0, d, traj, Ma, ny, \
-                 Y, R, p, muR, chunk, part);                                                    \
-    else                                                                                        \
-      OIC_LAUNCH(t, KC_STATS, s, (k_stats_mfma<NBV, false>), grid, dim3(256), 0, d, traj, Ma, ny,\
-                 Y, R, p, muR, chunk, part);                                                    \
+    if (f32) {                                                                                  \
+      if (vec) {                                                                                \
+        if (tall) OIC_STATS_LAUNCH(k_stats_mfma32, NBV, 8); else OIC_STATS_LAUNCH(k_stats_mfma32, NBV, 4); \
+      } else {                                                                                  \
+        if (tall) OIC_STATS_LAUNCH_NV(k_stats_mfma32, NBV, 8); else OIC_STATS_LAUNCH_NV(k_stats_mfma32, NBV, 4); \
+      }                                                                                         \
+    } else {                                                                                    \
+      if (vec) {                                                                                \
+        if (tall) OIC_STATS_LAUNCH(k_stats_mfma, NBV, 8); else OIC_STATS_LAUNCH(k_stats_mfma, NBV, 4); \
+      } else {                                                                                  \
+        if (tall) OIC_STATS_LAUNCH_NV(k_stats_mfma, NBV, 8); else OIC_STATS_LAUNCH_NV(k_stats_mfma, NBV, 4); \
+      }                                                                                         \
+    }                                                                                           \
     break;
   switch (NB) {
     OIC_STATS_CASE(1) OIC_STATS_CASE(2) OIC_STATS_CASE(3) OIC_STATS_CASE(4)
     OIC_STATS_CASE(5) OIC_STATS_CASE(6) OIC_STATS_CASE(7) OIC_STATS_CASE(8)
   }
 #undef OIC_STATS_CASE
+#undef OIC_STATS_LAUNCH
+#undef OIC_STATS_LAUNCH_NV
   const long long count = (long long)Mtot * p;
   OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 63) / 64)), dim3(64, RG), 0,
              part, splits, count, scale, S);
