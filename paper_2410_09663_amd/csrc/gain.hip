@@ -13,7 +13,7 @@ namespace oic {
 namespace {
 
 constexpr int kCholThreads = 512;                  // 8 waves
-constexpr int kLdsMaxP = 90;                       // two p x (p+1) FP64 arrays in the 160 KiB LDS
+constexpr int kLdsMaxP = 90;                       // two p8 x (p8+1) FP64 arrays (p8 <= 96) in the 160 KiB LDS
 constexpr int NBK = 8;                             // panel width
 constexpr int kMaxPanelsLds = (kLdsMaxP + NBK - 1) / NBK;  // 12
 
@@ -76,12 +76,15 @@ __device__ __forceinline__ void mfma_tile_update(double* M, int ld, int rows, in
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + lk + 4 * r, j = j0 + li;
-    acc[r] = (i < rows && j < cols) ? M[i * ld + j] : 0.0;
+    const double v = M[min(i, rows - 1) * ld + min(j, cols - 1)];  // clamped: loads need no branch
+    acc[r] = (i < rows && j < cols) ? v : 0.0;
   }
   for (int k0 = 0; k0 < K; k0 += 4) {
     const int k = k0 + lk;
-    const double av = (k < K) ? a(i0 + li, k) : 0.0;
-    const double bv = (k < K) ? sign * b(k, j0 + li) : 0.0;
+    const int kc = min(k, K - 1);  // clamped operand reads, zeroed past K
+    const double a_ = a(i0 + li, kc), b_ = b(kc, j0 + li);
+    const double av = (k < K) ? a_ : 0.0;
+    const double bv = (k < K) ? sign * b_ : 0.0;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
   }
 #pragma unroll
@@ -103,8 +106,8 @@ __device__ __forceinline__ void mfma_tile_update(double* M, int ld, int rows, in
 // a rank-8 update of the rows below, on the matrix cores), and (Sigma^Y)^{-1} = W^T W
 // is one more matrix-core product.  The odd leading dimension spreads the rows read by
 // the 16 lanes of an operand fragment over distinct LDS banks.
-template <int MAXPAN, bool SQUARE>
-__device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double* __restrict__ Sinv,
+template <int MAXPAN, bool SQUARE, bool PAD8 = false>
+__device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double* __restrict__ Sinv, int pout,
                                              int* __restrict__ flag) {
   const int ld = p + 1;
   __shared__ int bad;
@@ -125,7 +128,7 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
   // Factor the pb-th 8 x 8 diagonal block (wave 0 only; every update it receives is done).
   auto factor_diag = [&](int pb) {
     const int kb = pb * NBK;
-    const int nb = min(NBK, p - kb);
+    const int nb = PAD8 ? NBK : min(NBK, p - kb);
     // Every lane factors the whole 8 x 8 diagonal block in its own registers (no
     // cross-lane traffic; identity rows pad a short last panel), keeping the
     // reciprocal square roots for the block inverse.
@@ -134,13 +137,16 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
     for (int r = 0; r < NBK; ++r)
 #pragma unroll
       for (int c = 0; c < NBK; ++c)
-        a[r][c] = c > r ? 0.0 : ((r < nb) ? A[(kb + r) * ld + kb + c] : (r == c ? 1.0 : 0.0));
+        a[r][c] = c > r ? 0.0
+                        : ((r < nb) ? A[min(kb + r, p - 1) * ld + min(kb + c, p - 1)]  // clamped: no branch
+                                    : (r == c ? 1.0 : 0.0));
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < NBK; ++k) {
       const double d = a[k][k];
       if (!(d > 0.0 && isfinite(d))) ok = false;
-      rs[k] = (d > 0.0 && isfinite(d)) ? rsqrt_nr(d) : 1.0;
+      const double rk = rsqrt_nr(d);  // computed unconditionally, selected below (no branch)
+      rs[k] = (d > 0.0 && isfinite(d)) ? rk : 1.0;
       a[k][k] = d * rs[k];
 #pragma unroll
       for (int r = k + 1; r < NBK; ++r) a[r][k] *= rs[k];
@@ -178,7 +184,7 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
   for (int pb = 0; pb < npan; ++pb) {
     if (bad) break;  // uniform
     const int kb = pb * NBK;
-    const int nb = min(NBK, p - kb);
+    const int nb = PAD8 ? NBK : min(NBK, p - kb);
     const int r0 = kb + nb, rem = p - r0;
     // rows below: L21 = A21 L11^{-T}
     for (int i = r0 + tid; i < p; i += kCholThreads) {
@@ -227,8 +233,8 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
         const int tj = t - ti * (ti + 1) / 2;
         mfma_tile_update(
             A, ld, p, p, r0 + 16 * ti, r0 + 16 * tj, NBK,
-            [&](int i, int k) { return i < p ? A[i * ld + kb + k] : 0.0; },
-            [&](int k, int j) { return j < p ? A[j * ld + kb + k] : 0.0; }, -1.0);
+            [&](int i, int k) { const double v = A[min(i, p - 1) * ld + kb + k]; return i < p ? v : 0.0; },
+            [&](int k, int j) { const double v = A[min(j, p - 1) * ld + kb + k]; return j < p ? v : 0.0; }, -1.0);
       };
       if (wave == 0) {
         a22_tile(0);
@@ -242,8 +248,8 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
             const int ti = u / ntj, tj = u - ti * ntj;
             mfma_tile_update(
                 W, ld, p, cols, cols + 16 * ti, 16 * tj, nb,
-                [&](int i, int k) { return i < p ? A[i * ld + kb + k] : 0.0; },
-                [&](int k, int j) { return j < cols ? W[(kb + k) * ld + j] : 0.0; }, -1.0);
+                [&](int i, int k) { const double v = A[min(i, p - 1) * ld + kb + k]; return i < p ? v : 0.0; },
+                [&](int k, int j) { const double v = W[(kb + k) * ld + min(j, cols - 1)]; return j < cols ? v : 0.0; }, -1.0);
           }
         }
       }
@@ -279,9 +285,9 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + lk + 4 * r, j = j0 + li;
-        if (i < p && j < p) {
-          Sinv[i * p + j] = acc[r];
-          Sinv[j * p + i] = acc[r];
+        if (i < pout && j < pout) {
+          Sinv[i * pout + j] = acc[r];
+          Sinv[j * pout + i] = acc[r];
         }
       }
     }
@@ -292,24 +298,31 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const double* __restrict__ Syy,
                                                                double* __restrict__ Sinv,
                                                                int* __restrict__ flag) {
+  // Sigma^Y padded to p8 = p rounded up to a multiple of the panel width, with an identity
+  // block: the factor of the padded matrix is diag(L, I), and every panel is full (no
+  // branches on a short last panel).
   extern __shared__ double lds[];
+  const int p8 = (p + NBK - 1) / NBK * NBK;
   {
-    // every load of Sigma^Y in flight at once (p * p <= kLoadSlots * kCholThreads), then into LDS
-    constexpr int kLoadSlots = (kLdsMaxP * kLdsMaxP + kCholThreads - 1) / kCholThreads;
+    // every load of Sigma^Y in flight at once (p8 * p8 <= kLoadSlots * kCholThreads), then into LDS
+    constexpr int kMaxP8 = (kLdsMaxP + NBK - 1) / NBK * NBK;
+    constexpr int kLoadSlots = (kMaxP8 * kMaxP8 + kCholThreads - 1) / kCholThreads;
     double v[kLoadSlots];
 #pragma unroll
     for (int u = 0; u < kLoadSlots; ++u) {
       const int idx = threadIdx.x + kCholThreads * u;
-      v[u] = idx < p * p ? Syy[idx] : 0.0;
+      const int r = idx / p8, c = idx - r * p8;
+      v[u] = (r < p && c < p) ? Syy[r * p + c] : (r == c ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int u = 0; u < kLoadSlots; ++u) {
       const int idx = threadIdx.x + kCholThreads * u;
-      if (idx < p * p) lds[(idx / p) * (p + 1) + idx % p] = v[u];
+      const int r = idx / p8, c = idx - r * p8;
+      if (idx < p8 * p8) lds[r * (p8 + 1) + c] = v[u];
     }
   }
   __syncthreads();
-  chol_inverse<kMaxPanelsLds, true>(p, lds, lds + p * (p + 1), Sinv, flag);
+  chol_inverse<kMaxPanelsLds, true, true>(p8, lds, lds + p8 * (p8 + 1), Sinv, p, flag);
 }
 
 // K[a][b] = sum_c Sxy[a][c] Sinv[c][b], FP64, rounded to FP32 (any p).  Block (64, 4).
@@ -414,7 +427,7 @@ __global__ __launch_bounds__(kCholThreads) void k_potrf_diag(int p, double* __re
       nb * nb, [&](int e) { return A[(size_t)(kb + e / nb) * p + kb + e % nb]; },
       [&](int e, double v) { sA[(e / nb) * ld + e % nb] = v; });
   __syncthreads();
-  if (!chol_inverse<kPB / NBK, false>(nb, sA, sW, nullptr, flag)) return;
+  if (!chol_inverse<kPB / NBK, false>(nb, sA, sW, nullptr, 0, flag)) return;
   __syncthreads();
   double* out = Linv + (size_t)(kb / kPB) * kPB * kPB;
   for (int e = threadIdx.x; e < kPB * kPB; e += kCholThreads) {
@@ -650,13 +663,15 @@ size_t gain_trsm_lds(int p, int RB) {
 void launch_chol(hipStream_t s, Timer& t, int p, double* Syy, double* Lwork, double* Sinv, int* flag) {
   if (p <= kLdsMaxP) {
     static const bool attr_set = [] {  // thread-safe one-time set-up
+      constexpr int kMaxP8 = (kLdsMaxP + NBK - 1) / NBK * NBK;
       hipFuncSetAttribute((const void*)k_chol_inv_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          2 * kLdsMaxP * (kLdsMaxP + 1) * (int)sizeof(double));
+                          2 * kMaxP8 * (kMaxP8 + 1) * (int)sizeof(double));
       return true;
     }();
     (void)attr_set;
+    const int p8 = (p + NBK - 1) / NBK * NBK;  // padded order (identity block)
     OIC_LAUNCH(t, KC_CHOL, s, k_chol_inv_lds, dim3(1), dim3(kCholThreads),
-               2 * (size_t)p * (p + 1) * sizeof(double), p, Syy, Sinv, flag);
+               2 * (size_t)p8 * (p8 + 1) * sizeof(double), p, Syy, Sinv, flag);
     return;
   }
   // blocked: Syy is factored in place, the diagonal-block inverses go to Lwork
