@@ -64,7 +64,10 @@ __device__ __forceinline__ void staged_copy(int count, Load load, Store store) {
 
 // D(16x16 tile at rows i0, cols j0 of M, leading dimension ld) += sum_k Aop[i][k] Bop[k][j]
 // over k = 0..K-1 on the FP64 matrix cores, where the operands are read through the
-// functors a(i, k) and b(k, j) (zero outside their ranges).  Lane layout (16x16x4 f64):
+// functors a(i, k) and b(k, j).  Reads are clamped into range and never skipped (a load
+// under a branch costs a full LDS round trip): outside rows/cols the tile holds values
+// that are never stored, since each output element depends only on its own row of A,
+// column of B and accumulator; only the k >= K terms must be zeroed.  Lane layout (16x16x4 f64):
 // A[i][k] from lane i + 16g (k = 4s + g), B[k][j] from lane j + 16g, element r of lane
 // j + 16g holds D[g + 4r][j].
 template <typename FA, typename FB>
@@ -76,8 +79,7 @@ __device__ __forceinline__ void mfma_tile_update(double* M, int ld, int rows, in
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + lk + 4 * r, j = j0 + li;
-    const double v = M[min(i, rows - 1) * ld + min(j, cols - 1)];  // clamped: loads need no branch
-    acc[r] = (i < rows && j < cols) ? v : 0.0;
+    acc[r] = M[min(i, rows - 1) * ld + min(j, cols - 1)];
   }
   for (int k0 = 0; k0 < K; k0 += 4) {
     const int k = k0 + lk;
@@ -173,7 +175,9 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
           double v = 0.0;
 #pragma unroll
           for (int r = 0; r < NBK; ++r) v = (r == lane) ? a[r][c] : v;  // row `lane`, static indices
-          if (c <= lane) A[(kb + lane) * ld + kb + c] = v;
+          // zeros above the diagonal (that triangle is never read); a short last panel
+          // stops at column p - 1
+          if (PAD8 || c < nb) A[(kb + lane) * ld + kb + c] = v;
         }
       }
     }
@@ -182,7 +186,6 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
   if (wave == 0) factor_diag(0);
   __syncthreads();
   for (int pb = 0; pb < npan; ++pb) {
-    if (bad) break;  // uniform
     const int kb = pb * NBK;
     const int nb = PAD8 ? NBK : min(NBK, p - kb);
     const int r0 = kb + nb, rem = p - r0;
@@ -233,8 +236,8 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
         const int tj = t - ti * (ti + 1) / 2;
         mfma_tile_update(
             A, ld, p, p, r0 + 16 * ti, r0 + 16 * tj, NBK,
-            [&](int i, int k) { const double v = A[min(i, p - 1) * ld + kb + k]; return i < p ? v : 0.0; },
-            [&](int k, int j) { const double v = A[min(j, p - 1) * ld + kb + k]; return j < p ? v : 0.0; }, -1.0);
+            [&](int i, int k) { return A[min(i, p - 1) * ld + kb + k]; },
+            [&](int k, int j) { return A[min(j, p - 1) * ld + kb + k]; }, -1.0);
       };
       if (wave == 0) {
         a22_tile(0);
@@ -248,8 +251,8 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
             const int ti = u / ntj, tj = u - ti * ntj;
             mfma_tile_update(
                 W, ld, p, cols, cols + 16 * ti, 16 * tj, nb,
-                [&](int i, int k) { const double v = A[min(i, p - 1) * ld + kb + k]; return i < p ? v : 0.0; },
-                [&](int k, int j) { const double v = W[(kb + k) * ld + min(j, cols - 1)]; return j < cols ? v : 0.0; }, -1.0);
+                [&](int i, int k) { return A[min(i, p - 1) * ld + kb + k]; },
+                [&](int k, int j) { return W[(kb + k) * ld + min(j, cols - 1)]; }, -1.0);
           }
         }
       }
