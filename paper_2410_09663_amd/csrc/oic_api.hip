@@ -581,14 +581,16 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     const int Ma = (t + 1) * rr;
     launch_means_f64(s, h->timer, h->Y, p, N, m, h->muY);
     // Eq. (13b): Sigma^Y first; its Cholesky factor and inverse run on the side stream
-    // while Eq. (13c), Sigma^{XY}, runs here.
+    // while Eq. (13c), Sigma^{XY}, runs here.  Sigma^Y, which is factored, takes FP64
+    // products in the FP32 mode; Sigma^{XY}, which enters the gain linearly, takes FP32
+    // products folded into FP64 every 256 columns in every mode (twice the FP64 MFMA rate).
     const bool f32_stats = rollout_mode(h) != RM_FP32;  // FP32 statistics in the BF16 / FP8 modes
     launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->part_cap, h->Syy, f32_stats);
     hipEventRecord(h->ev_fork, s);
     hipStreamWaitEvent(h->side, h->ev_fork, 0);
     launch_chol(h->side, h->timer, p, h->Syy, h->Lwork, h->Sinv, h->flag);
     hipEventRecord(h->ev_join, h->side);
-    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S, f32_stats);
+    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S, true);
     hipStreamWaitEvent(s, h->ev_join, 0);
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
     launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
