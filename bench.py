@@ -58,6 +58,10 @@ def algorithmic_work(p, H, precision="fp32"):
             wr = 4.0 * n * m * N if k == L - 1 else ab * co * n * m * N
             add(cls, 2.0 * 9 * ci * co * n * m * N, rd + wr)
         add("stats", 2.0 * (Ma + pp) * pp * NM, 4.0 * (Ma + pp) * NM)
+        # time at peak: Sigma^{XY} on the FP32 matrix cores in every mode, Sigma^Y on the
+        # FP64 ones in the FP32 mode (FP32 otherwise); the class's peak is the FLOP-weighted one
+        yy_peak = PEAK["fp64"] if precision == "fp32" else PEAK["fp32"]
+        add("stats_t_peak", 2.0 * Ma * pp * NM / PEAK["fp32"] + 2.0 * pp * pp * NM / yy_peak, 0.0)
         add("update", 2.0 * Ma * pp * NM, 4.0 * (2 * Ma + pp) * NM)
         add("means", float(pp) * NM, 4.0 * pp * NM)
         add("chol", float(pp) ** 3, 16.0 * pp * pp)  # Cholesky, triangular inverse, W^T W
@@ -73,9 +77,11 @@ SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last"
              "noise": "noise.hip", "assemble": "noise.hip", "observe": "noise.hip", "init": "noise.hip"}
 
 
-def roofline_for(cls, flops, nbytes, ms, launches, precision, tag=None):
+def roofline_for(cls, flops, nbytes, ms, launches, precision, tag=None, t_peak=None):
     sec = ms * 1e-3
-    if cls in ("stats", "gain", "chol"):
+    if t_peak:  # a class whose launches run on matrix cores of different precisions
+        fpeak = flops / t_peak
+    elif cls in ("gain", "chol"):
         fpeak = PEAK["fp64"]
     elif cls.startswith("conv"):
         fpeak = {"bf16": PEAK["bf16"], "fp8": PEAK["fp8"]}.get(precision, PEAK["fp32"])
@@ -348,11 +354,12 @@ def main():
         if cnt == 0:
             continue
         f, b = work.get(cls, (0.0, 0.0))
-        per_class[cls] = {"launches": cnt, "total_ms": ms, "flop": f * K, "bytes": b * K}
+        per_class[cls] = {"launches": cnt, "total_ms": ms, "flop": f * K, "bytes": b * K,
+                          "t_peak": work.get(cls + "_t_peak", (0.0, 0.0))[0] * K}
     dom = max(per_class, key=lambda c: per_class[c]["total_ms"])
     d = per_class[dom]
     roof = roofline_for(dom, d["flop"], d["bytes"], d["total_ms"], d["launches"], args.precision,
-                        f"{args.workload}_{args.precision}")
+                        f"{args.workload}_{args.precision}", d["t_peak"])
     roof["measured"] = ("HIP events around each launch on the library stream, over the same "
                         "number of steps launched kernel by kernel right after the timed region")
     # every class that does matrix work, and the two figures the method's targets name:
@@ -361,7 +368,8 @@ def main():
     for cls in ("conv_first", "conv_mid", "conv_last", "stats", "gain", "update"):
         if cls in per_class and per_class[cls]["flop"] > 0:
             c = per_class[cls]
-            r = roofline_for(cls, c["flop"], c["bytes"], c["total_ms"], c["launches"], args.precision)
+            r = roofline_for(cls, c["flop"], c["bytes"], c["total_ms"], c["launches"], args.precision,
+                             t_peak=c["t_peak"])
             by_class[cls] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_launch_us")}
     conv = [per_class[c] for c in ("conv_first", "conv_mid", "conv_last") if c in per_class]
     conv_s = sum(c["total_ms"] for c in conv) * 1e-3
