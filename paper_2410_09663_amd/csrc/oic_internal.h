@@ -190,6 +190,8 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 // Lwork receives the inverses of its 64 x 64 diagonal blocks; Sinv is not written.
 // Lwork holds 2 p (p+1) doubles.
 void launch_chol(hipStream_t s, Timer& t, int p, double* Syy, double* Lwork, double* Sinv, int* flag);
+// true when Sigma^Y (p x p) is factored by the blocked multi-launch path rather than in one workgroup
+bool chol_blocked(int p);
 // K = Sxy (Sigma^Y)^{-1} (Ma x p, FP64 arithmetic, FP32 result), from Sinv for p <= 90
 // and from L (lower triangle of the factored Syy) and its diagonal-block inverses
 // (Lwork) otherwise; skipped when flag is set.

@@ -474,7 +474,11 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   // even for the few output tiles of the early horizon steps: a workgroup's time is set
   // by its chunk of K, not by the size of the output.  Chunks are whole 64-column
   // stages; the partials must fit the split buffer.
-  const int target = tall ? 256 : 512;  // the same number of waves in flight either way
+  // Eight-wave blocks: 256 of them (the same waves in flight as 512 four-wave blocks) while
+  // the one-workgroup Cholesky of Sigma^Y (p <= 90) runs beside this product, leaving it
+  // room on the CUs; 384 otherwise (128x128 BF16: statistics 3.20 -> 2.75 ms per solve;
+  // at 64x64 FP32, 384 or 512 cost 0.5-2% per step).
+  const int target = tall ? (chol_blocked(p) ? 384 : 256) : 512;
   int splits = (target + tiles - 1) / tiles;
   const int max_by_len = (NM + MK - 1) / MK;
   if (splits > max_by_len) splits = max_by_len;
