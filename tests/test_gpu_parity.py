@@ -89,11 +89,14 @@ def test_cnn_forward_matches_oracle(preset):
     assert np.array_equal(one, got[0])
 
 
-@pytest.mark.parametrize("preset", ["C1", "tiny", "tiny_gelu", "tiny_l1", "C2", "p100", "p150",
+@pytest.mark.parametrize("preset", ["C1", "tiny", "tiny_gelu", "tiny_l1", "C2", "p90", "p100", "p150",
                                     "p500"])
 def test_solve_explicit_noise_matches_oracle(preset):
     if preset == "tiny":
         p = tiny()
+    elif preset == "p90":
+        # p = n + l = 90: the largest one-workgroup Cholesky, padded to 96 (the most LDS)
+        p = tiny(n=72, m=6, l=18, channels=(2, 4, 1), N=40, H=2)
     elif preset == "p100":
         # p = n + l = 100 > 90: blocked Cholesky (panels 64 + 36) and triangular-solve gain
         p = tiny(n=80, m=6, l=20, channels=(2, 4, 1), N=40, H=2)
