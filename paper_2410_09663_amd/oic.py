@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import Optional, Sequence
 
 import numpy as np
@@ -70,6 +71,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2410_09663_amd.build` (no CPU fallback exists)")
+        # torch, when it is already loaded, brings up its own HIP runtime first: its first
+        # initialisation has failed ("no HIP GPUs") when it came after solves of this library
+        torch = sys.modules.get("torch")
+        if torch is not None and torch.cuda.is_available():
+            torch.cuda.init()
         L = ctypes.CDLL(LIB_PATH)
         vp, ci, cu64, cs = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
         sig = {
