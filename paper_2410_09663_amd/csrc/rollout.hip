@@ -513,11 +513,6 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   const int a0 = (rt * l) / row_tiles, a1 = ((rt + 1) * l) / row_tiles;
   const int ne = obs.U_cur ? (a1 - a0) * TC : 0;
   float pw = 0.f, pv = 0.f;
-  if (tid < ne && x0 + tid % TC < m) {
-    const int a = a0 + tid / TC, x = x0 + tid % TC;
-    pw = noise_value(obs.w, a, i, x, m);
-    pv = noise_value(obs.vu, a, i, x, m);
-  }
   {
     // X halo: 396 cells; U rows: l x 66; B rows: 6 x l  (l <= 64)
     constexpr int XS = (HR * HC + 255) / 256;
@@ -554,6 +549,21 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
       wv[u] = (e < 20 * COUT && kk < 18) ? w[o * 18 + kk] : 0.f;
     }
     const float bias_v = (tid < COUT && bias) ? bias[tid] : 0.f;
+    // the first noise pairs of the U rows, requested after the halo loads so that their
+    // latency overlaps (each noise value waits for its own loads)
+    if (tid < ne && x0 + tid % TC < m) {
+      const int a = a0 + tid / TC, x = x0 + tid % TC;
+      if (obs.w.diag && obs.vu.diag) {  // diagonal covariances: four loads, one wait
+        const float dw = obs.w.diag[a], dv = obs.vu.diag[a];
+        const float zw = obs.w.Z[((size_t)i * obs.w.rows + a) * m + x];
+        const float zv = obs.vu.Z[((size_t)i * obs.vu.rows + a) * m + x];
+        pw = dw * zw;
+        pv = dv * zv;
+      } else {
+        pw = noise_value(obs.w, a, i, x, m);
+        pv = noise_value(obs.vu, a, i, x, m);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < WS; ++u)
       if (tid + 256 * u < 20 * COUT) s_w[tid + 256 * u] = wv[u];
