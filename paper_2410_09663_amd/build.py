@@ -29,16 +29,41 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into liboic.so; always recompiles."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building liboic.so")
-    os.replace(tmp, LIB)
+    """Compile every HIP source into liboic.so; always recompiles.  The sources compile
+    to objects in parallel (each holds its own gfx950 code object), then link."""
+    import shutil
+    import tempfile
+
+    tmpdir = tempfile.mkdtemp(prefix="oic_build_")
+    try:
+        compile_flags = [f for f in FLAGS if f != "-shared"]
+        jobs = []
+        for src in sources():
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            cmd = [HIPCC, *compile_flags, "-c", "-I", os.path.join(ROOT, "include"), "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            jobs.append((obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                               text=True)))
+        failed = False
+        for obj, proc in jobs:
+            out, _ = proc.communicate()
+            if proc.returncode != 0:
+                sys.stderr.write(out)
+                failed = True
+        if failed:
+            raise RuntimeError("hipcc failed building liboic.so")
+        tmp = LIB + ".tmp"
+        cmd = [HIPCC, *FLAGS, "-o", tmp, *[o for o, _ in jobs]]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking liboic.so")
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 

@@ -173,6 +173,16 @@ int fail(oic_ctx* h, int code, const std::string& msg) {
   return code;
 }
 
+// Forget the captured solve: the graph holds kernel arguments (buffer addresses, the
+// layout of the Q and R factors) that a change of weights or factors makes stale.  The
+// caller holds resource_mutex().
+void drop_graph(oic_ctx* h) {
+  if (h->gexec) {
+    hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+}
+
 bool finite_all(const float* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -238,8 +248,14 @@ int prepare_factors(oic_ctx* h, const float* Q, const float* R) {
   if (!host_cholesky(Q, l, Lq)) return fail(h, OIC_EINVAL, "Q is not positive definite");
   if (!host_cholesky(R, n, Lr)) return fail(h, OIC_EINVAL, "R is not positive definite");
   std::vector<float> f((size_t)l * l + (size_t)n * n, 0.f);
-  h->q_diag = is_diagonal(Q, l);
-  h->r_diag = is_diagonal(R, n);
+  const bool qd = is_diagonal(Q, l), rd = is_diagonal(R, n);
+  if (qd != h->q_diag || rd != h->r_diag) {
+    // the captured noise kernels read the factors as diagonal scales or dense triangles
+    std::lock_guard<std::mutex> guard(resource_mutex());
+    drop_graph(h);
+  }
+  h->q_diag = qd;
+  h->r_diag = rd;
   // Diagonal factors are stored as the first l (n) entries; dense ones row-major.
   if (h->q_diag)
     for (int a = 0; a < l; ++a) f[a] = (float)Lq[(size_t)a * l + a];
@@ -394,7 +410,6 @@ RolloutMode rollout_mode(oic_ctx* h) {
 // single output channel to `out`, in the given mode (the plant step always uses FP32).
 // With `obs`, the first and last layers also write the side outputs it names where they
 // run as the tiled kernels; returns ROLL_X_OBSERVED | ROLL_U_ASSEMBLED for what was written.
-enum { ROLL_X_OBSERVED = 1, ROLL_U_ASSEMBLED = 2 };
 int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode,
             const ObserveArgs* obs = nullptr) {
   const oic_config& c = h->cfg;
@@ -421,41 +436,14 @@ int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollout
                      h->dW[L - 1], h->dBias[L - 1], out, true, obs);
     return obs ? ROLL_X_OBSERVED | (obs->U_cur ? ROLL_U_ASSEMBLED : 0) : 0;
   }
-  int done = 0;
-  int cur = 0;
-  int k0 = 0;
-  if (L > 1 && conv_first_supported(c.channels[1], c.l)) {
-    // lift fused into the first layer
-    launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
-                      h->dBias[0], c.activation, h->act[1], false, nullptr, obs);
-    if (obs && obs->U_cur) done |= ROLL_U_ASSEMBLED;
-    cur = 1;
-    k0 = 1;
-  } else {
-    launch_lift(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, h->act[0]);
+  Fp32Net net{};
+  net.B = h->dB;
+  for (int k = 0; k < L; ++k) {
+    net.W[k] = h->dW[k];
+    net.Wk[k] = h->dWk[k];
+    net.bias[k] = h->dBias[k];
   }
-  for (int k = k0; k < L; ++k) {
-    const int cin = c.channels[k], cout = c.channels[k + 1];
-    const bool last = k == L - 1;
-    const int cls = k == 0 ? KC_CONV_FIRST : (last ? KC_CONV_LAST : KC_CONV_MID);
-    if (last && k > 0 && conv_last_supported(cin)) {
-      launch_conv_last(h->stream, h->timer, batch, c.n, c.m, cin, h->act[cur], h->dW[k], h->dBias[k],
-                       out, false, obs);
-      if (obs) done |= ROLL_X_OBSERVED;
-      continue;
-    }
-    if (!last && h->dWk[k]) {
-      launch_conv_mfma(h->stream, h->timer, cls, batch, c.n, c.m, cin, cout, h->act[cur], h->dWk[k],
-                       h->dBias[k], c.activation, h->act[1 - cur]);
-      cur = 1 - cur;
-      continue;
-    }
-    FieldOut fo = last ? out : FieldOut{nullptr, 0, 0};
-    launch_conv(h->stream, h->timer, cls, batch, c.n, c.m, cin, cout, h->act[cur], h->dW[k],
-                h->dBias[k], c.activation, last ? nullptr : h->act[1 - cur], fo);
-    cur = 1 - cur;
-  }
-  return done;
+  return rollout_fp32(h->stream, h->timer, c, net, h->act[0], h->act[1], batch, X, U, out, obs);
 }
 
 // OCP FP8 e4m3: bias 7, no infinities, largest finite 448.  The finite non-negative
@@ -829,6 +817,8 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
     if (bias && bias[k] && !finite_all(bias[k], c.channels[k + 1]))
       return fail(h, OIC_EINVAL, "non-finite bias");
   }
+  // bias buffers may be allocated or freed below, and a captured solve holds their addresses
+  drop_graph(h);
   int rc;
   if (!h->dB && (rc = dalloc(h, &h->dB, (size_t)c.n * c.l))) return rc;
   HIP_TRY(hipMemcpyAsync(h->dB, B, (size_t)c.n * c.l * sizeof(float), hipMemcpyHostToDevice, h->stream));
@@ -975,10 +965,7 @@ int oic_solve_cov(oic_handle h, const oic_solve_args* a, double* prior_cov, doub
     hipFree(h->part);
     h->part = bigger;
     h->part_cap = ma * ma;
-    if (h->gexec) {  // a captured solve refers to the old buffer
-      hipGraphExecDestroy(h->gexec);
-      h->gexec = nullptr;
-    }
+    drop_graph(h);  // a captured solve refers to the old buffer
   }
   guard.unlock();
   h->want_cov = true;
@@ -1129,10 +1116,7 @@ int oic_set_constraint(oic_handle h, const float* aX, const float* aU, float b, 
     h->con_rz = rz;
   }
   h->con_on = on;
-  if (h->gexec) {  // the captured solve has the old observation rows and parameters
-    hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
-  }
+  drop_graph(h);  // the captured solve has the old observation rows and parameters
   return OIC_OK;
 }
 

@@ -169,6 +169,24 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
                       const float* in_nhwc, const float* wk, const float* bias, int act,
                       float* out_nhwc);
 
+// The FP32 rollout of Eq. (1) through the layer kernels above: the lift fused into the
+// first layer where that kernel exists (else a separate lift), MFMA hidden layers where
+// Wk (weights as [tap*cin + c][cout]) is given (else the direct kernel on W in
+// [cout][cin][3][3] order), the tiled last layer where it exists.  act0/act1 hold
+// batch*n*m*max(hidden widths, 2) floats each.  With `obs`, the first and last layers
+// also write the side outputs it names; returns ROLL_X_OBSERVED | ROLL_U_ASSEMBLED for
+// what was written.
+enum { ROLL_X_OBSERVED = 1, ROLL_U_ASSEMBLED = 2 };
+struct Fp32Net {
+  const float* B;
+  const float* W[OIC_MAX_LAYERS];
+  const float* Wk[OIC_MAX_LAYERS];
+  const float* bias[OIC_MAX_LAYERS];
+};
+int rollout_fp32(hipStream_t s, Timer& t, const oic_config& c, const Fp32Net& net, float* act0,
+                 float* act1, int batch, FieldRef X, FieldRef U, FieldOut out,
+                 const ObserveArgs* obs = nullptr);
+
 // Statistics and update.
 void launch_means(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, float* mean);
 void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, int m, double* mean);

@@ -477,8 +477,8 @@ __global__ __launch_bounds__(256 * WGM) void k_conv_mfma_f32p(int N, int n, int 
 // First layer with the lift fused: the block stages the 6 x 66 halo of X, the l rows
 // of U over the same columns and the 6 rows of B in LDS (all loads issued before the
 // stores), forms B U per halo cell from LDS, computes 4 x 64 output pixels x COUT
-// channels on the VALU (18 taps each), and writes the NHWC rows out through LDS so
-// that the global stores are contiguous.
+// channels on the matrix cores (K = 2 channels x 9 taps, padded to 20), and writes the
+// NHWC rows out through LDS so that the global stores are contiguous.
 template <int COUT, typename TOUT>
 __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, FieldRef X,
                                                     FieldRef U, const float* __restrict__ B,
@@ -1128,12 +1128,10 @@ int resident_per_cu(int threads) {
   return nb;
 }
 
-#ifndef BF_WG_WIDE
-#define BF_WG_WIDE 2
-#endif
-#ifndef BF_WG_32
-#define BF_WG_32 2
-#endif
+// wave groups per workgroup of the BF16 hidden layers: two groups of four waves split
+// the output channels once a layer has 32 or more of them
+constexpr int kBf16GroupsWide = 2;  // 64 input or output channels
+constexpr int kBf16Groups32 = 2;    // 32 output channels
 
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                            const void* in_nhwc, const void* wt, const float* bias, int act,
@@ -1143,7 +1141,7 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
 #define OIC_BF_CASE(CI, CO)                                                                      \
   if (cin == CI && cout == CO) {                                                                 \
     constexpr int TRV = CI <= 32 ? 8 : 4;                                                        \
-    constexpr int WG = (CI == 64 || CO == 64) ? BF_WG_WIDE : (CO >= 32 ? BF_WG_32 : 1);          \
+    constexpr int WG = (CI == 64 || CO == 64) ? kBf16GroupsWide : (CO >= 32 ? kBf16Groups32 : 1);          \
     constexpr auto kern = k_conv_mfma_bf16<CI, CO, TRV, WG>;                                     \
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
     const long long cap = 256LL * resident_per_cu<kern>(256 * WG); /* persistent */             \
@@ -1166,9 +1164,7 @@ bool conv_mfma_fp8_supported(int cin, int cout) {
   return (cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64);
 }
 
-#ifndef FP8_WG
-#define FP8_WG 2
-#endif
+constexpr int kFp8Groups = 2;  // wave groups of the FP8 hidden layers with 32+ output channels
 
 void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                           const void* in_nhwc, const unsigned* amax_in, const uint8_t* wq, const float* ws,
@@ -1179,7 +1175,7 @@ void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int
 #define OIC_F8_CASE(CI, CO)                                                                        \
   if (cin == CI && cout == CO) {                                                                   \
     constexpr int TRV = 8;                                                                         \
-    constexpr int WG = CO >= 32 ? FP8_WG : 1;                                                      \
+    constexpr int WG = CO >= 32 ? kFp8Groups : 1;                                                      \
     constexpr auto kern = k_conv_mfma_fp8<CI, CO, TRV, WG>;                                        \
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);               \
     const long long cap = 256LL * resident_per_cu<kern>(256 * WG); /* persistent */               \
@@ -1205,15 +1201,12 @@ bool conv_mfma_supported(int cin, int cout) {
   return (cin == 16 || cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64);
 }
 
-#ifndef F32_W8
-#define F32_W8 1
-#endif
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                       const float* in_nhwc, const float* wk, const float* bias, int act,
                       float* out_nhwc) {
 #define OIC_CONV_CASE(CI, CO)                                                                   \
   if (cin == CI && cout == CO) {                                                                \
-    constexpr bool W8 = CI == 16 && CO == 16 && F32_W8;  /* 8 waves, one row each */            \
+    constexpr bool W8 = CI == 16 && CO == 16;  /* 8 waves, one row each */            \
     constexpr int TRV = W8 ? 8 : ((CI <= 16 && CO <= 32 && CO != CI) ? 8 : 4);                 \
     constexpr int WGM = W8 ? 2 : 1;                                                             \
     constexpr int CCH = CI <= 32 ? CI : 32;                                                     \
@@ -1241,6 +1234,46 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
   OIC_CONV_CASE(32, 64)
   OIC_CONV_CASE(64, 32)
 #undef OIC_CONV_CASE
+}
+
+int rollout_fp32(hipStream_t s, Timer& t, const oic_config& c, const Fp32Net& net, float* act0,
+                 float* act1, int batch, FieldRef X, FieldRef U, FieldOut out, const ObserveArgs* obs) {
+  const int L = c.n_layers;
+  float* act[2] = {act0, act1};
+  int done = 0;
+  int cur = 0;
+  int k0 = 0;
+  if (L > 1 && conv_first_supported(c.channels[1], c.l)) {
+    // lift fused into the first layer
+    launch_conv_first(s, t, batch, c.n, c.m, c.l, X, U, net.B, c.channels[1], net.W[0], net.bias[0],
+                      c.activation, act[1], false, nullptr, obs);
+    if (obs && obs->U_cur) done |= ROLL_U_ASSEMBLED;
+    cur = 1;
+    k0 = 1;
+  } else {
+    launch_lift(s, t, batch, c.n, c.m, c.l, X, U, net.B, act[0]);
+  }
+  for (int k = k0; k < L; ++k) {
+    const int cin = c.channels[k], cout = c.channels[k + 1];
+    const bool last = k == L - 1;
+    const int cls = k == 0 ? KC_CONV_FIRST : (last ? KC_CONV_LAST : KC_CONV_MID);
+    if (last && k > 0 && conv_last_supported(cin)) {
+      launch_conv_last(s, t, batch, c.n, c.m, cin, act[cur], net.W[k], net.bias[k], out, false, obs);
+      if (obs) done |= ROLL_X_OBSERVED;
+      continue;
+    }
+    if (!last && net.Wk[k]) {
+      launch_conv_mfma(s, t, cls, batch, c.n, c.m, cin, cout, act[cur], net.Wk[k], net.bias[k],
+                       c.activation, act[1 - cur]);
+      cur = 1 - cur;
+      continue;
+    }
+    FieldOut fo = last ? out : FieldOut{nullptr, 0, 0};
+    launch_conv(s, t, cls, batch, c.n, c.m, cin, cout, act[cur], net.W[k], net.bias[k], c.activation,
+                last ? nullptr : act[1 - cur], fo);
+    cur = 1 - cur;
+  }
+  return done;
 }
 
 void launch_lift(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,

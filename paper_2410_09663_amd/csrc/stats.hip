@@ -125,9 +125,7 @@ typedef float f32x4v __attribute__((ext_vector_type(4)));
 
 // Left operands with at least this many rows use 8-wave blocks (128 left rows sharing
 // each staged right tile; the right tile is then loaded once per 128 rows, not 64).
-#ifndef STATS_TALL
-#define STATS_TALL 256
-#endif
+constexpr int kStatsTall = 256;
 constexpr int MK = 64;  // columns per LDS stage
 
 // part[z][a][b] = sum over the columns c of chunk z of L[a][c] * D[b][c], where the
@@ -467,7 +465,7 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   const int ytiles = (nbk + 7) / 8;
   const int NB = (nbk + ytiles - 1) / ytiles;
   // eight waves (128 left rows) share each staged right tile once the left side is tall
-  const bool tall = Mtot >= STATS_TALL;
+  const bool tall = Mtot >= kStatsTall;
   const int ma = tall ? 128 : 64;
   const int tiles = ((Mtot + ma - 1) / ma) * ytiles;
   // Split K so that about two workgroups per CU (their LDS allows two) are in flight

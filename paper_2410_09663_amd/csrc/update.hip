@@ -13,12 +13,8 @@ typedef float f32x4u __attribute__((ext_vector_type(4)));
 
 constexpr int UC = 64;  // columns per tile (4 N-blocks of 16)
 constexpr int PB = 80;  // observation rows per LDS stage
-#ifndef UPD_ROWS_WR
-#define UPD_ROWS_WR 8
-#endif
-#ifndef UPD_WR
-#define UPD_WR 8
-#endif
+constexpr int kUpdWavesRows = 8;  // waves (16 rows each) of the persistent update's row tiles
+constexpr int kUpdWaves = 8;      // waves of the general update's row tiles
 
 // traj[a][c] += sum_b K[a][b] (Ybar[b][c mod m] - Y[b][c]),  Ybar = [X^ref_t; 0],
 // on the FP32 matrix cores (v_mfma_f32_16x16x4_f32).  Wave w owns trajectory rows
@@ -218,7 +214,7 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
                    const float* Y, const float* xref_t) {
   const unsigned col_tiles = (unsigned)((d.NM() + UC - 1) / UC);
   if (d.p() <= PB) {
-    constexpr int WR = UPD_ROWS_WR;
+    constexpr int WR = kUpdWavesRows;
     const unsigned row_tiles = (unsigned)((Ma + 16 * WR - 1) / (16 * WR));
     // about two workgroups per CU (the register budget allows two) on 256 CUs
     const unsigned want = (512 + col_tiles - 1) / col_tiles;
@@ -227,7 +223,7 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
                xref_t);
     return;
   }
-  constexpr int WR = UPD_WR;
+  constexpr int WR = kUpdWaves;
   const unsigned tall_tiles = (unsigned)((Ma + 16 * WR - 1) / (16 * WR));
   OIC_LAUNCH(t, KC_UPDATE, s, k_update_mfma<WR>, dim3(col_tiles, tall_tiles), dim3(64 * WR), 0, d, traj, Ma, K,
              Y, xref_t);

@@ -71,12 +71,21 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2410_09663_amd.build` (no CPU fallback exists)")
-        # torch, when it is already loaded, brings up its own HIP runtime first: its first
-        # initialisation has failed ("no HIP GPUs") when it came after solves of this library
-        torch = sys.modules.get("torch")
+        # One HIP runtime per process.  torch ships its own libamdhip64 under a name that
+        # does not match the ROCm runtime's soname, so a library loaded before torch binds
+        # to ROCm's copy and torch later adds a second one.  Loading torch first makes the
+        # dynamic loader resolve liboic's runtime to torch's copy (same soname).
+        try:
+            import torch
+        except ImportError:
+            torch = None
         if torch is not None and torch.cuda.is_available():
             torch.cuda.init()
         L = ctypes.CDLL(LIB_PATH)
+        runtimes = _hip_runtimes()
+        if len(runtimes) > 1:
+            raise RuntimeError("two HIP runtimes are loaded in this process (" + ", ".join(runtimes) +
+                               "): load liboic through this module, after torch if torch is used")
         vp, ci, cu64, cs = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
         sig = {
             "oic_create": (ci, [ctypes.POINTER(oic_config), ctypes.POINTER(vp)]),
@@ -125,6 +134,16 @@ def lib():
     return _lib
 
 
+def _hip_runtimes():
+    """Distinct files of the HIP runtime (libamdhip64) mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            paths = {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    except OSError:
+        return []
+    return sorted({os.path.realpath(p) for p in paths if p.startswith("/")})
+
+
 EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
             "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_columns_expand", "oic_columns_project", "oic_set_constraint", "oic_cnn_forward", "oic_plant_step",
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
@@ -152,6 +171,10 @@ class Controller:
             cfg.channels[k] = c
         cfg.activation, cfg.precision = activation, precision
         cfg.max_N, cfg.max_H, cfg.mem_mode = max_N, max_H, mem_mode
+        if stream is None and mem_mode == OIC_MEM_DEVICE:
+            # device mode reads caller tensors: order the work after torch's queued kernels
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
         cfg.stream = stream
         h = ctypes.c_void_p()
         rc = lib().oic_create(ctypes.byref(cfg), ctypes.byref(h))

@@ -1,8 +1,8 @@
 """BF16 rollout (BF16 activations and weights on MFMA, FP32 accumulation; statistics FP64,
 gain FP64): errors against the FP64 oracle and against the FP32 GPU path.
 
-Bars (relative, Frobenius): 2e-2 on the smoothed control mean, 2e-2 on the state mean,
-and 2% on the closed-loop tracking cost."""
+Bars: 2e-2 on the smoothed control mean and on the state mean (normwise, and element-wise
+relative to the largest magnitude), and 2% on the closed-loop tracking cost."""
 import dataclasses
 
 import numpy as np
@@ -13,16 +13,11 @@ from oracle import cost as ocost
 from oracle import enks, philox
 from paper_2410_09663_amd import oic
 from paper_2410_09663_amd import workloads as wl
+from parity_util import assert_parity, max_relerr, relerr
 
 pytestmark = pytest.mark.gpu
 
 TOL_BF16 = 2e-2
-
-
-def relerr(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.mark.parametrize("preset", ["C2", "C3"])
@@ -37,11 +32,10 @@ def test_bf16_rollout_vs_oracle(preset):
         got = c.cnn_forward(X, U)
         plant = c.plant_step(X[0], U[0])
     ref = ocnn.cnn_forward(X, U, prob.B, prob.weights, p.activation)
-    e = relerr(got, ref)
-    print(f"{preset} bf16 rollout relerr {e:.2e}", flush=True)
-    assert e < TOL_BF16
+    e, e_max = assert_parity(got, ref, TOL_BF16, "rollout")
+    print(f"{preset} bf16 rollout relerr {e:.2e} (max {e_max:.2e})", flush=True)
     assert e > 1e-6  # it really ran in BF16
-    assert relerr(plant, ref[0]) < 1e-5  # the plant stays FP32
+    assert_parity(plant, ref[0], 1e-5, "plant")  # the plant stays FP32
 
 
 @pytest.mark.parametrize("preset,N,H", [("C2", 128, 10), ("C3", 32, 3)])
@@ -54,10 +48,10 @@ def test_bf16_solve_vs_oracle(preset, N, H):
         U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, N, H, noise=z)
     ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, N, H,
                      z.Z_init, z.Z_W, z.Z_VX, z.Z_VU)
-    eu, ex = relerr(U, ref.U_mean), relerr(X, ref.X_mean)
-    print(f"{preset} N={N} H={H} bf16: relerr U {eu:.2e} X {ex:.2e}", flush=True)
-    assert eu < TOL_BF16
-    assert ex < TOL_BF16
+    eu, eu_max = assert_parity(U, ref.U_mean, TOL_BF16, "U")
+    ex, ex_max = assert_parity(X, ref.X_mean, TOL_BF16, "X")
+    print(f"{preset} N={N} H={H} bf16: relerr U {eu:.2e} (max {eu_max:.2e}) X {ex:.2e} "
+          f"(max {ex_max:.2e})", flush=True)
 
 
 def test_bf16_vs_fp32_gpu_full_c3():
@@ -68,10 +62,9 @@ def test_bf16_vs_fp32_gpu_full_c3():
     for prec in (oic.OIC_PREC_FP32, oic.OIC_PREC_BF16):
         with oic.controller_for(prob, precision=prec) as c:
             outs[prec] = c.solve(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, seed=7, want_X=True)
-    eu = relerr(outs[oic.OIC_PREC_BF16][0], outs[oic.OIC_PREC_FP32][0])
-    ex = relerr(outs[oic.OIC_PREC_BF16][1], outs[oic.OIC_PREC_FP32][1])
+    eu, _ = assert_parity(outs[oic.OIC_PREC_BF16][0], outs[oic.OIC_PREC_FP32][0], TOL_BF16, "U")
+    ex, _ = assert_parity(outs[oic.OIC_PREC_BF16][1], outs[oic.OIC_PREC_FP32][1], TOL_BF16, "X")
     print(f"C3 full size bf16 vs fp32 GPU: relerr U {eu:.2e} X {ex:.2e}", flush=True)
-    assert eu < TOL_BF16 and ex < TOL_BF16
 
 
 def closed_loop(prob, precision, steps):
@@ -136,39 +129,68 @@ def test_fp8_rollout_vs_oracle(channels):
     print(f"{channels} fp8 rollout relerr {e:.2e} (bf16 {e16:.2e})", flush=True)
     assert e < TOL_FP8_ROLLOUT
     assert e > 2 * e16  # it really ran in FP8
-    assert relerr(plant, ref[0]) < 1e-5  # the plant stays FP32
+    assert_parity(plant, ref[0], 1e-5, "plant")  # the plant stays FP32
+
+
+TOL_FP8_BAR_U = 2e-2     # the stated bar on the smoothed control mean
+TOL_FP8_BAR_COST = 0.02  # and on the closed-loop tracking cost
+_cache = {}
+
+
+def _fp8_solve_errors():
+    if "solve" not in _cache:
+        p = fp8_preset()
+        prob = wl.make_problem(p)
+        Xref = wl.reference_window(p, 0)
+        z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=23)
+        with oic.controller_for(prob, precision=oic.OIC_PREC_FP8) as c:
+            U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
+        ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R,
+                         p.N, p.H, z.Z_init, z.Z_W, z.Z_VX, z.Z_VU)
+        _cache["solve"] = (relerr(U, ref.U_mean), relerr(X, ref.X_mean), max_relerr(U, ref.U_mean))
+    return _cache["solve"]
+
+
+def _fp8_cost_error():
+    if "cost" not in _cache:
+        prob = wl.make_problem(fp8_preset())
+        j32 = closed_loop(prob, oic.OIC_PREC_FP32, 10)
+        j8 = closed_loop(prob, oic.OIC_PREC_FP8, 10)
+        _cache["cost"] = (j32, j8, abs(j8 - j32) / j32)
+    return _cache["cost"]
 
 
 def test_fp8_solve_vs_oracle():
-    p = fp8_preset()
-    prob = wl.make_problem(p)
-    Xref = wl.reference_window(p, 0)
-    z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=23)
-    with oic.controller_for(prob, precision=oic.OIC_PREC_FP8) as c:
-        U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
-    ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N,
-                     p.H, z.Z_init, z.Z_W, z.Z_VX, z.Z_VU)
-    eu, ex = relerr(U, ref.U_mean), relerr(X, ref.X_mean)
-    print(f"fp8 solve: relerr U {eu:.2e} X {ex:.2e}", flush=True)
+    eu, ex, eu_max = _fp8_solve_errors()
+    print(f"fp8 solve: relerr U {eu:.2e} (max {eu_max:.2e}) X {ex:.2e}", flush=True)
     assert eu < TOL_FP8_U
     assert ex < TOL_BF16
 
 
+@pytest.mark.xfail(strict=True, reason="FP8 e4m3 misses the 2e-2 bar on U_hat (measured 2.6e-2 at 40x40)")
+def test_fp8_solve_meets_the_bar():
+    eu, _, eu_max = _fp8_solve_errors()
+    assert eu < TOL_FP8_BAR_U and eu_max < TOL_FP8_BAR_U
+
+
 def test_fp8_closed_loop_tracking_cost():
-    prob = wl.make_problem(fp8_preset())
-    j32 = closed_loop(prob, oic.OIC_PREC_FP32, 10)
-    j8 = closed_loop(prob, oic.OIC_PREC_FP8, 10)
-    print(f"fp8 closed-loop cost fp32 {j32:.6e} fp8 {j8:.6e} rel {abs(j8 - j32) / j32:.2e}", flush=True)
-    assert abs(j8 - j32) / j32 < TOL_FP8_COST
+    j32, j8, rel = _fp8_cost_error()
+    print(f"fp8 closed-loop cost fp32 {j32:.6e} fp8 {j8:.6e} rel {rel:.2e}", flush=True)
+    assert rel < TOL_FP8_COST
 
 
-@pytest.mark.slow
-def test_full_size_256_precisions_tracking_cost():
-    """256x256 field, 5-layer 64-channel GELU CNN, N = 512, H = 20: BF16 and FP8 against
-    the FP32 GPU path on the closed-loop tracking cost (3 steps) and on the first
-    solve's smoothed control mean (the FP64 oracle takes minutes per solve here).
-    Measured: BF16 U 1.0e-2, cost 1.4e-3; FP8 U 1.7e-1 (above the 2e-2 bar), cost 1.5e-2
-    (within the 2% bar)."""
+@pytest.mark.xfail(strict=True, reason="FP8 e4m3 misses the 2% cost bar at 40x40 (measured 3.7%)")
+def test_fp8_closed_loop_cost_meets_the_bar():
+    assert _fp8_cost_error()[2] < TOL_FP8_BAR_COST
+
+
+def _full_size_256():
+    """256x256 field, 5-layer 64-channel GELU CNN, N = 512, H = 20: FP32, BF16 and FP8
+    closed loops of 3 steps (the FP64 oracle takes minutes per solve here, so the
+    reduced precisions are compared with the FP32 GPU path): the first solve's smoothed
+    control mean and the closed-loop tracking cost."""
+    if "256" in _cache:
+        return _cache["256"]
     p = dataclasses.replace(wl.PRESETS["C4"], closed_loop_steps=3)
     prob = wl.make_problem(p)
     costs, first = {}, {}
@@ -186,12 +208,36 @@ def test_full_size_256_precisions_tracking_cost():
         Xrefs = np.stack([wl.reference_at(p, k) for k in range(4)])
         costs[prec] = ocost.closed_loop_cost(np.stack(Xs), np.stack(Us), np.zeros((p.l, p.m)), Xrefs,
                                              prob.R.astype(np.float64), prob.Q.astype(np.float64))
+    out = {}
     j32 = costs[oic.OIC_PREC_FP32]
-    bars = {oic.OIC_PREC_BF16: ("bf16", TOL_BF16, 0.02), oic.OIC_PREC_FP8: ("fp8", 0.25, 0.02)}
-    for prec, (name, tol_u, tol_cost) in bars.items():
+    for prec, name in ((oic.OIC_PREC_BF16, "bf16"), (oic.OIC_PREC_FP8, "fp8")):
         eu = relerr(first[prec], first[oic.OIC_PREC_FP32])
+        eu_max = max_relerr(first[prec], first[oic.OIC_PREC_FP32])
         rel = abs(costs[prec] - j32) / j32
-        print(f"256x256 {name}: U relerr vs fp32 {eu:.2e}, cost {costs[prec]:.6e} vs {j32:.6e} "
-              f"rel {rel:.2e}", flush=True)
-        assert eu < tol_u
-        assert rel < tol_cost
+        print(f"256x256 {name}: U relerr vs fp32 {eu:.2e} (max {eu_max:.2e}), cost {costs[prec]:.6e} "
+              f"vs {j32:.6e} rel {rel:.2e}", flush=True)
+        out[name] = (eu, eu_max, rel)
+    _cache["256"] = out
+    return out
+
+
+@pytest.mark.slow
+def test_full_size_256_bf16():
+    eu, eu_max, rel = _full_size_256()["bf16"]
+    assert eu < TOL_BF16 and eu_max < TOL_BF16
+    assert rel < 0.02
+
+
+@pytest.mark.slow
+def test_full_size_256_fp8_band():
+    """Regression band of the FP8 path (measured U 1.7e-1, cost 1.5e-2)."""
+    eu, _, rel = _full_size_256()["fp8"]
+    assert eu < 0.25
+    assert rel < 0.02
+
+
+@pytest.mark.slow
+@pytest.mark.xfail(strict=True, reason="FP8 e4m3 misses the 2e-2 bar on U_hat at 256x256 (measured 1.7e-1)")
+def test_full_size_256_fp8_meets_the_bar():
+    eu, eu_max, rel = _full_size_256()["fp8"]
+    assert eu < TOL_FP8_BAR_U and eu_max < TOL_FP8_BAR_U and rel < TOL_FP8_BAR_COST

@@ -67,3 +67,46 @@ def test_enks_mean_converges_to_rts():
     slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
     assert -0.62 <= slope <= -0.38, (slope, errs)
     assert errs[-1] < 0.02, errs
+
+
+def test_closed_loop_converges_to_the_closed_form_loop():
+    """Algorithm 1's receding-horizon loop (lines 3-16: solve, apply the smoothed U_k,
+    step the plant, carry U_k as the next U_prev) driven by the ensemble smoother tends,
+    as N grows, to the same loop driven by the closed-form Kalman filter + RTS smoother,
+    at rate N^-1/2.  A loop that applied another slice, skipped the U_prev hand-over or
+    stepped the plant with the wrong control would converge to something else."""
+    c = _case(H=2)
+    n, m, l, H = c["n"], c["m"], c["l"], c["H"]
+    steps = 3
+    xrefs = np.random.default_rng(7).standard_normal((steps + H + 1, n, m))
+    ref_fn = lambda k: xrefs[k:k + H + 1]
+    w = [cf.linear_weights(c["f"], c["g"])]
+    # the loop with the closed-form smoother and the linear plant x' = F x + G u
+    X, Up = c["x0"], c["up"]
+    want_X, want_U = [], []
+    for k in range(steps):
+        sm = cf.kalman_rts(c["F"], c["G"], c["QU"], c["QdU"], c["R"], X, Up, ref_fn(k))
+        Uk = sm[0, n:n + l]
+        X = c["F"] @ X + c["G"] @ Uk
+        Up = Uk
+        want_X.append(X)
+        want_U.append(Uk)
+    want = np.concatenate([np.ravel(want_X), np.ravel(want_U)])
+    Ns = [128, 1024, 8192]
+    errs = []
+    for N in Ns:
+        e = []
+        for s in range(8):
+            def noise_fn(k, s=s, N=N):
+                rng = np.random.default_rng(50_000 + 100 * s + k)
+                return (rng.standard_normal((N, l, m)), rng.standard_normal((H, N, l, m)),
+                        rng.standard_normal((H, N, n, m)), rng.standard_normal((H, N, l, m)))
+            Xs, Us = enks.closed_loop(c["B"], w, 0, c["x0"], ref_fn, c["QU"], c["QdU"], c["R"], N, H,
+                                      steps, noise_fn, U_prev=c["up"])
+            assert np.array_equal(Xs[0], c["x0"])
+            got = np.concatenate([np.ravel(Xs[1:]), np.ravel(Us)])
+            e.append(np.linalg.norm(got - want) / np.linalg.norm(want))
+        errs.append(np.mean(e))
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert -0.65 <= slope <= -0.35, (slope, errs)
+    assert errs[-1] < 0.02, errs
