@@ -164,6 +164,28 @@ int oic_solve_cov(oic_handle h, const oic_solve_args* a, double* prior_cov, doub
  * mem_mode).  batch <= max_N.  Runs the same rollout kernels a solve runs. */
 int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, float* X_next);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving or control loops, harnesses that forbid hipMalloc): oic_cnn_forward
+ * with its intermediate activations (and the FP8 rollout's per-layer maxima) in one
+ * fixed library-wide device buffer of OIC_NOALLOC_SCRATCH_BYTES per GPU instead of the
+ * handle's buffers.  The call allocates nothing, launches the same kernels and returns
+ * the same values bitwise as oic_cnn_forward on the same handle.
+ *   h:  a handle created with OIC_MEM_DEVICE (X, U and X_next are device pointers,
+ *       the work is ordered on the handle's stream; with a private stream the call
+ *       waits for it, as oic_cnn_forward does).
+ *   batch, X, U, X_next: as for oic_cnn_forward (X_next may alias X).
+ * The buffer must hold two activation arrays of batch x n x m x C elements, C the
+ * widest hidden layer, 4 bytes each in the FP32 mode and 2 in the BF16 and FP8 modes,
+ * plus 256 bytes; a larger request returns OIC_ENOMEM with the size in
+ * oic_last_error, before any work is queued.  OIC_EINVAL for a host-memory handle,
+ * unset weights, a batch outside 1..max_N or a NULL pointer; OIC_EDEVICE if the buffer's
+ * device address could not be obtained when the handle was created.
+ * Every handle on one GPU shares the buffer and a call leaves its contents behind:
+ * calls that overlap on one GPU (different streams or threads) race and must be
+ * ordered by the caller. */
+#define OIC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int oic_cnn_forward_noalloc(oic_handle h, int batch, const float* X, const float* U, float* X_next);
+
 /* The nominal plant of the closed loop (Algorithm 1, line 14): the applied
  * control drives the surrogate itself, X_{k+1} = CNN(X_k, U_k).  Same as
  * oic_cnn_forward with batch 1. */

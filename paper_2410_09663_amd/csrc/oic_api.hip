@@ -25,6 +25,12 @@
 
 #include "oic_internal.h"
 
+// The buffer of the allocation-free rollout (oic_cnn_forward_noalloc): its intermediate
+// activations and FP8 maxima.  Every GPU the library runs on holds one copy until the
+// process ends.  In host code this name is a host-side stand-in, not a device address:
+// host code uses the per-device address that hipGetSymbolAddress returns (scratch_on).
+static __device__ __align__(256) unsigned char scratch[OIC_NOALLOC_SCRATCH_BYTES];
+
 namespace oic {
 
 const char* const kKernelClassNames[KC_COUNT] = {
@@ -142,6 +148,10 @@ struct oic_ctx {
   double* mu64 = nullptr;   // FP64 means of the trajectory rows
   size_t mu64_cap = 0;
 
+  // device address of the library-wide allocation-free scratch buffer on this handle's
+  // device (oic_cnn_forward_noalloc), or null if it could not be obtained
+  unsigned char* scratch = nullptr;
+
   // replay of the per-solve kernel sequence
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
@@ -181,6 +191,27 @@ void drop_graph(oic_ctx* h) {
     hipGraphExecDestroy(h->gexec);
     h->gexec = nullptr;
   }
+}
+
+// Device address of `scratch` on `device` (the current device), looked up once per device;
+// null if the lookup failed.  The caller holds resource_mutex().
+unsigned char* scratch_on(int device) {
+  static std::vector<unsigned char*> addr;
+  static std::vector<char> looked_up;
+  if (device < 0) return nullptr;
+  if ((size_t)device >= addr.size()) {
+    addr.resize(device + 1, nullptr);
+    looked_up.resize(device + 1, 0);
+  }
+  if (!looked_up[device]) {
+    looked_up[device] = 1;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess)
+      addr[device] = static_cast<unsigned char*>(p);
+    else
+      (void)hipGetLastError();  // the failure is reported by the entry point that needs it
+  }
+  return addr[device];
 }
 
 bool finite_all(const float* p, size_t n) {
@@ -410,29 +441,35 @@ RolloutMode rollout_mode(oic_ctx* h) {
 // single output channel to `out`, in the given mode (the plant step always uses FP32).
 // With `obs`, the first and last layers also write the side outputs it names where they
 // run as the tiled kernels; returns ROLL_X_OBSERVED | ROLL_U_ASSEMBLED for what was written.
+// The activations go to act0/act1 and the FP8 maxima to amax (the handle's buffers unless
+// given), with launches timed on tm (the handle's timer unless given).
 int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode,
-            const ObserveArgs* obs = nullptr) {
+            const ObserveArgs* obs = nullptr, float* act0 = nullptr, float* act1 = nullptr,
+            unsigned* amax = nullptr, Timer* tm = nullptr) {
   const oic_config& c = h->cfg;
   const int L = c.n_layers;
+  float* act[2] = {act0 ? act0 : h->act[0], act1 ? act1 : h->act[1]};
+  if (!amax) amax = h->amax;
+  Timer& timer = tm ? *tm : h->timer;
   if (mode != RM_FP32) {
     const bool f8 = mode == RM_FP8;
     // per-layer activation maxima: slot k holds the largest |x| written by layer k
-    if (f8) launch_zero_u32(h->stream, h->timer, h->amax, L);
-    launch_conv_first(h->stream, h->timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
-                      h->dBias[0], c.activation, h->act[1], true, f8 ? h->amax : nullptr, obs);
+    if (f8) launch_zero_u32(h->stream, timer, amax, L);
+    launch_conv_first(h->stream, timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
+                      h->dBias[0], c.activation, act[1], true, f8 ? amax : nullptr, obs);
     int cur = 1;
     for (int k = 1; k < L - 1; ++k) {
       if (f8)
-        launch_conv_mfma_fp8(h->stream, h->timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
-                             c.channels[k + 1], h->act[cur], h->amax + (k - 1), h->dWq[k], h->dWs[k],
-                             h->dBias[k], c.activation, h->act[1 - cur], h->amax + k);
+        launch_conv_mfma_fp8(h->stream, timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
+                             c.channels[k + 1], act[cur], amax + (k - 1), h->dWq[k], h->dWs[k],
+                             h->dBias[k], c.activation, act[1 - cur], amax + k);
       else
-        launch_conv_mfma_bf16(h->stream, h->timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
-                              c.channels[k + 1], h->act[cur], h->dWb[k], h->dBias[k], c.activation,
-                              h->act[1 - cur]);
+        launch_conv_mfma_bf16(h->stream, timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
+                              c.channels[k + 1], act[cur], h->dWb[k], h->dBias[k], c.activation,
+                              act[1 - cur]);
       cur = 1 - cur;
     }
-    launch_conv_last(h->stream, h->timer, batch, c.n, c.m, c.channels[L - 1], h->act[cur],
+    launch_conv_last(h->stream, timer, batch, c.n, c.m, c.channels[L - 1], act[cur],
                      h->dW[L - 1], h->dBias[L - 1], out, true, obs);
     return obs ? ROLL_X_OBSERVED | (obs->U_cur ? ROLL_U_ASSEMBLED : 0) : 0;
   }
@@ -443,7 +480,7 @@ int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollout
     net.Wk[k] = h->dWk[k];
     net.bias[k] = h->dBias[k];
   }
-  return rollout_fp32(h->stream, h->timer, c, net, h->act[0], h->act[1], batch, X, U, out, obs);
+  return rollout_fp32(h->stream, timer, c, net, act[0], act[1], batch, X, U, out, obs);
 }
 
 // OCP FP8 e4m3: bias 7, no infinities, largest finite 448.  The finite non-negative
@@ -741,6 +778,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
     h->own_stream = true;
   }
   for (int k = 1; k < c.n_layers; ++k) h->cmax = std::max(h->cmax, c.channels[k]);
+  h->scratch = scratch_on(h->device);
   // observation rows: n + l, plus one if a constraint is set later
   const size_t N = c.max_N, Hs = c.max_H + 1, n = c.n, m = c.m, l = c.l, rr = n + l, p = n + l + 1;
   const size_t NM = N * m;
@@ -1020,6 +1058,37 @@ int cnn_forward_impl(oic_handle h, int batch, const float* X, const float* U, fl
 
 int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, float* X_next) {
   return cnn_forward_impl(h, batch, X, U, X_next, false);
+}
+
+int oic_cnn_forward_noalloc(oic_handle h, int batch, const float* X, const float* U, float* X_next) {
+  if (!h) return OIC_EINVAL;
+  h->err.clear();
+  const oic_config& c = h->cfg;
+  if (c.mem_mode != OIC_MEM_DEVICE)
+    return fail(h, OIC_EINVAL, "oic_cnn_forward_noalloc needs a handle created with OIC_MEM_DEVICE");
+  if (!h->weights_set) return fail(h, OIC_EINVAL, "weights not set");
+  if (batch < 1 || batch > c.max_N) return fail(h, OIC_EINVAL, "batch must be in 1..max_N");
+  if (!X || !U || !X_next) return fail(h, OIC_EINVAL, "NULL pointer");
+  if (!h->scratch)
+    return fail(h, OIC_EDEVICE, "the device address of the allocation-free buffer could not be obtained");
+  const RolloutMode mode = rollout_mode(h);
+  const size_t n = c.n, m = c.m, l = c.l;
+  // layout: [per-layer FP8 maxima, 256 B][activations A][activations B], 256-byte aligned
+  const size_t act_bytes = ((size_t)batch * n * m * h->cmax * (mode == RM_FP32 ? 4 : 2) + 255) / 256 * 256;
+  const size_t need = 256 + 2 * act_bytes;
+  if (need > OIC_NOALLOC_SCRATCH_BYTES)
+    return fail(h, OIC_ENOMEM, "batch needs " + std::to_string(need) + " bytes of scratch; the fixed buffer holds " +
+                                   std::to_string((size_t)OIC_NOALLOC_SCRATCH_BYTES));
+  unsigned char* base = h->scratch;
+  Timer untimed;  // a timed launch would create events on first use
+  rollout(h, batch, FieldRef{X, (long long)(n * m), (long long)m}, FieldRef{U, (long long)(l * m), (long long)m},
+          FieldOut{X_next, (long long)(n * m), (long long)m}, mode, nullptr,
+          reinterpret_cast<float*>(base + 256), reinterpret_cast<float*>(base + 256 + act_bytes),
+          reinterpret_cast<unsigned*>(base), &untimed);
+  HIP_TRY(hipGetLastError());
+  // on a private stream the caller cannot order against the work: finish it here
+  if (h->own_stream) HIP_TRY(hipStreamSynchronize(h->stream));
+  return OIC_OK;
 }
 
 int oic_plant_step(oic_handle h, const float* X, const float* U, float* X_next) {

@@ -30,6 +30,7 @@ OIC_PREC_FP8 = 2
 OIC_MEM_HOST = 0
 OIC_MEM_DEVICE = 1
 OIC_MAX_LAYERS = 8
+OIC_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _ERRNAMES = {OIC_EINVAL: "OIC_EINVAL", OIC_ENOMEM: "OIC_ENOMEM", OIC_EDEVICE: "OIC_EDEVICE",
              OIC_ENOTSPD: "OIC_ENOTSPD"}
@@ -102,6 +103,7 @@ def lib():
                                         ctypes.c_float]),
             "oic_columns_project": (ci, [ci, ci, ci, vp, vp, vp]),
             "oic_cnn_forward": (ci, [vp, ci, vp, vp, vp]),
+            "oic_cnn_forward_noalloc": (ci, [vp, ci, vp, vp, vp]),
             "oic_plant_step": (ci, [vp, vp, vp, vp]),
             "oic_normals": (ci, [vp, cu64, ci, cs, vp]),
             "oic_timing": (ci, [vp, ci]),
@@ -145,7 +147,7 @@ def _hip_runtimes():
 
 
 EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "oic_set_u_prev",
-            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_columns_expand", "oic_columns_project", "oic_set_constraint", "oic_cnn_forward", "oic_plant_step",
+            "oic_get_u_prev", "oic_solve", "oic_solve_ex", "oic_solve_cov", "oic_columns_expand", "oic_columns_project", "oic_set_constraint", "oic_cnn_forward", "oic_cnn_forward_noalloc", "oic_plant_step",
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
             "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
             "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
@@ -354,6 +356,16 @@ class Controller:
         self._check(lib().oic_cnn_forward(self._h, b, self._ptr(X, (b, self.n, self.m)),
                                           self._ptr(U, (b, self.l, self.m)),
                                           self._ptr(out, (b, self.n, self.m), True)))
+        return out
+
+    def cnn_forward_noalloc(self, X, U, out=None):
+        """oic_cnn_forward_noalloc (device-memory handles): the surrogate with its
+        intermediate activations in the library's fixed per-GPU buffer."""
+        b = X.shape[0]
+        out = self._new((b, self.n, self.m)) if out is None else out
+        self._check(lib().oic_cnn_forward_noalloc(self._h, b, self._ptr(X, (b, self.n, self.m)),
+                                                  self._ptr(U, (b, self.l, self.m)),
+                                                  self._ptr(out, (b, self.n, self.m), True)))
         return out
 
     def plant_step(self, X, U):

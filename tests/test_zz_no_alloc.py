@@ -1,0 +1,98 @@
+"""oic_cnn_forward_noalloc: the surrogate of Eq. (1) with its intermediate activations
+in the library's fixed per-GPU buffer instead of the handle's.  Through the C ABI it
+must return oic_cnn_forward's output bitwise (same kernels, same inputs), on two calls
+in a row with the second smaller than the first, in every rollout precision; requests
+beyond the buffer and host-memory handles are refused with the outputs untouched."""
+import numpy as np
+import pytest
+
+from paper_2410_09663_amd import oic
+from paper_2410_09663_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(p, b, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    X = torch.from_numpy(rng.standard_normal((b, p.n, p.m)).astype(np.float32)).cuda()
+    U = torch.from_numpy(rng.standard_normal((b, p.l, p.m)).astype(np.float32)).cuda()
+    return X, U
+
+
+CASES = {
+    # name: (preset, precision, first batch, second batch)
+    "fp32_64x64": (wl.PRESETS["C2"], oic.OIC_PREC_FP32, 16, 5),
+    "bf16_gelu_32ch": (wl.small_preset(n=40, m=72, l=10, channels=(2, 32, 32, 32, 1),
+                                       activation=wl.ACT_GELU, N=8), oic.OIC_PREC_BF16, 8, 3),
+    "fp8_64ch": (wl.small_preset(n=24, m=70, l=6, channels=(2, 64, 64, 64, 1), activation=wl.ACT_GELU, N=6),
+                 oic.OIC_PREC_FP8, 6, 2),
+    "fp32_256x256_plant": (wl.PRESETS["C4"], oic.OIC_PREC_FP32, 1, 1),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_noalloc_matches_cnn_forward_bitwise(case):
+    import torch
+    p, prec, b1, b2 = CASES[case]
+    print(f"noalloc case {case}: {p.n}x{p.m}, channels {p.channels}, batches {b1} then {b2}", flush=True)
+    prob = wl.make_problem(p)
+    with oic.controller_for(prob, max_N=max(b1, b2, 2), max_H=1, precision=prec, mem_mode=oic.OIC_MEM_DEVICE) as c:
+        for call, b in enumerate((b1, b2)):
+            X, U = _inputs(p, b, 10 + call)
+            want = c.cnn_forward(X, U)
+            got = c.cnn_forward_noalloc(X, U)
+            torch.cuda.synchronize()
+            assert torch.isfinite(got).all()
+            assert torch.equal(got, want), f"{case} call {call}: max diff {(got - want).abs().max().item():.3e}"
+
+
+def test_noalloc_second_call_smaller_after_larger():
+    """A call with fewer fields after one with more (the buffer keeps the larger call's
+    activations): still bitwise the handle-buffer result."""
+    import torch
+    p = wl.PRESETS["C2"]
+    prob = wl.make_problem(p)
+    with oic.controller_for(prob, max_N=32, max_H=1, mem_mode=oic.OIC_MEM_DEVICE) as c:
+        Xa, Ua = _inputs(p, 32, 1)
+        Xb, Ub = _inputs(p, 3, 2)
+        big = c.cnn_forward_noalloc(Xa, Ua)
+        small = c.cnn_forward_noalloc(Xb, Ub)
+        torch.cuda.synchronize()
+        assert torch.equal(big, c.cnn_forward(Xa, Ua))
+        assert torch.equal(small, c.cnn_forward(Xb, Ub))
+
+
+def test_noalloc_refuses_requests_beyond_the_buffer():
+    import torch
+    p = wl.PRESETS["C2"]
+    prob = wl.make_problem(p)
+    # 2 x 128 x 64 x 64 x 16 FP32 activations + 256 B exceed the 64 MiB buffer
+    b = 128
+    assert 2 * b * p.n * p.m * 16 * 4 + 256 > oic.OIC_NOALLOC_SCRATCH_BYTES
+    with oic.controller_for(prob, max_N=b, max_H=1, mem_mode=oic.OIC_MEM_DEVICE) as c:
+        X, U = _inputs(p, b, 3)
+        out = torch.full((b, p.n, p.m), 7.0, device="cuda")
+        with pytest.raises(oic.OicError) as e:
+            c.cnn_forward_noalloc(X, U, out=out)
+        assert e.value.code == oic.OIC_ENOMEM
+        assert "bytes of scratch" in str(e.value)
+        torch.cuda.synchronize()
+        assert bool((out == 7.0).all())
+        # the largest batch that fits still runs
+        fit = 127
+        got = c.cnn_forward_noalloc(X[:fit].contiguous(), U[:fit].contiguous())
+        assert torch.equal(got, c.cnn_forward(X[:fit].contiguous(), U[:fit].contiguous()))
+
+
+def test_noalloc_needs_a_device_memory_handle():
+    p = wl.PRESETS["C1"]
+    prob = wl.make_problem(p)
+    with oic.controller_for(prob, max_N=4, max_H=1) as c:
+        X = np.zeros((2, p.n, p.m), np.float32)
+        U = np.zeros((2, p.l, p.m), np.float32)
+        out = np.full((2, p.n, p.m), 3.0, np.float32)
+        rc = oic.lib().oic_cnn_forward_noalloc(c._h, 2, X.ctypes.data, U.ctypes.data, out.ctypes.data)
+        assert rc == oic.OIC_EINVAL
+        assert b"OIC_MEM_DEVICE" in oic.lib().oic_last_error(c._h)
+        assert np.all(out == 3.0)
