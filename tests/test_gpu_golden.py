@@ -1,0 +1,120 @@
+"""Full-size parity against the FP64 oracle, through the C ABI.
+
+The oracle takes minutes per solve at the 128x128 workload, so its results are computed
+once on the host by tests/golden/make_oracle_expected.py (which calls only the oracle and
+the seeded input generators) and stored under tests/golden/ with a digest of the inputs;
+each test recomputes the digest from the generators and refuses a stale file.
+
+Tolerances (each normwise, ||gpu - oracle||_F / ||oracle||_F, and element-wise,
+max |gpu - oracle| / max |oracle|):
+  * one FP32 solve: 1e-5 on U_hat and X_hat of every slice;
+  * one BF16-rollout solve: 2e-2 on U_hat and X_hat;
+  * FP32 closed loops: the per-solve bound accumulated over the loop, steps x 1e-5, on the
+    realised states and applied controls and on the closed-loop tracking cost (each step's
+    control is within 1e-5 of the oracle's and the plant is the same surrogate, so a
+    per-step deviation passes into the next state at most linearly over the loop);
+  * BF16 closed loops: tracking cost within 2% of the oracle's.
+"""
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+from paper_2410_09663_amd import oic
+from paper_2410_09663_amd import workloads as wl
+from parity_util import assert_parity, max_relerr, relerr
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+TOL_FP32 = 1e-5
+TOL_BF16 = 2e-2
+TOL_COST_BF16 = 2e-2
+
+
+def _maker():
+    spec = importlib.util.spec_from_file_location("make_oracle_expected",
+                                                  os.path.join(GOLDEN, "make_oracle_expected.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _load(name, digest):
+    path = os.path.join(GOLDEN, name)
+    assert os.path.exists(path), f"{path} is missing: run tests/golden/make_oracle_expected.py"
+    rec = np.load(path, allow_pickle=False)
+    assert str(rec["digest"]) == digest, f"{name} was computed from other inputs: regenerate it"
+    return rec
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_c3_full_solve_vs_oracle(precision):
+    """One solve of the 128x128 workload (l = 32, CNN 2-32-32-32-1 GELU, N = 256,
+    H = 10) on the oracle's explicit noise."""
+    mk = _maker()
+    p, prob, Xref, z = mk.c3_solve_inputs()
+    rec = _load("c3_solve_oracle.npz", mk.c3_solve_digest(prob, Xref, z))
+    prec = {"fp32": oic.OIC_PREC_FP32, "bf16": oic.OIC_PREC_BF16}[precision]
+    print(f"c3 full solve, {precision}: 128x128, N={p.N}, H={p.H}", flush=True)
+    with oic.controller_for(prob, precision=prec) as c:
+        U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
+    tol = TOL_FP32 if precision == "fp32" else TOL_BF16
+    eu, eum = assert_parity(U, rec["U_mean"], tol, f"C3 {precision} U_hat")
+    ex, exm = assert_parity(X, rec["X_mean"], tol, f"C3 {precision} X_hat")
+    print(f"C3 {precision} vs FP64 oracle: U_hat {eu:.2e} (max {eum:.2e}), X_hat {ex:.2e} (max {exm:.2e})",
+          flush=True)
+
+
+def _gpu_loop(prob, p, steps, refs, precision):
+    """The receding-horizon loop on the library: seeded solve at step k with key
+    noise_seed_base + k, apply U_hat_k, FP32 plant step; U_prev carried by the handle."""
+    X = prob.X0.copy()
+    Xs, Us = [X], []
+    with oic.controller_for(prob, precision=precision) as c:
+        for k in range(steps):
+            U, _ = c.solve(X, np.ascontiguousarray(refs[k:k + p.H + 1]), prob.Q, prob.R, p.N, p.H,
+                           p.noise_seed_base + k)
+            X = c.plant_step(X, U[0])
+            Xs.append(X)
+            Us.append(U[0])
+    return np.stack(Xs), np.stack(Us)
+
+
+def _loop_cost(Xs, Us, refs, prob):
+    """Closed-loop tracking cost from the library's FP64 stage cost."""
+    total = 0.0
+    Up = np.zeros_like(Us[0])
+    for k in range(Us.shape[0]):
+        total += oic.stage_cost(Xs[k + 1], refs[k + 1], Us[k], Us[k] - Up, prob.Q, prob.R)
+        Up = Us[k]
+    return total
+
+
+@pytest.mark.parametrize("case,precision", [("c2_loop", "fp32"), ("c2_loop", "bf16"),
+                                            ("c3_loop", "fp32"), ("c3_loop", "bf16")])
+def test_closed_loop_vs_oracle(case, precision):
+    """Free-running closed loops (Algorithm 1, lines 3-16) against the oracle's own loop on
+    the same Philox noise stream: realised states, applied controls, tracking cost."""
+    mk = _maker()
+    p, prob, steps, refs = mk.loop_inputs(case)
+    rec = _load(f"{case}_oracle.npz", mk.loop_digest(prob, refs, p))
+    print(f"{case} {precision}: {p.n}x{p.m}, N={p.N}, H={p.H}, {steps} steps", flush=True)
+    prec = {"fp32": oic.OIC_PREC_FP32, "bf16": oic.OIC_PREC_BF16}[precision]
+    Xs, Us = _gpu_loop(prob, p, steps, refs, prec)
+    cost = _loop_cost(Xs, Us, refs, prob)
+    cost_ref = float(rec["cost"])
+    dc = abs(cost - cost_ref) / abs(cost_ref)
+    eX, eXm = relerr(Xs, rec["Xs"]), max_relerr(Xs, rec["Xs"])
+    eU, eUm = relerr(Us, rec["Us"]), max_relerr(Us, rec["Us"])
+    print(f"{case} {precision} vs FP64 oracle loop: states {eX:.2e} (max {eXm:.2e}), controls {eU:.2e} "
+          f"(max {eUm:.2e}), cost {cost:.6g} vs {cost_ref:.6g} ({dc:.2e})", flush=True)
+    if precision == "fp32":
+        tol = steps * TOL_FP32
+        assert_parity(Xs, rec["Xs"], tol, f"{case} states")
+        assert_parity(Us, rec["Us"], tol, f"{case} controls")
+        assert dc < tol
+    else:
+        assert dc < TOL_COST_BF16
