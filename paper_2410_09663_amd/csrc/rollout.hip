@@ -474,6 +474,139 @@ __global__ __launch_bounds__(256 * WGM) void k_conv_mfma_f32p(int N, int n, int 
   }
 }
 
+// Persistent walk of `tiles` tiles by gridDim.x workgroups, aware of the eight XCDs:
+// workgroup b runs on XCD b mod 8, so the tiles are cut into eight contiguous ranges and
+// the workgroups of one XCD walk theirs side by side (tile = range start + b / 8,
+// then + gridDim.x / 8, ...).  Neighbouring tiles share halo rows; this keeps the
+// workgroups that read them at the same time behind the same L2.  When the grid is not
+// a multiple of eight, or exceeds the tiles, a plain stride is used.
+struct TileWalk {
+  int first, step, end;
+  __device__ TileWalk(int tiles) {
+    const int G = gridDim.x;
+    if ((G & 7) == 0 && tiles >= G) {
+      const int x = blockIdx.x & 7;
+      first = (int)((long long)tiles * x / 8) + (blockIdx.x >> 3);
+      step = G >> 3;
+      end = (int)((long long)tiles * (x + 1) / 8);
+    } else {
+      first = blockIdx.x;
+      step = G;
+      end = tiles;
+    }
+  }
+};
+
+// FP32 hidden layer CIN -> 64 on v_mfma_f32_16x16x4f32 with the weights held in
+// registers.  Wave w of the four-wave workgroup owns output channels 16w..16w+15 for
+// every pixel of a TR x 64 tile: its B fragments for all K = 9*CIN indices stay in
+// registers for the whole (persistent) kernel, so the LDS holds only the halo tile and
+// two workgroups fit on a CU (one stages its next tile while the other is on the matrix
+// cores).  K is walked in steps of 16 channels of one tap: lane (i, g) reads channels
+// c0+4g..c0+4g+3 of its pixel as one 16-byte LDS load and feeds them to four MFMAs, the
+// j-th taking channel c0+4g+j in k-slot g, with the weights permuted the same way (each
+// four-MFMA group then covers the 16 channels once).  The pixel stride in LDS is CIN+4
+// floats: the eight lanes of a 128-byte LDS phase read 8 consecutive pixels at a
+// 16-byte offset each, covering all banks.  Lane layout (16x16x4 f32): A[i][k] from lane
+// i + 16k, B[k][j] from lane j + 16k, element r of lane j + 16g holds D[4g + r][j].
+template <int CIN, int TR>
+__global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const float* __restrict__ in,
+                                                      const float* __restrict__ wk,
+                                                      const float* __restrict__ bias, int act,
+                                                      float* __restrict__ out) {
+  constexpr int COUT = 64, TC = 64;
+  constexpr int HR = TR + 2, HC = TC + 2;
+  constexpr int CP = CIN + 4;
+  constexpr int CG = CIN / 16;  // 16-channel groups per tap
+  constexpr int S = 9 * CG;     // K steps of 16 indices
+  constexpr int Q = CIN / 4;
+  constexpr int TOTAL = HR * HC * Q;    // float4 of one halo tile
+  constexpr int SLOTS = (TOTAL + 255) / 256;
+  constexpr int PASS = 4;               // float4 loads in flight per thread while staging
+  static_assert(CIN % 16 == 0, "16-channel K steps");
+  __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
+  const int col_tiles = (m + TC - 1) / TC;
+  const int row_tiles = (n + TR - 1) / TR;
+  const int tiles = N * row_tiles * col_tiles;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int o = 16 * w + li;
+  // this lane's weights: step s, MFMA j -> W[tap][c0 + 4 lk + j][o]
+  float wr[S][4];
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    const int tap = st / CG, c0 = (st % CG) * 16 + 4 * lk;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wr[st][j] = wk[((size_t)tap * CIN + c0 + j) * COUT + o];
+  }
+  const float bo = bias ? bias[o] : 0.f;
+  const TileWalk walk(tiles);
+  for (int tile = walk.first; tile < walk.end; tile += walk.step) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+    __syncthreads();  // every wave is done with the previous tile
+    // stage the (TR+2) x 66 x CIN halo, zero outside the field, PASS loads at a time
+#pragma unroll
+    for (int u0 = 0; u0 < SLOTS; u0 += PASS) {
+      f32x4 v[PASS];
+#pragma unroll
+      for (int u = 0; u < PASS; ++u) {
+        const int e = tid + (u0 + u) * 256;
+        v[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (u0 + u < SLOTS && e < TOTAL) {
+          const int q = e % Q, pix = e / Q;
+          const int xx = pix % HC, yy = pix / HC;
+          const int gy = y0 + yy - 1, gx = x0 + xx - 1;
+          if (gy >= 0 && gy < n && gx >= 0 && gx < m)
+            v[u] = *(const f32x4*)(in + (((size_t)i * n + gy) * m + gx) * CIN + 4 * q);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PASS; ++u) {
+        const int e = tid + (u0 + u) * 256;
+        if (u0 + u < SLOTS && e < TOTAL) *(f32x4*)(s_in + (e / Q) * CP + 4 * (e % Q)) = v[u];
+      }
+    }
+    __syncthreads();
+    f32x4 acc[TR][4];
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) acc[r][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int tap = st / CG, c0 = (st % CG) * 16 + 4 * lk;
+      const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+      for (int r = 0; r < TR; ++r)
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const f32x4 a = *(const f32x4*)(s_in + ((r + dy) * HC + 16 * mb + li + dx) * CP + c0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[r][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], wr[st][j], acc[r][mb], 0, 0, 0);
+        }
+      // keep each step's LDS reads beside its MFMAs: hoisting later steps' reads ahead
+      // would hold more A fragments live than the registers beside the weights allow
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < TR; ++r) {
+      const int y = y0 + r;
+      if (y >= n) continue;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int x = x0 + 16 * mb + 4 * lk + q;
+          if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = activate(acc[r][mb][q] + bo, act);
+        }
+    }
+  }
+}
+
 // First layer with the lift fused: the block stages the 6 x 66 halo of X, the l rows
 // of U over the same columns and the 6 rows of B in LDS (all loads issued before the
 // stores), forms B U per halo cell from LDS, computes 4 x 64 output pixels x COUT
@@ -1204,6 +1337,20 @@ bool conv_mfma_supported(int cin, int cout) {
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                       const float* in_nhwc, const float* wk, const float* bias, int act,
                       float* out_nhwc) {
+  if (cout == 64 && (cin == 32 || cin == 64)) {
+    // weights in registers, two persistent workgroups per CU
+    constexpr int TRV = 2;
+    const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);
+    const long long cap = 2LL * 256;
+    const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
+    if (cin == 64)
+      OIC_LAUNCH(t, kclass, s, (k_conv_f32r<64, TRV>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk, bias,
+                 act, out_nhwc);
+    else
+      OIC_LAUNCH(t, kclass, s, (k_conv_f32r<32, TRV>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk, bias,
+                 act, out_nhwc);
+    return;
+  }
 #define OIC_CONV_CASE(CI, CO)                                                                   \
   if (cin == CI && cout == CO) {                                                                \
     constexpr bool W8 = CI == 16 && CO == 16;  /* 8 waves, one row each */            \
