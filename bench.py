@@ -53,13 +53,24 @@ def algorithmic_work(p, H, precision="fp32"):
         work[k] = (f0 + f, b0 + b)
 
     L = len(p.channels) - 1
+    folded = last_layer_folded(p, precision)
+    px = n * m * N
     for t in range(1, H + 1):
         Ma = (t + 1) * rr
         for k, (ci, co) in enumerate(zip(p.channels[:-1], p.channels[1:])):
             cls = "conv_first" if k == 0 else ("conv_last" if k == L - 1 else "conv_mid")
-            rd = 4.0 * (n + l) * m * N if k == 0 else ab * ci * n * m * N
-            wr = 4.0 * n * m * N if k == L - 1 else ab * co * n * m * N
-            add(cls, 2.0 * 9 * ci * co * n * m * N, rd + wr)
+            rd = 4.0 * (n + l) * m * N if k == 0 else ab * ci * px
+            wr = 4.0 * px if k == L - 1 else ab * co * px
+            f = 2.0 * 9 * ci * co * px
+            if folded and k == L - 2:
+                # the last layer's products run in this launch's epilogue, which writes the
+                # nine FP32 tap planes instead of the activations
+                f += 2.0 * 9 * co * px
+                wr = 4.0 * 9 * px
+            if folded and k == L - 1:
+                # the remaining tap sum: nine planes read, the state written
+                f, rd = 9.0 * px, 4.0 * 9 * px
+            add(cls, f, rd + wr)
         add("stats", 2.0 * (Ma + pp) * pp * NM, 4.0 * (Ma + pp) * NM)
         # time at peak: Sigma^{XY} on the FP32 matrix cores in every mode, Sigma^Y on the
         # FP64 ones in the FP32 mode (FP32 otherwise); the class's peak is the FLOP-weighted one
@@ -71,6 +82,14 @@ def algorithmic_work(p, H, precision="fp32"):
         add("gain", 2.0 * pp * pp * Ma, 8.0 * (Ma * pp + pp * pp) + 4.0 * Ma * pp)
     add("means", float((H + 1) * rr) * NM, 4.0 * (H + 1) * rr * NM)  # final smoothed means
     return work
+
+
+def last_layer_folded(p, precision):
+    """Whether the library folds the last layer (C -> 1) into the last hidden layer's
+    epilogue: the FP32 rollout with a last hidden layer of 32 or 64 inputs and 64 outputs
+    (the library's conv_last_folds)."""
+    ch = p.channels
+    return precision == "fp32" and len(ch) >= 4 and ch[-2] == 64 and ch[-3] in (32, 64)
 
 
 MATRIX_CLASSES = ("conv_first", "conv_mid", "stats", "gain", "update")

@@ -509,11 +509,19 @@ struct TileWalk {
 // floats: the eight lanes of a 128-byte LDS phase read 8 consecutive pixels at a
 // 16-byte offset each, covering all banks.  Lane layout (16x16x4 f32): A[i][k] from lane
 // i + 16k, B[k][j] from lane j + 16k, element r of lane j + 16g holds D[4g + r][j].
-template <int CIN, int TR>
+//
+// LASTQ: this is the last hidden layer and the network's last layer (64 -> 1) is folded
+// into the epilogue.  The activated tile goes to LDS instead of HBM and the last layer's
+// per-tap partial sums P_tap(p) = sum_c wl[c][tap] h(p)[c] are formed on the matrix cores
+// (K = 64 channels, the 9 taps as the N side); they leave as nine FP32 planes
+// qout[tap][i][y][x] (plane stride N n m), and k_conv_last_sum adds the nine shifted
+// taps: out(y, x) = sum over (dy, dx) of P_(dy,dx)(y + dy - 1, x + dx - 1).  Per pixel the
+// hidden layer then writes 36 bytes instead of 256, and the last layer reads them once.
+template <int CIN, int TR, bool LASTQ>
 __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const float* __restrict__ in,
                                                       const float* __restrict__ wk,
                                                       const float* __restrict__ bias, int act,
-                                                      float* __restrict__ out) {
+                                                      float* __restrict__ out, const float* __restrict__ wl) {
   constexpr int COUT = 64, TC = 64;
   constexpr int HR = TR + 2, HC = TC + 2;
   constexpr int CP = CIN + 4;
@@ -524,7 +532,10 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
   constexpr int SLOTS = (TOTAL + 255) / 256;
   constexpr int PASS = 4;               // float4 loads in flight per thread while staging
   static_assert(CIN % 16 == 0, "16-channel K steps");
+  constexpr int HP = COUT + 4;  // pixel stride of the activated tile (LASTQ)
+  static_assert(!LASTQ || TR * TC * HP <= HR * HC * CP, "the activated tile reuses the halo's LDS");
   __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
+  __shared__ float s_wl[LASTQ ? COUT * 16 : 1];  // last layer [c][tap], taps 9..15 zero
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
   const int tiles = N * row_tiles * col_tiles;
@@ -532,6 +543,12 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
   const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int o = 16 * w + li;
+  if constexpr (LASTQ) {
+    for (int e = tid; e < COUT * 16; e += 256) {
+      const int c = e >> 4, tap = e & 15;
+      s_wl[e] = tap < 9 ? wl[c * 9 + tap] : 0.f;
+    }
+  }
   // this lane's weights: step s, MFMA j -> W[tap][c0 + 4 lk + j][o]
   float wr[S][4];
 #pragma unroll
@@ -592,19 +609,82 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
       // would hold more A fragments live than the registers beside the weights allow
       __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (!LASTQ) {
 #pragma unroll
-    for (int r = 0; r < TR; ++r) {
-      const int y = y0 + r;
-      if (y >= n) continue;
+      for (int r = 0; r < TR; ++r) {
+        const int y = y0 + r;
+        if (y >= n) continue;
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
+        for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int x = x0 + 16 * mb + 4 * lk + q;
-          if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = activate(acc[r][mb][q] + bo, act);
+          for (int q = 0; q < 4; ++q) {
+            const int x = x0 + 16 * mb + 4 * lk + q;
+            if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = activate(acc[r][mb][q] + bo, act);
+          }
+      }
+    } else {
+      __syncthreads();  // every wave is done with the halo tile
+      float* const s_h = s_in;  // activated tile [pixel][channel], pixel = r * 64 + x
+#pragma unroll
+      for (int r = 0; r < TR; ++r)
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            s_h[(r * TC + 16 * mb + 4 * lk + q) * HP + o] = activate(acc[r][mb][q] + bo, act);
+      __syncthreads();
+      // wave w: pixels 32w .. 32w+31 of the tile as two M-blocks, K = 64 channels in the
+      // same 16-channel steps as above, N = the 9 taps (padded to 16)
+      constexpr int MB2 = TR * TC / 64;  // M-blocks per wave
+#pragma unroll
+      for (int mb = 0; mb < MB2; ++mb) {
+        const int pb = (w * MB2 + mb) * 16;
+        f32x4 qa = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c0 = 0; c0 < COUT; c0 += 16) {
+          const f32x4 a = *(const f32x4*)(s_h + (pb + li) * HP + c0 + 4 * lk);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            qa = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], s_wl[(c0 + 4 * lk + j) * 16 + li], qa, 0, 0, 0);
         }
+        if (li < 9) {
+          const long long plane = (long long)N * n * m;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int px = pb + 4 * lk + q;
+            const int y = y0 + px / TC, x = x0 + px % TC;
+            if (y < n && x < m) out[li * plane + ((long long)i * n + y) * m + x] = qa[q];
+          }
+        }
+      }
     }
   }
+}
+
+// The last layer from the nine tap planes of k_conv_f32r<..., true>: out(y, x) = bias +
+// the sum over the 3 x 3 taps of P_tap at (y + dy - 1, x + dx - 1), zero outside the
+// field; writes the strided field and, with obs.Y, the X rows of Ybar (Eq. (12)).
+__global__ __launch_bounds__(256) void k_conv_last_sum(int N, int n, int m, const float* __restrict__ q,
+                                                       const float* __restrict__ bias, FieldOut fo,
+                                                       ObserveArgs obs) {
+  const long long plane = (long long)N * n * m;
+  const int x = blockIdx.y * 256 + threadIdx.x;
+  const int y = blockIdx.x % n, i = blockIdx.x / n;
+  if (x >= m) return;
+  float acc = bias ? bias[0] : 0.f;
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy) {
+    const int yy = y + dy - 1;
+    if (yy < 0 || yy >= n) continue;
+    const float* row = q + ((long long)i * n + yy) * m;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int xx = x + dx - 1;
+      if (xx >= 0 && xx < m) acc += row[(3 * dy + dx) * plane + xx];
+    }
+  }
+  fo.base[i * fo.si + y * fo.sy + x] = acc;
+  if (obs.Y) obs.Y[y * obs.NM + (long long)i * m + x] = acc + noise_value(obs.vx, y, i, x, m);
 }
 
 // First layer with the lift fused: the block stages the 6 x 66 halo of X, the l rows
@@ -1344,11 +1424,11 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
     const long long cap = 2LL * 256;
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
     if (cin == 64)
-      OIC_LAUNCH(t, kclass, s, (k_conv_f32r<64, TRV>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk, bias,
-                 act, out_nhwc);
+      OIC_LAUNCH(t, kclass, s, (k_conv_f32r<64, TRV, false>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk,
+                 bias, act, out_nhwc, nullptr);
     else
-      OIC_LAUNCH(t, kclass, s, (k_conv_f32r<32, TRV>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk, bias,
-                 act, out_nhwc);
+      OIC_LAUNCH(t, kclass, s, (k_conv_f32r<32, TRV, false>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk,
+                 bias, act, out_nhwc, nullptr);
     return;
   }
 #define OIC_CONV_CASE(CI, CO)                                                                   \
@@ -1383,6 +1463,26 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
 #undef OIC_CONV_CASE
 }
 
+bool conv_last_folds(int cin, int cout) { return cout == 64 && (cin == 32 || cin == 64); }
+
+void launch_conv_mfma_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const float* in_nhwc,
+                           const float* wk, const float* bias, int act, const float* w_last,
+                           const float* bias_last, float* qbuf, FieldOut fo, const ObserveArgs* obs) {
+  constexpr int TRV = 2;
+  const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);
+  const long long cap = 2LL * 256;
+  const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
+  if (cin == 64)
+    OIC_LAUNCH(t, KC_CONV_MID, s, (k_conv_f32r<64, TRV, true>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk,
+               bias, act, qbuf, w_last);
+  else
+    OIC_LAUNCH(t, KC_CONV_MID, s, (k_conv_f32r<32, TRV, true>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk,
+               bias, act, qbuf, w_last);
+  const ObserveArgs oa = obs ? *obs : ObserveArgs{};
+  OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+             0, N, n, m, qbuf, bias_last, fo, oa);
+}
+
 int rollout_fp32(hipStream_t s, Timer& t, const oic_config& c, const Fp32Net& net, float* act0,
                  float* act1, int batch, FieldRef X, FieldRef U, FieldOut out, const ObserveArgs* obs) {
   const int L = c.n_layers;
@@ -1408,6 +1508,13 @@ int rollout_fp32(hipStream_t s, Timer& t, const oic_config& c, const Fp32Net& ne
       launch_conv_last(s, t, batch, c.n, c.m, cin, act[cur], net.W[k], net.bias[k], out, false, obs);
       if (obs) done |= ROLL_X_OBSERVED;
       continue;
+    }
+    if (k == L - 2 && k > 0 && net.Wk[k] && conv_last_folds(cin, cout) && c.channels[L] == 1) {
+      // the last hidden layer with the last layer folded into its epilogue
+      launch_conv_mfma_last(s, t, batch, c.n, c.m, cin, act[cur], net.Wk[k], net.bias[k], c.activation,
+                            net.W[L - 1], net.bias[L - 1], act[1 - cur], out, obs);
+      if (obs) done |= ROLL_X_OBSERVED;
+      break;
     }
     if (!last && net.Wk[k]) {
       launch_conv_mfma(s, t, cls, batch, c.n, c.m, cin, cout, act[cur], net.Wk[k], net.bias[k],

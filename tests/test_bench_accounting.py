@@ -27,6 +27,24 @@ def test_hidden_layer_work_is_the_convolution_count():
     assert fb == pytest.approx(f) and bb == pytest.approx(b / 2)
 
 
+def test_folded_last_layer_keeps_the_network_flops():
+    """With the last layer folded into the last hidden layer's epilogue (FP32, 64-channel
+    hidden layers) the conv FLOPs per step are the network's, and the last layer's class
+    moves the nine FP32 tap planes and the state instead of the activations."""
+    p = wl.PRESETS["C4"]
+    assert bench.last_layer_folded(p, "fp32") and not bench.last_layer_folded(p, "bf16")
+    px = p.n * p.m * p.N
+    ch = p.channels
+    net = sum(2.0 * 9 * a * b * px for a, b in zip(ch[:-1], ch[1:]))
+    for prec in ("fp32", "bf16"):
+        work = bench.algorithmic_work(p, 1, prec)
+        conv = sum(work[c][0] for c in ("conv_first", "conv_mid")) + (
+            0.0 if bench.last_layer_folded(p, prec) else work["conv_last"][0])
+        assert conv == pytest.approx(net)
+    f, b = bench.algorithmic_work(p, 1, "fp32")["conv_last"]
+    assert b == pytest.approx(4.0 * 10 * px)
+
+
 def test_statistics_peak_lies_between_the_two_matrix_core_peaks():
     p = wl.PRESETS["C2"]
     for prec, lo, hi in (("fp32", bench.PEAK["fp64"], bench.PEAK["fp32"]),

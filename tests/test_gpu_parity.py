@@ -50,9 +50,15 @@ def test_device_normals_match_oracle(kind, count):
 
 
 @pytest.mark.parametrize("preset", ["C1", "C2", "tiny", "tiny_gelu", "wide", "deep_a", "deep_b",
-                                    "c16_ragged", "c16_l16"])
+                                    "c16_ragged", "c16_l16", "fold64", "fold32"])
 def test_cnn_forward_matches_oracle(preset):
-    if preset == "tiny":
+    if preset == "fold64":
+        # 64 -> 64 -> 1: the last layer folded into the last hidden layer's epilogue; 9 rows
+        # and 70 columns leave ragged row and column tiles
+        p = wl.small_preset(n=9, m=70, l=4, channels=(2, 64, 64, 64, 1), activation=wl.ACT_GELU, N=3)
+    elif preset == "fold32":
+        p = wl.small_preset(n=7, m=67, l=3, channels=(2, 16, 32, 64, 1), N=4)
+    elif preset == "tiny":
         p = tiny()
     elif preset == "c16_ragged":
         # 2-16-16-1 with ragged row (13) and column (70 = 64 + 6) tiles
@@ -86,9 +92,12 @@ def test_cnn_forward_matches_oracle(preset):
 
 
 @pytest.mark.parametrize("preset", ["C1", "tiny", "tiny_gelu", "tiny_l1", "C2", "p90", "p100", "p150",
-                                    "p500"])
+                                    "p500", "fold64"])
 def test_solve_explicit_noise_matches_oracle(preset):
-    if preset == "tiny":
+    if preset == "fold64":
+        # 64-channel hidden layers with the last layer folded, on a ragged 20 x 72 field
+        p = tiny(n=20, m=72, l=5, channels=(2, 64, 64, 1), act=wl.ACT_GELU, N=12, H=3)
+    elif preset == "tiny":
         p = tiny()
     elif preset == "p90":
         # p = n + l = 90: the largest one-workgroup Cholesky, padded to 96 (the most LDS)
