@@ -713,7 +713,11 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   // vectors, 256x256 C=64 141 -> 171 ms)
   constexpr bool VEC = sizeof(TOUT) == 2 && COUT <= 32;
   constexpr int OPAD = VEC ? COUT + 4 : COUT + 1;
-  __shared__ __attribute__((aligned(16))) float s_out[TR * TC * OPAD];
+  // 64 output channels leave straight from the accumulators (each 16-lane group stores
+  // one pixel's 16 consecutive channels): without the output tile the LDS holds five
+  // workgroups per CU instead of one
+  constexpr bool DIRECT = COUT >= 64;
+  __shared__ __attribute__((aligned(16))) float s_out[DIRECT ? 1 : TR * TC * OPAD];
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
   int bid = blockIdx.x;
@@ -840,6 +844,31 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
         for (int nb = 0; nb < NB; ++nb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[mb][nb], 0, 0, 0);
       }
+    }
+    if constexpr (DIRECT) {
+      // wave w owns output row w of the tile
+      const int y = y0 + w;
+      float vmax = 0.f;
+      if (y < n) {
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int o = nb * 16 + li;
+            const float bo = s_bias[o];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int x = x0 + mb * 16 + 4 * lk + r;
+              if (x < m) {
+                const float v = activate(acc[mb][nb][r] + bo, act);
+                store_act(out + (((size_t)i * n + y) * m + x) * COUT + o, v);
+                vmax = fmaxf(vmax, fabsf(v));
+              }
+            }
+          }
+      }
+      if (amax) amax_publish(vmax, amax);
+      return;
     }
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
