@@ -188,6 +188,105 @@ __global__ __launch_bounds__(64 * WR) void k_update_rows(Dims d, float* __restri
   }
 }
 
+// The same update for larger p, persistent over 64-column strips: a workgroup forms the
+// strip's innovation tile E[b][c] = Ybar_t[b][c mod m] - Y[b][c] once, transposed in LDS
+// (E^T[c][b], pixel stride P16 + 4 floats), and its eight waves then walk 16-row blocks
+// of the trajectory independently (no barrier until the next strip): a wave reads its
+// block's gain rows straight into registers (they are shared by every strip, so they
+// come from L2) and, per 16 observation rows b, lane (i, g) takes K[a0 + i][b0 + 4g + j]
+// for the j-th of four MFMAs against E^T rows read as one 16-byte LDS load, the pairs
+// (g, j) covering the 16 rows once.  The trajectory tile is read and written once per
+// step.  P16 is p rounded up to the instantiated size (gain and innovation are zero
+// beyond p).
+constexpr int kStripWaves = 8;
+template <int P16>
+__global__ __launch_bounds__(64 * kStripWaves) void k_update_strip(Dims d, float* __restrict__ traj, int Ma,
+                                                               const float* __restrict__ K,
+                                                               const float* __restrict__ Y,
+                                                               const float* __restrict__ xref) {
+  constexpr int NT = 64 * kStripWaves;
+  constexpr int EP = P16;  // a multiple of 32 floats: E^T[c][b] sits at c*EP + (b ^ 4 (c mod 8))
+  constexpr int S = P16 / 16;
+  static_assert(P16 % 32 == 0, "row stride a multiple of the 32 banks");
+  __shared__ __attribute__((aligned(16))) float sE[UC * EP];
+  const int NM = (int)d.NM();
+  const int m = d.m, n = d.n, p = d.p();
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int strips = (NM + UC - 1) / UC;
+  const int row_blocks = (Ma + 15) / 16;
+  for (int strip = blockIdx.x; strip < strips; strip += gridDim.x) {
+    const int c0 = strip * UC;
+    __syncthreads();  // every wave is done with the previous strip's tile
+    for (int e = tid; e < P16 * UC; e += NT) {
+      const int b = e / UC, cl = e % UC;
+      const int c = c0 + cl;
+      float v = 0.f;
+      if (b < p && c < NM) v = (b < n ? xref[(size_t)b * m + c % m] : 0.f) - Y[(size_t)b * NM + c];
+      // the XOR moves whole 4-float groups, so a lane's 16-byte read stays in one piece,
+      // and puts the eight 16-byte reads of one LDS phase (8 consecutive c) in 8 bank groups
+      sE[cl * EP + (b ^ (4 * (cl & 7)))] = v;
+    }
+    __syncthreads();
+    for (int rb = w; rb < row_blocks; rb += kStripWaves) {
+      const int a0 = rb * 16;
+      // this lane's gain values: row a0 + li, columns 16s + 4lk + j
+      float kr[S][4];
+      const int ka = a0 + li;
+      if ((p & 3) == 0) {  // 16-byte aligned gain rows: one vector load per step
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+          const int b = 16 * st + 4 * lk;
+          f32x4u v = f32x4u{0.f, 0.f, 0.f, 0.f};
+          if (ka < Ma && b < p) v = *(const f32x4u*)(K + (size_t)ka * p + b);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) kr[st][j] = v[j];
+        }
+      } else {
+#pragma unroll
+        for (int st = 0; st < S; ++st)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int b = 16 * st + 4 * lk + j;
+            kr[st][j] = (ka < Ma && b < p) ? K[(size_t)ka * p + b] : 0.f;
+          }
+      }
+      float old[4][4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = a0 + 4 * lk + r, c = c0 + 16 * nb + li;
+          old[nb][r] = (a < Ma && c < NM) ? traj[(size_t)a * NM + c] : 0.f;
+        }
+      f32x4u acc[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4u{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < S; ++st)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const int cl = 16 * nb + li;
+          const f32x4u e = *(const f32x4u*)(sE + cl * EP + ((16 * st + 4 * lk) ^ (4 * (cl & 7))));
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kr[st][j], e[j], acc[nb], 0, 0, 0);
+          // one step's LDS reads at a time beside its MFMAs (hoisting them all would
+          // need more registers than the gain rows leave)
+          if (nb == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = a0 + 4 * lk + r, c = c0 + 16 * nb + li;
+          if (a < Ma && c < NM) traj[(size_t)a * NM + c] = old[nb][r] + acc[nb][r];
+        }
+    }
+  }
+}
+
 // Smoothed means of every slice -> U_out (H+1, l, m), X_out (H+1, n, m) and U_hat_k.
 __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restrict__ Uout,
                           float* __restrict__ Xout, float* __restrict__ Uprev) {
@@ -223,6 +322,22 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
                xref_t);
     return;
   }
+  // strips: one workgroup per CU (the transposed innovation tile fills most of its LDS)
+  const unsigned strips = col_tiles < 256 ? col_tiles : 256;
+#define OIC_STRIP_CASE(P16V)                                                                            \
+  if (d.p() <= P16V) {                                                                                  \
+    OIC_LAUNCH(t, KC_UPDATE, s, k_update_strip<P16V>, dim3(strips), dim3(64 * kStripWaves), 0, d, traj, Ma, K, \
+               Y, xref_t);                                                                              \
+    return;                                                                                             \
+  }
+  OIC_STRIP_CASE(128)
+  OIC_STRIP_CASE(192)
+  OIC_STRIP_CASE(256)
+  OIC_STRIP_CASE(320)
+  OIC_STRIP_CASE(384)
+  OIC_STRIP_CASE(448)
+  OIC_STRIP_CASE(512)
+#undef OIC_STRIP_CASE
   constexpr int WR = kUpdWaves;
   const unsigned tall_tiles = (unsigned)((Ma + 16 * WR - 1) / (16 * WR));
   OIC_LAUNCH(t, KC_UPDATE, s, k_update_mfma<WR>, dim3(col_tiles, tall_tiles), dim3(64 * WR), 0, d, traj, Ma, K,
