@@ -388,6 +388,123 @@ __global__ __launch_bounds__(64 * WL) void k_stats_mfma32(Dims d, const float* _
     }
 }
 
+// The FP32-matrix-core products again, for row lengths N*m divisible by 4, with less LDS
+// traffic: a lane reads its A fragments straight from global memory into registers (each
+// left row belongs to one wave, so it gains nothing from LDS), four 16-column groups of a
+// 64-column stage as 16-byte loads, and only the centred right tile goes through LDS,
+// double-buffered so that one barrier per stage suffices.  K is permuted inside each
+// 16-column group: lane (i, g) supplies columns 4g..4g+3 of its row to four MFMAs, the
+// j-th taking column 4g+j in k-slot g, and reads the same four columns of the right rows
+// as one 16-byte LDS load.  Sums as in k_stats_mfma32: FP32 over four stages, then FP64.
+constexpr int SV_W = 8;       // waves per block, 16 left rows each
+constexpr int SV_CP = MK + 4;  // right-tile row stride in LDS (16-byte reads without bank conflicts)
+template <int NB>
+__global__ __launch_bounds__(64 * SV_W) void k_stats_v4(Dims d, const float* __restrict__ traj, int Ma, int ny,
+                                                        const float* __restrict__ Y, const float* __restrict__ R,
+                                                        int p, const double* __restrict__ muY, int chunk,
+                                                        int xt, int ytiles, int tiles,
+                                                        double* __restrict__ part) {
+  constexpr int RB = NB * 16, NT = 64 * SV_W;
+  // XCD-aware tile order (workgroup b runs on XCD b mod 8): the workgroups of one XCD take
+  // consecutive logical tiles, whose right tiles vary fastest, so the left rows they share
+  // and the right-tile stages of one split are read into that XCD's L2 once
+  const int G = gridDim.x;
+  const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+  if (L >= tiles) return;
+  const int ty = L % ytiles, tx = (L / ytiles) % xt, tz = L / (ytiles * xt);
+  constexpr int BQ = RB * MK / 4;            // float4 of the right tile
+  constexpr int BV = (BQ + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) float sB[2][RB * SV_CP];
+  const int NM = (int)d.NM();
+  const int m = d.m;
+  const int Mtot = Ma + ny;
+  const int a0 = tx * (16 * SV_W);
+  const int b0 = ty * RB;
+  const int c_begin = tz * chunk;
+  const int c_end = min(c_begin + chunk, NM);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int arow = a0 + 16 * w + li;
+  const float* asrc = arow < Mtot ? (arow < Ma ? traj + (size_t)arow * NM : Y + (size_t)(arow - Ma) * NM) : nullptr;
+  f32x4v acc[NB];
+  f64x4 tot[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    tot[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  f32x4v an[4], bn[BV];
+  auto load_stage = [&](int c0) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int c = c0 + 16 * g + 4 * lk;
+      an[g] = (asrc && c < c_end) ? *(const f32x4v*)(asrc + c) : f32x4v{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + NT * u;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int b = b0 + r, c = c0 + 4 * q;
+      bn[u] = (e < BQ && b < p && c < c_end) ? *(const f32x4v*)(R + (size_t)b * NM + c)
+                                             : f32x4v{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  if (c_begin < c_end) load_stage(c_begin);
+  int stage = 0;
+  for (int c0 = c_begin; c0 < c_end; c0 += MK, ++stage) {
+    float* const sb = sB[stage & 1];
+    f32x4v ac[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) ac[g] = an[g];
+    // right tile centred in FP64, rounded to FP32 (zero past the chunk and past p)
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + NT * u;
+      if (e >= BQ) continue;
+      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int b = b0 + r, c = c0 + 4 * q;
+      int x = c % m;
+      const double* mu = muY + (size_t)(b < p ? b : 0) * m;
+      f32x4v v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool live = b < p && c + j < c_end;
+        v[j] = live ? (float)((double)bn[u][j] - mu[x]) : 0.f;
+        x = (x + 1 == m) ? 0 : x + 1;
+      }
+      *(f32x4v*)(sb + r * SV_CP + 4 * q) = v;
+    }
+    __syncthreads();  // this stage's right tile is in LDS; the other buffer is free again
+    if (c0 + MK < c_end) load_stage(c0 + MK);  // the next stage's operands, in flight meanwhile
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const f32x4v b = *(const f32x4v*)(sb + (16 * nb + li) * SV_CP + 16 * g + 4 * lk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[g][j], b[j], acc[nb], 0, 0, 0);
+      }
+    if ((stage & 3) == 3) {  // fold the FP32 sums of the last four stages into FP64
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[nb][r] += (double)acc[nb][r];
+        acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+  double* out = part + (size_t)tz * Mtot * p;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = a0 + 16 * w + 4 * lk + r;
+      const int b = b0 + nb * 16 + li;
+      if (a < Mtot && b < p) out[(size_t)a * p + b] = tot[nb][r] + (double)acc[nb][r];
+    }
+}
+
 // S[idx] = scale * sum_z part[z][idx].  Block (64, RG): lane x owns output idx, and the
 // RG threads of a column sum interleaved subsets of the splits (z = y, y + RG, ...), which
 // are then added in the order y = 0, 1, ..., RG - 1: a fixed order, so the result is
@@ -460,6 +577,40 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
                   double* S, double scale, bool f32) {
   const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
+  if (f32 && NM % 4 == 0) {
+    // right rows per block: NB*16 with NB <= 5, balanced over grid.y tiles
+    const int nbk = (p + 15) / 16;
+    const int ytiles = (nbk + 4) / 5;
+    const int NBv = (nbk + ytiles - 1) / ytiles;
+    const int xt = (Mtot + 16 * SV_W - 1) / (16 * SV_W);
+    const int tiles = xt * ytiles;
+    // about two eight-wave workgroups per CU in flight; chunks are whole 64-column stages
+    // and the partials must fit the split buffer
+    int splits = (512 + tiles - 1) / tiles;
+    const int max_by_len = (NM + MK - 1) / MK;
+    if (splits > max_by_len) splits = max_by_len;
+    const size_t by_cap = part_cap / ((size_t)Mtot * p);
+    if ((size_t)splits > by_cap) splits = (int)by_cap;
+    if (splits < 1) splits = 1;
+    int chunk = (NM + splits - 1) / splits;
+    chunk = (chunk + MK - 1) / MK * MK;
+    splits = (NM + chunk - 1) / chunk;
+    const int all = tiles * splits;
+    const dim3 grid((unsigned)((all + 7) / 8 * 8));  // whole groups of eight for the XCD order
+    switch (NBv) {
+#define OIC_SV_CASE(NBV)                                                                                 \
+  case NBV:                                                                                              \
+    OIC_LAUNCH(t, KC_STATS, s, k_stats_v4<NBV>, grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, R, p, muR, chunk, \
+               xt, ytiles, all, part);                                                                   \
+    break;
+      OIC_SV_CASE(1) OIC_SV_CASE(2) OIC_SV_CASE(3) OIC_SV_CASE(4) OIC_SV_CASE(5)
+#undef OIC_SV_CASE
+    }
+    const long long count = (long long)Mtot * p;
+    OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 63) / 64)), dim3(64, RG), 0,
+               part, splits, count, scale, S);
+    return;
+  }
   // right rows per block: NB*16 with NB <= 8, balanced over grid.y tiles
   const int nbk = (p + 15) / 16;
   const int ytiles = (nbk + 7) / 8;
