@@ -111,6 +111,7 @@ struct oic_ctx {
   float* traj = nullptr;
   float* Y = nullptr;
   float* act[2] = {nullptr, nullptr};
+  size_t act_floats = 0;  // capacity of each activation buffer in floats
   float* mu_traj = nullptr;
   double* muY = nullptr;  // FP64 means of Ybar
   double* S = nullptr;     // Sigma^{XY} (Ma x p)
@@ -610,12 +611,19 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     // products in the FP32 mode; Sigma^{XY}, which enters the gain linearly, takes FP32
     // products folded into FP64 every 256 columns in every mode (twice the FP64 MFMA rate).
     const bool f32_stats = rollout_mode(h) != RM_FP32;  // FP32 statistics in the BF16 / FP8 modes
-    launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->part_cap, h->Syy, f32_stats);
+    // the FP32 products take Ybar centred once per step (FP64 subtraction, FP32 result) in
+    // the first activation buffer, which the rollout is done with until the next step
+    const float* Yc = nullptr;
+    if (NM % 4 == 0 && (size_t)p * NM <= h->act_floats) {
+      launch_center(s, h->timer, h->Y, p, (int)NM, m, h->muY, h->act[0]);
+      Yc = h->act[0];
+    }
+    launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->part_cap, h->Syy, f32_stats, Yc);
     hipEventRecord(h->ev_fork, s);
     hipStreamWaitEvent(h->side, h->ev_fork, 0);
     launch_chol(h->side, h->timer, p, h->Syy, h->Lwork, h->Sinv, h->flag);
     hipEventRecord(h->ev_join, h->side);
-    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S, true);
+    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S, true, Yc);
     hipStreamWaitEvent(s, h->ev_join, 0);
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
     launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
@@ -786,8 +794,9 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   int rc = OIC_OK;
   rc = rc ? rc : dalloc(h, &h->traj, Hs * rr * NM);
   rc = rc ? rc : dalloc(h, &h->Y, p * NM);
-  rc = rc ? rc : dalloc(h, &h->act[0], activation_floats(c));
-  rc = rc ? rc : dalloc(h, &h->act[1], activation_floats(c));
+  h->act_floats = activation_floats(c);
+  rc = rc ? rc : dalloc(h, &h->act[0], h->act_floats);
+  rc = rc ? rc : dalloc(h, &h->act[1], h->act_floats);
   rc = rc ? rc : dalloc(h, &h->mu_traj, Ma_max * m);
   rc = rc ? rc : dalloc(h, &h->muY, p * m);  // doubles
   rc = rc ? rc : dalloc(h, &h->S, (Ma_max + p) * p);

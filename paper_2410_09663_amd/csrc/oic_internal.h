@@ -194,14 +194,21 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
 // row b; left rows are the first Ma trajectory rows followed by the first ny rows of Ybar.
 // f32: the products on the FP32 matrix cores (right operand rounded to FP32 after
 // centring, FP32 sums over at most 256 columns, FP64 beyond), for the mixed-precision modes.
+// Yc: Ybar already centred (FP32, p x N*m, from launch_center) for the FP32-matrix-core
+// products, or null to centre inside the product kernel.
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
-                  const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32 = false);
+                  const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32 = false,
+                  const float* Yc = nullptr);
+// Rc[b][c] = R[b][c] - mu[b][c mod m] (FP64 subtraction, FP32 result) for rows x NM floats
+// (rows * NM divisible by 4).
+void launch_center(hipStream_t s, Timer& t, const float* R, int rows, int NM, int m, const double* mu,
+                   float* Rc);
 // The same sums against an arbitrary right operand, times scale: S[a][b] = scale *
 // sum_c L[a][c] (R[b][c] - muR[b][c mod m]) for the nr rows of R (row length N*m), S
 // with leading dimension nr.  part_cap must hold at least (Ma + ny) * nr doubles.
 void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const float* R, int nr, const double* muR, double* part, size_t part_cap,
-                  double* S, double scale, bool f32 = false);
+                  double* S, double scale, bool f32 = false, const float* Rc = nullptr);
 // FP64 Cholesky factor of the p x p Syy; flag is set to 1 when a pivot is not positive
 // and finite.  p <= 90 (one workgroup, LDS): Sinv = (Sigma^Y)^{-1}, Syy untouched.
 // p > 90 (blocked, chip-wide): Syy is overwritten by L in its lower triangle and

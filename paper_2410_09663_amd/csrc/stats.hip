@@ -390,15 +390,16 @@ __global__ __launch_bounds__(64 * WL) void k_stats_mfma32(Dims d, const float* _
 
 // The FP32-matrix-core products again, for row lengths N*m divisible by 4, with less LDS
 // traffic: a lane reads its A fragments straight from global memory into registers (each
-// left row belongs to one wave, so it gains nothing from LDS), four 16-column groups of a
-// 64-column stage as 16-byte loads, and only the centred right tile goes through LDS,
+// left row belongs to one wave, so it gains nothing from LDS), eight 16-column groups of a
+// 128-column stage as 16-byte loads, and only the centred right tile goes through LDS,
 // double-buffered so that one barrier per stage suffices.  K is permuted inside each
 // 16-column group: lane (i, g) supplies columns 4g..4g+3 of its row to four MFMAs, the
 // j-th taking column 4g+j in k-slot g, and reads the same four columns of the right rows
-// as one 16-byte LDS load.  Sums as in k_stats_mfma32: FP32 over four stages, then FP64.
-constexpr int SV_W = 8;       // waves per block, 16 left rows each
-constexpr int SV_CP = MK + 4;  // right-tile row stride in LDS (16-byte reads without bank conflicts)
-template <int NB>
+// as one 16-byte LDS load.  Sums as in k_stats_mfma32: FP32 over 256 columns, then FP64.
+constexpr int SV_W = 8;          // waves per block, 16 left rows each
+constexpr int SV_MK = 128;       // columns per stage: 8 groups of 16, about 2 us of MFMAs per wave
+constexpr int SV_CP = SV_MK + 4;  // right-tile row stride in LDS (16-byte reads without bank conflicts)
+template <int NB, bool CENTRED>  // CENTRED: R holds the centred rows already (muY unused)
 __global__ __launch_bounds__(64 * SV_W) void k_stats_v4(Dims d, const float* __restrict__ traj, int Ma, int ny,
                                                         const float* __restrict__ Y, const float* __restrict__ R,
                                                         int p, const double* __restrict__ muY, int chunk,
@@ -412,7 +413,8 @@ __global__ __launch_bounds__(64 * SV_W) void k_stats_v4(Dims d, const float* __r
   const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
   if (L >= tiles) return;
   const int ty = L % ytiles, tx = (L / ytiles) % xt, tz = L / (ytiles * xt);
-  constexpr int BQ = RB * MK / 4;            // float4 of the right tile
+  constexpr int GR = SV_MK / 16;             // 16-column groups per stage
+  constexpr int BQ = RB * SV_MK / 4;         // float4 of the right tile
   constexpr int BV = (BQ + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) float sB[2][RB * SV_CP];
   const int NM = (int)d.NM();
@@ -434,17 +436,17 @@ __global__ __launch_bounds__(64 * SV_W) void k_stats_v4(Dims d, const float* __r
     acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
     tot[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  f32x4v an[4], bn[BV];
+  f32x4v an[GR], bn[BV];
   auto load_stage = [&](int c0) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < GR; ++g) {
       const int c = c0 + 16 * g + 4 * lk;
       an[g] = (asrc && c < c_end) ? *(const f32x4v*)(asrc + c) : f32x4v{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int u = 0; u < BV; ++u) {
       const int e = tid + NT * u;
-      const int r = e / (MK / 4), q = e % (MK / 4);
+      const int r = e / (SV_MK / 4), q = e % (SV_MK / 4);
       const int b = b0 + r, c = c0 + 4 * q;
       bn[u] = (e < BQ && b < p && c < c_end) ? *(const f32x4v*)(R + (size_t)b * NM + c)
                                              : f32x4v{0.f, 0.f, 0.f, 0.f};
@@ -452,40 +454,42 @@ __global__ __launch_bounds__(64 * SV_W) void k_stats_v4(Dims d, const float* __r
   };
   if (c_begin < c_end) load_stage(c_begin);
   int stage = 0;
-  for (int c0 = c_begin; c0 < c_end; c0 += MK, ++stage) {
+  for (int c0 = c_begin; c0 < c_end; c0 += SV_MK, ++stage) {
     float* const sb = sB[stage & 1];
-    f32x4v ac[4];
+    f32x4v ac[GR];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) ac[g] = an[g];
+    for (int g = 0; g < GR; ++g) ac[g] = an[g];
     // right tile centred in FP64, rounded to FP32 (zero past the chunk and past p)
 #pragma unroll
     for (int u = 0; u < BV; ++u) {
       const int e = tid + NT * u;
       if (e >= BQ) continue;
-      const int r = e / (MK / 4), q = e % (MK / 4);
-      const int b = b0 + r, c = c0 + 4 * q;
-      int x = c % m;
-      const double* mu = muY + (size_t)(b < p ? b : 0) * m;
-      f32x4v v;
+      const int r = e / (SV_MK / 4), q = e % (SV_MK / 4);
+      f32x4v v = bn[u];  // zero past the chunk and past p already
+      if constexpr (!CENTRED) {
+        const int b = b0 + r, c = c0 + 4 * q;
+        int x = c % m;
+        const double* mu = muY + (size_t)(b < p ? b : 0) * m;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bool live = b < p && c + j < c_end;
-        v[j] = live ? (float)((double)bn[u][j] - mu[x]) : 0.f;
-        x = (x + 1 == m) ? 0 : x + 1;
+        for (int j = 0; j < 4; ++j) {
+          const bool live = b < p && c + j < c_end;
+          v[j] = live ? (float)((double)bn[u][j] - mu[x]) : 0.f;
+          x = (x + 1 == m) ? 0 : x + 1;
+        }
       }
       *(f32x4v*)(sb + r * SV_CP + 4 * q) = v;
     }
     __syncthreads();  // this stage's right tile is in LDS; the other buffer is free again
-    if (c0 + MK < c_end) load_stage(c0 + MK);  // the next stage's operands, in flight meanwhile
+    if (c0 + SV_MK < c_end) load_stage(c0 + SV_MK);  // the next stage's operands, in flight meanwhile
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < GR; ++g)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const f32x4v b = *(const f32x4v*)(sb + (16 * nb + li) * SV_CP + 16 * g + 4 * lk);
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[g][j], b[j], acc[nb], 0, 0, 0);
       }
-    if ((stage & 3) == 3) {  // fold the FP32 sums of the last four stages into FP64
+    if ((stage & 1) == 1) {  // fold the FP32 sums of the last 256 columns into FP64
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
 #pragma unroll
@@ -503,6 +507,29 @@ __global__ __launch_bounds__(64 * SV_W) void k_stats_v4(Dims d, const float* __r
       const int b = b0 + nb * 16 + li;
       if (a < Mtot && b < p) out[(size_t)a * p + b] = tot[nb][r] + (double)acc[nb][r];
     }
+}
+
+// Rc[b][c] = R[b][c] - mu[b][c mod m], the subtraction in FP64, rounded to FP32: the
+// centred right operand of the FP32 statistics, formed once per horizon step instead of
+// in every workgroup's staging (there its FP64 mean loads sat between each stage's loads
+// and its barrier).
+__global__ __launch_bounds__(256) void k_center_rows(const float* __restrict__ R, int rows, int NM, int m,
+                                                     const double* __restrict__ mu, float* __restrict__ Rc) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;  // float4 index
+  const long long total = (long long)rows * NM / 4;
+  if (q >= total) return;
+  const long long e = 4 * q;
+  const int b = (int)(e / NM), c = (int)(e - (long long)b * NM);
+  const f32x4v v = *(const f32x4v*)(R + e);
+  const double* mb = mu + (size_t)b * m;
+  int x = c % m;
+  f32x4v o;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    o[j] = (float)((double)v[j] - mb[x]);
+    x = (x + 1 == m) ? 0 : x + 1;
+  }
+  *(f32x4v*)(Rc + e) = o;
 }
 
 // S[idx] = scale * sum_z part[z][idx].  Block (64, RG): lane x owns output idx, and the
@@ -572,9 +599,16 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
              rows, N, m, mean);
 }
 
+void launch_center(hipStream_t s, Timer& t, const float* R, int rows, int NM, int m, const double* mu,
+                   float* Rc) {
+  const long long total = (long long)rows * NM / 4;
+  OIC_LAUNCH(t, KC_MEANS, s, k_center_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, R, rows, NM, m,
+             mu, Rc);
+}
+
 void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const float* R, int p, const double* muR, double* part, size_t part_cap,
-                  double* S, double scale, bool f32) {
+                  double* S, double scale, bool f32, const float* Rc) {
   const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
   if (f32 && NM % 4 == 0) {
@@ -587,21 +621,25 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
     // about two eight-wave workgroups per CU in flight; chunks are whole 64-column stages
     // and the partials must fit the split buffer
     int splits = (512 + tiles - 1) / tiles;
-    const int max_by_len = (NM + MK - 1) / MK;
+    const int max_by_len = (NM + SV_MK - 1) / SV_MK;
     if (splits > max_by_len) splits = max_by_len;
     const size_t by_cap = part_cap / ((size_t)Mtot * p);
     if ((size_t)splits > by_cap) splits = (int)by_cap;
     if (splits < 1) splits = 1;
     int chunk = (NM + splits - 1) / splits;
-    chunk = (chunk + MK - 1) / MK * MK;
+    chunk = (chunk + SV_MK - 1) / SV_MK * SV_MK;
     splits = (NM + chunk - 1) / chunk;
     const int all = tiles * splits;
     const dim3 grid((unsigned)((all + 7) / 8 * 8));  // whole groups of eight for the XCD order
     switch (NBv) {
 #define OIC_SV_CASE(NBV)                                                                                 \
   case NBV:                                                                                              \
-    OIC_LAUNCH(t, KC_STATS, s, k_stats_v4<NBV>, grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, R, p, muR, chunk, \
-               xt, ytiles, all, part);                                                                   \
+    if (Rc)                                                                                              \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_v4<NBV, true>), grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, Rc, p, \
+                 muR, chunk, xt, ytiles, all, part);                                                     \
+    else                                                                                                 \
+      OIC_LAUNCH(t, KC_STATS, s, (k_stats_v4<NBV, false>), grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, R, p, \
+                 muR, chunk, xt, ytiles, all, part);                                                     \
     break;
       OIC_SV_CASE(1) OIC_SV_CASE(2) OIC_SV_CASE(3) OIC_SV_CASE(4) OIC_SV_CASE(5)
 #undef OIC_SV_CASE
@@ -674,8 +712,9 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 }
 
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
-                  const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32) {
-  launch_cross(s, t, d, traj, Ma, ny, Y, Y, d.p(), muY, part, part_cap, S, 1.0, f32);
+                  const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32,
+                  const float* Yc) {
+  launch_cross(s, t, d, traj, Ma, ny, Y, Y, d.p(), muY, part, part_cap, S, 1.0, f32, Yc);
 }
 
 }  // namespace oic

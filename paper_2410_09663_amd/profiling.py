@@ -31,6 +31,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 
 CLASS_OF = [  # kernel-name prefix -> class, first match wins
     ("k_conv_first", "conv_first"), ("k_conv_last", "conv_last"), ("k_conv_mfma", "conv_mid"),
+    ("k_conv_f32r", "conv_mid"),
     ("k_conv_direct", "conv_mid"), ("k_lift", "lift"), ("k_stats_reduce", "stats_reduce"),
     ("k_stats", "stats"), ("k_update", "update"), ("k_chol", "chol"), ("k_potrf", "chol"),
     ("k_gain", "gain"), ("k_normals", "noise"), ("k_means", "means"), ("k_init_slice0", "init"),
@@ -45,7 +46,7 @@ SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last"
 
 
 def kernel_class(name: str) -> str:
-    base = name.split("(")[0].strip()
+    base = name.replace("(anonymous namespace)::", "").split("(")[0].strip()
     base = re.sub(r"^(void\s+)?(\w+::)*", "", base)
     for prefix, cls in CLASS_OF:
         if base.startswith(prefix):
@@ -55,7 +56,7 @@ def kernel_class(name: str) -> str:
 
 def short_name(name: str) -> str:
     """Kernel name without namespaces, parameter list and 'void'."""
-    s = re.sub(r"\(.*$", "", name.strip())
+    s = re.sub(r"\(.*$", "", name.replace("(anonymous namespace)::", "").strip())
     s = re.sub(r"^void\s+", "", s)
     s = re.sub(r"\boic::(\(anonymous namespace\)::)?", "", s)
     return s.strip()
