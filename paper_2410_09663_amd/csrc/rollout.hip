@@ -527,14 +527,20 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
   constexpr int CP = CIN + 4;
   constexpr int CG = CIN / 16;  // 16-channel groups per tap
   constexpr int S = 9 * CG;     // K steps of 16 indices
-  constexpr int Q = CIN / 4;
-  constexpr int TOTAL = HR * HC * Q;    // float4 of one halo tile
-  constexpr int SLOTS = (TOTAL + 255) / 256;
-  constexpr int PASS = 4;               // float4 loads in flight per thread while staging
+  // The halo arrives by LDS-direct buffer loads: 16-byte slot s of the tile (pixel s / SLOT,
+  // channels 4 (s mod SLOT) ..; the last slot of a pixel is its padding) is loaded by lane
+  // s mod 64 of wave-instruction s / 64, which writes 64 consecutive slots.  Slots outside
+  // the field (and the padding) take an offset past the end of the buffer, which the
+  // hardware returns as zeros.  No registers hold the halo and a tile costs one memory
+  // round trip.
+  constexpr int SLOT = CIN / 4 + 1;
+  constexpr int TOTAL_SLOTS = HR * HC * SLOT;
+  constexpr int INSTR = (TOTAL_SLOTS + 63) / 64;
   static_assert(CIN % 16 == 0, "16-channel K steps");
+  static_assert(CP == 4 * SLOT, "pixel stride = whole slots");
   constexpr int HP = COUT + 4;  // pixel stride of the activated tile (LASTQ)
   static_assert(!LASTQ || TR * TC * HP <= HR * HC * CP, "the activated tile reuses the halo's LDS");
-  __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
+  __shared__ __attribute__((aligned(16))) float s_in[INSTR * 64 * 4];
   __shared__ float s_wl[LASTQ ? COUT * 16 : 1];  // last layer [c][tap], taps 9..15 zero
   const int col_tiles = (m + TC - 1) / TC;
   const int row_tiles = (n + TR - 1) / TR;
@@ -564,27 +570,30 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
     const int rt = rest % row_tiles, i = rest / row_tiles;
     const int y0 = rt * TR, x0 = ct * TC;
     __syncthreads();  // every wave is done with the previous tile
-    // stage the (TR+2) x 66 x CIN halo, zero outside the field, PASS loads at a time
+    {
+      // member i's image as the buffer (its byte size fits the 32-bit record count: the
+      // launcher checks), the halo's zero padding from out-of-range offsets
+      const unsigned nrec = (unsigned)n * m * CIN * 4;
+      const __amdgpu_buffer_rsrc_t rsrc =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)i * n * m * CIN), (short)0, (int)nrec, 0x00020000);
 #pragma unroll
-    for (int u0 = 0; u0 < SLOTS; u0 += PASS) {
-      f32x4 v[PASS];
-#pragma unroll
-      for (int u = 0; u < PASS; ++u) {
-        const int e = tid + (u0 + u) * 256;
-        v[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (u0 + u < SLOTS && e < TOTAL) {
-          const int q = e % Q, pix = e / Q;
-          const int xx = pix % HC, yy = pix / HC;
+      for (int u = 0; u < (INSTR + 3) / 4; ++u) {
+        const int ins = w + 4 * u;  // wave-uniform
+        if (ins < INSTR) {
+          int slot = ins * 64 + lane;
+          // recompute the slot's coordinates for every tile: hoisted out of the tile loop
+          // they would not fit the registers beside the weights
+          asm volatile("" : "+v"(slot));
+          const int pix = slot / SLOT, q = slot - pix * SLOT;
+          const int yy = pix / HC, xx = pix - yy * HC;
           const int gy = y0 + yy - 1, gx = x0 + xx - 1;
-          if (gy >= 0 && gy < n && gx >= 0 && gx < m)
-            v[u] = *(const f32x4*)(in + (((size_t)i * n + gy) * m + gx) * CIN + 4 * q);
+          const bool live = slot < TOTAL_SLOTS && q < CIN / 4 && gy >= 0 && gy < n && gx >= 0 && gx < m;
+          const unsigned voff = live ? (unsigned)(((gy * m + gx) * CIN + 4 * q) * 4) : nrec;
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(s_in + ins * 256),
+                                                   16, (int)voff, 0, 0, 0);
         }
       }
-#pragma unroll
-      for (int u = 0; u < PASS; ++u) {
-        const int e = tid + (u0 + u) * 256;
-        if (u0 + u < SLOTS && e < TOTAL) *(f32x4*)(s_in + (e / Q) * CP + 4 * (e % Q)) = v[u];
-      }
+      __builtin_amdgcn_s_waitcnt(0);  // the LDS-direct loads have landed (vmcnt)
     }
     __syncthreads();
     f32x4 acc[TR][4];
@@ -1443,10 +1452,14 @@ bool conv_mfma_supported(int cin, int cout) {
   return (cin == 16 || cin == 32 || cin == 64) && (cout == 16 || cout == 32 || cout == 64);
 }
 
+// k_conv_f32r addresses one member's input image through a buffer resource: its byte
+// size must fit the 32-bit record count and offsets
+static bool f32r_fits(int n, int m, int cin) { return (long long)n * m * cin * 4 < (1LL << 31); }
+
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                       const float* in_nhwc, const float* wk, const float* bias, int act,
                       float* out_nhwc) {
-  if (cout == 64 && (cin == 32 || cin == 64)) {
+  if (cout == 64 && (cin == 32 || cin == 64) && f32r_fits(n, m, cin)) {
     // weights in registers, two persistent workgroups per CU
     constexpr int TRV = 2;
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);
@@ -1492,7 +1505,9 @@ void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, 
 #undef OIC_CONV_CASE
 }
 
-bool conv_last_folds(int cin, int cout) { return cout == 64 && (cin == 32 || cin == 64); }
+bool conv_last_folds(int n, int m, int cin, int cout) {
+  return cout == 64 && (cin == 32 || cin == 64) && f32r_fits(n, m, cin);
+}
 
 void launch_conv_mfma_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const float* in_nhwc,
                            const float* wk, const float* bias, int act, const float* w_last,
@@ -1538,7 +1553,7 @@ int rollout_fp32(hipStream_t s, Timer& t, const oic_config& c, const Fp32Net& ne
       if (obs) done |= ROLL_X_OBSERVED;
       continue;
     }
-    if (k == L - 2 && k > 0 && net.Wk[k] && conv_last_folds(cin, cout) && c.channels[L] == 1) {
+    if (k == L - 2 && k > 0 && net.Wk[k] && conv_last_folds(c.n, c.m, cin, cout) && c.channels[L] == 1) {
       // the last hidden layer with the last layer folded into its epilogue
       launch_conv_mfma_last(s, t, batch, c.n, c.m, cin, act[cur], net.Wk[k], net.bias[k], c.activation,
                             net.W[L - 1], net.bias[L - 1], act[1 - cur], out, obs);
