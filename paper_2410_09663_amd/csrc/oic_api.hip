@@ -101,6 +101,7 @@ struct oic_ctx {
   float* dW[OIC_MAX_LAYERS] = {};
   float* dWk[OIC_MAX_LAYERS] = {};     // [tap*cin + c][cout] FP32 copies for the MFMA layers
   uint16_t* dWb[OIC_MAX_LAYERS] = {};  // [cout][tap*cin + c] BF16 copies for the BF16 rollout
+  uint16_t* dWl2 = nullptr;            // last layer as a BF16 pair [hi, lo][16 taps][c] (folded BF16 rollout)
   uint8_t* dWq[OIC_MAX_LAYERS] = {};   // [cout][tap*cin + c, zero-padded to 128] e4m3 for FP8
   float* dWs[OIC_MAX_LAYERS] = {};     // per-output-channel scales of dWq
   unsigned* amax = nullptr;            // per-layer activation maxima of an FP8 rollout
@@ -349,6 +350,7 @@ void free_all(oic_ctx* h) {
     f(h->dBias[k]);
   }
   f(h->amax);
+  f(h->dWl2);
   f(h->traj);
   f(h->Y);
   f(h->act[0]);
@@ -442,14 +444,15 @@ RolloutMode rollout_mode(oic_ctx* h) {
 // single output channel to `out`, in the given mode (the plant step always uses FP32).
 // With `obs`, the first and last layers also write the side outputs it names where they
 // run as the tiled kernels; returns ROLL_X_OBSERVED | ROLL_U_ASSEMBLED for what was written.
-// The activations go to act0/act1 and the FP8 maxima to amax (the handle's buffers unless
-// given), with launches timed on tm (the handle's timer unless given).
+// The activations go to act0/act1 (each act_cap floats) and the FP8 maxima to amax (the
+// handle's buffers unless given), with launches timed on tm (the handle's timer unless given).
 int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, RolloutMode mode,
             const ObserveArgs* obs = nullptr, float* act0 = nullptr, float* act1 = nullptr,
-            unsigned* amax = nullptr, Timer* tm = nullptr) {
+            unsigned* amax = nullptr, Timer* tm = nullptr, size_t act_cap = 0) {
   const oic_config& c = h->cfg;
   const int L = c.n_layers;
   float* act[2] = {act0 ? act0 : h->act[0], act1 ? act1 : h->act[1]};
+  const size_t cap = act0 ? act_cap : h->act_floats;
   if (!amax) amax = h->amax;
   Timer& timer = tm ? *tm : h->timer;
   if (mode != RM_FP32) {
@@ -460,6 +463,13 @@ int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollout
                       h->dBias[0], c.activation, act[1], true, f8 ? amax : nullptr, obs);
     int cur = 1;
     for (int k = 1; k < L - 1; ++k) {
+      if (!f8 && k == L - 2 && h->dWl2 && conv_last_folds_bf16(c.channels[k], c.channels[k + 1]) &&
+          (size_t)9 * batch * c.n * c.m <= cap) {
+        // the last hidden layer with the last layer folded into its epilogue
+        launch_conv_mfma_bf16_last(h->stream, timer, batch, c.n, c.m, c.channels[k], act[cur], h->dWb[k],
+                                   h->dBias[k], c.activation, h->dWl2, h->dBias[L - 1], act[1 - cur], out, obs);
+        return obs ? ROLL_X_OBSERVED | (obs->U_cur ? ROLL_U_ASSEMBLED : 0) : 0;
+      }
       if (f8)
         launch_conv_mfma_fp8(h->stream, timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
                              c.channels[k + 1], act[cur], amax + (k - 1), h->dWq[k], h->dWs[k],
@@ -925,6 +935,23 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
       if (!h->dWb[k] && (rc = dalloc(h, &h->dWb[k], cnt))) return rc;
       HIP_TRY(hipMemcpy(h->dWb[k], wb.data(), cnt * sizeof(uint16_t), hipMemcpyHostToDevice));
     }
+    if (c.precision == OIC_PREC_BF16 && k == c.n_layers - 1 && k >= 2 && cout == 1 &&
+        conv_last_folds_bf16(c.channels[k - 1], cin)) {
+      // the last layer as a BF16 pair for the folded epilogue: [hi, lo][tap (16, zero past 9)][c]
+      std::vector<uint16_t> w2((size_t)2 * 16 * cin, 0);
+      for (int ci = 0; ci < cin; ++ci)
+        for (int tap = 0; tap < 9; ++tap) {
+          const float v = W[k][(size_t)ci * 9 + tap];
+          const uint16_t hi = host_bf16(v);
+          uint32_t hb = (uint32_t)hi << 16;
+          float hf;
+          memcpy(&hf, &hb, sizeof(hf));
+          w2[(size_t)tap * cin + ci] = hi;
+          w2[(size_t)(16 + tap) * cin + ci] = host_bf16(v - hf);
+        }
+      if (!h->dWl2 && (rc = dalloc(h, &h->dWl2, w2.size()))) return rc;
+      HIP_TRY(hipMemcpy(h->dWl2, w2.data(), w2.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
     if (bias && bias[k]) {
       if (!h->dBias[k] && (rc = dalloc(h, &h->dBias[k], (size_t)c.channels[k + 1]))) return rc;
       HIP_TRY(hipMemcpyAsync(h->dBias[k], bias[k], c.channels[k + 1] * sizeof(float),
@@ -1093,7 +1120,7 @@ int oic_cnn_forward_noalloc(oic_handle h, int batch, const float* X, const float
   rollout(h, batch, FieldRef{X, (long long)(n * m), (long long)m}, FieldRef{U, (long long)(l * m), (long long)m},
           FieldOut{X_next, (long long)(n * m), (long long)m}, mode, nullptr,
           reinterpret_cast<float*>(base + 256), reinterpret_cast<float*>(base + 256 + act_bytes),
-          reinterpret_cast<unsigned*>(base), &untimed);
+          reinterpret_cast<unsigned*>(base), &untimed, act_bytes / sizeof(float));
   HIP_TRY(hipGetLastError());
   // on a private stream the caller cannot order against the work: finish it here
   if (h->own_stream) HIP_TRY(hipStreamSynchronize(h->stream));

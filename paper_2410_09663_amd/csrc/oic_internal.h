@@ -148,6 +148,14 @@ bool conv_mfma_bf16_supported(int cin, int cout);
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                            const void* in_nhwc, const void* wt, const float* bias, int act,
                            void* out_nhwc);
+// The last BF16 hidden layer (cin 32 or 64 -> 64) with the last layer (64 -> 1) folded into
+// its epilogue: wl2 holds the last layer's weights as a BF16 pair [hi, lo][tap padded to 16]
+// [c]; qbuf receives nine FP32 tap planes (9 N n m floats), then the tap sum writes fo and,
+// with obs, the X rows of Ybar.
+bool conv_last_folds_bf16(int cin, int cout);
+void launch_conv_mfma_bf16_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
+                                const void* wt, const float* bias, int act, const uint16_t* wl2,
+                                const float* bias_last, float* qbuf, FieldOut fo, const ObserveArgs* obs);
 // FP8 hidden layer: BF16 NHWC in and out, input scale from *amax_in (largest |x| of the
 // input layer), weights wq [cout][K padded to 128] e4m3 with per-channel scales ws;
 // folds the largest |output| into *amax_out.

@@ -988,12 +988,20 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 // Row strides in LDS are padded by 8 elements so the 16 lanes of a fragment hit
 // distinct banks.  Lane layout (16x16x32): A[i][k] for k = 8g..8g+7 from lane i + 16g,
 // B[k][j] for k = 8g..8g+7 from lane j + 16g, element r of lane j + 16g holds D[4g + r][j].
-template <int CIN, int COUT, int TR, int WG>
+//
+// LASTQ (64 output channels): the network's last layer (64 -> 1) is folded into the
+// epilogue as in k_conv_f32r: from the activated BF16 tile in LDS, the nine per-tap partial
+// sums P_tap(p) = sum_c wl[c][tap] h(p)[c] are formed on the BF16 matrix cores with the
+// last layer's weights as a BF16 pair wl = hi + lo (wl2[0] and wl2[1], [tap padded to
+// 16][c], exact to about 16 bits) and leave as nine FP32 planes (out, plane stride N n m)
+// for k_conv_last_sum.
+template <int CIN, int COUT, int TR, int WG, bool LASTQ = false>
 __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m,
                                                         const bf16_t* __restrict__ in,
                                                         const bf16_t* __restrict__ wt,
                                                         const float* __restrict__ bias, int act,
-                                                        bf16_t* __restrict__ out) {
+                                                        bf16_t* __restrict__ out,
+                                                        const bf16_t* __restrict__ wl2) {
   constexpr int TC = 64;
   constexpr int HR = TR + 2, HC = TC + 2;
   constexpr int CP = CIN + 8;
@@ -1123,12 +1131,46 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
         }
     }
     __syncthreads();
-    constexpr int QV = COUT / 8;  // 16-byte vectors per pixel
-    for (int e = tid; e < TR * TC * QV; e += NT) {
-      const int px = e / QV, q = e - px * QV;
-      const int y = y0 + px / TC, x = x0 + px % TC;
-      if (y < n && x < m)
-        *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+    if constexpr (!LASTQ) {
+      constexpr int QV = COUT / 8;  // 16-byte vectors per pixel
+      for (int e = tid; e < TR * TC * QV; e += NT) {
+        const int px = e / QV, q = e - px * QV;
+        const int y = y0 + px / TC, x = x0 + px % TC;
+        if (y < n && x < m)
+          *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+      }
+    } else {
+      static_assert(COUT % 32 == 0, "whole 32-channel K steps");
+      constexpr int NWV = NT / 64;               // waves
+      constexpr int MBT = TR * TC / 16;          // M-blocks of the tile
+      static_assert(MBT % NWV == 0, "whole M-blocks per wave");
+      const int wave = tid >> 6;
+      const long long plane = (long long)N * n * m;
+      float* const qout = reinterpret_cast<float*>(out);
+#pragma unroll
+      for (int u = 0; u < MBT / NWV; ++u) {
+        const int pb = (wave * (MBT / NWV) + u) * 16;
+        f32x4 qa = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < COUT / 32; ++ks) {
+          const bf16x8_t a =
+              __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_out + (pb + li) * OP + 32 * ks + 8 * lk));
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2) {
+            const bf16x8_t b = __builtin_bit_cast(
+                bf16x8_t, *(const u16x8*)(wl2 + ((size_t)h2 * 16 + li) * COUT + 32 * ks + 8 * lk));
+            qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, qa, 0, 0, 0);
+          }
+        }
+        if (li < 9) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int px = pb + 4 * lk + r;
+            const int y = y0 + px / TC, x = x0 + px % TC;
+            if (y < n && x < m) qout[li * plane + ((long long)i * n + y) * m + x] = qa[r];
+          }
+        }
+      }
     }
   }
 }
@@ -1398,7 +1440,7 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
     const long long cap = 256LL * resident_per_cu<kern>(256 * WG); /* persistent */             \
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                               \
     OIC_LAUNCH(t, kclass, s, kern, dim3(blocks), dim3(256 * WG), 0, N, n, m,                     \
-               (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out_nhwc);         \
+               (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out_nhwc, nullptr); \
     return;                                                                                      \
   }
   OIC_BF_CASE(16, 16)
@@ -1409,6 +1451,29 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
   OIC_BF_CASE(32, 64)
   OIC_BF_CASE(64, 32)
 #undef OIC_BF_CASE
+}
+
+bool conv_last_folds_bf16(int cin, int cout) { return cout == 64 && (cin == 32 || cin == 64); }
+
+void launch_conv_mfma_bf16_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
+                                const void* wt, const float* bias, int act, const uint16_t* wl2,
+                                const float* bias_last, float* qbuf, FieldOut fo, const ObserveArgs* obs) {
+#define OIC_BFL_CASE(CI)                                                                         \
+  if (cin == CI) {                                                                               \
+    constexpr int TRV = CI <= 32 ? 8 : 4;                                                        \
+    constexpr auto kern = k_conv_mfma_bf16<CI, 64, TRV, kBf16GroupsWide, true>;                  \
+    const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
+    const long long cap = 256LL * resident_per_cu<kern>(256 * kBf16GroupsWide);                  \
+    const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                               \
+    OIC_LAUNCH(t, KC_CONV_MID, s, kern, dim3(blocks), dim3(256 * kBf16GroupsWide), 0, N, n, m,    \
+               (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)qbuf, (const bf16_t*)wl2); \
+  }
+  OIC_BFL_CASE(32)
+  OIC_BFL_CASE(64)
+#undef OIC_BFL_CASE
+  const ObserveArgs oa = obs ? *obs : ObserveArgs{};
+  OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+             0, N, n, m, qbuf, bias_last, fo, oa);
 }
 
 bool conv_mfma_fp8_supported(int cin, int cout) {

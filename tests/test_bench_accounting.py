@@ -32,11 +32,12 @@ def test_folded_last_layer_keeps_the_network_flops():
     hidden layers) the conv FLOPs per step are the network's, and the last layer's class
     moves the nine FP32 tap planes and the state instead of the activations."""
     p = wl.PRESETS["C4"]
-    assert bench.last_layer_folded(p, "fp32") and not bench.last_layer_folded(p, "bf16")
+    assert bench.last_layer_folded(p, "fp32") and bench.last_layer_folded(p, "bf16")
+    assert not bench.last_layer_folded(p, "fp8")
     px = p.n * p.m * p.N
     ch = p.channels
     net = sum(2.0 * 9 * a * b * px for a, b in zip(ch[:-1], ch[1:]))
-    for prec in ("fp32", "bf16"):
+    for prec in ("fp32", "bf16", "fp8"):
         work = bench.algorithmic_work(p, 1, prec)
         conv = sum(work[c][0] for c in ("conv_first", "conv_mid")) + (
             0.0 if bench.last_layer_folded(p, prec) else work["conv_last"][0])

@@ -20,9 +20,14 @@ pytestmark = pytest.mark.gpu
 TOL_BF16 = 2e-2
 
 
-@pytest.mark.parametrize("preset", ["C2", "C3"])
+FOLD64 = wl.small_preset(n=20, m=72, l=5, channels=(2, 64, 64, 64, 1), activation=wl.ACT_GELU, N=8, H=3)
+FOLD32 = wl.small_preset(n=13, m=66, l=4, channels=(2, 32, 64, 1), N=8, H=3)
+
+
+@pytest.mark.parametrize("preset", ["C2", "C3", "fold64", "fold32"])
 def test_bf16_rollout_vs_oracle(preset):
-    p = wl.PRESETS[preset]
+    # fold64 / fold32: the last layer folded into the last BF16 hidden layer (64 outputs)
+    p = {"fold64": FOLD64, "fold32": FOLD32}.get(preset) or wl.PRESETS[preset]
     prob = wl.make_problem(p)
     rng = np.random.default_rng(0)
     b = 8
@@ -38,9 +43,9 @@ def test_bf16_rollout_vs_oracle(preset):
     assert_parity(plant, ref[0], 1e-5, "plant")  # the plant stays FP32
 
 
-@pytest.mark.parametrize("preset,N,H", [("C2", 128, 10), ("C3", 32, 3)])
+@pytest.mark.parametrize("preset,N,H", [("C2", 128, 10), ("C3", 32, 3), ("fold64", 12, 3)])
 def test_bf16_solve_vs_oracle(preset, N, H):
-    p = dataclasses.replace(wl.PRESETS[preset], N=N, H=H)
+    p = dataclasses.replace(FOLD64 if preset == "fold64" else wl.PRESETS[preset], N=N, H=H)
     prob = wl.make_problem(p)
     Xref = wl.reference_window(p, 0)
     z = wl.host_noise(p.n, p.m, p.l, N, H, seed=21)

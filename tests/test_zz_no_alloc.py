@@ -25,6 +25,8 @@ CASES = {
     "fp32_64x64": (wl.PRESETS["C2"], oic.OIC_PREC_FP32, 16, 5),
     "bf16_gelu_32ch": (wl.small_preset(n=40, m=72, l=10, channels=(2, 32, 32, 32, 1),
                                        activation=wl.ACT_GELU, N=8), oic.OIC_PREC_BF16, 8, 3),
+    "bf16_fold_64ch": (wl.small_preset(n=20, m=72, l=5, channels=(2, 64, 64, 1), activation=wl.ACT_GELU, N=6),
+                       oic.OIC_PREC_BF16, 6, 2),
     "fp8_64ch": (wl.small_preset(n=24, m=70, l=6, channels=(2, 64, 64, 64, 1), activation=wl.ACT_GELU, N=6),
                  oic.OIC_PREC_FP8, 6, 2),
     "fp32_256x256_plant": (wl.PRESETS["C4"], oic.OIC_PREC_FP32, 1, 1),
