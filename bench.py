@@ -86,10 +86,10 @@ def algorithmic_work(p, H, precision="fp32"):
 
 def last_layer_folded(p, precision):
     """Whether the library folds the last layer (C -> 1) into the last hidden layer's
-    epilogue: the FP32 and BF16 rollouts with a last hidden layer of 32 or 64 inputs and 64
-    outputs (the library's conv_last_folds / conv_last_folds_bf16; not the FP8 rollout)."""
+    epilogue: every rollout precision, with a last hidden layer of 32 or 64 inputs and 64
+    outputs (the library's conv_last_folds / conv_last_folds_bf16)."""
     ch = p.channels
-    return precision in ("fp32", "bf16") and len(ch) >= 4 and ch[-2] == 64 and ch[-3] in (32, 64)
+    return precision in ("fp32", "bf16", "fp8") and len(ch) >= 4 and ch[-2] == 64 and ch[-3] in (32, 64)
 
 
 MATRIX_CLASSES = ("conv_first", "conv_mid", "stats", "gain", "update")

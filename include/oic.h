@@ -176,7 +176,7 @@ int oic_cnn_forward(oic_handle h, int batch, const float* X, const float* U, flo
  *   batch, X, U, X_next: as for oic_cnn_forward (X_next may alias X).
  * The buffer must hold two activation arrays of batch x n x m x C elements, C the
  * widest hidden layer, 4 bytes each in the FP32 mode and 2 in the BF16 and FP8 modes,
- * plus 256 bytes; a larger request returns OIC_ENOMEM with the size in
+ * plus 2 KiB; a larger request returns OIC_ENOMEM with the size in
  * oic_last_error, before any work is queued.  OIC_EINVAL for a host-memory handle,
  * unset weights, a batch outside 1..max_N or a NULL pointer; OIC_EDEVICE if the buffer's
  * device address could not be obtained when the handle was created.

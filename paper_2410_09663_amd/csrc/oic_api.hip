@@ -458,22 +458,28 @@ int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollout
   if (mode != RM_FP32) {
     const bool f8 = mode == RM_FP8;
     // per-layer activation maxima: slot k holds the largest |x| written by layer k
-    if (f8) launch_zero_u32(h->stream, timer, amax, L);
+    if (f8) launch_zero_u32(h->stream, timer, amax, L * kAmaxSlots);
     launch_conv_first(h->stream, timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
                       h->dBias[0], c.activation, act[1], true, f8 ? amax : nullptr, obs);
     int cur = 1;
     for (int k = 1; k < L - 1; ++k) {
-      if (!f8 && k == L - 2 && h->dWl2 && conv_last_folds_bf16(c.channels[k], c.channels[k + 1]) &&
+      if (k == L - 2 && h->dWl2 && conv_last_folds_bf16(c.channels[k], c.channels[k + 1]) &&
           (size_t)9 * batch * c.n * c.m <= cap) {
         // the last hidden layer with the last layer folded into its epilogue
-        launch_conv_mfma_bf16_last(h->stream, timer, batch, c.n, c.m, c.channels[k], act[cur], h->dWb[k],
-                                   h->dBias[k], c.activation, h->dWl2, h->dBias[L - 1], act[1 - cur], out, obs);
+        if (f8)
+          launch_conv_mfma_fp8_last(h->stream, timer, batch, c.n, c.m, c.channels[k], act[cur],
+                                    amax + (size_t)(k - 1) * kAmaxSlots,
+                                    h->dWq[k], h->dWs[k], h->dBias[k], c.activation, h->dWl2, h->dBias[L - 1],
+                                    act[1 - cur], out, obs);
+        else
+          launch_conv_mfma_bf16_last(h->stream, timer, batch, c.n, c.m, c.channels[k], act[cur], h->dWb[k],
+                                     h->dBias[k], c.activation, h->dWl2, h->dBias[L - 1], act[1 - cur], out, obs);
         return obs ? ROLL_X_OBSERVED | (obs->U_cur ? ROLL_U_ASSEMBLED : 0) : 0;
       }
       if (f8)
         launch_conv_mfma_fp8(h->stream, timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
-                             c.channels[k + 1], act[cur], amax + (k - 1), h->dWq[k], h->dWs[k],
-                             h->dBias[k], c.activation, act[1 - cur], amax + k);
+                             c.channels[k + 1], act[cur], amax + (size_t)(k - 1) * kAmaxSlots, h->dWq[k],
+                             h->dWs[k], h->dBias[k], c.activation, act[1 - cur], amax + (size_t)k * kAmaxSlots);
       else
         launch_conv_mfma_bf16(h->stream, timer, KC_CONV_MID, batch, c.n, c.m, c.channels[k],
                               c.channels[k + 1], act[cur], h->dWb[k], h->dBias[k], c.activation,
@@ -821,7 +827,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
     rc = OIC_EDEVICE;
   rc = rc ? rc : dalloc(h, &h->K, Ma_max * p);
   rc = rc ? rc : dalloc(h, &h->flag, 1);
-  rc = rc ? rc : dalloc(h, &h->amax, OIC_MAX_LAYERS);
+  rc = rc ? rc : dalloc(h, &h->amax, (size_t)OIC_MAX_LAYERS * kAmaxSlots);
   for (int k = 0; k < 5 && !rc; ++k) rc = dalloc(h, &h->Z[k], noise_floats(c, k));
   rc = rc ? rc : dalloc(h, &h->con_a, n + l);
   rc = rc ? rc : dalloc(h, &h->Uprev, l * m);
@@ -935,7 +941,7 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
       if (!h->dWb[k] && (rc = dalloc(h, &h->dWb[k], cnt))) return rc;
       HIP_TRY(hipMemcpy(h->dWb[k], wb.data(), cnt * sizeof(uint16_t), hipMemcpyHostToDevice));
     }
-    if (c.precision == OIC_PREC_BF16 && k == c.n_layers - 1 && k >= 2 && cout == 1 &&
+    if ((c.precision == OIC_PREC_BF16 || c.precision == OIC_PREC_FP8) && k == c.n_layers - 1 && k >= 2 && cout == 1 &&
         conv_last_folds_bf16(c.channels[k - 1], cin)) {
       // the last layer as a BF16 pair for the folded epilogue: [hi, lo][tap (16, zero past 9)][c]
       std::vector<uint16_t> w2((size_t)2 * 16 * cin, 0);
@@ -1109,9 +1115,10 @@ int oic_cnn_forward_noalloc(oic_handle h, int batch, const float* X, const float
     return fail(h, OIC_EDEVICE, "the device address of the allocation-free buffer could not be obtained");
   const RolloutMode mode = rollout_mode(h);
   const size_t n = c.n, m = c.m, l = c.l;
-  // layout: [per-layer FP8 maxima, 256 B][activations A][activations B], 256-byte aligned
+  // layout: [per-layer FP8 maxima][activations A][activations B], 256-byte aligned
+  constexpr size_t head = ((size_t)OIC_MAX_LAYERS * kAmaxSlots * sizeof(unsigned) + 255) / 256 * 256;
   const size_t act_bytes = ((size_t)batch * n * m * h->cmax * (mode == RM_FP32 ? 4 : 2) + 255) / 256 * 256;
-  const size_t need = 256 + 2 * act_bytes;
+  const size_t need = head + 2 * act_bytes;
   if (need > OIC_NOALLOC_SCRATCH_BYTES)
     return fail(h, OIC_ENOMEM, "batch needs " + std::to_string(need) + " bytes of scratch; the fixed buffer holds " +
                                    std::to_string((size_t)OIC_NOALLOC_SCRATCH_BYTES));
@@ -1119,7 +1126,7 @@ int oic_cnn_forward_noalloc(oic_handle h, int batch, const float* X, const float
   Timer untimed;  // a timed launch would create events on first use
   rollout(h, batch, FieldRef{X, (long long)(n * m), (long long)m}, FieldRef{U, (long long)(l * m), (long long)m},
           FieldOut{X_next, (long long)(n * m), (long long)m}, mode, nullptr,
-          reinterpret_cast<float*>(base + 256), reinterpret_cast<float*>(base + 256 + act_bytes),
+          reinterpret_cast<float*>(base + head), reinterpret_cast<float*>(base + head + act_bytes),
           reinterpret_cast<unsigned*>(base), &untimed, act_bytes / sizeof(float));
   HIP_TRY(hipGetLastError());
   // on a private stream the caller cannot order against the work: finish it here

@@ -22,6 +22,11 @@
 
 namespace oic {
 
+// An FP8 rollout keeps each layer's largest |activation| as kAmaxSlots partial maxima
+// (publishers spread their atomic maxima over the slots; readers take the maximum of all),
+// so that a layer's hundreds of thousands of waves do not queue on one address.
+constexpr int kAmaxSlots = 64;
+
 enum KernelClass {
   KC_NOISE = 0,
   KC_INIT,
@@ -156,6 +161,11 @@ bool conv_last_folds_bf16(int cin, int cout);
 void launch_conv_mfma_bf16_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
                                 const void* wt, const float* bias, int act, const uint16_t* wl2,
                                 const float* bias_last, float* qbuf, FieldOut fo, const ObserveArgs* obs);
+// The last FP8 hidden layer (cin 32 or 64 -> 64) with the last layer folded, as above.
+void launch_conv_mfma_fp8_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
+                               const unsigned* amax_in, const uint8_t* wq, const float* ws, const float* bias,
+                               int act, const uint16_t* wl2, const float* bias_last, float* qbuf, FieldOut fo,
+                               const ObserveArgs* obs);
 // FP8 hidden layer: BF16 NHWC in and out, input scale from *amax_in (largest |x| of the
 // input layer), weights wq [cout][K padded to 128] e4m3 with per-channel scales ws;
 // folds the largest |output| into *amax_out.

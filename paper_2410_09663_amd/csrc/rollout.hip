@@ -57,10 +57,21 @@ __device__ __forceinline__ void store_act(bf16_t* p, float v) { *p = to_bf16(v);
 // Largest |value| written by a wave, folded into *amax (the bit pattern of a
 // non-negative float orders like the float, so an integer max is exact and the
 // result does not depend on the order of the atomics).
+// The wave's maximum goes to one of the layer's kAmaxSlots slots, chosen by workgroup and
+// wave so that the atomics of a launch spread over all of them.
 __device__ __forceinline__ void amax_publish(float v, unsigned* amax) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(v));
+  const unsigned slot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kAmaxSlots;
+  if ((threadIdx.x & 63) == 0) atomicMax(amax + slot, __float_as_uint(v));
+}
+
+// The layer's largest |activation|: the maximum over its slots.
+__device__ __forceinline__ float amax_read(const unsigned* __restrict__ amax) {
+  unsigned mx = 0u;
+#pragma unroll 8
+  for (int s = 0; s < kAmaxSlots; ++s) mx = max(mx, amax[s]);
+  return __uint_as_float(mx);
 }
 
 __global__ void k_zero_u32(unsigned* __restrict__ p, int count) {
@@ -980,6 +991,48 @@ __global__ __launch_bounds__(256) void k_conv_last(int N, int n, int m, const TI
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
+// Folded last layer (64 -> 1) from an activated BF16 tile in LDS, s_out[pixel][channel]
+// with pixel stride OP (pixel = tile row * TC + column): the nine per-tap partial sums
+// P_tap(p) = sum_c wl[c][tap] h(p)[c] on the BF16 matrix cores, K = the COUT channels in
+// steps of 32, N = the taps (padded to 16), the weights as a BF16 pair wl2 = [hi, lo]
+// [16 taps][COUT]; the sums leave as nine FP32 planes qout[tap][i][y][x] (plane stride
+// N n m).  The NT threads' waves take whole 16-pixel M-blocks of the tile.
+template <int COUT, int TR, int TC, int OP, int NT>
+__device__ __forceinline__ void fold_last_epilogue(const bf16_t* s_out, const bf16_t* __restrict__ wl2,
+                                                   float* __restrict__ qout, int N, int n, int m, int i, int y0,
+                                                   int x0, int tid) {
+  static_assert(COUT % 32 == 0, "whole 32-channel K steps");
+  constexpr int NWV = NT / 64;       // waves
+  constexpr int MBT = TR * TC / 16;  // M-blocks of the tile
+  static_assert(MBT % NWV == 0, "whole M-blocks per wave");
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const long long plane = (long long)N * n * m;
+#pragma unroll
+  for (int u = 0; u < MBT / NWV; ++u) {
+    const int pb = (wave * (MBT / NWV) + u) * 16;
+    f32x4 qa = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < COUT / 32; ++ks) {
+      const bf16x8_t a = __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_out + (pb + li) * OP + 32 * ks + 8 * lk));
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const bf16x8_t b =
+            __builtin_bit_cast(bf16x8_t, *(const u16x8*)(wl2 + ((size_t)h2 * 16 + li) * COUT + 32 * ks + 8 * lk));
+        qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, qa, 0, 0, 0);
+      }
+    }
+    if (li < 9) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int px = pb + 4 * lk + r;
+        const int y = y0 + px / TC, x = x0 + px % TC;
+        if (y < n && x < m) qout[li * plane + ((long long)i * n + y) * m + x] = qa[r];
+      }
+    }
+  }
+}
+
 // Hidden layer in BF16 on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation): the
 // same tiling as the FP32 kernel, but each k-step covers 32 K-indices (tap, channel)
 // and every lane supplies 8 consecutive channels of one tap for A and 8 consecutive
@@ -1140,37 +1193,7 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
           *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
       }
     } else {
-      static_assert(COUT % 32 == 0, "whole 32-channel K steps");
-      constexpr int NWV = NT / 64;               // waves
-      constexpr int MBT = TR * TC / 16;          // M-blocks of the tile
-      static_assert(MBT % NWV == 0, "whole M-blocks per wave");
-      const int wave = tid >> 6;
-      const long long plane = (long long)N * n * m;
-      float* const qout = reinterpret_cast<float*>(out);
-#pragma unroll
-      for (int u = 0; u < MBT / NWV; ++u) {
-        const int pb = (wave * (MBT / NWV) + u) * 16;
-        f32x4 qa = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < COUT / 32; ++ks) {
-          const bf16x8_t a =
-              __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_out + (pb + li) * OP + 32 * ks + 8 * lk));
-#pragma unroll
-          for (int h2 = 0; h2 < 2; ++h2) {
-            const bf16x8_t b = __builtin_bit_cast(
-                bf16x8_t, *(const u16x8*)(wl2 + ((size_t)h2 * 16 + li) * COUT + 32 * ks + 8 * lk));
-            qa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, qa, 0, 0, 0);
-          }
-        }
-        if (li < 9) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int px = pb + 4 * lk + r;
-            const int y = y0 + px / TC, x = x0 + px % TC;
-            if (y < n && x < m) qout[li * plane + ((long long)i * n + y) * m + x] = qa[r];
-          }
-        }
-      }
+      fold_last_epilogue<COUT, TR, TC, OP, NT>(s_out, wl2, reinterpret_cast<float*>(out), N, n, m, i, y0, x0, tid);
     }
   }
 }
@@ -1187,7 +1210,11 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
 // k order), B[k][j] likewise from lane j + 16g, element r of lane j + 16g holds
 // D[4g + r][j].  CIN is a multiple of 32, so the 32 K-indices of a lane are 32
 // consecutive channels of one tap.
-template <int CIN, int COUT, int TR, int WG>
+//
+// LASTQ (64 output channels): the network's last layer is folded into the epilogue as in
+// the BF16 kernel (fold_last_epilogue): out then receives nine FP32 tap planes and no
+// maximum is published (no FP8 layer follows).
+template <int CIN, int COUT, int TR, int WG, bool LASTQ = false>
 __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
                                                             const bf16_t* __restrict__ in,
                                                             const unsigned* __restrict__ amax_in,
@@ -1195,7 +1222,8 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
                                                             const float* __restrict__ ws,
                                                             const float* __restrict__ bias, int act,
                                                             bf16_t* __restrict__ out,
-                                                            unsigned* __restrict__ amax_out) {
+                                                            unsigned* __restrict__ amax_out,
+                                                            const bf16_t* __restrict__ wl2) {
   static_assert(CIN % 32 == 0, "32 channels per lane fragment");
   constexpr int TC = 64;
   constexpr int HR = TR + 2, HC = TC + 2;
@@ -1225,7 +1253,7 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = (tid >> 6) & 3, ng = tid >> 8;
   const int li = lane & 15, lk = lane >> 4;
-  const float amx = __uint_as_float(*amax_in);
+  const float amx = amax_read(amax_in);
   const float sa = amx > 0.f ? amx * (1.0f / 448.0f) : 1.0f;
   const float inv_sa = 1.0f / sa;
   {
@@ -1343,15 +1371,19 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
         }
     }
     __syncthreads();
-    constexpr int QV = COUT / 8;
-    for (int e = tid; e < TR * TC * QV; e += NT) {
-      const int px = e / QV, q = e - px * QV;
-      const int y = y0 + px / TC, x = x0 + px % TC;
-      if (y < n && x < m)
-        *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+    if constexpr (LASTQ) {
+      fold_last_epilogue<COUT, TR, TC, OP, NT>(s_out, wl2, reinterpret_cast<float*>(out), N, n, m, i, y0, x0, tid);
+    } else {
+      constexpr int QV = COUT / 8;
+      for (int e = tid; e < TR * TC * QV; e += NT) {
+        const int px = e / QV, q = e - px * QV;
+        const int y = y0 + px / TC, x = x0 + px % TC;
+        if (y < n && x < m)
+          *(u16x8*)(out + (((size_t)i * n + y) * m + x) * COUT + 8 * q) = *(const u16x8*)(s_out + px * OP + 8 * q);
+      }
     }
   }
-  amax_publish(vmax, amax_out);
+  if constexpr (!LASTQ) amax_publish(vmax, amax_out);
 }
 
 }  // namespace
@@ -1497,7 +1529,7 @@ void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int
     const long long cap = 256LL * resident_per_cu<kern>(256 * WG); /* persistent */               \
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                                 \
     OIC_LAUNCH(t, kclass, s, kern, dim3(blocks), dim3(256 * WG), 0, N, n, m, (const bf16_t*)in_nhwc, \
-               amax_in, wq, ws, bias, act, (bf16_t*)out_nhwc, amax_out);                           \
+               amax_in, wq, ws, bias, act, (bf16_t*)out_nhwc, amax_out, nullptr);                  \
     return;                                                                                        \
   }
   OIC_F8_CASE(32, 16)
@@ -1507,6 +1539,29 @@ void launch_conv_mfma_fp8(hipStream_t s, Timer& t, int kclass, int N, int n, int
   OIC_F8_CASE(64, 32)
   OIC_F8_CASE(64, 64)
 #undef OIC_F8_CASE
+}
+
+void launch_conv_mfma_fp8_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
+                               const unsigned* amax_in, const uint8_t* wq, const float* ws, const float* bias,
+                               int act, const uint16_t* wl2, const float* bias_last, float* qbuf, FieldOut fo,
+                               const ObserveArgs* obs) {
+#define OIC_F8L_CASE(CI)                                                                            \
+  if (cin == CI) {                                                                                  \
+    constexpr int TRV = 8;                                                                          \
+    constexpr auto kern = k_conv_mfma_fp8<CI, 64, TRV, kFp8Groups, true>;                           \
+    const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);                \
+    const long long cap = 256LL * resident_per_cu<kern>(256 * kFp8Groups);                          \
+    const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                                  \
+    OIC_LAUNCH(t, KC_CONV_MID, s, kern, dim3(blocks), dim3(256 * kFp8Groups), 0, N, n, m,            \
+               (const bf16_t*)in_nhwc, amax_in, wq, ws, bias, act, (bf16_t*)qbuf, (unsigned*)nullptr, \
+               (const bf16_t*)wl2);                                                                 \
+  }
+  OIC_F8L_CASE(32)
+  OIC_F8L_CASE(64)
+#undef OIC_F8L_CASE
+  const ObserveArgs oa = obs ? *obs : ObserveArgs{};
+  OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+             0, N, n, m, qbuf, bias_last, fo, oa);
 }
 
 void launch_zero_u32(hipStream_t s, Timer& t, unsigned* p, int count) {

@@ -32,8 +32,8 @@ def test_folded_last_layer_keeps_the_network_flops():
     hidden layers) the conv FLOPs per step are the network's, and the last layer's class
     moves the nine FP32 tap planes and the state instead of the activations."""
     p = wl.PRESETS["C4"]
-    assert bench.last_layer_folded(p, "fp32") and bench.last_layer_folded(p, "bf16")
-    assert not bench.last_layer_folded(p, "fp8")
+    assert all(bench.last_layer_folded(p, prec) for prec in ("fp32", "bf16", "fp8"))
+    assert not bench.last_layer_folded(wl.PRESETS["C3"], "fp32")  # 32 -> 32 last hidden layer
     px = p.n * p.m * p.N
     ch = p.channels
     net = sum(2.0 * 9 * a * b * px for a, b in zip(ch[:-1], ch[1:]))

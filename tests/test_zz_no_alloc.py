@@ -69,9 +69,9 @@ def test_noalloc_refuses_requests_beyond_the_buffer():
     import torch
     p = wl.PRESETS["C2"]
     prob = wl.make_problem(p)
-    # 2 x 128 x 64 x 64 x 16 FP32 activations + 256 B exceed the 64 MiB buffer
+    # 2 x 128 x 64 x 64 x 16 FP32 activations + 2 KiB exceed the 64 MiB buffer
     b = 128
-    assert 2 * b * p.n * p.m * 16 * 4 + 256 > oic.OIC_NOALLOC_SCRATCH_BYTES
+    assert 2 * b * p.n * p.m * 16 * 4 + 2048 > oic.OIC_NOALLOC_SCRATCH_BYTES
     with oic.controller_for(prob, max_N=b, max_H=1, mem_mode=oic.OIC_MEM_DEVICE) as c:
         X, U = _inputs(p, b, 3)
         out = torch.full((b, p.n, p.m), 7.0, device="cuda")
