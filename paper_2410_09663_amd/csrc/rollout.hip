@@ -1198,6 +1198,150 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
   }
 }
 
+// Hidden layer in BF16 with the weights held in registers (cin 32 or 64 -> cout 32 or 64),
+// the BF16 counterpart of k_conv_f32r: each wave owns 32 output channels (two N-blocks)
+// for TR/RG rows of a TR x 64 tile (RG = 4 waves / (cout / 32) channel groups), holds its
+// B fragments for all K = 9 cin indices (8 consecutive channels of one tap per lane and
+// k-step of 32), so the LDS holds only the BF16 halo tile and every 16-byte A fragment
+// read feeds two MFMAs (v_mfma_f32_16x16x32_bf16).  The halo arrives by LDS-direct buffer
+// loads (16-byte slots, one padding slot per pixel, out-of-field slots zero-filled by the
+// buffer bounds); two persistent workgroups per CU walk the tiles in the XCD-aware order.
+// LASTQ (cout 64): the network's last layer is folded into the epilogue
+// (fold_last_epilogue); otherwise the BF16 outputs leave straight from the accumulators.
+// Lane layout (16x16x32): A[i][k] for k = 8g..8g+7 from lane i + 16g, B[k][j] likewise
+// from lane j + 16g, element r of lane j + 16g holds D[4g + r][j].
+template <int CIN, int COUT, int TR, bool LASTQ>
+__global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, const bf16_t* __restrict__ in,
+                                                       const bf16_t* __restrict__ wt,
+                                                       const float* __restrict__ bias, int act,
+                                                       bf16_t* __restrict__ out, const bf16_t* __restrict__ wl2) {
+  static_assert(CIN % 32 == 0 && COUT % 32 == 0, "32-channel K steps and channel groups");
+  constexpr int TC = 64, HR = TR + 2, HC = TC + 2;
+  constexpr int NG = COUT / 32;          // channel groups (one per wave of a row group)
+  constexpr int RG = 4 / NG;             // row groups
+  static_assert(TR % RG == 0, "whole rows per wave");
+  constexpr int RW = TR / RG;            // rows per wave
+  constexpr int CPB = CIN + 8;           // pixel stride in LDS (bf16): CIN / 8 data slots + 1 padding slot
+  constexpr int SLOT = CPB / 8;
+  constexpr int TOTAL_SLOTS = HR * HC * SLOT;
+  constexpr int INSTR = (TOTAL_SLOTS + 63) / 64;
+  constexpr int KS = 9 * CIN / 32;       // k-steps
+  constexpr int CG = CIN / 32;           // k-steps per tap
+  constexpr int OP = COUT + 8;           // pixel stride of the activated tile (LASTQ)
+  static_assert(!LASTQ || TR * TC * OP <= INSTR * 64 * 8, "the activated tile reuses the halo's LDS");
+  __shared__ __attribute__((aligned(16))) bf16_t s_in[INSTR * 64 * 8];
+  const int col_tiles = (m + TC - 1) / TC;
+  const int row_tiles = (n + TR - 1) / TR;
+  const int tiles = N * row_tiles * col_tiles;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ng = w % NG, rg = w / NG;
+  // this lane's weights: k-step ks, N-block nb -> W[32 ng + 16 nb + li][32 ks + 8 lk .. +7]
+  bf16x8_t wr[KS][2];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+      wr[ks][nb] = __builtin_bit_cast(
+          bf16x8_t, *(const u16x8*)(wt + (size_t)(32 * ng + 16 * nb + li) * (9 * CIN) + 32 * ks + 8 * lk));
+  float bo[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) bo[nb] = bias ? bias[32 * ng + 16 * nb + li] : 0.f;
+  const TileWalk walk(tiles);
+  // LDS-direct loads of tile `tl`'s (TR+2) x 66 x CIN halo into buffer `dst`
+  auto issue_halo = [&](int tl, bf16_t* dst) {
+    const int ct = tl % col_tiles, rest = tl / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+    const unsigned nrec = (unsigned)n * m * CIN * 2;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)i * n * m * CIN), (short)0, (int)nrec, 0x00020000);
+#pragma unroll
+    for (int u = 0; u < (INSTR + 3) / 4; ++u) {
+      const int ins = w + 4 * u;  // wave-uniform
+      if (ins < INSTR) {
+        int slot = ins * 64 + lane;
+        asm volatile("" : "+v"(slot));  // recomputed per tile (registers)
+        const int pix = slot / SLOT, q = slot - pix * SLOT;
+        const int yy = pix / HC, xx = pix - yy * HC;
+        const int gy = y0 + yy - 1, gx = x0 + xx - 1;
+        const bool live = slot < TOTAL_SLOTS && q < CIN / 8 && gy >= 0 && gy < n && gx >= 0 && gx < m;
+        const unsigned voff = live ? (unsigned)(((gy * m + gx) * CIN + 8 * q) * 2) : nrec;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(dst + ins * 512), 16,
+                                                 (int)voff, 0, 0, 0);
+      }
+    }
+  };
+  for (int tile = walk.first; tile < walk.end; tile += walk.step) {
+    const int ct = tile % col_tiles, rest = tile / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+    __syncthreads();  // every wave is done with the previous tile
+    issue_halo(tile, s_in);
+    __builtin_amdgcn_s_waitcnt(0);  // the LDS-direct loads have landed (vmcnt)
+    __syncthreads();
+    f32x4 acc[RW][4][2];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[r][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int tap = ks / CG, c0 = (ks % CG) * 32 + 8 * lk;
+      const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int ry = rg * RW + r;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const bf16x8_t a =
+              __builtin_bit_cast(bf16x8_t, *(const u16x8*)(s_in + ((ry + dy) * HC + 16 * mb + li + dx) * CPB + c0));
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[r][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wr[ks][nb], acc[r][mb][nb], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one step's fragments live at a time
+    }
+    if constexpr (!LASTQ) {
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int y = y0 + rg * RW + r;
+        if (y >= n) continue;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            const int o = 32 * ng + 16 * nb + li;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int x = x0 + 16 * mb + 4 * lk + q;
+              if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = to_bf16(activate(acc[r][mb][nb][q] + bo[nb], act));
+            }
+          }
+      }
+    } else {
+      __syncthreads();  // every wave is done with the halo tile
+      bf16_t* const s_out = s_in;
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              s_out[((rg * RW + r) * TC + 16 * mb + 4 * lk + q) * OP + 32 * ng + 16 * nb + li] =
+                  to_bf16(activate(acc[r][mb][nb][q] + bo[nb], act));
+      __syncthreads();
+      fold_last_epilogue<COUT, TR, TC, OP, 256>(s_out, wl2, reinterpret_cast<float*>(out), N, n, m, i, y0, x0, tid);
+    }
+  }
+}
+
 // Hidden layer in FP8 (OCP e4m3) on the gfx950 matrix cores
 // (v_mfma_scale_f32_16x16x128_f8f6f4 with unit block scales, FP32 accumulation).
 // Weights arrive quantised per output channel, wq[o][k] = W[o][k] / ws[o], with K
@@ -1458,9 +1602,31 @@ int resident_per_cu(int threads) {
 constexpr int kBf16GroupsWide = 2;  // 64 input or output channels
 constexpr int kBf16Groups32 = 2;    // 32 output channels
 
+// k_conv_bf16r addresses one member's input image through a buffer resource
+static bool bf16r_fits(int n, int m, int cin) { return (long long)n * m * cin * 2 < (1LL << 31); }
+
+// one output row per wave: 2 tile rows at 64 output channels (two channel groups), 4 at 32
+template <int CI, int CO, bool LASTQ>
+void launch_bf16r(hipStream_t s, Timer& t, int kclass, int N, int n, int m, const void* in_nhwc, const void* wt,
+                  const float* bias, int act, void* out, const uint16_t* wl2) {
+  constexpr int TRV = 4 / (CO / 32);
+  const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);
+  const long long cap = 2LL * 256;
+  const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
+  OIC_LAUNCH(t, kclass, s, (k_conv_bf16r<CI, CO, TRV, LASTQ>), dim3(blocks), dim3(256), 0, N, n, m,
+             (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out, (const bf16_t*)wl2);
+}
+
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                            const void* in_nhwc, const void* wt, const float* bias, int act,
                            void* out_nhwc) {
+  if ((cin == 32 || cin == 64) && (cout == 32 || cout == 64) && bf16r_fits(n, m, cin)) {
+    if (cin == 32 && cout == 32) launch_bf16r<32, 32, false>(s, t, kclass, N, n, m, in_nhwc, wt, bias, act, out_nhwc, nullptr);
+    if (cin == 32 && cout == 64) launch_bf16r<32, 64, false>(s, t, kclass, N, n, m, in_nhwc, wt, bias, act, out_nhwc, nullptr);
+    if (cin == 64 && cout == 32) launch_bf16r<64, 32, false>(s, t, kclass, N, n, m, in_nhwc, wt, bias, act, out_nhwc, nullptr);
+    if (cin == 64 && cout == 64) launch_bf16r<64, 64, false>(s, t, kclass, N, n, m, in_nhwc, wt, bias, act, out_nhwc, nullptr);
+    return;
+  }
   // pairs with 64 channels hold one workgroup per CU (their weights fill most of the LDS):
   // there two groups of four waves split the output channels of each tile
 #define OIC_BF_CASE(CI, CO)                                                                      \
@@ -1490,6 +1656,14 @@ bool conv_last_folds_bf16(int cin, int cout) { return cout == 64 && (cin == 32 |
 void launch_conv_mfma_bf16_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
                                 const void* wt, const float* bias, int act, const uint16_t* wl2,
                                 const float* bias_last, float* qbuf, FieldOut fo, const ObserveArgs* obs) {
+  if (bf16r_fits(n, m, cin)) {
+    if (cin == 64) launch_bf16r<64, 64, true>(s, t, KC_CONV_MID, N, n, m, in_nhwc, wt, bias, act, qbuf, wl2);
+    else launch_bf16r<32, 64, true>(s, t, KC_CONV_MID, N, n, m, in_nhwc, wt, bias, act, qbuf, wl2);
+    const ObserveArgs oa = obs ? *obs : ObserveArgs{};
+    OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+               0, N, n, m, qbuf, bias_last, fo, oa);
+    return;
+  }
 #define OIC_BFL_CASE(CI)                                                                         \
   if (cin == CI) {                                                                               \
     constexpr int TRV = CI <= 32 ? 8 : 4;                                                        \

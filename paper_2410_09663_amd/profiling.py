@@ -31,7 +31,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 
 CLASS_OF = [  # kernel-name prefix -> class, first match wins
     ("k_conv_first", "conv_first"), ("k_conv_last", "conv_last"), ("k_conv_mfma", "conv_mid"),
-    ("k_conv_f32r", "conv_mid"),
+    ("k_conv_f32r", "conv_mid"), ("k_conv_bf16r", "conv_mid"),
     ("k_conv_direct", "conv_mid"), ("k_lift", "lift"), ("k_stats_reduce", "stats_reduce"),
     ("k_stats", "stats"), ("k_update", "update"), ("k_chol", "chol"), ("k_potrf", "chol"),
     ("k_gain", "gain"), ("k_normals", "noise"), ("k_means", "means"), ("k_init_slice0", "init"),
