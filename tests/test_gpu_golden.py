@@ -15,12 +15,14 @@ max |gpu - oracle| / max |oracle|):
     per-step deviation passes into the next state at most linearly over the loop);
   * BF16 closed loops: tracking cost within 2% of the oracle's.
 """
+import dataclasses
 import importlib.util
 import os
 
 import numpy as np
 import pytest
 
+from oracle import enks
 from paper_2410_09663_amd import oic
 from paper_2410_09663_amd import workloads as wl
 from parity_util import assert_parity, max_relerr, relerr
@@ -118,3 +120,48 @@ def test_closed_loop_vs_oracle(case, precision):
         assert dc < tol
     else:
         assert dc < TOL_COST_BF16
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_256_rollout_full_batch_sampled_members(precision):
+    """The 256x256 workload's CNN (2-64-64-64-64-1, GELU) on all N = 512 members in one
+    call, the launch configuration of the benchmark's rollout; three members (first, one
+    inside, last) checked against the FP64 oracle's forward pass of those members alone."""
+    import torch
+    from oracle import cnn as ocnn
+    p = wl.PRESETS["C4"]
+    prob = wl.make_problem(p)
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((p.N, p.n, p.m)).astype(np.float32)
+    U = (0.3 * rng.standard_normal((p.N, p.l, p.m))).astype(np.float32)
+    prec = {"fp32": oic.OIC_PREC_FP32, "bf16": oic.OIC_PREC_BF16}[precision]
+    print(f"256x256 rollout, {precision}, batch {p.N}", flush=True)
+    with oic.controller_for(prob, max_N=p.N, max_H=1, precision=prec, mem_mode=oic.OIC_MEM_DEVICE) as c:
+        got = c.cnn_forward(torch.from_numpy(X).cuda(), torch.from_numpy(U).cuda())
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+    tol = TOL_FP32 if precision == "fp32" else TOL_BF16
+    for i in (0, 301, p.N - 1):
+        ref = ocnn.cnn_forward(X[i:i + 1], U[i:i + 1], prob.B, prob.weights, p.activation)[0]
+        e, emax = assert_parity(got[i], ref, tol, f"member {i}")
+        print(f"member {i}: relerr {e:.2e} (max {emax:.2e})", flush=True)
+
+
+def test_256_grid_solve_vs_oracle():
+    """One FP32 solve on the full 256x256 grid and CNN with l = 64, a reduced ensemble and
+    horizon (N = 48, H = 1: the oracle's rollout of every member is FP64 NumPy on the
+    host), explicit noise: U_hat and X_hat of both slices against the FP64 oracle."""
+    p = dataclasses.replace(wl.PRESETS["C4"], N=48, H=1)
+    prob = wl.make_problem(p)
+    Xref = wl.reference_window(p, 0)
+    z = wl.host_noise(p.n, p.m, p.l, p.N, p.H, seed=41)
+    print("256x256 grid solve, N=48, H=1", flush=True)
+    with oic.controller_for(prob, precision=oic.OIC_PREC_FP32) as c:
+        U, X = c.solve_ex(prob.X0, Xref, prob.Q, prob.R, p.N, p.H, noise=z)
+    print("oracle solve", flush=True)
+    ref = enks.solve(prob.B, prob.weights, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N, p.H,
+                     z.Z_init, z.Z_W, z.Z_VX, z.Z_VU)
+    eu, eum = assert_parity(U, ref.U_mean, TOL_FP32, "U_hat")
+    ex, exm = assert_parity(X, ref.X_mean, TOL_FP32, "X_hat")
+    print(f"256x256 N=48 H=1 fp32 vs FP64 oracle: U_hat {eu:.2e} (max {eum:.2e}), X_hat {ex:.2e} (max {exm:.2e})",
+          flush=True)
