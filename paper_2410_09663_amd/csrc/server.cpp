@@ -50,7 +50,14 @@ struct Request {
   std::vector<float> X0, ref;
   uint64_t seed = 0;
   Clock::time_point submitted;
+  int bypassed = 0;  // later requests started while this one waited for memory
 };
+
+// A request that waits for memory while later requests start is passed over at most
+// this many times; after that no later request starts ahead of it, so the solves in
+// flight finish, their controllers become idle and evictable, and it is admitted.  This
+// bounds the wait of a large controller behind a stream of small ones.
+constexpr int kMaxBypass = 8;
 
 struct Result {
   bool done = false;
@@ -156,20 +163,29 @@ void worker(oic_server* s) {
   for (;;) {
     // oldest request whose controller is idle
     auto it = s->queue.end();
+    auto blocked = s->queue.end();  // oldest request held back by memory alone
     s->cv_work.wait(lk, [&] {
       if (s->stop) return true;
       // oldest request whose controller is idle and whose buffers fit (admission by
-      // HBM footprint: otherwise it waits until memory frees up)
+      // HBM footprint: otherwise it waits until memory frees up); nothing starts behind a
+      // request that has waited for memory past kMaxBypass
+      blocked = s->queue.end();
       for (auto q = s->queue.begin(); q != s->queue.end(); ++q) {
         const Controller& c = *s->ctrls[q->controller];
-        if (!c.busy && can_admit(s, c)) {
+        if (c.busy) continue;
+        if (can_admit(s, c)) {
           it = q;
           return true;
+        }
+        if (blocked == s->queue.end()) {
+          blocked = q;
+          if (q->bypassed >= kMaxBypass) return false;  // reserved: wait for memory to free up
         }
       }
       return false;
     });
     if (s->stop) return;
+    if (blocked != s->queue.end() && blocked < it) blocked->bypassed++;
     Request req = std::move(*it);
     s->queue.erase(it);
     Controller& c = *s->ctrls[req.controller];

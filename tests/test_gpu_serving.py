@@ -78,3 +78,32 @@ def test_controller_larger_than_budget_is_rejected():
         with pytest.raises(oic.OicError) as e:
             srv.add(pr, pr.preset.N, pr.preset.H)
         assert e.value.code == oic.OIC_ENOMEM
+
+
+def test_large_controller_is_not_starved_by_small_ones():
+    """A controller that needs every other controller evicted is admitted after a bounded
+    number of later requests have passed it (then nothing more starts ahead of it), even
+    while two small controllers keep the budget busy with a continuous stream."""
+    small = [wl.make_problem(dataclasses.replace(wl.PRESETS["C1"], name=f"s{k}", seed_W=20 + k)) for k in range(2)]
+    big = wl.make_problem(dataclasses.replace(wl.PRESETS["C2"], name="big", n=48, m=48, l=8, N=96, H=6,
+                                              grf_length=4.0, ref_center=(24.0, 12.0)))
+    fs = oic.Server.footprint(small[0], small[0].preset.N, small[0].preset.H)
+    fb = oic.Server.footprint(big, big.preset.N, big.preset.H)
+    budget = fb + fs // 2  # the big controller fits only with both small ones evicted
+    assert 2 * fs <= budget
+    with oic.Server(hbm_budget_bytes=budget, max_inflight=2) as srv:
+        sid = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in small]
+        bid = srv.add(big, big.preset.N, big.preset.H)
+        sub = []
+        for k in range(2):
+            p = small[k].preset
+            sub.append((sid[k], srv.submit(sid[k], small[k].X0, wl.reference_window(p, 0), k)))
+        tb = srv.submit(bid, big.X0, wl.reference_window(big.preset, 0), 99)
+        for r in range(40):
+            k = r % 2
+            p = small[k].preset
+            sub.append((sid[k], srv.submit(sid[k], small[k].X0, wl.reference_window(p, r + 1), 100 + r)))
+        lat_small = [srv.wait(c, t)[2] for c, t in sub]
+        lat_big = srv.wait(bid, tb)[2]
+    print(f"big controller latency {lat_big:.1f} ms; small requests: last {lat_small[-1]:.1f} ms", flush=True)
+    assert lat_big < lat_small[-1]
