@@ -43,13 +43,33 @@ __device__ __forceinline__ float activate(float v, int act) {
   return 0.5f * v * (1.0f + fast_erf(v * 0.70710678118654752f));  // GELU, erf form
 }
 
-// BF16 storage: round to nearest even (activations are finite), and back by shifting.
-typedef unsigned short bf16_t;
-__device__ __forceinline__ bf16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
+// erf on [0, 3.5] as z (c0 + c1 z + ... + c8 z^8), a near-minimax fit written by
+// gen_erf_poly.py: absolute error below 5e-5, no transcendental instructions; erf = 1
+// beyond 3.5 (1 - erf(3.5) = 7.4e-7).
+constexpr float kErfPoly[9] = {1.128599286e+00f, -9.842433967e-03f, -3.096332252e-01f, -1.855238527e-01f,
+                               3.807112873e-01f, -2.126811743e-01f, 5.888256058e-02f, -8.328038268e-03f,
+                               4.819448804e-04f};
+__device__ __forceinline__ float poly_erf(float x) {
+  const float z = fminf(fabsf(x), 3.5f);
+  float p = kErfPoly[8];
+#pragma unroll
+  for (int k = 7; k >= 0; --k) p = fmaf(p, z, kErfPoly[k]);
+  return copysignf(p * z, x);
 }
+
+// The activation of the layers whose outputs are stored in BF16 (the BF16 and FP8
+// rollouts): GELU through poly_erf, whose error (< 5e-5 absolute in erf) is far below
+// BF16's rounding of the stored value (2^-9 relative); tanh as in activate.
+__device__ __forceinline__ float activate_lp(float v, int act) {
+  if (act == OIC_ACT_TANH) return fast_tanh(v);
+  const float h = 0.5f * v;
+  return fmaf(h, poly_erf(v * 0.70710678118654752f), h);  // GELU, erf form
+}
+
+// BF16 storage: round to nearest even (the hardware conversion; activations are finite),
+// and back by shifting.
+typedef unsigned short bf16_t;
+__device__ __forceinline__ bf16_t to_bf16(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
 __device__ __forceinline__ float from_bf16(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ void store_act(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_act(bf16_t* p, float v) { *p = to_bf16(v); }
@@ -880,7 +900,8 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
             for (int r = 0; r < 4; ++r) {
               const int x = x0 + mb * 16 + 4 * lk + r;
               if (x < m) {
-                const float v = activate(acc[mb][nb][r] + bo, act);
+                const float v = sizeof(TOUT) == 2 ? activate_lp(acc[mb][nb][r] + bo, act)
+                                                  : activate(acc[mb][nb][r] + bo, act);
                 store_act(out + (((size_t)i * n + y) * m + x) * COUT + o, v);
                 vmax = fmaxf(vmax, fabsf(v));
               }
@@ -900,7 +921,8 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int px = (4 * w + mb) * 16 + 4 * lk + r;
-          s_out[px * OPAD + o] = activate(acc[mb][nb][r] + bo, act);
+          s_out[px * OPAD + o] = sizeof(TOUT) == 2 ? activate_lp(acc[mb][nb][r] + bo, act)
+                                                   : activate(acc[mb][nb][r] + bo, act);
         }
       }
   }
@@ -1179,7 +1201,7 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int tx = mb * 16 + 4 * lk + r;
-            s_out[(ty * TC + tx) * OP + o] = to_bf16(activate(acc[rw][mb][nb][r] + bo, act));
+            s_out[(ty * TC + tx) * OP + o] = to_bf16(activate_lp(acc[rw][mb][nb][r] + bo, act));
           }
         }
     }
@@ -1319,7 +1341,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int x = x0 + 16 * mb + 4 * lk + q;
-              if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = to_bf16(activate(acc[r][mb][nb][q] + bo[nb], act));
+              if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = to_bf16(activate_lp(acc[r][mb][nb][q] + bo[nb], act));
             }
           }
       }
@@ -1335,7 +1357,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               s_out[((rg * RW + r) * TC + 16 * mb + 4 * lk + q) * OP + 32 * ng + 16 * nb + li] =
-                  to_bf16(activate(acc[r][mb][nb][q] + bo[nb], act));
+                  to_bf16(activate_lp(acc[r][mb][nb][q] + bo[nb], act));
       __syncthreads();
       fold_last_epilogue<COUT, TR, TC, OP, 256>(s_out, wl2, reinterpret_cast<float*>(out), N, n, m, i, y0, x0, tid);
     }
@@ -1508,7 +1530,7 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int tx = mb * 16 + 4 * lk + r;
-            const float v = activate(fmaf(acc[rw][mb][nb][r], sc, bo), act);
+            const float v = activate_lp(fmaf(acc[rw][mb][nb][r], sc, bo), act);
             s_out[(ty * TC + tx) * OP + o] = to_bf16(v);
             if (y0 + ty < n && x0 + tx < m) vmax = fmaxf(vmax, fabsf(v));
           }
