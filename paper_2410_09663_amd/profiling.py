@@ -31,7 +31,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 
 CLASS_OF = [  # kernel-name prefix -> class, first match wins
     ("k_conv_first", "conv_first"), ("k_conv_last", "conv_last"), ("k_conv_mfma", "conv_mid"),
-    ("k_conv_f32r", "conv_mid"), ("k_conv_bf16r", "conv_mid"),
+    ("k_conv_f32r", "conv_mid"), ("k_conv_bf16r", "conv_mid"), ("k_center", "means"),
     ("k_conv_direct", "conv_mid"), ("k_lift", "lift"), ("k_stats_reduce", "stats_reduce"),
     ("k_stats", "stats"), ("k_update", "update"), ("k_chol", "chol"), ("k_potrf", "chol"),
     ("k_gain", "gain"), ("k_normals", "noise"), ("k_means", "means"), ("k_init_slice0", "init"),
@@ -240,11 +240,28 @@ def counters_table(dirs):
                 e[c].append(x)
                 if c not in names:
                     names.append(c)
-    lines = ["| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    # derived: matrix-core busy fraction (GRBM_GUI_ACTIVE sums the 8 XCDs, the MFMA busy
+    # cycles the 1024 SIMDs) and LDS bank-conflict cycles per LDS instruction
+    derived = []
+    if "GRBM_GUI_ACTIVE" in names and "SQ_VALU_MFMA_BUSY_CYCLES" in names:
+        derived.append(("MFMA busy", lambda e: (_mean(e, "SQ_VALU_MFMA_BUSY_CYCLES") / 1024.0) /
+                        max(_mean(e, "GRBM_GUI_ACTIVE") / 8.0, 1e-30), "{:.1%}"))
+    if "SQ_INSTS_LDS" in names and "SQ_LDS_BANK_CONFLICT" in names:
+        derived.append(("LDS conflict cycles / LDS instr", lambda e: _mean(e, "SQ_LDS_BANK_CONFLICT") /
+                        max(_mean(e, "SQ_INSTS_LDS"), 1e-30), "{:.2f}"))
+    lines = ["| kernel | dispatches | " + " | ".join(names + [d[0] for d in derived]) + " |",
+             "|---|---|" + "---|" * (len(names) + len(derived))]
     for (name, small), e in per.items():
         cells = [f"{sum(e[c]) / len(e[c]):.4g}" if e.get(c) else "" for c in names]
-        lines.append(f"| `{name}`{' (small grid)' if small else ''} | " + " | ".join(cells) + " |")
+        cells += [fmt.format(f(e)) if all(e.get(c) for c in names[:1]) else "" for _, f, fmt in derived]
+        cnt = max(len(v) for v in e.values()) if e else 0
+        lines.append(f"| `{name}`{' (small grid)' if small else ''} | {cnt} | " + " | ".join(cells) + " |")
     return "\n".join(lines)
+
+
+def _mean(e, c):
+    v = e.get(c) or [0.0]
+    return sum(v) / len(v)
 
 
 def main(argv=None):
