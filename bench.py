@@ -216,8 +216,11 @@ def serve_main(args):
     Three runs over the same request list: (1) every request submitted at once (capacity,
     solves/s); (2) Poisson arrivals at the offered rate (default 400 solves/s, above
     capacity: latency is queue-dominated); (3) Poisson arrivals at 70% of the measured
-    capacity.  Then the same requests in the plain FP32 single-request form (one solve at
-    a time, FP32 rollout), whose solves/s gives the speed-up."""
+    capacity.  Then each distinct shape solved alone (resident, graph warm), summed over the
+    request list: the served makespan against that sum shows how much of the GPU time the
+    overlap of concurrent solves recovers.  Last, the same requests in the plain FP32
+    single-request form (one solve at a time, FP32 rollout), whose solves/s gives the
+    speed-up."""
     from paper_2410_09663_amd import oic
     from paper_2410_09663_amd import workloads as wl
 
@@ -287,6 +290,31 @@ def serve_main(args):
     out.update({"value": cap["solves_per_s"], "capacity": cap,
                 "offered": dict(offered, rate=args.rate),
                 "sustainable": dict(sustained, rate=sustain_rate), "server": st})
+    # each distinct (grid, N, H) solved alone on a resident controller (graph warm), summed
+    # over the request list: the GPU time the requests need without any overlap
+    print("[serve] solo solve times per shape", file=sys.stderr, flush=True)
+    shape_ms = {}
+    for c, pr in enumerate(probs):
+        p = pr.preset
+        key = (p.n, p.N, p.H)
+        if key in shape_ms:
+            continue
+        with oic.controller_for(pr, precision=wl.PREC_BF16) as h:
+            X0, ref, _ = inputs(c, 0)
+            ts = []
+            for k in range(4):
+                t0 = time.perf_counter()
+                h.solve(X0, ref, pr.Q, pr.R, p.N, p.H, 1 + k, want_X=True)
+                ts.append(time.perf_counter() - t0)
+        shape_ms[key] = 1e3 * float(np.median(ts[1:]))
+    solo_by_grid = {}
+    for c in ctrl_of:
+        p = probs[int(c)].preset
+        solo_by_grid[p.n] = solo_by_grid.get(p.n, 0.0) + 1e-3 * shape_ms[(p.n, p.N, p.H)]
+    solo_sum = sum(solo_by_grid.values())
+    out["solo"] = {"sum_s": solo_sum, "by_grid_s": {str(g): v for g, v in sorted(solo_by_grid.items())},
+                   "capacity_makespan_over_sum": cap["makespan_s"] / solo_sum,
+                   "shape_ms": {f"{g}x{g} N={N} H={H}": v for (g, N, H), v in sorted(shape_ms.items())}}
     if not args.no_fp32_baseline:
         with oic.Server(budget, max_inflight=1) as srv:
             ids = [srv.add(pr, pr.preset.N, pr.preset.H, precision=wl.PREC_FP32) for pr in probs]

@@ -254,7 +254,8 @@ int oic_columns_project(int l, int m, int q, const float* U, const float* T, flo
  * admitted continuously: a pool of max_inflight worker threads runs the oldest
  * request whose controller is idle and whose device footprint fits the HBM
  * budget, evicting least-recently-used idle controllers (keeping their U_prev on
- * the host) to make room; otherwise the request waits.  Solves of different
+ * the host) to make room, or taking over the handle of an idle controller of the same
+ * shape; otherwise the request waits.  Solves of different
  * controllers overlap on the device; solves of one controller run in submission
  * order.  Each result is the same as the controller's solve alone.  All array
  * arguments are HOST pointers, copied before the call returns. */
@@ -290,10 +291,12 @@ int oic_server_submit(oic_server_handle s, int controller_id, const float* X0, c
 int oic_server_wait(oic_server_handle s, long long ticket, float* U_out, float* X_out,
                     double* latency_ms, double* queue_ms);
 
-/* Counters: completed solves, controller admissions and evictions, device bytes
- * held now and at peak. Any pointer may be NULL. */
+/* Counters: completed solves, controller admissions and evictions, admissions that
+ * took over the handle of an evicted controller of the same shape (weights and U_prev
+ * swapped in place, no device allocation), device bytes held now and at peak. Any
+ * pointer may be NULL. */
 int oic_server_stats(oic_server_handle s, long long* completed, long long* admissions,
-                     long long* evictions, size_t* bytes_in_use, size_t* peak_bytes);
+                     long long* evictions, long long* recycled, size_t* bytes_in_use, size_t* peak_bytes);
 
 /* Reason for the last failed oic_server_wait. */
 const char* oic_server_last_error(oic_server_handle s);

@@ -880,8 +880,31 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
     if (bias && bias[k] && !finite_all(bias[k], c.channels[k + 1]))
       return fail(h, OIC_EINVAL, "non-finite bias");
   }
-  // bias buffers may be allocated or freed below, and a captured solve holds their addresses
-  drop_graph(h);
+  // A captured solve holds the weight buffers' addresses, not their contents: it stays valid
+  // when new values are copied into the same buffers and is dropped only if a buffer is
+  // allocated or freed here (first call, or a bias switched on or off).
+  const auto addresses = [h]() {
+    std::vector<const void*> a{h->dB, h->dWl2};
+    for (int k = 0; k < OIC_MAX_LAYERS; ++k) {
+      a.push_back(h->dW[k]);
+      a.push_back(h->dWk[k]);
+      a.push_back(h->dWb[k]);
+      a.push_back(h->dWq[k]);
+      a.push_back(h->dWs[k]);
+      a.push_back(h->dBias[k]);
+    }
+    return a;
+  };
+  const std::vector<const void*> before = addresses();
+  struct DropIfMoved {
+    oic_ctx* h;
+    const std::vector<const void*>& before;
+    decltype(addresses)& now;
+    ~DropIfMoved() {
+      if (now() != before) drop_graph(h);
+    }
+  } drop_if_moved{h, before, addresses};
+  h->weights_set = false;  // until every copy below has succeeded
   int rc;
   if (!h->dB && (rc = dalloc(h, &h->dB, (size_t)c.n * c.l))) return rc;
   HIP_TRY(hipMemcpyAsync(h->dB, B, (size_t)c.n * c.l * sizeof(float), hipMemcpyHostToDevice, h->stream));

@@ -75,7 +75,7 @@ struct oic_server {
   std::deque<Request> queue;
   std::map<long long, Result> results;
   long long next_ticket = 1, tick = 0;
-  long long completed = 0, evictions = 0, admissions = 0;
+  long long completed = 0, evictions = 0, admissions = 0, recycled = 0;
   size_t peak_used = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -98,12 +98,69 @@ bool can_admit(const oic_server* s, const Controller& c) {
   return s->used - reclaimable + c.footprint <= s->budget;
 }
 
+// Whether handles created from a and b have the same buffers and captured solve: same
+// grid, control rows, layer widths, activation, precision and (N, H).
+bool same_shape(const oic_config& a, const oic_config& b) {
+  if (a.n != b.n || a.m != b.m || a.l != b.l || a.n_layers != b.n_layers || a.activation != b.activation ||
+      a.precision != b.precision || a.max_N != b.max_N || a.max_H != b.max_H || a.mem_mode != b.mem_mode)
+    return false;
+  for (int k = 0; k <= a.n_layers; ++k)
+    if (a.channels[k] != b.channels[k]) return false;
+  return true;
+}
+
+// Loads c's surrogate and applied control into a handle (a new one, or one taken over
+// from an evicted controller of the same shape).
+int load_controller(oic_handle h, const Controller& c) {
+  std::vector<const float*> wp, bp;
+  for (auto& w : c.W) wp.push_back(w.data());
+  for (auto& b : c.bias) bp.push_back(b.empty() ? nullptr : b.data());
+  int rc = oic_set_weights(h, c.B.data(), wp.data(), bp.data());
+  if (rc != OIC_OK) return rc;
+  if (!c.u_prev.empty()) return oic_set_u_prev(h, c.u_prev.data());
+  const std::vector<float> zero((size_t)c.cfg.l * c.cfg.m, 0.f);  // a first admission
+  return oic_set_u_prev(h, zero.data());
+}
+
 // Called with the lock held, right after the scheduling decision (same lock hold, so
-// the budget check and the reservation are atomic).  Chooses the LRU idle victims,
-// takes them and c's footprint out of the budget at once, then releases the lock for
-// the slow part (saving the victims' U_prev, freeing them, creating c's handle).
+// the budget check and the reservation are atomic).  If c does not fit beside the
+// resident controllers and an idle one has c's shape, c takes over its handle: the evicted controller's U_prev is saved, c's
+// weights and U_prev are copied into the same buffers, and the handle's captured solve
+// stays valid (no device allocation, no free, no new capture).  Otherwise chooses the LRU
+// idle victims, takes them and c's footprint out of the budget at once, then releases
+// the lock for the slow part (saving the victims' U_prev, freeing them, creating c's
+// handle).
 int make_resident(oic_server* s, Controller& c, std::unique_lock<std::mutex>& lk) {
   if (c.h) return OIC_OK;
+  Controller* donor = nullptr;
+  if (s->used + c.footprint > s->budget)  // someone has to go: prefer a controller of c's shape
+    for (auto& o : s->ctrls)
+      if (o->h && !o->busy && o.get() != &c && same_shape(o->cfg, c.cfg) &&
+          (!donor || o->last_used < donor->last_used))
+        donor = o.get();
+  if (donor) {
+    oic_handle h = donor->h;
+    donor->h = nullptr;
+    donor->busy = true;  // its requests wait until its state is saved
+    s->evictions++;
+    lk.unlock();
+    donor->u_prev.resize((size_t)donor->cfg.l * donor->cfg.m);
+    int rc = oic_get_u_prev(h, donor->u_prev.data());
+    if (rc == OIC_OK) rc = load_controller(h, c);
+    lk.lock();
+    donor->busy = false;
+    if (rc != OIC_OK) {
+      lk.unlock();
+      oic_destroy(h);
+      lk.lock();
+      s->used -= donor->footprint;
+      return rc;
+    }
+    c.h = h;  // same footprint: the budget is unchanged
+    s->admissions++;
+    s->recycled++;
+    return OIC_OK;
+  }
   std::vector<std::pair<oic_handle, Controller*>> victims;
   while (s->used + c.footprint > s->budget) {
     Controller* victim = nullptr;
@@ -137,11 +194,7 @@ int make_resident(oic_server* s, Controller& c, std::unique_lock<std::mutex>& lk
   oic_handle h = nullptr;
   int rc = oic_create(&c.cfg, &h);
   if (rc == OIC_OK) {
-    std::vector<const float*> wp, bp;
-    for (auto& w : c.W) wp.push_back(w.data());
-    for (auto& b : c.bias) bp.push_back(b.empty() ? nullptr : b.data());
-    rc = oic_set_weights(h, c.B.data(), wp.data(), bp.data());
-    if (rc == OIC_OK && !c.u_prev.empty()) rc = oic_set_u_prev(h, c.u_prev.data());
+    rc = load_controller(h, c);
     if (rc != OIC_OK) {
       oic_destroy(h);
       h = nullptr;
@@ -326,12 +379,13 @@ int oic_server_wait(oic_server_handle s, long long ticket, float* U_out, float* 
 }
 
 int oic_server_stats(oic_server_handle s, long long* completed, long long* admissions,
-                     long long* evictions, size_t* bytes_in_use, size_t* peak_bytes) {
+                     long long* evictions, long long* recycled, size_t* bytes_in_use, size_t* peak_bytes) {
   if (!s) return OIC_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
   if (completed) *completed = s->completed;
   if (admissions) *admissions = s->admissions;
   if (evictions) *evictions = s->evictions;
+  if (recycled) *recycled = s->recycled;
   if (bytes_in_use) *bytes_in_use = s->used;
   if (peak_bytes) *peak_bytes = s->peak_used;
   return OIC_OK;

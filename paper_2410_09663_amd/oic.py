@@ -123,6 +123,7 @@ def lib():
             "oic_server_stats": (ci, [vp, ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
             "oic_server_last_error": (ctypes.c_char_p, [vp]),
             "oic_footprint_bytes": (cs, [ctypes.POINTER(oic_config)]),
@@ -547,11 +548,11 @@ class Server:
         return U, X, lat.value, q.value
 
     def stats(self):
-        c, a, e = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        c, a, e, r = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
         u, pk = ctypes.c_size_t(), ctypes.c_size_t()
-        lib().oic_server_stats(self._s, ctypes.byref(c), ctypes.byref(a), ctypes.byref(e),
+        lib().oic_server_stats(self._s, ctypes.byref(c), ctypes.byref(a), ctypes.byref(e), ctypes.byref(r),
                                ctypes.byref(u), ctypes.byref(pk))
-        return {"completed": c.value, "admissions": a.value, "evictions": e.value,
+        return {"completed": c.value, "admissions": a.value, "evictions": e.value, "recycled": r.value,
                 "bytes_in_use": u.value, "peak_bytes": pk.value}
 
     def close(self):

@@ -107,3 +107,47 @@ def test_large_controller_is_not_starved_by_small_ones():
         lat_big = srv.wait(bid, tb)[2]
     print(f"big controller latency {lat_big:.1f} ms; small requests: last {lat_small[-1]:.1f} ms", flush=True)
     assert lat_big < lat_small[-1]
+
+
+@pytest.mark.parametrize("shape", ["c1_fp32", "bf16_32ch"])
+def test_same_shape_admission_takes_over_the_handle(shape):
+    """Two controllers of one shape with different weights, a budget for one handle and
+    alternating requests: every admission after the first takes over the other
+    controller's handle (weights and U_prev swapped in place, the captured solve kept).
+    Each result is bitwise the controller's solve alone, so the taken-over solve reads the
+    new weights, the evicted controller's U_prev comes back on its return, and a first
+    admission starts from U_prev = 0."""
+    if shape == "c1_fp32":
+        base = wl.PRESETS["C1"]
+    else:
+        base = dataclasses.replace(wl.PRESETS["C3"], n=32, m=32, l=8, N=32, H=3, grf_length=4.0,
+                                   ref_center=(16.0, 8.0), precision=wl.PREC_BF16)
+    problems = [wl.make_problem(dataclasses.replace(base, name=f"{shape}{k}", seed_W=31 + k, seed_B=41 + k,
+                                                    seed_X0=51 + k)) for k in range(2)]
+    steps = 3
+    reqs = []
+    for k in range(steps):
+        for cid, pr in enumerate(problems):
+            p = pr.preset
+            reqs.append((cid, (pr.X0 * (1.0 + 0.1 * k)).astype(np.float32), wl.reference_window(p, k),
+                         200 * cid + k))
+    alone = {}
+    for cid, pr in enumerate(problems):
+        with oic.Server(hbm_budget_bytes=8 << 30, max_inflight=1) as srv:
+            sid = srv.add(pr, pr.preset.N, pr.preset.H)
+            for (c, X0, ref, seed) in reqs:
+                if c == cid:
+                    alone[(c, seed)] = srv.wait(sid, srv.submit(sid, X0, ref, seed))[:2]
+    fp = oic.Server.footprint(problems[0], base.N, base.H)
+    with oic.Server(hbm_budget_bytes=int(1.5 * fp), max_inflight=1) as srv:
+        ids = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in problems]
+        for (c, X0, ref, seed) in reqs:
+            U, X, _, _ = srv.wait(ids[c], srv.submit(ids[c], X0, ref, seed))
+            Ua, Xa = alone[(c, seed)]
+            assert np.array_equal(U, Ua), (c, seed)
+            assert np.array_equal(X, Xa), (c, seed)
+        st = srv.stats()
+    print(f"{shape}: {st}", flush=True)
+    assert st["completed"] == len(reqs)
+    assert st["admissions"] == len(reqs) and st["recycled"] == len(reqs) - 1
+    assert st["peak_bytes"] == fp
