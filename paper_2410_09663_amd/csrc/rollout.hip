@@ -43,33 +43,71 @@ __device__ __forceinline__ float activate(float v, int act) {
   return 0.5f * v * (1.0f + fast_erf(v * 0.70710678118654752f));  // GELU, erf form
 }
 
-// erf on [0, 3.5] as z (c0 + c1 z + ... + c8 z^8), a near-minimax fit written by
-// gen_erf_poly.py: absolute error below 5e-5, no transcendental instructions; erf = 1
-// beyond 3.5 (1 - erf(3.5) = 7.4e-7).
-constexpr float kErfPoly[9] = {1.128599286e+00f, -9.842433967e-03f, -3.096332252e-01f, -1.855238527e-01f,
-                               3.807112873e-01f, -2.126811743e-01f, 5.888256058e-02f, -8.328038268e-03f,
-                               4.819448804e-04f};
-__device__ __forceinline__ float poly_erf(float x) {
-  const float z = fminf(fabsf(x), 3.5f);
-  float p = kErfPoly[8];
+// GELU from a polynomial erf with no transcendental instructions: erf(z) on [0, 3.5] is
+// fitted by z (c0 + ... + c8 z^8) (absolute error below 5e-5; erf = 1 beyond 3.5, where
+// 1 - erf(3.5) = 7.4e-7), and since erf is odd, GELU(x) = x/2 + |x| erf(|x|/sqrt2)/2 =
+// fma(|x| a, Q(a), x/2) with a = min(|x|, 3.5 sqrt2) and q_k = c_k / (2 sqrt2^(k+1)).
+// Coefficients written by gen_erf_poly.py; twelve instructions per value.
+constexpr float kGeluPoly[9] = {3.990201056e-01f, -2.460608492e-03f, -5.473593995e-02f, -2.319048159e-02f,
+                                3.365044296e-02f, -1.329257339e-02f, 2.602266148e-03f, -2.602511959e-04f,
+                                1.064957814e-05f};
+__device__ __forceinline__ float poly_gelu(float x) {
+  const float a = fabsf(x);
+  const float ac = fminf(a, 4.94974746830583f);
+  float p = kGeluPoly[8];
 #pragma unroll
-  for (int k = 7; k >= 0; --k) p = fmaf(p, z, kErfPoly[k]);
-  return copysignf(p * z, x);
+  for (int k = 7; k >= 0; --k) p = fmaf(p, ac, kGeluPoly[k]);
+  return fmaf(a * ac, p, 0.5f * x);
 }
 
 // The activation of the layers whose outputs are stored in BF16 (the BF16 and FP8
-// rollouts): GELU through poly_erf, whose error (< 5e-5 absolute in erf) is far below
+// rollouts): GELU through poly_gelu, whose error (|x|/2 times the erf fit's) is far below
 // BF16's rounding of the stored value (2^-9 relative); tanh as in activate.
 __device__ __forceinline__ float activate_lp(float v, int act) {
   if (act == OIC_ACT_TANH) return fast_tanh(v);
-  const float h = 0.5f * v;
-  return fmaf(h, poly_erf(v * 0.70710678118654752f), h);  // GELU, erf form
+  return poly_gelu(v);
+}
+
+// The activation as a compile-time choice: epilogues that evaluate it for every output
+// element branch on the runtime code once per tile and run a straight-line body for it.
+template <int A>
+struct ActC {
+  static constexpr int value = A;
+};
+template <int ACT>
+__device__ __forceinline__ float activate_c(float v) {
+  if constexpr (ACT == OIC_ACT_TANH)
+    return fast_tanh(v);
+  else
+    return 0.5f * v * (1.0f + fast_erf(v * 0.70710678118654752f));  // GELU, erf form
+}
+template <int ACT>
+__device__ __forceinline__ float activate_lp_c(float v) {
+  if constexpr (ACT == OIC_ACT_TANH) {
+    return fast_tanh(v);
+  } else {
+    return poly_gelu(v);
+  }
+}
+// Runs f(ActC<act>{}) for the runtime activation code.
+template <typename F>
+__device__ __forceinline__ void with_activation(int act, F&& f) {
+  if (act == OIC_ACT_TANH)
+    f(ActC<OIC_ACT_TANH>{});
+  else
+    f(ActC<OIC_ACT_GELU>{});
 }
 
 // BF16 storage: round to nearest even (the hardware conversion; activations are finite),
 // and back by shifting.
 typedef unsigned short bf16_t;
 __device__ __forceinline__ bf16_t to_bf16(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
+// Two values as one 32-bit word of BF16s (lo in the low half): one v_cvt_pk_bf16_f32.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
+}
 __device__ __forceinline__ float from_bf16(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ void store_act(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_act(bf16_t* p, float v) { *p = to_bf16(v); }
@@ -875,7 +913,10 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
       const int off = (tap / 3) * HC + tap % 3;
       float b[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) b[nb] = nb * 16 + li < COUT ? s_w[kq * COUT + nb * 16 + li] : 0.f;
+      for (int nb = 0; nb < NB; ++nb) {
+        const int o = DIRECT ? NB * li + nb : nb * 16 + li;  // DIRECT: a lane holds NB adjacent channels
+        b[nb] = o < COUT ? s_w[kq * COUT + o] : 0.f;
+      }
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
         const int px = (4 * w + mb) * 16 + li;  // pixel (px / 64, px % 64) of the tile
@@ -886,27 +927,40 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
       }
     }
     if constexpr (DIRECT) {
-      // wave w owns output row w of the tile
+      // wave w owns output row w of the tile; lane (li, lk) holds channels NB li .. NB li + NB-1
+      // of pixels 16 mb + 4 lk + r and stores them as one vector (16 B FP32, 8 B BF16)
+      static_assert(NB == 4, "four adjacent channels per lane");
       const int y = y0 + w;
       float vmax = 0.f;
       if (y < n) {
+        float bo[NB];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+        for (int nb = 0; nb < NB; ++nb) bo[nb] = s_bias[NB * li + nb];
+        TOUT* const orow = out + (((size_t)i * n + y) * m + x0) * COUT + NB * li;
+        const bool full = x0 + TC <= m;
+        with_activation(act, [&](auto actc) {
+          constexpr int ACT = decltype(actc)::value;
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const int o = nb * 16 + li;
-            const float bo = s_bias[o];
+          for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int x = x0 + mb * 16 + 4 * lk + r;
-              if (x < m) {
-                const float v = sizeof(TOUT) == 2 ? activate_lp(acc[mb][nb][r] + bo, act)
-                                                  : activate(acc[mb][nb][r] + bo, act);
-                store_act(out + (((size_t)i * n + y) * m + x) * COUT + o, v);
-                vmax = fmaxf(vmax, fabsf(v));
+              const int px = mb * 16 + 4 * lk + r;
+              if (full || x0 + px < m) {
+                float v[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                  v[nb] = sizeof(TOUT) == 2 ? activate_lp_c<ACT>(acc[mb][nb][r] + bo[nb])
+                                            : activate_c<ACT>(acc[mb][nb][r] + bo[nb]);
+                  vmax = fmaxf(vmax, fabsf(v[nb]));
+                }
+                if constexpr (sizeof(TOUT) == 2)
+                  *reinterpret_cast<u32x2*>(orow + (size_t)px * COUT) = u32x2{pack_bf16x2(v[0], v[1]),
+                                                                              pack_bf16x2(v[2], v[3])};
+                else
+                  *reinterpret_cast<f32x4*>(orow + (size_t)px * COUT) = f32x4{v[0], v[1], v[2], v[3]};
               }
             }
-          }
+        });
       }
       if (amax) amax_publish(vmax, amax);
       return;
@@ -1247,6 +1301,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
   constexpr int SLOT = CPB / 8;
   constexpr int TOTAL_SLOTS = HR * HC * SLOT;
   constexpr int INSTR = (TOTAL_SLOTS + 63) / 64;
+  constexpr int SPW = (INSTR + 3) / 4;   // halo load instructions per wave (at most)
   constexpr int KS = 9 * CIN / 32;       // k-steps
   constexpr int CG = CIN / 32;           // k-steps per tap
   constexpr int OP = COUT + 8;           // pixel stride of the activated tile (LASTQ)
@@ -1259,57 +1314,72 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
   const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ng = w % NG, rg = w / NG;
-  // this lane's weights: k-step ks, N-block nb -> W[32 ng + 16 nb + li][32 ks + 8 lk .. +7]
+  // Output channel of column li in N-block nb: 32 ng + 2 li + nb, so that a lane holds two
+  // adjacent channels of each of its pixels and stores them as one 32-bit word.
+  // This lane's weights: k-step ks, N-block nb -> W[32 ng + 2 li + nb][32 ks + 8 lk .. +7].
   bf16x8_t wr[KS][2];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
       wr[ks][nb] = __builtin_bit_cast(
-          bf16x8_t, *(const u16x8*)(wt + (size_t)(32 * ng + 16 * nb + li) * (9 * CIN) + 32 * ks + 8 * lk));
+          bf16x8_t, *(const u16x8*)(wt + (size_t)(32 * ng + 2 * li + nb) * (9 * CIN) + 32 * ks + 8 * lk));
   float bo[2];
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) bo[nb] = bias ? bias[32 * ng + 16 * nb + li] : 0.f;
-  const TileWalk walk(tiles);
-  // LDS-direct loads of tile `tl`'s (TR+2) x 66 x CIN halo into buffer `dst`
-  auto issue_halo = [&](int tl, bf16_t* dst) {
-    const int ct = tl % col_tiles, rest = tl / col_tiles;
-    const int rt = rest % row_tiles, i = rest / row_tiles;
-    const int y0 = rt * TR, x0 = ct * TC;
-    const unsigned nrec = (unsigned)n * m * CIN * 2;
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)i * n * m * CIN), (short)0, (int)nrec, 0x00020000);
-#pragma unroll
-    for (int u = 0; u < (INSTR + 3) / 4; ++u) {
-      const int ins = w + 4 * u;  // wave-uniform
-      if (ins < INSTR) {
-        int slot = ins * 64 + lane;
-        asm volatile("" : "+v"(slot));  // recomputed per tile (registers)
-        const int pix = slot / SLOT, q = slot - pix * SLOT;
-        const int yy = pix / HC, xx = pix - yy * HC;
-        const int gy = y0 + yy - 1, gx = x0 + xx - 1;
-        const bool live = slot < TOTAL_SLOTS && q < CIN / 8 && gy >= 0 && gy < n && gx >= 0 && gx < m;
-        const unsigned voff = live ? (unsigned)(((gy * m + gx) * CIN + 8 * q) * 2) : nrec;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(dst + ins * 512), 16,
-                                                 (int)voff, 0, 0, 0);
-      }
-    }
+  for (int nb = 0; nb < 2; ++nb) bo[nb] = bias ? bias[32 * ng + 2 * li + nb] : 0.f;
+  // The halo slots this lane loads, fixed for every tile: byte offset from the tile's
+  // origin pixel and column offset (-1..64); slots past the halo or on a padding slot get
+  // a column offset that fails the column test.  Rows above or below the field need no
+  // test: their offsets fall outside the member's buffer range, whose loads return zeros.
+  // With the last layer folded in (LASTQ), or more than ten loads per lane, the registers
+  // are needed elsewhere: the offsets are then recomputed for every tile.
+  constexpr bool PRE = !LASTQ && SPW <= 10;
+  auto slot_offsets = [&](int u, int& rel, int& gxo) {
+    int slot = (w + 4 * u) * 64 + lane;
+    if constexpr (!PRE) asm volatile("" : "+v"(slot));  // keep the recomputation in the tile loop
+    const int pix = slot / SLOT, q = slot - pix * SLOT;
+    const int yy = pix / HC, xx = pix - yy * HC;
+    const bool valid = w + 4 * u < INSTR && slot < TOTAL_SLOTS && q < CIN / 8;
+    rel = (((yy - 1) * m + (xx - 1)) * CIN + 8 * q) * 2;
+    gxo = valid ? xx - 1 : -(1 << 24);
   };
+  int rel[SPW], gxo[SPW];
+  if constexpr (PRE)
+#pragma unroll
+    for (int u = 0; u < SPW; ++u) slot_offsets(u, rel[u], gxo[u]);
+  const TileWalk walk(tiles);
+  const unsigned nrec = (unsigned)n * m * CIN * 2;
   for (int tile = walk.first; tile < walk.end; tile += walk.step) {
     const int ct = tile % col_tiles, rest = tile / col_tiles;
     const int rt = rest % row_tiles, i = rest / row_tiles;
     const int y0 = rt * TR, x0 = ct * TC;
     __syncthreads();  // every wave is done with the previous tile
-    issue_halo(tile, s_in);
+    {
+      // LDS-direct loads of the (TR+2) x 66 x CIN halo
+      const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(in + (size_t)i * n * m * CIN), (short)0, (int)nrec, 0x00020000);
+      const unsigned tb = (unsigned)(y0 * m + x0) * CIN * 2;
+#pragma unroll
+      for (int u = 0; u < SPW; ++u) {
+        const int ins = w + 4 * u;  // wave-uniform
+        if (ins < INSTR) {
+          if constexpr (!PRE) slot_offsets(u, rel[u], gxo[u]);
+          // modulo 2^32: a row above the field wraps to a huge offset, one below lands past nrec
+          const unsigned voff = (unsigned)(x0 + gxo[u]) < (unsigned)m ? tb + (unsigned)rel[u] : nrec;
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(s_in + ins * 512),
+                                                   16, (int)voff, 0, 0, 0);
+        }
+      }
+    }
     __builtin_amdgcn_s_waitcnt(0);  // the LDS-direct loads have landed (vmcnt)
     __syncthreads();
-    f32x4 acc[RW][4][2];
+    f32x4 acc[RW][4][2];  // start from the bias
 #pragma unroll
     for (int r = 0; r < RW; ++r)
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) acc[r][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < 2; ++nb) acc[r][mb][nb] = f32x4{bo[nb], bo[nb], bo[nb], bo[nb]};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int tap = ks / CG, c0 = (ks % CG) * 32 + 8 * lk;
@@ -1329,35 +1399,49 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
       __builtin_amdgcn_sched_barrier(0);  // one step's fragments live at a time
     }
     if constexpr (!LASTQ) {
+      with_activation(act, [&](auto actc) {
+        constexpr int ACT = decltype(actc)::value;
 #pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const int y = y0 + rg * RW + r;
-        if (y >= n) continue;
+        for (int r = 0; r < RW; ++r) {
+          const int y = y0 + rg * RW + r;
+          if (y >= n) continue;
+          unsigned* const orow =
+              reinterpret_cast<unsigned*>(out + (((size_t)i * n + y) * m + x0) * COUT + 32 * ng + 2 * li);
+          if (x0 + TC <= m) {
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+            for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
-            const int o = 32 * ng + 16 * nb + li;
+              for (int q = 0; q < 4; ++q)
+                orow[(16 * mb + 4 * lk + q) * (COUT / 2)] = pack_bf16x2(
+                    activate_lp_c<ACT>(acc[r][mb][0][q]), activate_lp_c<ACT>(acc[r][mb][1][q]));
+          } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int x = x0 + 16 * mb + 4 * lk + q;
-              if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = to_bf16(activate_lp(acc[r][mb][nb][q] + bo[nb], act));
-            }
+            for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int px = 16 * mb + 4 * lk + q;
+                if (x0 + px < m)
+                  orow[px * (COUT / 2)] = pack_bf16x2(activate_lp_c<ACT>(acc[r][mb][0][q]),
+                                                      activate_lp_c<ACT>(acc[r][mb][1][q]));
+              }
           }
-      }
+        }
+      });
     } else {
       __syncthreads();  // every wave is done with the halo tile
       bf16_t* const s_out = s_in;
+      with_activation(act, [&](auto actc) {
+        constexpr int ACT = decltype(actc)::value;
 #pragma unroll
-      for (int r = 0; r < RW; ++r)
+        for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
+          for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              s_out[((rg * RW + r) * TC + 16 * mb + 4 * lk + q) * OP + 32 * ng + 16 * nb + li] =
-                  to_bf16(activate_lp(acc[r][mb][nb][q] + bo[nb], act));
+              *reinterpret_cast<unsigned*>(s_out + ((rg * RW + r) * TC + 16 * mb + 4 * lk + q) * OP + 32 * ng +
+                                           2 * li) =
+                  pack_bf16x2(activate_lp_c<ACT>(acc[r][mb][0][q]), activate_lp_c<ACT>(acc[r][mb][1][q]));
+      });
       __syncthreads();
       fold_last_epilogue<COUT, TR, TC, OP, 256>(s_out, wl2, reinterpret_cast<float*>(out), N, n, m, i, y0, x0, tid);
     }
