@@ -6,6 +6,8 @@
 // is dropped: it cancels in the gain.  The products accumulate in FP64 and the
 // split-K partial sums are reduced in a fixed order (no atomics), so results are
 // deterministic.
+#include <atomic>
+
 #include "oic_internal.h"
 
 namespace oic {
@@ -606,6 +608,18 @@ void launch_center(hipStream_t s, Timer& t, const float* R, int rows, int NM, in
              mu, Rc);
 }
 
+// Compute units of the current device, read once per device.
+int device_cus() {
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int v = cus[dev].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 256;
+  cus[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
+
 void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const float* R, int p, const double* muR, double* part, size_t part_cap,
                   double* S, double scale, bool f32, const float* Rc) {
@@ -618,17 +632,30 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
     const int NBv = (nbk + ytiles - 1) / ytiles;
     const int xt = (Mtot + 16 * SV_W - 1) / (16 * SV_W);
     const int tiles = xt * ytiles;
-    // about two eight-wave workgroups per CU in flight; chunks are whole 64-column stages
-    // and the partials must fit the split buffer
-    int splits = (512 + tiles - 1) / tiles;
-    const int max_by_len = (NM + SV_MK - 1) / SV_MK;
-    if (splits > max_by_len) splits = max_by_len;
+    // K split: a workgroup's time is set by its chunk of K, and one eight-wave workgroup fits
+    // a CU (its LDS), so the launch takes ceil(tiles * splits / CUs) rounds of one chunk each.
+    // Choose the split count that minimises rounds x (chunk + two stages of fixed cost per
+    // workgroup); chunks are whole SV_MK-column stages and the partials must fit the split
+    // buffer.  (At 256x256, N = 512: 12 to 220 tiles over the horizon; "enough splits for
+    // two rounds" left a third round of a few workgroups on most steps.)
+    const int slots = device_cus();
+    int max_splits = (NM + SV_MK - 1) / SV_MK;
     const size_t by_cap = part_cap / ((size_t)Mtot * p);
-    if ((size_t)splits > by_cap) splits = (int)by_cap;
-    if (splits < 1) splits = 1;
-    int chunk = (NM + splits - 1) / splits;
-    chunk = (chunk + SV_MK - 1) / SV_MK * SV_MK;
-    splits = (NM + chunk - 1) / chunk;
+    if ((size_t)max_splits > by_cap) max_splits = (int)by_cap;
+    if (max_splits > 64) max_splits = 64;
+    int splits = 1, chunk = (NM + SV_MK - 1) / SV_MK * SV_MK;
+    long long best = -1;
+    for (int sp = 1; sp <= max_splits; ++sp) {
+      const int ch = ((NM + sp - 1) / sp + SV_MK - 1) / SV_MK * SV_MK;
+      const int eff = (NM + ch - 1) / ch;
+      const long long rounds = ((long long)tiles * eff + slots - 1) / slots;
+      const long long cost = rounds * (ch + 2 * SV_MK);
+      if (best < 0 || cost < best) {
+        best = cost;
+        splits = eff;
+        chunk = ch;
+      }
+    }
     const int all = tiles * splits;
     const dim3 grid((unsigned)((all + 7) / 8 * 8));  // whole groups of eight for the XCD order
     switch (NBv) {
@@ -675,6 +702,25 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   int chunk = (NM + splits - 1) / splits;
   chunk = (chunk + MK - 1) / MK * MK;
   splits = (NM + chunk - 1) / chunk;
+  if (tall) {
+    // one eight-wave workgroup per CU (its LDS): as for the FP32 product above, the split
+    // count that minimises rounds x (chunk + two stages of fixed cost) over the CUs
+    const int slots = device_cus();
+    int max_splits = max_by_len;
+    if ((size_t)max_splits > by_cap) max_splits = (int)by_cap;
+    if (max_splits > 64) max_splits = 64;
+    long long best = -1;
+    for (int sp = 1; sp <= max_splits; ++sp) {
+      const int ch = ((NM + sp - 1) / sp + MK - 1) / MK * MK;
+      const int eff = (NM + ch - 1) / ch;
+      const long long cost = (((long long)tiles * eff + slots - 1) / slots) * (ch + 2 * MK);
+      if (best < 0 || cost < best) {
+        best = cost;
+        splits = eff;
+        chunk = ch;
+      }
+    }
+  }
   const dim3 grid((unsigned)((Mtot + ma - 1) / ma), (unsigned)ytiles, (unsigned)splits);
   const bool vec = NM % 4 == 0;
 #define OIC_STATS_LAUNCH(KERN, NBV, WLV)                                                        \
