@@ -1363,29 +1363,34 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
     for (int u = 0; u < SPW; ++u) slot_offsets(u, rel[u], gxo[u]);
   const TileWalk walk(tiles);
   const unsigned nrec = (unsigned)n * m * CIN * 2;
+  // LDS-direct loads of tile tl's (TR+2) x 66 x CIN halo into s_in; the caller has made sure
+  // no wave still reads s_in
+  auto issue_halo = [&](int tl) {
+    const int ct = tl % col_tiles, rest = tl / col_tiles;
+    const int rt = rest % row_tiles, i = rest / row_tiles;
+    const int y0 = rt * TR, x0 = ct * TC;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)i * n * m * CIN), (short)0, (int)nrec, 0x00020000);
+    const unsigned tb = (unsigned)(y0 * m + x0) * CIN * 2;
+#pragma unroll
+    for (int u = 0; u < SPW; ++u) {
+      const int ins = w + 4 * u;  // wave-uniform
+      if (ins < INSTR) {
+        if constexpr (!PRE) slot_offsets(u, rel[u], gxo[u]);
+        // modulo 2^32: a row above the field wraps to a huge offset, one below lands past nrec
+        const unsigned voff = (unsigned)(x0 + gxo[u]) < (unsigned)m ? tb + (unsigned)rel[u] : nrec;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(s_in + ins * 512),
+                                                 16, (int)voff, 0, 0, 0);
+      }
+    }
+  };
+  if (walk.first < walk.end) issue_halo(walk.first);
   for (int tile = walk.first; tile < walk.end; tile += walk.step) {
     const int ct = tile % col_tiles, rest = tile / col_tiles;
     const int rt = rest % row_tiles, i = rest / row_tiles;
     const int y0 = rt * TR, x0 = ct * TC;
-    __syncthreads();  // every wave is done with the previous tile
-    {
-      // LDS-direct loads of the (TR+2) x 66 x CIN halo
-      const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(in + (size_t)i * n * m * CIN), (short)0, (int)nrec, 0x00020000);
-      const unsigned tb = (unsigned)(y0 * m + x0) * CIN * 2;
-#pragma unroll
-      for (int u = 0; u < SPW; ++u) {
-        const int ins = w + 4 * u;  // wave-uniform
-        if (ins < INSTR) {
-          if constexpr (!PRE) slot_offsets(u, rel[u], gxo[u]);
-          // modulo 2^32: a row above the field wraps to a huge offset, one below lands past nrec
-          const unsigned voff = (unsigned)(x0 + gxo[u]) < (unsigned)m ? tb + (unsigned)rel[u] : nrec;
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(s_in + ins * 512),
-                                                   16, (int)voff, 0, 0, 0);
-        }
-      }
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // the LDS-direct loads have landed (vmcnt)
+    const int next = tile + walk.step;
+    __builtin_amdgcn_s_waitcnt(0);  // this tile's LDS-direct loads have landed (vmcnt)
     __syncthreads();
     f32x4 acc[RW][4][2];  // start from the bias
 #pragma unroll
@@ -1413,6 +1418,9 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
       __builtin_amdgcn_sched_barrier(0);  // one step's fragments live at a time
     }
     if constexpr (!LASTQ) {
+      // the next tile's halo lands while this tile's epilogue (no LDS) runs
+      __syncthreads();  // every wave is done reading the halo
+      if (next < walk.end) issue_halo(next);
       with_activation(act, [&](auto actc) {
         constexpr int ACT = decltype(actc)::value;
 #pragma unroll
@@ -1458,6 +1466,8 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
       });
       __syncthreads();
       fold_last_epilogue<COUT, TR, TC, OP, 256>(s_out, wl2, reinterpret_cast<float*>(out), N, n, m, i, y0, x0, tid);
+      __syncthreads();  // every wave is done with the activated tile
+      if (next < walk.end) issue_halo(next);
     }
   }
 }
