@@ -1560,6 +1560,13 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
       }
     }
   };
+  // Output channel of column li in N-block nb: with an even number of N-blocks per wave they
+  // pair up (nb = 2h, 2h + 1) so that a lane holds two adjacent channels, 32 h + 2 li and
+  // + 1, of each of its pixels (one 4-byte LDS write); otherwise 16 nb + li.
+  constexpr bool PAIR = NBW % 2 == 0;
+  auto out_channel = [&](int nb) {
+    return PAIR ? ng * NBW * 16 + 32 * (nb >> 1) + 2 * li + (nb & 1) : (ng * NBW + nb) * 16 + li;
+  };
   float vmax = 0.f;
   int tile = blockIdx.x;
   if (tile < tiles) load_halo(tile);
@@ -1600,7 +1607,7 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
       i32x8 b[NBW];
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) {
-        const uint8_t* src = s_w + ((ng * NBW + nb) * 16 + li) * KDP + k0;
+        const uint8_t* src = s_w + out_channel(nb) * KDP + k0;
         const u32x4 v0 = *(const u32x4*)src, v1 = *(const u32x4*)(src + 16);
         b[nb] = i32x8{(int)v0[0], (int)v0[1], (int)v0[2], (int)v0[3], (int)v1[0], (int)v1[1], (int)v1[2],
                       (int)v1[3]};
@@ -1625,24 +1632,49 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_fp8(int N, int n, int m,
     // [pixel][channel], then 16-byte NHWC stores; the largest |output| of the valid
     // pixels goes to amax_out once the block is done.
     __syncthreads();  // every wave is done with the halo tile
+    {
+      float sc[NBW], bo[NBW];
 #pragma unroll
-    for (int rw = 0; rw < RPW; ++rw) {
-      const int ty = w + 4 * rw;
+      for (int nb = 0; nb < NBW; ++nb) {
+        const int o = out_channel(nb);
+        sc[nb] = sa * ws[o];
+        bo[nb] = bias ? bias[o] : 0.f;
+      }
+      const bool full = y0 + TR <= n && x0 + TC <= m;
+      with_activation(act, [&](auto actc) {
+        constexpr int ACT = decltype(actc)::value;
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
+        for (int rw = 0; rw < RPW; ++rw) {
+          const int ty = w + 4 * rw;
 #pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) {
-          const int o = (ng * NBW + nb) * 16 + li;
-          const float sc = sa * ws[o];
-          const float bo = bias ? bias[o] : 0.f;
+          for (int mb = 0; mb < 4; ++mb) {
+            if constexpr (PAIR) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int tx = mb * 16 + 4 * lk + r;
-            const float v = activate_lp(fmaf(acc[rw][mb][nb][r], sc, bo), act);
-            s_out[(ty * TC + tx) * OP + o] = to_bf16(v);
-            if (y0 + ty < n && x0 + tx < m) vmax = fmaxf(vmax, fabsf(v));
+              for (int h = 0; h < NBW / 2; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int tx = mb * 16 + 4 * lk + r;
+                  const float v0 = activate_lp_c<ACT>(fmaf(acc[rw][mb][2 * h][r], sc[2 * h], bo[2 * h]));
+                  const float v1 =
+                      activate_lp_c<ACT>(fmaf(acc[rw][mb][2 * h + 1][r], sc[2 * h + 1], bo[2 * h + 1]));
+                  *reinterpret_cast<unsigned*>(s_out + (ty * TC + tx) * OP + out_channel(2 * h)) =
+                      pack_bf16x2(v0, v1);
+                  if (full || (y0 + ty < n && x0 + tx < m)) vmax = fmaxf(vmax, fmaxf(fabsf(v0), fabsf(v1)));
+                }
+            } else {
+#pragma unroll
+              for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int tx = mb * 16 + 4 * lk + r;
+                  const float v = activate_lp_c<ACT>(fmaf(acc[rw][mb][nb][r], sc[nb], bo[nb]));
+                  s_out[(ty * TC + tx) * OP + out_channel(nb)] = to_bf16(v);
+                  if (full || (y0 + ty < n && x0 + tx < m)) vmax = fmaxf(vmax, fabsf(v));
+                }
+            }
           }
         }
+      });
     }
     __syncthreads();
     if constexpr (LASTQ) {
