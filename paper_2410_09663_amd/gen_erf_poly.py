@@ -12,7 +12,8 @@ argument scaling and the factor 1/2 folded into the coefficients:
 twelve instructions per value and no transcendental ones.  Prints q as C++ float literals,
 the maximum absolute error of the erf fit on a fine grid (4.9e-5, well below BF16's
 rounding of the activations, 2^-9 relative) and that of the GELU evaluated in FP32 on
-[-10, 10] (3.5e-4, at |x| = 10: |x|/2 times the erf error).
+[-10, 10] (3.5e-4, at |x| = 10: |x|/2 times the erf error plus the FP32 rounding of the
+Horner sum, 3.5e-5 relative).
 
 Usage: python -m paper_2410_09663_amd.gen_erf_poly
 """

@@ -8,6 +8,7 @@ max |gpu - oracle| / max |oracle|):
     a 1-ulp FP64 difference in log/cos may flip an FP32 rounding, so at most
     1 in 10^5 values may differ, by 1 ulp).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -479,3 +480,34 @@ def test_graph_recaptured_when_bias_changes():
     assert_parity(graph[0][0], ref_b.U_mean, TOL_FP32, "biased U")
     assert_parity(graph[1][0], oracle_solve(prob, Xref, z).U_mean, TOL_FP32, "unbiased U")
     assert np.array_equal(graph[0][0], graph[2][0])
+
+
+@pytest.mark.parametrize("shape", ["fp32_tanh", "bf16_fold64"])
+def test_new_weights_in_the_same_buffers_reach_a_replayed_solve(shape):
+    """oic_set_weights with a new surrogate of the same shape and no change of biases keeps
+    the captured solve (its buffers are rewritten in place): graph replays give the eager
+    results bitwise for both surrogates, in both orders, and the FP32 replays match the
+    oracle with the weights of their own step. The BF16 case covers the re-laid-out BF16
+    weights and the folded last layer's BF16 pair."""
+    if shape == "fp32_tanh":
+        p = tiny(n=8, m=7, l=2, channels=(2, 6, 1), N=9, H=3)
+    else:
+        p = dataclasses.replace(wl.small_preset(n=12, m=70, l=3, channels=(2, 64, 64, 64, 1),
+                                                activation=wl.ACT_GELU, N=6, H=2), precision=wl.PREC_BF16)
+    prob = wl.make_problem(p)
+    W2 = wl.he_weights(p.channels, seed=1234)
+    B2 = wl.lift_matrix(p.n, p.l, seed=4321)
+    first = lambda c: c.set_weights(prob.B, prob.weights)
+    second = lambda c: c.set_weights(B2, W2)
+    QR = (prob.Q, prob.R)
+    eager, graph = _graph_vs_eager(prob, p, [(first, QR), (second, QR), (first, QR)])
+    for k, ((Ue, Xe), (Ug, Xg)) in enumerate(zip(eager, graph)):
+        assert np.array_equal(Ue, Ug) and np.array_equal(Xe, Xg), k
+    assert np.array_equal(graph[0][0], graph[2][0])
+    assert not np.array_equal(graph[0][0], graph[1][0])
+    if shape == "fp32_tanh":
+        z = philox.solve_noise(3, p.n, p.m, p.l, p.N, p.H)
+        Xref = wl.reference_window(p, 0)
+        ref2 = enks.solve(B2, W2, p.activation, prob.X0, Xref, prob.Q, prob.Q, prob.R, p.N, p.H, *z)
+        assert_parity(graph[1][0], ref2.U_mean, TOL_FP32, "second surrogate U")
+        assert_parity(graph[0][0], oracle_solve(prob, Xref, z).U_mean, TOL_FP32, "first surrogate U")
