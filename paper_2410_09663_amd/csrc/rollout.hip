@@ -61,8 +61,9 @@ __device__ __forceinline__ float poly_gelu(float x) {
 }
 
 // The activation of the layers whose outputs are stored in BF16 (the BF16 and FP8
-// rollouts): GELU through poly_gelu, whose error (|x|/2 times the erf fit's) is far below
-// BF16's rounding of the stored value (2^-9 relative); tanh as in activate.
+// rollouts): GELU through poly_gelu, whose error (|x|/2 times the erf fit's, plus the FP32
+// rounding of the Horner sum: at most 3.5e-5 relative) is far below BF16's rounding of the
+// stored value (2^-9 relative); tanh as in activate.
 __device__ __forceinline__ float activate_lp(float v, int act) {
   if (act == OIC_ACT_TANH) return fast_tanh(v);
   return poly_gelu(v);
@@ -1348,16 +1349,18 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
   // With the last layer folded in (LASTQ), or more than ten loads per lane, the registers
   // are needed elsewhere: the offsets are then recomputed for every tile.
   constexpr bool PRE = !LASTQ && SPW <= 10;
-  auto slot_offsets = [&](int u, int& rel, int& gxo) {
+  auto slot_offsets = [&](int u, unsigned& rel, int& gxo) {
     int slot = (w + 4 * u) * 64 + lane;
     if constexpr (!PRE) asm volatile("" : "+v"(slot));  // keep the recomputation in the tile loop
     const int pix = slot / SLOT, q = slot - pix * SLOT;
     const int yy = pix / HC, xx = pix - yy * HC;
     const bool valid = w + 4 * u < INSTR && slot < TOTAL_SLOTS && q < CIN / 8;
-    rel = (((yy - 1) * m + (xx - 1)) * CIN + 8 * q) * 2;
+    // modulo 2^32 (negative for the row above the tile)
+    rel = ((unsigned)((yy - 1) * m + (xx - 1)) * CIN + 8u * q) * 2u;
     gxo = valid ? xx - 1 : -(1 << 24);
   };
-  int rel[SPW], gxo[SPW];
+  unsigned rel[SPW];
+  int gxo[SPW];
   if constexpr (PRE)
 #pragma unroll
     for (int u = 0; u < SPW; ++u) slot_offsets(u, rel[u], gxo[u]);
@@ -1378,7 +1381,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, cons
       if (ins < INSTR) {
         if constexpr (!PRE) slot_offsets(u, rel[u], gxo[u]);
         // modulo 2^32: a row above the field wraps to a huge offset, one below lands past nrec
-        const unsigned voff = (unsigned)(x0 + gxo[u]) < (unsigned)m ? tb + (unsigned)rel[u] : nrec;
+        const unsigned voff = (unsigned)(x0 + gxo[u]) < (unsigned)m ? tb + rel[u] : nrec;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(s_in + ins * 512),
                                                  16, (int)voff, 0, 0, 0);
       }
