@@ -634,12 +634,14 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
       launch_center(s, h->timer, h->Y, p, (int)NM, m, h->muY, h->act[0]);
       Yc = h->act[0];
     }
-    launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->part_cap, h->Syy, f32_stats, Yc);
+    // the BF16 / FP8 modes take the FP32 products as three BF16 products of split operands
+    const bool b3 = f32_stats;
+    launch_stats(s, h->timer, d, h->traj, 0, p, h->Y, h->muY, h->part, h->part_cap, h->Syy, f32_stats, Yc, b3);
     hipEventRecord(h->ev_fork, s);
     hipStreamWaitEvent(h->side, h->ev_fork, 0);
     launch_chol(h->side, h->timer, p, h->Syy, h->Lwork, h->Sinv, h->flag);
     hipEventRecord(h->ev_join, h->side);
-    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S, true, Yc);
+    launch_stats(s, h->timer, d, h->traj, Ma, 0, h->Y, h->muY, h->part, h->part_cap, h->S, true, Yc, b3);
     hipStreamWaitEvent(s, h->ev_join, 0);
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
     launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);

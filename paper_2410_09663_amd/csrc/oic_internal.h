@@ -213,10 +213,12 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
 // f32: the products on the FP32 matrix cores (right operand rounded to FP32 after
 // centring, FP32 sums over at most 256 columns, FP64 beyond), for the mixed-precision modes.
 // Yc: Ybar already centred (FP32, p x N*m, from launch_center) for the FP32-matrix-core
-// products, or null to centre inside the product kernel.
+// products, or null to centre inside the product kernel.  b3 (with f32 and Yc): the FP32
+// products as three BF16 matrix-core products of split operands (about 2^-16 relative
+// per product), for the BF16 and FP8 modes.
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32 = false,
-                  const float* Yc = nullptr);
+                  const float* Yc = nullptr, bool b3 = false);
 // Rc[b][c] = R[b][c] - mu[b][c mod m] (FP64 subtraction, FP32 result) for rows x NM floats
 // (rows * NM divisible by 4).
 void launch_center(hipStream_t s, Timer& t, const float* R, int rows, int NM, int m, const double* mu,
@@ -226,7 +228,7 @@ void launch_center(hipStream_t s, Timer& t, const float* R, int rows, int NM, in
 // with leading dimension nr.  part_cap must hold at least (Ma + ny) * nr doubles.
 void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const float* R, int nr, const double* muR, double* part, size_t part_cap,
-                  double* S, double scale, bool f32 = false, const float* Rc = nullptr);
+                  double* S, double scale, bool f32 = false, const float* Rc = nullptr, bool b3 = false);
 // FP64 Cholesky factor of the p x p Syy; flag is set to 1 when a pivot is not positive
 // and finite.  p <= 90 (one workgroup, LDS): Sinv = (Sigma^Y)^{-1}, Syy untouched.
 // p > 90 (blocked, chip-wide): Syy is overwritten by L in its lower triangle and

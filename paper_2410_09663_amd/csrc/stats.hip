@@ -511,6 +511,142 @@ __global__ __launch_bounds__(64 * SV_W) void k_stats_v4(Dims d, const float* __r
     }
 }
 
+// Split of FP32 values into BF16 pairs v ~ hi + lo (hi = v rounded to nearest BF16, lo =
+// the rounded remainder v - hi, which FP32 holds exactly): the pair keeps 16 significant
+// bits, and hi_a hi_b + hi_a lo_b + lo_a hi_b misses a product by about 2^-16 of it (the
+// dropped lo_a lo_b and the remainders below lo).
+typedef __bf16 bf16x8s __attribute__((ext_vector_type(8)));
+typedef float f32x2s __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2s __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4s __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2s __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split2(float v0, float v1, unsigned& hi, unsigned& lo) {
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2s{v0, v1}, bf16x2s));
+  const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2s{v0 - h0, v1 - h1}, bf16x2s));
+}
+
+// The FP32 statistics of the BF16 and FP8 modes with the products split into three BF16
+// matrix-core products (v_mfma_f32_16x16x32_bf16: hi hi + hi lo + lo hi, FP32 accumulation,
+// relative error about 2^-16 per product, far below those modes' rollout error), at a
+// sixth of the FP32 matrix-core cycles.  Same tiling, XCD-aware order, FP64 fold every 256
+// columns and split-K partials as k_stats_v4.  K steps of 32 columns: lane (i, g) reads
+// columns 8g..8g+7 of its left row (two 16-byte loads) and splits them in registers; the
+// centred right tile is split once while staged and sits in LDS as two BF16 planes (hi,
+// lo), from which a lane reads the same 8 columns of a right row as one 16-byte load each.
+constexpr int SB_CP = SV_MK + 8;  // right-plane row stride in LDS (BF16): 272 bytes
+template <int NB>
+__global__ __launch_bounds__(64 * SV_W) void k_stats_b3(Dims d, const float* __restrict__ traj, int Ma, int ny,
+                                                        const float* __restrict__ Y, const float* __restrict__ Rc,
+                                                        int p, int chunk, int xt, int ytiles, int tiles,
+                                                        double* __restrict__ part) {
+  constexpr int RB = NB * 16, NT = 64 * SV_W;
+  const int G = gridDim.x;
+  const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+  if (L >= tiles) return;
+  const int ty = L % ytiles, tx = (L / ytiles) % xt, tz = L / (ytiles * xt);
+  constexpr int GR = SV_MK / 32;             // 32-column K steps per stage
+  constexpr int BQ = RB * SV_MK / 4;         // float4 of the right tile
+  constexpr int BV = (BQ + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][2][RB * SB_CP];  // [stage][hi, lo]
+  const int NM = (int)d.NM();
+  const int Mtot = Ma + ny;
+  const int a0 = tx * (16 * SV_W);
+  const int b0 = ty * RB;
+  const int c_begin = tz * chunk;
+  const int c_end = min(c_begin + chunk, NM);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int arow = a0 + 16 * w + li;
+  const float* asrc = arow < Mtot ? (arow < Ma ? traj + (size_t)arow * NM : Y + (size_t)(arow - Ma) * NM) : nullptr;
+  f32x4v acc[NB];
+  f64x4 tot[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    tot[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  f32x4v an[GR][2], bn[BV];
+  auto load_stage = [&](int c0) {
+#pragma unroll
+    for (int g = 0; g < GR; ++g)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = c0 + 32 * g + 8 * lk + 4 * h;
+        an[g][h] = (asrc && c < c_end) ? *(const f32x4v*)(asrc + c) : f32x4v{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + NT * u;
+      const int r = e / (SV_MK / 4), q = e % (SV_MK / 4);
+      const int b = b0 + r, c = c0 + 4 * q;
+      bn[u] = (e < BQ && b < p && c < c_end) ? *(const f32x4v*)(Rc + (size_t)b * NM + c)
+                                             : f32x4v{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  if (c_begin < c_end) load_stage(c_begin);
+  int stage = 0;
+  for (int c0 = c_begin; c0 < c_end; c0 += SV_MK, ++stage) {
+    __bf16* const sh = sB[stage & 1][0];
+    __bf16* const sl = sB[stage & 1][1];
+    // this stage's left fragments, split
+    bf16x8s ah[GR], al[GR];
+#pragma unroll
+    for (int g = 0; g < GR; ++g) {
+      unsigned h[4], lo[4];
+      split2(an[g][0][0], an[g][0][1], h[0], lo[0]);
+      split2(an[g][0][2], an[g][0][3], h[1], lo[1]);
+      split2(an[g][1][0], an[g][1][1], h[2], lo[2]);
+      split2(an[g][1][2], an[g][1][3], h[3], lo[3]);
+      ah[g] = __builtin_bit_cast(bf16x8s, u32x4s{h[0], h[1], h[2], h[3]});
+      al[g] = __builtin_bit_cast(bf16x8s, u32x4s{lo[0], lo[1], lo[2], lo[3]});
+    }
+    // the right tile, split into its two planes (zero past the chunk and past p already)
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int e = tid + NT * u;
+      if (e >= BQ) continue;
+      const int r = e / (SV_MK / 4), q = e % (SV_MK / 4);
+      unsigned h[2], lo[2];
+      split2(bn[u][0], bn[u][1], h[0], lo[0]);
+      split2(bn[u][2], bn[u][3], h[1], lo[1]);
+      *(u32x2s*)(sh + r * SB_CP + 4 * q) = u32x2s{h[0], h[1]};
+      *(u32x2s*)(sl + r * SB_CP + 4 * q) = u32x2s{lo[0], lo[1]};
+    }
+    __syncthreads();  // this stage's right planes are in LDS; the other buffer is free again
+    if (c0 + SV_MK < c_end) load_stage(c0 + SV_MK);  // the next stage's operands, in flight meanwhile
+#pragma unroll
+    for (int g = 0; g < GR; ++g)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int off = (16 * nb + li) * SB_CP + 32 * g + 8 * lk;
+        const bf16x8s bh = *(const bf16x8s*)(sh + off);
+        const bf16x8s bl = *(const bf16x8s*)(sl + off);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[g], bh, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bl, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[g], bh, acc[nb], 0, 0, 0);
+      }
+    if ((stage & 1) == 1) {  // fold the FP32 sums of the last 256 columns into FP64
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tot[nb][r] += (double)acc[nb][r];
+        acc[nb] = f32x4v{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+  double* out = part + (size_t)tz * Mtot * p;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = a0 + 16 * w + 4 * lk + r;
+      const int b = b0 + nb * 16 + li;
+      if (a < Mtot && b < p) out[(size_t)a * p + b] = tot[nb][r] + (double)acc[nb][r];
+    }
+}
+
 // Rc[b][c] = R[b][c] - mu[b][c mod m], the subtraction in FP64, rounded to FP32: the
 // centred right operand of the FP32 statistics, formed once per horizon step instead of
 // in every workgroup's staging (there its FP64 mean loads sat between each stage's loads
@@ -622,7 +758,7 @@ int device_cus() {
 
 void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const float* R, int p, const double* muR, double* part, size_t part_cap,
-                  double* S, double scale, bool f32, const float* Rc) {
+                  double* S, double scale, bool f32, const float* Rc, bool b3) {
   const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
   if (f32 && NM % 4 == 0) {
@@ -661,7 +797,10 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
     switch (NBv) {
 #define OIC_SV_CASE(NBV)                                                                                 \
   case NBV:                                                                                              \
-    if (Rc)                                                                                              \
+    if (Rc && b3)                                                                                        \
+      OIC_LAUNCH(t, KC_STATS, s, k_stats_b3<NBV>, grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, Rc, p, chunk, \
+                 xt, ytiles, all, part);                                                                 \
+    else if (Rc)                                                                                         \
       OIC_LAUNCH(t, KC_STATS, s, (k_stats_v4<NBV, true>), grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, Rc, p, \
                  muR, chunk, xt, ytiles, all, part);                                                     \
     else                                                                                                 \
@@ -759,8 +898,8 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 
 void launch_stats(hipStream_t s, Timer& t, const Dims& d, const float* traj, int Ma, int ny,
                   const float* Y, const double* muY, double* part, size_t part_cap, double* S, bool f32,
-                  const float* Yc) {
-  launch_cross(s, t, d, traj, Ma, ny, Y, Y, d.p(), muY, part, part_cap, S, 1.0, f32, Yc);
+                  const float* Yc, bool b3) {
+  launch_cross(s, t, d, traj, Ma, ny, Y, Y, d.p(), muY, part, part_cap, S, 1.0, f32, Yc, b3);
 }
 
 }  // namespace oic
