@@ -243,8 +243,9 @@ bool chol_blocked(int p);
 void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv,
                  const double* L, const double* Linv, float* K, const int* flag);
 // Analysis of the first Ma trajectory rows (in place).
+// b3: the products as three BF16 matrix-core products of split operands (BF16 / FP8 modes).
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
-                   const float* Y, const float* xref_t);
+                   const float* Y, const float* xref_t, bool b3 = false);
 void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,
                     float* Xout, float* Uprev);
 

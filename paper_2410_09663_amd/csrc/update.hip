@@ -287,6 +287,122 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_update_strip(Dims d, float
   }
 }
 
+// Split of FP32 values into BF16 pairs v ~ hi + lo (hi = v rounded to nearest BF16, lo =
+// the rounded remainder, which FP32 holds exactly): 16 significant bits per pair.
+typedef __bf16 bf16x8u __attribute__((ext_vector_type(8)));
+typedef float f32x2u __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2u __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void split2u(float v0, float v1, unsigned& hi, unsigned& lo) {
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2u{v0, v1}, bf16x2u));
+  const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2u{v0 - h0, v1 - h1}, bf16x2u));
+}
+
+// k_update_strip for the BF16 and FP8 modes: the products K E as three BF16 matrix-core
+// products of split operands (v_mfma_f32_16x16x32_bf16: hi hi + hi lo + lo hi, relative
+// error about 2^-16 per product, FP32 accumulation), at a sixth of the FP32 matrix-core
+// cycles.  The strip's innovation tile is split once into two BF16 planes E^T[c][b] (hi,
+// lo; row stride P16 + 8 so that the 16-byte reads of 16 consecutive columns fall in
+// distinct bank groups); a wave splits its block's gain rows in registers, lane (i, g)
+// taking K[a0 + i][32 s + 8 g .. + 7] for K step s against the 16-byte reads of the same
+// eight rows b of E^T.  Trajectory tile read once, written once, as in k_update_strip.
+template <int P16>
+__global__ __launch_bounds__(64 * kStripWaves) void k_update_strip_b3(Dims d, float* __restrict__ traj, int Ma,
+                                                                  const float* __restrict__ K,
+                                                                  const float* __restrict__ Y,
+                                                                  const float* __restrict__ xref) {
+  constexpr int NT = 64 * kStripWaves;
+  constexpr int EP = P16 + 8;  // BF16 elements per column of a plane
+  constexpr int S = P16 / 32;
+  static_assert(P16 % 32 == 0, "32-row K steps");
+  __shared__ __attribute__((aligned(16))) __bf16 sE[2][UC * EP];  // [hi, lo]
+  const int NM = (int)d.NM();
+  const int m = d.m, n = d.n, p = d.p();
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int strips = (NM + UC - 1) / UC;
+  const int row_blocks = (Ma + 15) / 16;
+  for (int strip = blockIdx.x; strip < strips; strip += gridDim.x) {
+    const int c0 = strip * UC;
+    __syncthreads();  // every wave is done with the previous strip's tile
+    for (int e = tid; e < (P16 / 2) * UC; e += NT) {
+      const int b = 2 * (e / UC), cl = e % UC;
+      const int c = c0 + cl;
+      float v[2] = {0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (b + k < p && c < NM)
+          v[k] = (b + k < n ? xref[(size_t)(b + k) * m + c % m] : 0.f) - Y[(size_t)(b + k) * NM + c];
+      unsigned hi, lo;
+      split2u(v[0], v[1], hi, lo);
+      *(unsigned*)(sE[0] + cl * EP + b) = hi;
+      *(unsigned*)(sE[1] + cl * EP + b) = lo;
+    }
+    __syncthreads();
+    for (int rb = w; rb < row_blocks; rb += kStripWaves) {
+      const int a0 = rb * 16;
+      // this lane's gain values, split: row a0 + li, columns 32 s + 8 lk .. + 7
+      bf16x8u kh[S], kl[S];
+      const int ka = a0 + li;
+#pragma unroll
+      for (int st = 0; st < S; ++st) {
+        float kv[8];
+        const int b = 32 * st + 8 * lk;
+        if ((p & 3) == 0) {  // 16-byte aligned gain rows
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            f32x4u v = f32x4u{0.f, 0.f, 0.f, 0.f};
+            if (ka < Ma && b + 4 * h < p) v = *(const f32x4u*)(K + (size_t)ka * p + b + 4 * h);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) kv[4 * h + j] = v[j];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) kv[j] = (ka < Ma && b + j < p) ? K[(size_t)ka * p + b + j] : 0.f;
+        }
+        unsigned h[4], lo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) split2u(kv[2 * q], kv[2 * q + 1], h[q], lo[q]);
+        kh[st] = __builtin_bit_cast(bf16x8u, u32x4u{h[0], h[1], h[2], h[3]});
+        kl[st] = __builtin_bit_cast(bf16x8u, u32x4u{lo[0], lo[1], lo[2], lo[3]});
+      }
+      float old[4][4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = a0 + 4 * lk + r, c = c0 + 16 * nb + li;
+          old[nb][r] = (a < Ma && c < NM) ? traj[(size_t)a * NM + c] : 0.f;
+        }
+      f32x4u acc[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4u{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < S; ++st)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const int off = (16 * nb + li) * EP + 32 * st + 8 * lk;
+          const bf16x8u eh = *(const bf16x8u*)(sE[0] + off);
+          const bf16x8u el = *(const bf16x8u*)(sE[1] + off);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl[st], eh, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh[st], el, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh[st], eh, acc[nb], 0, 0, 0);
+          // one step's LDS reads at a time beside its MFMAs
+          if (nb == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = a0 + 4 * lk + r, c = c0 + 16 * nb + li;
+          if (a < Ma && c < NM) traj[(size_t)a * NM + c] = old[nb][r] + acc[nb][r];
+        }
+    }
+  }
+}
+
 // Smoothed means of every slice -> U_out (H+1, l, m), X_out (H+1, n, m) and U_hat_k.
 __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restrict__ Uout,
                           float* __restrict__ Xout, float* __restrict__ Uprev) {
@@ -310,7 +426,7 @@ __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restric
 }  // namespace
 
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
-                   const float* Y, const float* xref_t) {
+                   const float* Y, const float* xref_t, bool b3) {
   const unsigned col_tiles = (unsigned)((d.NM() + UC - 1) / UC);
   if (d.p() <= PB) {
     constexpr int WR = kUpdWavesRows;
@@ -326,6 +442,13 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
   const unsigned strips = col_tiles < 256 ? col_tiles : 256;
 #define OIC_STRIP_CASE(P16V)                                                                            \
   if (d.p() <= P16V) {                                                                                  \
+    if constexpr (P16V <= 448) { /* beyond, the split gain rows would not fit the registers */     \
+      if (b3) {                                                                                         \
+        OIC_LAUNCH(t, KC_UPDATE, s, k_update_strip_b3<P16V>, dim3(strips), dim3(64 * kStripWaves), 0, d, \
+                   traj, Ma, K, Y, xref_t);                                                             \
+        return;                                                                                         \
+      }                                                                                                 \
+    }                                                                                                   \
     OIC_LAUNCH(t, KC_UPDATE, s, k_update_strip<P16V>, dim3(strips), dim3(64 * kStripWaves), 0, d, traj, Ma, K, \
                Y, xref_t);                                                                              \
     return;                                                                                             \
