@@ -645,7 +645,10 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     hipStreamWaitEvent(s, h->ev_join, 0);
     // Eq. (14b): gain, then line 10: analysis of every stored slice.
     launch_gain(s, h->timer, p, Ma, h->S, h->Sinv, h->Syy, h->Lwork, h->K, h->flag);
-    launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m, b3);
+    // (the split-K partials of the statistics are consumed by now: their buffer takes the
+    // split gain of the BF16 / FP8 update)
+    launch_update(s, h->timer, d, h->traj, Ma, h->K, h->Y, dRef + (size_t)t * n * m, b3, h->part,
+                  h->part_cap * sizeof(double));
     // Line 11 / Eq. (14c): covariance after the analysis (optional)
     if (h->want_cov) enqueue_cov(h, d, Ma, h->cov_post + cov_offset(rr, t));
   }

@@ -243,9 +243,12 @@ bool chol_blocked(int p);
 void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, const double* Sinv,
                  const double* L, const double* Linv, float* K, const int* flag);
 // Analysis of the first Ma trajectory rows (in place).
-// b3: the products as three BF16 matrix-core products of split operands (BF16 / FP8 modes).
+// b3: the products as three BF16 matrix-core products of split operands (BF16 / FP8 modes);
+// scratch (scratch_bytes, free during the call) then receives the split gain, or the update
+// splits the gain rows itself where scratch is null or too small.
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
-                   const float* Y, const float* xref_t, bool b3 = false);
+                   const float* Y, const float* xref_t, bool b3 = false, void* scratch = nullptr,
+                   size_t scratch_bytes = 0);
 void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,
                     float* Xout, float* Uprev);
 

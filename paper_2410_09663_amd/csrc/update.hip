@@ -299,6 +299,25 @@ __device__ __forceinline__ void split2u(float v0, float v1, unsigned& hi, unsign
   lo = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2u{v0 - h0, v1 - h1}, bf16x2u));
 }
 
+// The gain split once per horizon step for k_update_strip_b3: planes hi and lo of
+// rows16 x P16 BF16 values (rows16 = Ma rounded up to 16), zeros past Ma and p.  One
+// thread per 8 consecutive values of a row.
+__global__ void k_split_gain(const float* __restrict__ K, int Ma, int p, int rows16, int P16,
+                             __bf16* __restrict__ Khl) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int groups = P16 / 8;
+  if (e >= (long long)rows16 * groups) return;
+  const int a = (int)(e / groups), b = (int)(e % groups) * 8;
+  float v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (a < Ma && b + j < p) ? K[(size_t)a * p + b + j] : 0.f;
+  unsigned h[4], lo[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) split2u(v[2 * q], v[2 * q + 1], h[q], lo[q]);
+  *(u32x4u*)(Khl + (size_t)a * P16 + b) = u32x4u{h[0], h[1], h[2], h[3]};
+  *(u32x4u*)(Khl + (size_t)rows16 * P16 + (size_t)a * P16 + b) = u32x4u{lo[0], lo[1], lo[2], lo[3]};
+}
+
 // k_update_strip for the BF16 and FP8 modes: the products K E as three BF16 matrix-core
 // products of split operands (v_mfma_f32_16x16x32_bf16: hi hi + hi lo + lo hi, relative
 // error about 2^-16 per product, FP32 accumulation), at a sixth of the FP32 matrix-core
@@ -307,9 +326,12 @@ __device__ __forceinline__ void split2u(float v0, float v1, unsigned& hi, unsign
 // distinct bank groups); a wave splits its block's gain rows in registers, lane (i, g)
 // taking K[a0 + i][32 s + 8 g .. + 7] for K step s against the 16-byte reads of the same
 // eight rows b of E^T.  Trajectory tile read once, written once, as in k_update_strip.
+// Khl: the gain already split (k_split_gain: planes hi and lo, rows padded to whole 16-row
+// blocks and P16 columns, zeros past Ma and p), or null to split each block's rows here.
 template <int P16>
 __global__ __launch_bounds__(64 * kStripWaves) void k_update_strip_b3(Dims d, float* __restrict__ traj, int Ma,
                                                                   const float* __restrict__ K,
+                                                                  const __bf16* __restrict__ Khl,
                                                                   const float* __restrict__ Y,
                                                                   const float* __restrict__ xref) {
   constexpr int NT = 64 * kStripWaves;
@@ -346,6 +368,14 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_update_strip_b3(Dims d, fl
       // this lane's gain values, split: row a0 + li, columns 32 s + 8 lk .. + 7
       bf16x8u kh[S], kl[S];
       const int ka = a0 + li;
+      if (Khl) {
+        const size_t plane = (size_t)row_blocks * 16 * P16;
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+          kh[st] = *(const bf16x8u*)(Khl + (size_t)ka * P16 + 32 * st + 8 * lk);
+          kl[st] = *(const bf16x8u*)(Khl + plane + (size_t)ka * P16 + 32 * st + 8 * lk);
+        }
+      } else {
 #pragma unroll
       for (int st = 0; st < S; ++st) {
         float kv[8];
@@ -367,6 +397,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_update_strip_b3(Dims d, fl
         for (int q = 0; q < 4; ++q) split2u(kv[2 * q], kv[2 * q + 1], h[q], lo[q]);
         kh[st] = __builtin_bit_cast(bf16x8u, u32x4u{h[0], h[1], h[2], h[3]});
         kl[st] = __builtin_bit_cast(bf16x8u, u32x4u{lo[0], lo[1], lo[2], lo[3]});
+      }
       }
       float old[4][4];
 #pragma unroll
@@ -426,7 +457,7 @@ __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restric
 }  // namespace
 
 void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, const float* K,
-                   const float* Y, const float* xref_t, bool b3) {
+                   const float* Y, const float* xref_t, bool b3, void* scratch, size_t scratch_bytes) {
   const unsigned col_tiles = (unsigned)((d.NM() + UC - 1) / UC);
   if (d.p() <= PB) {
     constexpr int WR = kUpdWavesRows;
@@ -444,8 +475,16 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
   if (d.p() <= P16V) {                                                                                  \
     if constexpr (P16V <= 448) { /* beyond, the split gain rows would not fit the registers */     \
       if (b3) {                                                                                         \
+        const int rows16 = (Ma + 15) / 16 * 16;                                                         \
+        __bf16* khl = nullptr;                                                                          \
+        if (scratch && (size_t)2 * rows16 * P16V * 2 <= scratch_bytes) {                                \
+          khl = reinterpret_cast<__bf16*>(scratch);                                                     \
+          const long long items = (long long)rows16 * (P16V / 8);                                      \
+          OIC_LAUNCH(t, KC_UPDATE, s, k_split_gain, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, K, Ma, \
+                     d.p(), rows16, P16V, khl);                                                         \
+        }                                                                                               \
         OIC_LAUNCH(t, KC_UPDATE, s, k_update_strip_b3<P16V>, dim3(strips), dim3(64 * kStripWaves), 0, d, \
-                   traj, Ma, K, Y, xref_t);                                                             \
+                   traj, Ma, K, khl, Y, xref_t);                                                        \
         return;                                                                                         \
       }                                                                                                 \
     }                                                                                                   \
