@@ -1,5 +1,7 @@
-"""BF16 rollout (BF16 activations and weights on MFMA, FP32 accumulation; statistics FP64,
-gain FP64): errors against the FP64 oracle and against the FP32 GPU path.
+"""BF16 rollout (BF16 activations and weights on MFMA, FP32 accumulation; statistics and
+update as three BF16 matrix-core products of split operands, about 2^-16 per product, with
+FP32 sums folded into FP64; gain FP64): errors against the FP64 oracle and against the FP32
+GPU path.
 
 Bars: 2e-2 on the smoothed control mean and on the state mean (normwise, and element-wise
 relative to the largest magnitude), and 2% on the closed-loop tracking cost."""
@@ -22,12 +24,15 @@ TOL_BF16 = 2e-2
 
 FOLD64 = wl.small_preset(n=20, m=72, l=5, channels=(2, 64, 64, 64, 1), activation=wl.ACT_GELU, N=8, H=3)
 FOLD32 = wl.small_preset(n=13, m=66, l=4, channels=(2, 32, 64, 1), N=8, H=3)
+# odd p = n + l = 97 (> 80: strip update with its gain split into BF16 planes, gain rows not
+# 16-byte aligned; statistics with a partial right tile)
+RAGGED_P = wl.small_preset(n=90, m=20, l=7, channels=(2, 16, 16, 1), N=12, H=3)
 
 
-@pytest.mark.parametrize("preset", ["C2", "C3", "fold64", "fold32"])
+@pytest.mark.parametrize("preset", ["C2", "C3", "fold64", "fold32", "ragged_p"])
 def test_bf16_rollout_vs_oracle(preset):
     # fold64 / fold32: the last layer folded into the last BF16 hidden layer (64 outputs)
-    p = {"fold64": FOLD64, "fold32": FOLD32}.get(preset) or wl.PRESETS[preset]
+    p = {"fold64": FOLD64, "fold32": FOLD32, "ragged_p": RAGGED_P}.get(preset) or wl.PRESETS[preset]
     prob = wl.make_problem(p)
     rng = np.random.default_rng(0)
     b = 8
@@ -43,9 +48,10 @@ def test_bf16_rollout_vs_oracle(preset):
     assert_parity(plant, ref[0], 1e-5, "plant")  # the plant stays FP32
 
 
-@pytest.mark.parametrize("preset,N,H", [("C2", 128, 10), ("C3", 32, 3), ("fold64", 12, 3)])
+@pytest.mark.parametrize("preset,N,H", [("C2", 128, 10), ("C3", 32, 3), ("fold64", 12, 3), ("ragged_p", 32, 3)])
 def test_bf16_solve_vs_oracle(preset, N, H):
-    p = dataclasses.replace(FOLD64 if preset == "fold64" else wl.PRESETS[preset], N=N, H=H)
+    base = {"fold64": FOLD64, "ragged_p": RAGGED_P}.get(preset) or wl.PRESETS[preset]
+    p = dataclasses.replace(base, N=N, H=H)
     prob = wl.make_problem(p)
     Xref = wl.reference_window(p, 0)
     z = wl.host_noise(p.n, p.m, p.l, N, H, seed=21)
