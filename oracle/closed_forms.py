@@ -149,3 +149,98 @@ def dense_ls(F, G, QU, QdU, R, x0, u_prev, xref, uref=None):
             out[t, n:n + l, c] = u[t]
             out[t, n + l:, c] = u[t] - (u_prev[:, c] if t == 0 else u[t - 1])
     return out
+
+
+def conv_matrix(w2d, n, m) -> np.ndarray:
+    """(n m) x (n m) matrix of a zero-padded 3x3 cross-correlation on an n x m field, vec
+    index y m + x: (T vec(a))[y m + x] = sum_{dy,dx} w2d[dy][dx] a[y+dy-1, x+dx-1]."""
+    T = np.zeros((n * m, n * m))
+    for y in range(n):
+        for x in range(m):
+            for dy in range(3):
+                for dx in range(3):
+                    yy, xx = y + dy - 1, x + dx - 1
+                    if 0 <= yy < n and 0 <= xx < m:
+                        T[y * m + x, yy * m + xx] += w2d[dy][dx]
+    return T
+
+
+def pooled_recursion(w, B, QU, QdU, R, x0, u_prev, xref, uref=None, pooled=True):
+    """The ensemble smoother's limit N -> infinity for one linear conv layer with a full
+    3x3 kernel w (1, 2, 3, 3), which mixes columns so that the matrix-normal assumption
+    no longer holds exactly.  Everything stays linear and Gaussian, so the stored
+    trajectory (every slice [x; u; du], vectorised, index (slice, row, column)) has an
+    exact Gaussian mean and covariance P; what the ensemble method changes is the gain:
+    pooled over the m columns (Eqs. (13b,c) with the sample sums replaced by their
+    expectations),
+        K = (sum_c P_{zY}[c, c]) (sum_c P_{YY}[c, c] + m diag(R, Q_U))^{-1},
+    where [c, c] takes the rows of column c on both sides, applied to every column
+    (I_m kron K), and the perturbed-observation covariance update for an arbitrary gain
+    (Joseph form),
+        P+ = (I - KH) P (I - KH)^T + K (diag(R, Q_U) kron I_m) K^T.
+    Process noise [0; w; w] with w ~ MN(0, Q_dU, I_m); observations [x_t; u_t] + v with
+    v ~ MN(0, diag(R, Q_U), I_m) and observed value [xref_t; uref]; prior x_k fixed,
+    u_k = u_prev + w_0, du_k = w_0.  Returns the smoothed means (H+1, n+2l, m).
+    pooled=False: the exact Kalman smoother of the same vectorised system instead (gain
+    P H^T (H P H^T + diag(R, Q_U) kron I_m)^{-1}, no pooling), from which the pooled limit
+    departs when the conv mixes columns."""
+    w = np.asarray(w, np.float64)
+    B = np.asarray(B, np.float64)
+    n, m = x0.shape
+    l = B.shape[1]
+    H = xref.shape[0] - 1
+    r = n + 2 * l
+    p = n + l
+    S = r * m  # one slice, vectorised (row, column)
+    uref = np.zeros((l, m)) if uref is None else uref
+    Ax = conv_matrix(w[0, 0], n, m)
+    Au = conv_matrix(w[0, 1], n, m) @ np.kron(B, np.eye(m))  # (n m) x (l m): B U per column, then the conv
+    Qw = np.kron(QdU, np.eye(m))
+    Rv = np.zeros((p * m, p * m))
+    Rv[:n * m, :n * m] = np.kron(R, np.eye(m))
+    Rv[n * m:, n * m:] = np.kron(QU, np.eye(m))
+    Robs = np.zeros((p, p))
+    Robs[:n, :n] = R
+    Robs[n:, n:] = QU
+    xs, us, ds = slice(0, n * m), slice(n * m, (n + l) * m), slice((n + l) * m, S)
+    mu = np.concatenate([x0.reshape(-1), u_prev.reshape(-1), np.zeros(l * m)])
+    P = np.zeros((S, S))
+    P[us, us] = P[us, ds] = P[ds, us] = P[ds, ds] = Qw
+    for t in range(1, H + 1):
+        D = mu.size
+        # forecast: the new slice from the last one
+        T = np.zeros((S, D))
+        last = D - S
+        T[xs, last + xs.start:last + xs.stop] = Ax
+        T[xs, last + us.start:last + us.stop] = Au
+        T[us, last + us.start:last + us.stop] = np.eye(l * m)
+        Qs = np.zeros((S, S))
+        Qs[us, us] = Qs[us, ds] = Qs[ds, us] = Qs[ds, ds] = Qw
+        mu = np.concatenate([mu, T @ mu])
+        P = np.block([[P, P @ T.T], [T @ P, T @ P @ T.T + Qs]])
+        D = mu.size
+        # observation of the new slice's x and u rows
+        Hm = np.zeros((p * m, D))
+        Hm[:, D - S:D - S + p * m] = np.eye(p * m)
+        PzY = P @ Hm.T
+        PYY = Hm @ P @ Hm.T
+        rows = (t + 1) * r
+        Szy = np.zeros((rows, p))
+        Syy = m * Robs
+        for c in range(m):
+            zc = np.arange(rows) * m + c  # (slice, row) at column c
+            yc = np.arange(p) * m + c
+            Szy += PzY[np.ix_(zc, yc)]
+            Syy = Syy + PYY[np.ix_(yc, yc)]
+        if pooled:
+            K = Szy @ np.linalg.inv(Syy)
+            Kf = np.zeros((D, p * m))
+            for c in range(m):
+                Kf[np.ix_(np.arange(rows) * m + c, np.arange(p) * m + c)] = K
+        else:
+            Kf = PzY @ np.linalg.inv(PYY + Rv)
+        y = np.concatenate([xref[t].reshape(-1), uref.reshape(-1)])
+        mu = mu + Kf @ (y - Hm @ mu)
+        IKH = np.eye(D) - Kf @ Hm
+        P = IKH @ P @ IKH.T + Kf @ Rv @ Kf.T
+    return mu.reshape(H + 1, r, m)
