@@ -633,6 +633,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
 #pragma unroll
     for (int j = 0; j < 4; ++j) wr[st][j] = wk[((size_t)tap * CIN + c0 + j) * COUT + o];
   }
+  const float bo = bias ? bias[o] : 0.f;
   const TileWalk walk(tiles);
   for (int tile = walk.first; tile < walk.end; tile += walk.step) {
     const int ct = tile % col_tiles, rest = tile / col_tiles;
@@ -679,45 +680,30 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           const f32x4 a = *(const f32x4*)(s_in + ((r + dy) * HC + 16 * mb + li + dx) * CP + c0);
-          // without LASTQ the weights are the A operand and the pixels B: lane (i, g) ends
-          // with channels 16 w + 4 g .. + 3 of pixel 16 mb + i (one 16-byte store); with
-          // LASTQ (whose epilogue needs the registers this layout costs) pixels are A: lane
-          // (i, g) ends with channel 16 w + i of pixels 16 mb + 4 g .. + 3
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            acc[r][mb] = LASTQ ? __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], wr[st][j], acc[r][mb], 0, 0, 0)
-                               : __builtin_amdgcn_mfma_f32_16x16x4f32(wr[st][j], a[j], acc[r][mb], 0, 0, 0);
+            acc[r][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], wr[st][j], acc[r][mb], 0, 0, 0);
         }
       // keep each step's LDS reads beside its MFMAs: hoisting later steps' reads ahead
       // would hold more A fragments live than the registers beside the weights allow
       __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (!LASTQ) {
-      // bias of this lane's output channels 16 w + 4 lk .. + 3 (read per tile: no registers
-      // held across the K loop)
-      const f32x4 bo = bias ? *(const f32x4*)(bias + 16 * w + 4 * lk) : f32x4{0.f, 0.f, 0.f, 0.f};
-      with_activation(act, [&](auto actc) {
-        constexpr int ACT = decltype(actc)::value;
 #pragma unroll
-        for (int r = 0; r < TR; ++r) {
-          const int y = y0 + r;
-          if (y >= n) continue;
-          float* const orow = out + (((size_t)i * n + y) * m + x0) * COUT + 16 * w + 4 * lk;
-          const bool full = x0 + TC <= m;
+      for (int r = 0; r < TR; ++r) {
+        const int y = y0 + r;
+        if (y >= n) continue;
 #pragma unroll
-          for (int mb = 0; mb < 4; ++mb)
-            if (full || x0 + 16 * mb + li < m) {
-              f32x4 v;
+        for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-              for (int q = 0; q < 4; ++q) v[q] = activate_c<ACT>(acc[r][mb][q] + bo[q]);
-              *reinterpret_cast<f32x4*>(orow + (size_t)(16 * mb + li) * COUT) = v;
-            }
-        }
-      });
+          for (int q = 0; q < 4; ++q) {
+            const int x = x0 + 16 * mb + 4 * lk + q;
+            if (x < m) out[(((size_t)i * n + y) * m + x) * COUT + o] = activate(acc[r][mb][q] + bo, act);
+          }
+      }
     } else {
       __syncthreads();  // every wave is done with the halo tile
       float* const s_h = s_in;  // activated tile [pixel][channel], pixel = r * 64 + x
-      const float bo = bias ? bias[o] : 0.f;
 #pragma unroll
       for (int r = 0; r < TR; ++r)
 #pragma unroll

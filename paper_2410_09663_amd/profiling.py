@@ -37,6 +37,7 @@ CLASS_OF = [  # kernel-name prefix -> class, first match wins
     ("k_gain", "gain"), ("k_normals", "noise"), ("k_means", "means"), ("k_init_slice0", "init"),
     ("k_assemble", "assemble"), ("k_observe", "observe"), ("k_constraint", "observe"),
     ("k_extract", "extract"), ("k_copy_jobs", "copy"), ("k_zero_u32", "assemble"),
+    ("k_split_gain", "update"),
 ]
 SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last": "rollout.hip",
              "stats": "stats.hip", "stats_reduce": "stats.hip", "means": "stats.hip", "chol": "gain.hip",
@@ -45,7 +46,25 @@ SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last"
              "lift": "rollout.hip"}
 
 
+def _demangle_simple(name: str) -> str:
+    """Names the profiler left mangled (e.g. with __bf16 parameters): the function
+    identifier in the library's anonymous namespace and its integer / bool template
+    arguments, as 'k_name<a, b>'."""
+    m = re.match(r"_ZN3oic12_GLOBAL__N_1(\d+)", name)
+    if not m:
+        return name
+    k = int(m.group(1))
+    ident = name[m.end():m.end() + k]
+    rest = name[m.end() + k:]
+    args = []
+    if rest.startswith("I"):
+        for a in re.finditer(r"L([ib])(\d+)E", rest[1:rest.find("EE") + 2] if "EE" in rest else rest[1:]):
+            args.append(("true" if a.group(2) == "1" else "false") if a.group(1) == "b" else a.group(2))
+    return f"{ident}<{', '.join(args)}>" if args else ident
+
+
 def kernel_class(name: str) -> str:
+    name = _demangle_simple(name)
     base = name.replace("(anonymous namespace)::", "").split("(")[0].strip()
     base = re.sub(r"^(void\s+)?(\w+::)*", "", base)
     for prefix, cls in CLASS_OF:
@@ -56,6 +75,7 @@ def kernel_class(name: str) -> str:
 
 def short_name(name: str) -> str:
     """Kernel name without namespaces, parameter list and 'void'."""
+    name = _demangle_simple(name)
     s = re.sub(r"\(.*$", "", name.replace("(anonymous namespace)::", "").strip())
     s = re.sub(r"^void\s+", "", s)
     s = re.sub(r"\boic::(\(anonymous namespace\)::)?", "", s)
