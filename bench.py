@@ -463,8 +463,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(member sharding over several GPUs is a design, not built)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (sharding the ensemble members "
+                                   "over several GPUs is described in the design notes, not implemented)"}))
         sys.exit(2)
 
     import torch

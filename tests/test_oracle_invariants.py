@@ -1,4 +1,5 @@
-"""Invariants and limits the method fixes (spec check (ii) and more)."""
+"""Invariants and limits the method fixes: symmetric positive semi-definite covariances and
+the sign of the covariance update, the lambda normalisation, and more."""
 import numpy as np
 import pytest
 

@@ -1,4 +1,4 @@
-"""Pins the whole smoother in the linear-Gaussian case (spec check (i)).
+"""Pins the whole smoother in the linear-Gaussian case.
 
 A single linear conv layer whose kernel is nonzero only in its centre column acts
 column by column, so the matrix-normal assumption holds exactly.  Then:
