@@ -464,7 +464,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: --gpus must be 1 (sharding the ensemble members "
-                                   "over several GPUs is described in the design notes, not implemented)"}))
+                                   "over several GPUs is not implemented)"}))
         sys.exit(2)
 
     import torch
