@@ -1,6 +1,6 @@
 """CNN surrogate of Eq. (1): X_{k+1} = CNN_theta(X_k, U_k), in FP64.
 
-Conventions (the paper gives none; readings are listed in the design notes):
+Conventions (the paper gives none; these are the readings taken here):
 * the control enters as a second input channel B @ U, with B in R^{n x l};
 * every layer is a 3x3 cross-correlation with zero padding of one cell and
   stride one, weights in [C_out][C_in][3][3] order, optional bias;
