@@ -762,9 +762,9 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
   const int Mtot = Ma + ny;
   const int NM = (int)d.NM();
   if (f32 && NM % 4 == 0) {
-    // right rows per block: NB*16 with NB <= 5, balanced over grid.y tiles
+    // right rows per block: NB*16 with NB <= 7, balanced over grid.y tiles
     const int nbk = (p + 15) / 16;
-    const int ytiles = (nbk + 4) / 5;
+    const int ytiles = (nbk + 6) / 7;
     const int NBv = (nbk + ytiles - 1) / ytiles;
     const int xt = (Mtot + 16 * SV_W - 1) / (16 * SV_W);
     const int tiles = xt * ytiles;
@@ -807,7 +807,8 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
       OIC_LAUNCH(t, KC_STATS, s, (k_stats_v4<NBV, false>), grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, R, p, \
                  muR, chunk, xt, ytiles, all, part);                                                     \
     break;
-      OIC_SV_CASE(1) OIC_SV_CASE(2) OIC_SV_CASE(3) OIC_SV_CASE(4) OIC_SV_CASE(5)
+      OIC_SV_CASE(1) OIC_SV_CASE(2) OIC_SV_CASE(3) OIC_SV_CASE(4) OIC_SV_CASE(5) OIC_SV_CASE(6)
+      OIC_SV_CASE(7)
 #undef OIC_SV_CASE
     }
     const long long count = (long long)Mtot * p;
