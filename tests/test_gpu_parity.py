@@ -93,9 +93,18 @@ def test_cnn_forward_matches_oracle(preset):
 
 
 @pytest.mark.parametrize("preset", ["C1", "tiny", "tiny_gelu", "tiny_l1", "C2", "p90", "p100", "p150",
-                                    "p500", "fold64"])
+                                    "p500", "fold64", "smallest", "l_eq_n", "N2"])
 def test_solve_explicit_noise_matches_oracle(preset):
-    if preset == "fold64":
+    if preset == "smallest":
+        # the smallest configuration the library accepts: a 4 x 5 field, one control row,
+        # two members ((N - 1) m = 5 = n + l observation rows), one horizon step
+        p = tiny(n=4, m=5, l=1, channels=(2, 3, 1), N=2, H=1)
+    elif preset == "l_eq_n":
+        p = tiny(n=4, m=6, l=4, channels=(2, 3, 1), N=4, H=2)
+    elif preset == "N2":
+        # two members over a wide field
+        p = tiny(n=6, m=40, l=2, channels=(2, 8, 1), N=2, H=3)
+    elif preset == "fold64":
         # 64-channel hidden layers with the last layer folded, on a ragged 20 x 72 field
         p = tiny(n=20, m=72, l=5, channels=(2, 64, 64, 1), act=wl.ACT_GELU, N=12, H=3)
     elif preset == "tiny":
