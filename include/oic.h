@@ -246,6 +246,52 @@ int oic_set_constraint(oic_handle h, const float* aX, const float* aU, float b, 
 int oic_columns_expand(int l, int q, int m, const float* u, const float* T, float* U);
 int oic_columns_project(int l, int m, int q, const float* U, const float* T, float* u);
 
+/* ---- Groups: same-shape solves of several controllers in shared launches ----
+ *
+ * Serving many controllers (the closed loop of Algorithm 1 run for each of them) repeats
+ * the same kernels with the same shapes.  A group holds `slots` handles of one
+ * configuration whose device buffers lie in equal slabs of one allocation; one launch of
+ * each kernel of a solve then serves any subset of the slots (the kernels' grids are
+ * repeated over the slots), and that sequence is captured once into a HIP graph and
+ * replayed for every batch.  Each slot computes exactly what its own solve computes, so
+ * a slot's results are bitwise the same alone and in any batch.
+ *
+ * Every slot is an ordinary handle (oic_group_slot) for oic_set_weights, oic_set_u_prev,
+ * oic_get_u_prev and solves of its own; it belongs to the group (oic_destroy ignores it)
+ * and a slot without bias for a layer holds a zero bias (identical results).  A group
+ * solve and calls on its slots must not overlap.  Several slots per group need
+ * precision OIC_PREC_BF16 with a BF16 kernel for every layer (OIC_EINVAL otherwise);
+ * one slot takes any configuration. */
+#define OIC_MAX_GROUP_SLOTS 64
+typedef struct oic_group* oic_group_handle;
+
+/* Device bytes of a group of `slots` slots created with cfg. */
+size_t oic_group_footprint_bytes(const oic_config* cfg, int slots);
+
+/* A group of 1..OIC_MAX_GROUP_SLOTS slots, each as oic_create(cfg) would make it.
+ * OIC_EINVAL (bad configuration or slot count), OIC_ENOMEM, OIC_EDEVICE. */
+int oic_group_create(const oic_config* cfg, int slots, oic_group_handle* out);
+
+/* Frees the group and its slots.  NULL-safe. */
+void oic_group_destroy(oic_group_handle g);
+
+/* The handle of slot `slot` (0 <= slot < slots), or NULL. */
+oic_handle oic_group_slot(oic_group_handle g, int slot);
+
+/* One solve (as oic_solve_ex, Algorithm 1 lines 4-13) for each of `count` distinct
+ * slots: request i runs on slot slots[i] with args[i] (array memory per the group's
+ * mem_mode), in one launch per kernel for all of them on slot 0's stream.  The
+ * requests share N, horizon, the noise source (seeded or explicit) and whether Q and R
+ * are diagonal; a request that differs, or whose slot has a constraint, covariance
+ * outputs or timing set, fails alone.  rc_out (NULL or count ints) receives each
+ * request's status; the return value is the first failure's (OIC_OK if none), and
+ * oic_group_last_error names its slot and reason.  A request that fails writes no
+ * output.  count 1 is the slot's own solve. */
+int oic_group_solve(oic_group_handle g, int count, const int* slots, const oic_solve_args* args, int* rc_out);
+
+/* Reason for the last failed oic_group_solve. */
+const char* oic_group_last_error(oic_group_handle g);
+
 /* ---- Serving: one request loop for many independent controllers ----
  *
  * A server owns a set of controllers, each a handle of its own (own stream,

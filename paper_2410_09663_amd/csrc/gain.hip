@@ -300,7 +300,11 @@ __device__ __forceinline__ bool chol_inverse(int p, double* A, double* W, double
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const double* __restrict__ Syy,
                                                                double* __restrict__ Sinv,
-                                                               int* __restrict__ flag) {
+                                                               int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(Syy);
+  OIC_GSH(Sinv);
+  OIC_GSH(flag);
   // Sigma^Y padded to p8 = p rounded up to a multiple of the panel width, with an identity
   // block: the factor of the padded matrix is diag(L, I), and every panel is full (no
   // branches on a short last panel).
@@ -332,7 +336,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_lds(int p, const doub
 __global__ __launch_bounds__(256) void k_gain_product(int p, int Ma, const double* __restrict__ Sxy,
                                                       const double* __restrict__ Sinv,
                                                       float* __restrict__ K,
-                                                      const int* __restrict__ flag) {
+                                                      const int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(Sxy);
+  OIC_GSH(Sinv);
+  OIC_GSH(K);
+  OIC_GSH(flag);
   if (*flag) return;
   const int b = blockIdx.y * 64 + threadIdx.x;
   const int a = blockIdx.x * 4 + threadIdx.y;
@@ -352,7 +361,12 @@ template <int NB>
 __global__ __launch_bounds__(256) void k_gain_mfma(int p, int Ma, const double* __restrict__ Sxy,
                                                    const double* __restrict__ Sinv,
                                                    float* __restrict__ K,
-                                                   const int* __restrict__ flag) {
+                                                   const int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(Sxy);
+  OIC_GSH(Sinv);
+  OIC_GSH(K);
+  OIC_GSH(flag);
   constexpr int P16 = NB * 16;
   __shared__ double sS[P16 * (P16 + 1)];
   if (*flag) return;
@@ -419,7 +433,11 @@ constexpr int kPBP = kPB + 1;  // padded LDS leading dimension
 
 __global__ __launch_bounds__(kCholThreads) void k_potrf_diag(int p, double* __restrict__ A, int kb,
                                                              double* __restrict__ Linv,
-                                                             int* __restrict__ flag) {
+                                                             int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(Linv);
+  OIC_GSH(flag);
   extern __shared__ double lds[];  // 2 x kPB x (kPB + 1)
   if (*flag) return;  // an earlier step failed; the solve reports it
   const int nb = min(kPB, p - kb);
@@ -445,7 +463,11 @@ __global__ __launch_bounds__(kCholThreads) void k_potrf_diag(int p, double* __re
 // rows against the panel's four 16-column blocks.
 __global__ __launch_bounds__(256) void k_potrf_trsm(int p, double* __restrict__ A, int kb,
                                                     const double* __restrict__ Linv,
-                                                    const int* __restrict__ flag) {
+                                                    const int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(Linv);
+  OIC_GSH(flag);
   __shared__ double sL[kPB * kPBP];
   __shared__ double sR[64 * kPBP];
   if (*flag) return;
@@ -487,7 +509,10 @@ __global__ __launch_bounds__(256) void k_potrf_trsm(int p, double* __restrict__ 
 // Trailing update of the lower triangle: 64 x 64 tile (ti, tj), ti >= tj, of the
 // rows/columns from r0 = kb + nb: A22 -= L21[ti] L21[tj]^T.
 __global__ __launch_bounds__(256) void k_potrf_syrk(int p, double* __restrict__ A, int kb,
-                                                    const int* __restrict__ flag) {
+                                                    const int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(flag);
   __shared__ double sI[64 * kPBP];
   __shared__ double sJ[64 * kPBP];
   if (*flag) return;
@@ -550,7 +575,13 @@ template <int RB>
 __global__ __launch_bounds__(256) void k_gain_trsm(int p, int Ma, const double* __restrict__ Sxy,
                                                    const double* __restrict__ A,
                                                    const double* __restrict__ Linv,
-                                                   float* __restrict__ K, const int* __restrict__ flag) {
+                                                   float* __restrict__ K, const int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(Sxy);
+  OIC_GSH(A);
+  OIC_GSH(Linv);
+  OIC_GSH(K);
+  OIC_GSH(flag);
   extern __shared__ double lds[];
   constexpr int RT = RB / 16;       // row tiles
   constexpr int TPW = RT * 4 / 4;   // tiles per wave
@@ -673,7 +704,7 @@ void launch_chol(hipStream_t s, Timer& t, int p, double* Syy, double* Lwork, dou
     }();
     (void)attr_set;
     const int p8 = (p + NBK - 1) / NBK * NBK;  // padded order (identity block)
-    OIC_LAUNCH(t, KC_CHOL, s, k_chol_inv_lds, dim3(1), dim3(kCholThreads),
+    OIC_GLAUNCH(t, KC_CHOL, s, k_chol_inv_lds, dim3(1), dim3(kCholThreads),
                2 * (size_t)p8 * (p8 + 1) * sizeof(double), p, Syy, Sinv, flag);
     return;
   }
@@ -686,13 +717,13 @@ void launch_chol(hipStream_t s, Timer& t, int p, double* Syy, double* Lwork, dou
   }();
   (void)diag_attr;
   for (int kb = 0; kb < p; kb += kPB) {
-    OIC_LAUNCH(t, KC_CHOL, s, k_potrf_diag, dim3(1), dim3(kCholThreads), diag_lds, p, Syy, kb, Lwork,
+    OIC_GLAUNCH(t, KC_CHOL, s, k_potrf_diag, dim3(1), dim3(kCholThreads), diag_lds, p, Syy, kb, Lwork,
                flag);
     const int rem = p - kb - std::min(kPB, p - kb);
     if (rem <= 0) break;
     const int nt = (rem + 63) / 64;
-    OIC_LAUNCH(t, KC_CHOL, s, k_potrf_trsm, dim3((unsigned)nt), dim3(256), 0, p, Syy, kb, Lwork, flag);
-    OIC_LAUNCH(t, KC_CHOL, s, k_potrf_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, p, Syy, kb,
+    OIC_GLAUNCH(t, KC_CHOL, s, k_potrf_trsm, dim3((unsigned)nt), dim3(256), 0, p, Syy, kb, Lwork, flag);
+    OIC_GLAUNCH(t, KC_CHOL, s, k_potrf_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, p, Syy, kb,
                flag);
   }
 }
@@ -716,21 +747,21 @@ void launch_gain(hipStream_t s, Timer& t, int p, int Ma, const double* Sxy, cons
     (void)attr_set;
     const dim3 g((unsigned)((Ma + RB - 1) / RB));
     if (big)
-      OIC_LAUNCH(t, KC_GAIN, s, k_gain_trsm<32>, g, dim3(256), bytes, p, Ma, Sxy, L, Linv, K, flag);
+      OIC_GLAUNCH(t, KC_GAIN, s, k_gain_trsm<32>, g, dim3(256), bytes, p, Ma, Sxy, L, Linv, K, flag);
     else
-      OIC_LAUNCH(t, KC_GAIN, s, k_gain_trsm<16>, g, dim3(256), bytes, p, Ma, Sxy, L, Linv, K, flag);
+      OIC_GLAUNCH(t, KC_GAIN, s, k_gain_trsm<16>, g, dim3(256), bytes, p, Ma, Sxy, L, Linv, K, flag);
     return;
   }
   const int nbk = (p + 15) / 16;
   const dim3 g((unsigned)((Ma + 63) / 64));
   switch (nbk) {
 #define OIC_GAIN_CASE(NBV) \
-  case NBV: OIC_LAUNCH(t, KC_GAIN, s, k_gain_mfma<NBV>, g, dim3(256), 0, p, Ma, Sxy, Sinv, K, flag); return;
+  case NBV: OIC_GLAUNCH(t, KC_GAIN, s, k_gain_mfma<NBV>, g, dim3(256), 0, p, Ma, Sxy, Sinv, K, flag); return;
     OIC_GAIN_CASE(1) OIC_GAIN_CASE(2) OIC_GAIN_CASE(3) OIC_GAIN_CASE(4)
     OIC_GAIN_CASE(5) OIC_GAIN_CASE(6)
 #undef OIC_GAIN_CASE
     default:
-      OIC_LAUNCH(t, KC_GAIN, s, k_gain_product, dim3((unsigned)((Ma + 3) / 4), (unsigned)((p + 63) / 64)),
+      OIC_GLAUNCH(t, KC_GAIN, s, k_gain_product, dim3((unsigned)((Ma + 3) / 4), (unsigned)((p + 63) / 64)),
                  dim3(64, 4), 0, p, Ma, Sxy, Sinv, K, flag);
   }
 }

@@ -51,7 +51,10 @@ __device__ __forceinline__ float philox_normal(uint64_t seed, uint32_t kind, uin
 // The seed is read from device memory so that a captured solve can be replayed with a
 // new seed without touching the graph.
 __global__ void k_normals(float* __restrict__ out, size_t count, const uint64_t* __restrict__ seed_ptr,
-                          uint32_t kind) {
+                          uint32_t kind, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(out);
+  OIC_GSH(seed_ptr);
   const uint64_t seed = *seed_ptr;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
@@ -61,7 +64,13 @@ __global__ void k_normals(float* __restrict__ out, size_t count, const uint64_t*
 // Slice k of every member: X rows = X_k (no spread), U rows = U_prev + W_0^i.  Also
 // clears the positive-definiteness flag of the solve.
 __global__ void k_init_slice0(Dims d, float* __restrict__ traj, const float* __restrict__ X0,
-                              const float* __restrict__ Uprev, NoiseRef w0, int* __restrict__ flag) {
+                              const float* __restrict__ Uprev, NoiseRef w0, int* __restrict__ flag, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(traj);
+  OIC_GSH(X0);
+  OIC_GSH(Uprev);
+  OIC_GSH(w0);
+  OIC_GSH(flag);
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *flag = 0;
   const int NM = (int)d.NM();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
@@ -79,7 +88,10 @@ __global__ void k_init_slice0(Dims d, float* __restrict__ traj, const float* __r
 }
 
 // U rows of slice t: U_t^i = U_{t-1}^i (after the analysis at t-1) + W_t^i.
-__global__ void k_assemble_u(Dims d, float* __restrict__ traj, int step, NoiseRef w) {
+__global__ void k_assemble_u(Dims d, float* __restrict__ traj, int step, NoiseRef w, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(traj);
+  OIC_GSH(w);
   const int NM = (int)d.NM();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
@@ -92,7 +104,12 @@ __global__ void k_assemble_u(Dims d, float* __restrict__ traj, int step, NoiseRe
 
 // Ybar^i_t = [X_t^i + V_X^i; U_t^i + V_U^i].
 __global__ void k_observe(Dims d, const float* __restrict__ traj, int step, float* __restrict__ Y,
-                          NoiseRef vx, NoiseRef vu, int row0) {
+                          NoiseRef vx, NoiseRef vu, int row0, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(traj);
+  OIC_GSH(Y);
+  OIC_GSH(vx);
+  OIC_GSH(vu);
   const int NM = (int)d.NM();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = row0 + (int)blockIdx.y;
@@ -144,23 +161,23 @@ void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, const uin
   if (!count) return;
   size_t blocks = (count + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  OIC_LAUNCH(t, KC_NOISE, s, k_normals, dim3((unsigned)blocks), dim3(256), 0, out, count, seed, kind);
+  OIC_GLAUNCH(t, KC_NOISE, s, k_normals, dim3((unsigned)blocks), dim3(256), 0, out, count, seed, kind);
 }
 
 void launch_init_slice0(hipStream_t s, Timer& t, const Dims& d, float* traj, const float* X0,
                         const float* Uprev, NoiseRef w0, int* flag) {
-  OIC_LAUNCH(t, KC_INIT, s, k_init_slice0, row_grid(d.NM(), d.rr()), dim3(256), 0, d, traj, X0,
+  OIC_GLAUNCH(t, KC_INIT, s, k_init_slice0, row_grid(d.NM(), d.rr()), dim3(256), 0, d, traj, X0,
              Uprev, w0, flag);
 }
 
 void launch_assemble_u(hipStream_t s, Timer& t, const Dims& d, float* traj, int step, NoiseRef w) {
-  OIC_LAUNCH(t, KC_ASSEMBLE, s, k_assemble_u, row_grid(d.NM(), d.l), dim3(256), 0, d, traj, step, w);
+  OIC_GLAUNCH(t, KC_ASSEMBLE, s, k_assemble_u, row_grid(d.NM(), d.l), dim3(256), 0, d, traj, step, w);
 }
 
 void launch_observe(hipStream_t s, Timer& t, const Dims& d, const float* traj, int step, float* Y,
                     NoiseRef vx, NoiseRef vu, int row0, int row1) {
   if (row1 <= row0) return;
-  OIC_LAUNCH(t, KC_OBSERVE, s, k_observe, row_grid(d.NM(), row1 - row0), dim3(256), 0, d, traj, step, Y,
+  OIC_GLAUNCH(t, KC_OBSERVE, s, k_observe, row_grid(d.NM(), row1 - row0), dim3(256), 0, d, traj, step, Y,
              vx, vu, row0);
 }
 

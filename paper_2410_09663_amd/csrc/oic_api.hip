@@ -37,6 +37,11 @@ const char* const kKernelClassNames[KC_COUNT] = {
     "noise", "init", "lift", "conv_first", "conv_mid", "conv_last", "assemble", "observe",
     "means", "stats", "stats_reduce", "chol", "gain", "update", "extract", "copy"};
 
+LaunchGroup& launch_group() {
+  thread_local LaunchGroup g;
+  return g;
+}
+
 void Timer::reset() {
   cursor = 0;
   pending_class.clear();
@@ -154,11 +159,34 @@ struct oic_ctx {
   // device (oic_cnn_forward_noalloc), or null if it could not be obtained
   unsigned char* scratch = nullptr;
 
+  // A slot of a group (oic_group_create): every device buffer, the weights included, is
+  // carved from `slab` (slab_cap bytes) in a fixed order, so that it sits at the same
+  // offset as in the group's other slots.  The group owns the memory and the handle.
+  char* slab = nullptr;
+  size_t slab_cap = 0, slab_used = 0;
+
   // replay of the per-solve kernel sequence
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
   int gN = 0, gH = 0;
   bool gSeeded = false;
+};
+
+// Handles of one configuration whose buffers lie in equal slabs of one allocation, so
+// that one launch per kernel serves any subset of them (see Grp).
+struct oic_group {
+  oic_config cfg{};
+  int slots = 0;
+  size_t slab = 0;         // bytes per slot (the stride of the grouped launches)
+  char* region = nullptr;  // slots x slab bytes
+  std::vector<oic_ctx*> h;
+  int* dactive = nullptr;  // device: 1 for the slots of the batch being solved
+  int* hactive = nullptr;  // pinned staging of dactive
+  int* hflags = nullptr;   // pinned: each slot's positive-definiteness flag after a batch
+  hipGraphExec_t gexec = nullptr;  // the captured grouped solve and its key
+  int gN = 0, gH = 0;
+  bool gSeeded = false, gQd = true, gRd = true;
+  std::string err;
 };
 
 namespace {
@@ -306,19 +334,21 @@ int prepare_factors(oic_ctx* h, const float* Q, const float* R) {
   return OIC_OK;
 }
 
-NoiseRef noise_ref(oic_ctx* h, const float* Z, bool is_q) {
+// Noise source over the handle's factors, stored as diagonal scales (q_diag / r_diag)
+// or dense triangles.
+NoiseRef noise_ref(oic_ctx* h, const float* Z, bool is_q, bool q_diag, bool r_diag) {
   NoiseRef r;
   r.Z = Z;
   const int l = h->cfg.l;
   if (is_q) {
     r.rows = l;
-    r.diag = h->q_diag ? h->fac : nullptr;
-    r.L = h->q_diag ? nullptr : h->fac;
+    r.diag = q_diag ? h->fac : nullptr;
+    r.L = q_diag ? nullptr : h->fac;
   } else {
     r.rows = h->cfg.n;
     const float* fr = h->fac + (size_t)l * l;
-    r.diag = h->r_diag ? fr : nullptr;
-    r.L = h->r_diag ? nullptr : fr;
+    r.diag = r_diag ? fr : nullptr;
+    r.L = r_diag ? nullptr : fr;
   }
   return r;
 }
@@ -326,6 +356,17 @@ NoiseRef noise_ref(oic_ctx* h, const float* Z, bool is_q) {
 template <typename T>
 int dalloc(oic_ctx* h, T** p, size_t count) {
   if (count == 0) count = 1;
+  if (h->slab) {
+    const size_t bytes = (count * sizeof(T) + 255) / 256 * 256;
+    if (h->slab_used + bytes > h->slab_cap) {
+      *p = nullptr;
+      h->err = "the group slot's buffers exceed its slab";
+      return OIC_ENOMEM;
+    }
+    *p = reinterpret_cast<T*>(h->slab + h->slab_used);
+    h->slab_used += bytes;
+    return OIC_OK;
+  }
   hipError_t e = hipMalloc((void**)p, count * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
@@ -337,8 +378,8 @@ int dalloc(oic_ctx* h, T** p, size_t count) {
 }
 
 void free_all(oic_ctx* h) {
-  auto f = [](void* p) {
-    if (p) hipFree(p);
+  auto f = [h](void* p) {
+    if (p && !h->slab) hipFree(p);  // a group slot's buffers are the group's
   };
   f(h->dB);
   for (int k = 0; k < OIC_MAX_LAYERS; ++k) {
@@ -425,6 +466,14 @@ size_t handle_bytes(const oic_config& c) {
   for (int k = 0; k < c.n_layers; ++k)  // FP32, MFMA-layout FP32, BF16 and FP8 copies at most
     weights += (size_t)c.channels[k + 1] * c.channels[k] * 9 * 11 + (size_t)c.channels[k + 1] * 8;
   return 4 * floats + 8 * doubles + weights + 4096;
+}
+
+// Bytes of one group slot: handle_bytes with every buffer rounded up to 256 bytes,
+// rounded up to 2 MiB.
+size_t group_slab_bytes(const oic_config& c) {
+  const size_t buffers = 32 + 8 * (size_t)OIC_MAX_LAYERS;
+  const size_t b = handle_bytes(c) + 256 * buffers;
+  return (b + (2u << 20) - 1) / (2u << 20) * (2u << 20);
 }
 
 }  // namespace oic
@@ -543,25 +592,25 @@ uint16_t host_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-int copy_in(oic_ctx* h, float* dst, const float* src, size_t count) {
+// Copies in the handle's memory mode on stream s (the handle's stream if null).
+int copy_in(oic_ctx* h, float* dst, const float* src, size_t count, hipStream_t s = nullptr) {
+  if (!s) s = h->stream;
   if (h->cfg.mem_mode == OIC_MEM_HOST)
-    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyHostToDevice, s));
   else
-    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToDevice, s));
   return OIC_OK;
 }
 
-int copy_out(oic_ctx* h, float* dst, const float* src, size_t count) {
+int copy_out(oic_ctx* h, float* dst, const float* src, size_t count, hipStream_t s = nullptr) {
+  if (!s) s = h->stream;
   if (h->cfg.mem_mode == OIC_MEM_HOST)
-    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToHost, s));
   else
-    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(float), hipMemcpyDeviceToDevice, s));
   return OIC_OK;
 }
 
-// Every kernel of one solve, in order, on the handle's stream.  Reads only handle-owned
-// buffers (inputs and noise are copied in beforehand; the seed is in device memory),
-// so the same sequence can be captured once and replayed.
 // Offset (in doubles) of horizon step t's block in the covariance outputs: the blocks
 // of steps 1..t-1, each ((s+1) rr)^2.
 size_t cov_offset(int rr, int t) {
@@ -578,7 +627,12 @@ void enqueue_cov(oic_ctx* h, const Dims& d, int Ma, double* out) {
                1.0 / ((double)d.m * d.N));
 }
 
-void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
+// Every kernel of one solve, in order, on the handle's stream.  Reads only handle-owned
+// buffers (inputs and noise are copied in beforehand; the seed is in device memory),
+// so the same sequence can be captured once and replayed.  `mode` is the rollout's
+// arithmetic and q_diag / r_diag the layout of the noise factors; inside a group
+// (launch_group) the launches serve every active slot.
+void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded, RolloutMode mode, bool q_diag, bool r_diag) {
   const oic_config& c = h->cfg;
   const int N = d.N, H = d.H, n = c.n, m = c.m, l = c.l, rr = d.rr(), p = d.p();
   const long long NM = d.NM();
@@ -592,7 +646,7 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     for (int k = 0; k < 4 + d.nc; ++k) launch_normals(s, h->timer, h->Z[k], cnt[k], h->dseed, (uint32_t)k);
   const float* const* Zd = h->Z;
   // Line 4: initial ensemble (also clears the failure flag).
-  launch_init_slice0(s, h->timer, d, h->traj, dX0, dUp, noise_ref(h, Zd[0], true), h->flag);
+  launch_init_slice0(s, h->timer, d, h->traj, dX0, dUp, noise_ref(h, Zd[0], true, q_diag, r_diag), h->flag);
   for (int t = 1; t <= H; ++t) {
     const size_t slice = (size_t)rr * NM;
     float* prev = h->traj + (size_t)(t - 1) * slice;
@@ -604,11 +658,11 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     // first-layer workgroup cost more than the separate launch saves.
     const bool small = (long long)l * NM <= (1LL << 17);
     const ObserveArgs oa{small ? cur + (size_t)n * NM : nullptr, h->Y, NM,
-                         noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true),
-                         noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false),
-                         noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true)};
+                         noise_ref(h, Zd[1] + (size_t)(t - 1) * N * l * m, true, q_diag, r_diag),
+                         noise_ref(h, Zd[2] + (size_t)(t - 1) * N * n * m, false, q_diag, r_diag),
+                         noise_ref(h, Zd[3] + (size_t)(t - 1) * N * l * m, true, q_diag, r_diag)};
     const int done = rollout(h, N, FieldRef{prev, m, NM}, FieldRef{prev + (size_t)n * NM, m, NM},
-                             FieldOut{cur, m, NM}, rollout_mode(h), &oa);
+                             FieldOut{cur, m, NM}, mode, &oa);
     if (!(done & ROLL_U_ASSEMBLED)) launch_assemble_u(s, h->timer, d, h->traj, t, oa.w);
     launch_observe(s, h->timer, d, h->traj, t, h->Y, oa.vx, oa.vu, (done & ROLL_X_OBSERVED) ? n : 0,
                    (done & ROLL_U_ASSEMBLED) ? n : n + l);
@@ -626,7 +680,7 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
     // while Eq. (13c), Sigma^{XY}, runs here.  Sigma^Y, which is factored, takes FP64
     // products in the FP32 mode; Sigma^{XY}, which enters the gain linearly, takes FP32
     // products folded into FP64 every 256 columns in every mode (twice the FP64 MFMA rate).
-    const bool f32_stats = rollout_mode(h) != RM_FP32;  // FP32 statistics in the BF16 / FP8 modes
+    const bool f32_stats = mode != RM_FP32;  // FP32 statistics in the BF16 / FP8 modes
     // the FP32 products take Ybar centred once per step (FP64 subtraction, FP32 result) in
     // the first activation buffer, which the rollout is done with until the next step
     const float* Yc = nullptr;
@@ -659,7 +713,10 @@ void enqueue_solve(oic_ctx* h, const Dims& d, bool seeded) {
   launch_extract(s, h->timer, d, h->mu_traj, sU, sX, h->Uprev_new);
 }
 
-int solve_impl(oic_ctx* h, const oic_solve_args* a) {
+// First stage of a solve: checks the arguments, factors Q and R, and queues the copies
+// of the inputs (and of explicit noise, or the seed) into the handle's buffers on stream
+// s.  Sets d and whether the solve draws its own noise.
+int solve_begin(oic_ctx* h, const oic_solve_args* a, hipStream_t s, Dims& d, bool& seeded) {
   if (!h) return OIC_EINVAL;
   h->err.clear();
   if (!a) return fail(h, OIC_EINVAL, "NULL argument block");
@@ -686,10 +743,9 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   int rc = prepare_factors(h, a->Q, a->R);
   if (rc) return rc;
 
-  Dims d{c.n, c.m, c.l, N, H};
+  d = Dims{c.n, c.m, c.l, N, H};
   d.nc = h->con_on ? 1 : 0;
   const int n = c.n, m = c.m, l = c.l;
-  hipStream_t s = h->stream;
 
   // Inputs into device memory.
   float* dX0 = h->io;
@@ -703,10 +759,10 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
                            {a->U_prev ? a->U_prev : h->Uprev, dUp, (long long)l * m}};
     launch_copy_jobs(s, h->timer, in, 3, nullptr, a->seed, explicit_noise ? nullptr : h->dseed);
   } else {
-    if ((rc = copy_in(h, dX0, a->X0, (size_t)n * m))) return rc;
-    if ((rc = copy_in(h, dRef, a->reference, (size_t)(H + 1) * n * m))) return rc;
+    if ((rc = copy_in(h, dX0, a->X0, (size_t)n * m, s))) return rc;
+    if ((rc = copy_in(h, dRef, a->reference, (size_t)(H + 1) * n * m, s))) return rc;
     if (a->U_prev) {
-      if ((rc = copy_in(h, dUp, a->U_prev, (size_t)l * m))) return rc;
+      if ((rc = copy_in(h, dUp, a->U_prev, (size_t)l * m, s))) return rc;
     } else {
       HIP_TRY(hipMemcpyAsync(dUp, h->Uprev, (size_t)l * m * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
@@ -716,54 +772,48 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   const float* zsrc[5] = {a->Z_init, a->Z_W, a->Z_VX, a->Z_VU, a->Z_VZ};
   if (explicit_noise) {
     for (int k = 0; k < 4 + d.nc; ++k)
-      if ((rc = copy_in(h, h->Z[k], zsrc[k], cnt[k]))) return rc;
+      if ((rc = copy_in(h, h->Z[k], zsrc[k], cnt[k], s))) return rc;
   } else if (!dev) {
+    // (the pinned staging word is read by the copy engine later: one solve at a time
+    // per handle)
     *h->hseed = a->seed;
     HIP_TRY(hipMemcpyAsync(h->dseed, h->hseed, sizeof(uint64_t), hipMemcpyHostToDevice, s));
   }
-  const bool seeded = !explicit_noise;
-  if (h->use_graph && !h->timer.enabled && !h->want_cov) {
-    if (!h->gexec || h->gN != N || h->gH != H || h->gSeeded != seeded) {
-      std::lock_guard<std::mutex> guard(resource_mutex());
-      if (h->gexec) {
-        hipGraphExecDestroy(h->gexec);
-        h->gexec = nullptr;
-      }
-      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-      enqueue_solve(h, d, seeded);
-      hipGraph_t g = nullptr;
-      HIP_TRY(hipStreamEndCapture(s, &g));
-      hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        h->gexec = nullptr;
-        return fail(h, OIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
-      h->gN = N;
-      h->gH = H;
-      h->gSeeded = seeded;
-    }
-    HIP_TRY(hipGraphLaunch(h->gexec, s));
-  } else {
-    enqueue_solve(h, d, seeded);
-  }
+  seeded = !explicit_noise;
+  return OIC_OK;
+}
+
+// Queues the outputs of a device-memory solve (and the carried U_prev) on stream s,
+// skipped on the device when the positive-definiteness flag is set, then the flag into
+// *flag_host (pinned or pageable host memory, read after s is synchronised).
+int solve_end(oic_ctx* h, const oic_solve_args* a, hipStream_t s, int* flag_host) {
+  const oic_config& c = h->cfg;
+  const int H = a->horizon, n = c.n, m = c.m, l = c.l;
   float* sU = h->out_stage;
   float* sX = sU + (size_t)(c.max_H + 1) * l * m;
-  if (dev) {
+  if (c.mem_mode == OIC_MEM_DEVICE) {
     // outputs and the carried U_prev in one launch, which does nothing if the solve failed
     const CopyJob out[3] = {{sU, a->U_out, (long long)(H + 1) * l * m},
                             {sX, a->X_out, a->X_out ? (long long)(H + 1) * n * m : 0},
                             {h->Uprev_new, h->Uprev, (long long)l * m}};
     launch_copy_jobs(s, h->timer, out, 3, h->flag, 0, nullptr);
   }
-  int flag = 0;
-  HIP_TRY(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  h->timer.harvest();
+  HIP_TRY(hipMemcpyAsync(flag_host, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  return OIC_OK;
+}
+
+// Last stage, after stream s is synchronised: the flag's verdict, and the outputs of a
+// host-memory solve.
+int solve_finish(oic_ctx* h, const oic_solve_args* a, hipStream_t s, int flag) {
+  const oic_config& c = h->cfg;
+  const int H = a->horizon, n = c.n, m = c.m, l = c.l;
   if (flag) return fail(h, OIC_ENOTSPD, "Sigma^Ybar is not positive definite at some horizon step");
-  if (!dev) {
-    if ((rc = copy_out(h, a->U_out, sU, (size_t)(H + 1) * l * m))) return rc;
-    if (a->X_out && (rc = copy_out(h, a->X_out, sX, (size_t)(H + 1) * n * m))) return rc;
+  if (c.mem_mode == OIC_MEM_HOST) {
+    float* sU = h->out_stage;
+    float* sX = sU + (size_t)(c.max_H + 1) * l * m;
+    int rc;
+    if ((rc = copy_out(h, a->U_out, sU, (size_t)(H + 1) * l * m, s))) return rc;
+    if (a->X_out && (rc = copy_out(h, a->X_out, sX, (size_t)(H + 1) * n * m, s))) return rc;
     HIP_TRY(hipMemcpyAsync(h->Uprev, h->Uprev_new, (size_t)l * m * sizeof(float),
                            hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -771,15 +821,83 @@ int solve_impl(oic_ctx* h, const oic_solve_args* a) {
   return OIC_OK;
 }
 
-}  // namespace
+// Captures enqueue_solve on stream s into *exec (replacing what it held).  The caller
+// holds resource_mutex().
+int capture_solve(oic_ctx* h, hipStream_t s, hipGraphExec_t* exec, const Dims& d, bool seeded, RolloutMode mode,
+                  bool q_diag, bool r_diag) {
+  if (*exec) {
+    hipGraphExecDestroy(*exec);
+    *exec = nullptr;
+  }
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  enqueue_solve(h, d, seeded, mode, q_diag, r_diag);
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamEndCapture(s, &g));
+  hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    *exec = nullptr;
+    return fail(h, OIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return OIC_OK;
+}
 
-extern "C" {
+int solve_impl(oic_ctx* h, const oic_solve_args* a) {
+  Dims d{};
+  bool seeded = false;
+  int rc = solve_begin(h, a, h ? h->stream : nullptr, d, seeded);
+  if (rc) return rc;
+  hipStream_t s = h->stream;
+  const RolloutMode mode = rollout_mode(h);
+  if (h->use_graph && !h->timer.enabled && !h->want_cov) {
+    if (!h->gexec || h->gN != d.N || h->gH != d.H || h->gSeeded != seeded) {
+      std::lock_guard<std::mutex> guard(resource_mutex());
+      if ((rc = capture_solve(h, s, &h->gexec, d, seeded, mode, h->q_diag, h->r_diag))) return rc;
+      h->gN = d.N;
+      h->gH = d.H;
+      h->gSeeded = seeded;
+    }
+    HIP_TRY(hipGraphLaunch(h->gexec, s));
+  } else {
+    enqueue_solve(h, d, seeded, mode, h->q_diag, h->r_diag);
+  }
+  int flag = 0;
+  if ((rc = solve_end(h, a, s, &flag))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  h->timer.harvest();
+  return solve_finish(h, a, s, flag);
+}
 
-int oic_create(const oic_config* cfg, oic_handle* out) {
-  if (!cfg || !out) return OIC_EINVAL;
-  std::lock_guard<std::mutex> guard(resource_mutex());
+// Weight buffers of every layer that oic_set_weights fills for this configuration, in a
+// fixed order (a group slot holds them from the start: a slot never allocates later, and
+// its buffers keep the same offsets as the other slots').
+int reserve_weights(oic_ctx* h) {
+  const oic_config& c = h->cfg;
+  int rc = dalloc(h, &h->dB, (size_t)c.n * c.l);
+  for (int k = 0; k < c.n_layers && !rc; ++k) {
+    const int cin = c.channels[k], cout = c.channels[k + 1];
+    const size_t cnt = (size_t)cout * cin * 9;
+    rc = dalloc(h, &h->dW[k], cnt);
+    if (!rc && k < c.n_layers - 1 && conv_mfma_supported(cin, cout)) rc = dalloc(h, &h->dWk[k], cnt);
+    if (!rc && c.precision == OIC_PREC_FP8 && k > 0 && k < c.n_layers - 1 && conv_mfma_fp8_supported(cin, cout)) {
+      const size_t kd128 = ((size_t)9 * cin + 127) / 128 * 128;
+      rc = dalloc(h, &h->dWq[k], (size_t)cout * kd128);
+      if (!rc) rc = dalloc(h, &h->dWs[k], (size_t)cout);
+    }
+    if (!rc && c.precision == OIC_PREC_BF16 && k > 0 && k < c.n_layers - 1 && conv_mfma_bf16_supported(cin, cout))
+      rc = dalloc(h, &h->dWb[k], cnt);
+    if (!rc && (c.precision == OIC_PREC_BF16 || c.precision == OIC_PREC_FP8) && k == c.n_layers - 1 && k >= 2 &&
+        cout == 1 && conv_last_folds_bf16(c.channels[k - 1], cin))
+      rc = dalloc(h, &h->dWl2, (size_t)2 * 16 * cin);
+    if (!rc) rc = dalloc(h, &h->dBias[k], (size_t)cout);
+  }
+  return rc;
+}
+
+// A new handle for c (the caller holds resource_mutex()).  With a slab, every device
+// buffer comes from it (a group slot) and the weight buffers are reserved at once.
+int create_handle(const oic_config& c, char* slab, size_t slab_cap, oic_ctx** out) {
   *out = nullptr;
-  const oic_config& c = *cfg;
   if (c.n < 4 || c.m < 4 || c.l < 1 || c.l > c.n || c.n_layers < 1 || c.n_layers > OIC_MAX_LAYERS ||
       c.max_N < 2 || c.max_H < 1 || (c.activation != OIC_ACT_TANH && c.activation != OIC_ACT_GELU) ||
       (c.precision != OIC_PREC_FP32 && c.precision != OIC_PREC_BF16 && c.precision != OIC_PREC_FP8) ||
@@ -793,6 +911,8 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   oic_ctx* h = new (std::nothrow) oic_ctx();
   if (!h) return OIC_ENOMEM;
   h->cfg = c;
+  h->slab = slab;
+  h->slab_cap = slab_cap;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return OIC_EDEVICE;
@@ -850,6 +970,7 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   if (!rc && hipMemsetAsync(h->Uprev, 0, l * m * sizeof(float), h->stream) != hipSuccess)
     rc = OIC_EDEVICE;
   if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = OIC_EDEVICE;
+  if (!rc && slab) rc = reserve_weights(h);
   if (rc) {
     free_all(h);
     if (h->own_stream) hipStreamDestroy(h->stream);
@@ -860,14 +981,28 @@ int oic_create(const oic_config* cfg, oic_handle* out) {
   return OIC_OK;
 }
 
-void oic_destroy(oic_handle h) {
-  if (!h) return;
-  std::lock_guard<std::mutex> guard(resource_mutex());
+void destroy_handle(oic_ctx* h) {
   hipStreamSynchronize(h->stream);
   free_all(h);
   h->timer.destroy();
   if (h->own_stream) hipStreamDestroy(h->stream);
   delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oic_create(const oic_config* cfg, oic_handle* out) {
+  if (!cfg || !out) return OIC_EINVAL;
+  std::lock_guard<std::mutex> guard(resource_mutex());
+  return create_handle(*cfg, nullptr, 0, out);
+}
+
+void oic_destroy(oic_handle h) {
+  if (!h || h->slab) return;  // a group slot goes with its group
+  std::lock_guard<std::mutex> guard(resource_mutex());
+  destroy_handle(h);
 }
 
 const char* oic_last_error(oic_handle h) { return h ? h->err.c_str() : "NULL handle"; }
@@ -990,6 +1125,10 @@ int oic_set_weights(oic_handle h, const float* B, const float* const* W, const f
       if (!h->dBias[k] && (rc = dalloc(h, &h->dBias[k], (size_t)c.channels[k + 1]))) return rc;
       HIP_TRY(hipMemcpyAsync(h->dBias[k], bias[k], c.channels[k + 1] * sizeof(float),
                              hipMemcpyHostToDevice, h->stream));
+    } else if (h->dBias[k] && h->slab) {
+      // a group slot keeps its buffer (the slots share one set of launches): no bias is
+      // a zero bias, which every kernel adds as exactly what it uses without one
+      HIP_TRY(hipMemsetAsync(h->dBias[k], 0, c.channels[k + 1] * sizeof(float), h->stream));
     } else if (h->dBias[k]) {
       hipFree(h->dBias[k]);
       h->dBias[k] = nullptr;
@@ -1308,6 +1447,188 @@ int oic_columns_project(int l, int m, int q, const float* U, const float* T, flo
     for (int i = 0; i < q; ++i) u[(size_t)a * q + i] = (float)y[i];
   }
   return OIC_OK;
+}
+
+size_t oic_group_footprint_bytes(const oic_config* cfg, int slots) {
+  if (!cfg || slots < 1) return 0;
+  return (size_t)slots * group_slab_bytes(*cfg) + 4096;
+}
+
+int oic_group_create(const oic_config* cfg, int slots, oic_group_handle* out) {
+  if (!cfg || !out || slots < 1 || slots > OIC_MAX_GROUP_SLOTS) return OIC_EINVAL;
+  *out = nullptr;
+  const oic_config& c = *cfg;
+  // several slots per launch: the BF16 rollout and the statistics and update of its mode
+  if (slots > 1 && (c.precision != OIC_PREC_BF16 || !bf16_rollout_possible(c))) return OIC_EINVAL;
+  std::lock_guard<std::mutex> guard(resource_mutex());
+  oic_group* g = new (std::nothrow) oic_group();
+  if (!g) return OIC_ENOMEM;
+  g->cfg = c;
+  g->slots = slots;
+  g->slab = group_slab_bytes(c);
+  int rc = OIC_OK;
+  if (hipMalloc((void**)&g->region, g->slab * slots) != hipSuccess) {
+    g->region = nullptr;
+    rc = OIC_ENOMEM;
+  }
+  for (int i = 0; i < slots && !rc; ++i) {
+    oic_ctx* h = nullptr;
+    rc = create_handle(c, g->region + (size_t)i * g->slab, g->slab, &h);
+    if (!rc) g->h.push_back(h);
+  }
+  if (!rc && hipMalloc((void**)&g->dactive, slots * sizeof(int)) != hipSuccess) {
+    g->dactive = nullptr;
+    rc = OIC_ENOMEM;
+  }
+  if (!rc && (hipHostMalloc((void**)&g->hactive, slots * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+              hipHostMalloc((void**)&g->hflags, slots * sizeof(int), hipHostMallocDefault) != hipSuccess))
+    rc = OIC_ENOMEM;
+  if (rc) {
+    for (oic_ctx* h : g->h) destroy_handle(h);
+    if (g->region) hipFree(g->region);
+    if (g->dactive) hipFree(g->dactive);
+    if (g->hactive) hipHostFree(g->hactive);
+    if (g->hflags) hipHostFree(g->hflags);
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return OIC_OK;
+}
+
+void oic_group_destroy(oic_group_handle g) {
+  if (!g) return;
+  std::lock_guard<std::mutex> guard(resource_mutex());
+  for (oic_ctx* h : g->h) hipStreamSynchronize(h->stream);
+  if (g->gexec) hipGraphExecDestroy(g->gexec);
+  for (oic_ctx* h : g->h) destroy_handle(h);
+  hipFree(g->region);
+  hipFree(g->dactive);
+  hipHostFree(g->hactive);
+  hipHostFree(g->hflags);
+  delete g;
+}
+
+oic_handle oic_group_slot(oic_group_handle g, int slot) {
+  return g && slot >= 0 && slot < g->slots ? g->h[slot] : nullptr;
+}
+
+const char* oic_group_last_error(oic_group_handle g) { return g ? g->err.c_str() : "NULL group"; }
+
+int oic_group_solve(oic_group_handle g, int count, const int* slots, const oic_solve_args* args, int* rc_out) {
+  if (!g) return OIC_EINVAL;
+  g->err.clear();
+  if (count < 1 || count > g->slots || !slots || !args) {
+    g->err = "count must be 1 .. slots, with slots and args given";
+    return OIC_EINVAL;
+  }
+  std::vector<char> on(g->slots, 0);
+  for (int i = 0; i < count; ++i) {
+    if (slots[i] < 0 || slots[i] >= g->slots || on[slots[i]]) {
+      g->err = "slot indices must be distinct and below the group's slot count";
+      return OIC_EINVAL;
+    }
+    on[slots[i]] = 1;
+  }
+  std::vector<int> rcs(count, OIC_OK);
+  auto report = [&]() {
+    int first = OIC_OK;
+    for (int i = 0; i < count; ++i) {
+      if (rc_out) rc_out[i] = rcs[i];
+      if (rcs[i] && !first) {
+        first = rcs[i];
+        g->err = "slot " + std::to_string(slots[i]) + ": " + g->h[slots[i]]->err;
+      }
+    }
+    return first;
+  };
+  if (count == 1) {  // one request: the slot's own solve
+    rcs[0] = solve_impl(g->h[slots[0]], &args[0]);
+    return report();
+  }
+  oic_ctx* h0 = g->h[0];
+  hipStream_t s = h0->stream;
+  // inputs of every request into its slot, on slot 0's stream; the batch's N, horizon,
+  // noise source and factor layout come from its first request that passes the checks
+  Dims d{};
+  bool seeded = false, qd = true, rd = true, have = false;
+  for (int i = 0; i < count; ++i) {
+    oic_ctx* h = g->h[slots[i]];
+    on[slots[i]] = 0;
+    if (h->con_on || h->want_cov || h->timer.enabled) {
+      rcs[i] = fail(h, OIC_EINVAL, "grouped solves take no constraint, covariance outputs or timing");
+      continue;
+    }
+    Dims di{};
+    bool si = false;
+    rcs[i] = solve_begin(h, &args[i], s, di, si);
+    if (rcs[i]) continue;
+    if (!have) {
+      d = di;
+      seeded = si;
+      qd = h->q_diag;
+      rd = h->r_diag;
+      have = true;
+    } else if (di.N != d.N || di.H != d.H || si != seeded || h->q_diag != qd || h->r_diag != rd) {
+      rcs[i] = fail(h, OIC_EINVAL, "N, horizon, noise source or Q/R structure differs from the batch's");
+      continue;
+    }
+    on[slots[i]] = 1;
+  }
+  if (!have) return report();
+  for (int k = 0; k < g->slots; ++k) g->hactive[k] = on[k];
+  int rc = OIC_OK;
+  hipError_t e = hipMemcpyAsync(g->dactive, g->hactive, g->slots * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    g->err = std::string("hipMemcpyAsync: ") + hipGetErrorString(e);
+    return OIC_EDEVICE;
+  }
+  {
+    // the kernels of the solve, once for all slots
+    LaunchGroup& lg = launch_group();
+    lg = LaunchGroup{(unsigned)g->slots, Grp{g->slab, g->dactive}, false};
+    struct Reset {
+      ~Reset() { launch_group() = LaunchGroup{}; }
+    } reset;
+    if (h0->use_graph) {
+      if (!g->gexec || g->gN != d.N || g->gH != d.H || g->gSeeded != seeded || g->gQd != qd || g->gRd != rd) {
+        std::lock_guard<std::mutex> guard(resource_mutex());
+        rc = capture_solve(h0, s, &g->gexec, d, seeded, RM_BF16, qd, rd);
+        if (!rc && lg.unsupported) {
+          hipGraphExecDestroy(g->gexec);
+          g->gexec = nullptr;
+        }
+        g->gN = d.N;
+        g->gH = d.H;
+        g->gSeeded = seeded;
+        g->gQd = qd;
+        g->gRd = rd;
+      }
+      if (!rc && g->gexec && hipGraphLaunch(g->gexec, s) != hipSuccess) rc = OIC_EDEVICE;
+    } else {
+      enqueue_solve(h0, d, seeded, RM_BF16, qd, rd);
+    }
+    if (rc) {
+      g->err = "capture of the grouped solve failed: " + h0->err;
+      hipStreamSynchronize(s);
+      return rc;
+    }
+    if (lg.unsupported) {
+      g->err = "this configuration's solve uses a kernel without a grouped form";
+      hipStreamSynchronize(s);
+      return OIC_EINVAL;
+    }
+  }
+  for (int i = 0; i < count; ++i)
+    if (!rcs[i]) rcs[i] = solve_end(g->h[slots[i]], &args[i], s, &g->hflags[slots[i]]);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    g->err = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
+    return OIC_EDEVICE;
+  }
+  for (int i = 0; i < count; ++i)
+    if (!rcs[i]) rcs[i] = solve_finish(g->h[slots[i]], &args[i], s, g->hflags[slots[i]]);
+  return report();
 }
 
 int oic_set_graph(oic_handle h, int enable) {

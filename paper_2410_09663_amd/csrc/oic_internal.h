@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/oic.h"
@@ -84,6 +85,35 @@ struct Dims {
   __host__ __device__ long long NM() const { return (long long)N * m; }
 };
 
+// ---- grouped launches ----
+// A group is a set of handles of one configuration whose device buffers all sit at the
+// same offsets inside equal slabs, slot g's slab `stride` bytes after slot 0's.  One
+// launch then serves every slot: its grid is the plain grid repeated over blockIdx.z =
+// slot, every buffer address a kernel receives is slot 0's and the kernel moves it by
+// blockIdx.z * stride, and a slot whose entry in `active` is 0 leaves at once (the same
+// captured launches serve any subset of the slots).  Each slot's workgroups do exactly
+// what the plain launch does on that slot's buffers, so a slot's results do not depend
+// on the other slots.  A plain launch has one z-slice, stride 0 and no mask.
+struct Grp {
+  unsigned long long stride;
+  const int* active;
+};
+// The group the launches of the calling thread go to (one slot and no mask by default).
+// Launchers of kernels with a grouped form repeat their grid over `slots` z-slices and
+// pass `g`; any other launch made while slots > 1 is not made and sets `unsupported`.
+struct LaunchGroup {
+  unsigned slots = 1;
+  Grp g{0, nullptr};
+  bool unsupported = false;
+};
+LaunchGroup& launch_group();
+
+template <typename T>
+__device__ __forceinline__ T* gshift(T* p, unsigned long long off) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<typename std::remove_const<T>::type*>(p)) + off)
+           : p;
+}
+
 // ---- kernel launchers (defined in the .hip files) ----
 void launch_normals(hipStream_t s, Timer& t, float* out, size_t count, const uint64_t* seed,
                     uint32_t kind);
@@ -131,6 +161,29 @@ struct FieldOut {
   float* base;
   long long si, sy;
 };
+__device__ __forceinline__ NoiseRef gshift(NoiseRef r, unsigned long long off) {
+  r.Z = gshift(r.Z, off);
+  r.diag = gshift(r.diag, off);
+  r.L = gshift(r.L, off);
+  return r;
+}
+__device__ __forceinline__ ObserveArgs gshift(ObserveArgs o, unsigned long long off) {
+  o.U_cur = gshift(o.U_cur, off);
+  o.Y = gshift(o.Y, off);
+  o.w = gshift(o.w, off);
+  o.vx = gshift(o.vx, off);
+  o.vu = gshift(o.vu, off);
+  return o;
+}
+__device__ __forceinline__ FieldRef gshift(FieldRef f, unsigned long long off) {
+  f.base = gshift(f.base, off);
+  return f;
+}
+__device__ __forceinline__ FieldOut gshift(FieldOut f, unsigned long long off) {
+  f.base = gshift(f.base, off);
+  return f;
+}
+
 void launch_lift(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
                  const float* B, float* out_nhwc);
 void launch_conv(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
@@ -182,6 +235,8 @@ bool bf16_rollout_possible(const oic_config& c);
 size_t activation_floats(const oic_config& c);
 // Device bytes a handle created with c holds (the serving admission footprint).
 size_t handle_bytes(const oic_config& c);
+// Device bytes of one slot of a group created with c (the stride of its grouped launches).
+size_t group_slab_bytes(const oic_config& c);
 bool conv_mfma_supported(int cin, int cout);
 void launch_conv_mfma(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
                       const float* in_nhwc, const float* wk, const float* bias, int act,
@@ -255,9 +310,34 @@ void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj
 }  // namespace oic
 
 // Launch `kernel` on `stream`, bracketed by timing events of class `cls` when enabled.
+// A kernel without a grouped form is not launched inside a group (see LaunchGroup).
 #define OIC_LAUNCH(timer, cls, stream, kernel, grid, block, shmem, ...)          \
   do {                                                                         \
+    if (::oic::launch_group().slots > 1) {                                     \
+      ::oic::launch_group().unsupported = true;                                \
+      break;                                                                   \
+    }                                                                          \
     int oic_ti_ = (timer).begin((cls), (stream));                              \
     hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);       \
     (timer).end(oic_ti_, (stream));                                            \
   } while (0)
+
+// Launch a kernel that has a grouped form (its last parameter is a Grp, its body starts
+// with OIC_GROUP_ENTER): the grid is repeated over the calling thread's group slots.
+#define OIC_GLAUNCH(timer, cls, stream, kernel, grid, block, shmem, ...)                 \
+  do {                                                                                 \
+    const ::oic::LaunchGroup& oic_lg_ = ::oic::launch_group();                         \
+    dim3 oic_gr_ = (grid);                                                             \
+    oic_gr_.z *= oic_lg_.slots;                                                        \
+    int oic_ti_ = (timer).begin((cls), (stream));                                      \
+    hipLaunchKernelGGL(kernel, oic_gr_, block, shmem, stream, __VA_ARGS__, oic_lg_.g); \
+    (timer).end(oic_ti_, (stream));                                                    \
+  } while (0)
+
+// First statement of a kernel with a grouped form: leave if this slot is not active,
+// else the byte offset of this slot's buffers is oic_goff_ (move each address with
+// OIC_GSH).
+#define OIC_GROUP_ENTER(grp)                                          \
+  if ((grp).active && !(grp).active[blockIdx.z]) return;              \
+  const unsigned long long oic_goff_ = (unsigned long long)blockIdx.z * (grp).stride
+#define OIC_GSH(x) x = ::oic::gshift(x, oic_goff_)

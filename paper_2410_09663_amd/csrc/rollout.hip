@@ -745,7 +745,12 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32r(int N, int n, int m, const
 // field; writes the strided field and, with obs.Y, the X rows of Ybar (Eq. (12)).
 __global__ __launch_bounds__(256) void k_conv_last_sum(int N, int n, int m, const float* __restrict__ q,
                                                        const float* __restrict__ bias, FieldOut fo,
-                                                       ObserveArgs obs) {
+                                                       ObserveArgs obs, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(q);
+  OIC_GSH(bias);
+  OIC_GSH(fo);
+  OIC_GSH(obs);
   const long long plane = (long long)N * n * m;
   const int x = blockIdx.y * 256 + threadIdx.x;
   const int y = blockIdx.x % n, i = blockIdx.x / n;
@@ -777,7 +782,16 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
                                                     const float* __restrict__ w,
                                                     const float* __restrict__ bias, int act,
                                                     TOUT* __restrict__ out, unsigned* __restrict__ amax,
-                                                    ObserveArgs obs) {
+                                                    ObserveArgs obs, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(X);
+  OIC_GSH(U);
+  OIC_GSH(B);
+  OIC_GSH(w);
+  OIC_GSH(bias);
+  OIC_GSH(out);
+  OIC_GSH(amax);
+  OIC_GSH(obs);
   constexpr int TR = 4, TC = 64, HR = TR + 2, HC = TC + 2;
   constexpr int LMAX = 64;
   __shared__ float s_x[HR * HC];
@@ -1025,7 +1039,13 @@ template <int CIN, typename TIN>
 __global__ __launch_bounds__(256) void k_conv_last(int N, int n, int m, const TIN* __restrict__ in,
                                                    const float* __restrict__ w,
                                                    const float* __restrict__ bias, FieldOut fo,
-                                                   ObserveArgs obs) {
+                                                   ObserveArgs obs, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(in);
+  OIC_GSH(w);
+  OIC_GSH(bias);
+  OIC_GSH(fo);
+  OIC_GSH(obs);
   constexpr int TR = 4, TC = 64, HR = TR + 2, HC = TC + 2, CP = CIN + 1;
   __shared__ __attribute__((aligned(16))) float s_in[HR * HC * CP];
   __shared__ float s_w[9 * CIN];
@@ -1131,7 +1151,13 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
                                                         const bf16_t* __restrict__ wt,
                                                         const float* __restrict__ bias, int act,
                                                         bf16_t* __restrict__ out,
-                                                        const bf16_t* __restrict__ wl2) {
+                                                        const bf16_t* __restrict__ wl2, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(in);
+  OIC_GSH(wt);
+  OIC_GSH(bias);
+  OIC_GSH(out);
+  OIC_GSH(wl2);
   constexpr int TC = 64;
   constexpr int HR = TR + 2, HC = TC + 2;
   constexpr int CP = CIN + 8;
@@ -1291,7 +1317,14 @@ template <int CIN, int COUT, int TR, bool LASTQ>
 __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, const bf16_t* __restrict__ in,
                                                        const bf16_t* __restrict__ wt,
                                                        const float* __restrict__ bias, int act,
-                                                       bf16_t* __restrict__ out, const bf16_t* __restrict__ wl2) {
+                                                       bf16_t* __restrict__ out, const bf16_t* __restrict__ wl2,
+                                                       Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(in);
+  OIC_GSH(wt);
+  OIC_GSH(bias);
+  OIC_GSH(out);
+  OIC_GSH(wl2);
   static_assert(CIN % 32 == 0 && COUT % 32 == 0, "32-channel K steps and channel groups");
   constexpr int TC = 64, HR = TR + 2, HC = TC + 2;
   constexpr int NG = COUT / 32;          // channel groups (one per wave of a row group)
@@ -1696,10 +1729,10 @@ void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, Fiel
 #define OIC_FIRST_CASE(CO)                                                                        \
   if (cout == CO) {                                                                               \
     if (bf16)                                                                                     \
-      OIC_LAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, bf16_t>), dim3(blocks), dim3(256), 0, N, n, \
+      OIC_GLAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, bf16_t>), dim3(blocks), dim3(256), 0, N, n, \
                  m, l, X, U, B, w, bias, act, (bf16_t*)out_nhwc, amax, oa);                       \
     else                                                                                          \
-      OIC_LAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, float>), dim3(blocks), dim3(256), 0, N, n,  \
+      OIC_GLAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, float>), dim3(blocks), dim3(256), 0, N, n,  \
                  m, l, X, U, B, w, bias, act, (float*)out_nhwc, amax, oa);                        \
     return;                                                                                       \
   }
@@ -1717,10 +1750,10 @@ void launch_conv_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, con
 #define OIC_LAST_CASE(CI)                                                                         \
   if (cin == CI) {                                                                                \
     if (bf16)                                                                                     \
-      OIC_LAUNCH(t, KC_CONV_LAST, s, (k_conv_last<CI, bf16_t>), dim3(blocks), dim3(256), 0, N, n, m, \
+      OIC_GLAUNCH(t, KC_CONV_LAST, s, (k_conv_last<CI, bf16_t>), dim3(blocks), dim3(256), 0, N, n, m, \
                  (const bf16_t*)in_nhwc, w, bias, fo, oa);                                        \
     else                                                                                          \
-      OIC_LAUNCH(t, KC_CONV_LAST, s, (k_conv_last<CI, float>), dim3(blocks), dim3(256), 0, N, n, m,  \
+      OIC_GLAUNCH(t, KC_CONV_LAST, s, (k_conv_last<CI, float>), dim3(blocks), dim3(256), 0, N, n, m,  \
                  (const float*)in_nhwc, w, bias, fo, oa);                                         \
     return;                                                                                       \
   }
@@ -1764,7 +1797,7 @@ void launch_bf16r(hipStream_t s, Timer& t, int kclass, int N, int n, int m, cons
   const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);
   const long long cap = 2LL * 256;
   const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
-  OIC_LAUNCH(t, kclass, s, (k_conv_bf16r<CI, CO, TRV, LASTQ>), dim3(blocks), dim3(256), 0, N, n, m,
+  OIC_GLAUNCH(t, kclass, s, (k_conv_bf16r<CI, CO, TRV, LASTQ>), dim3(blocks), dim3(256), 0, N, n, m,
              (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out, (const bf16_t*)wl2);
 }
 
@@ -1788,7 +1821,7 @@ void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, in
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
     const long long cap = 256LL * resident_per_cu<kern>(256 * WG); /* persistent */             \
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                               \
-    OIC_LAUNCH(t, kclass, s, kern, dim3(blocks), dim3(256 * WG), 0, N, n, m,                     \
+    OIC_GLAUNCH(t, kclass, s, kern, dim3(blocks), dim3(256 * WG), 0, N, n, m,                    \
                (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out_nhwc, nullptr); \
     return;                                                                                      \
   }
@@ -1811,7 +1844,7 @@ void launch_conv_mfma_bf16_last(hipStream_t s, Timer& t, int N, int n, int m, in
     if (cin == 64) launch_bf16r<64, 64, true>(s, t, KC_CONV_MID, N, n, m, in_nhwc, wt, bias, act, qbuf, wl2);
     else launch_bf16r<32, 64, true>(s, t, KC_CONV_MID, N, n, m, in_nhwc, wt, bias, act, qbuf, wl2);
     const ObserveArgs oa = obs ? *obs : ObserveArgs{};
-    OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+    OIC_GLAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
                0, N, n, m, qbuf, bias_last, fo, oa);
     return;
   }
@@ -1822,14 +1855,14 @@ void launch_conv_mfma_bf16_last(hipStream_t s, Timer& t, int N, int n, int m, in
     const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);             \
     const long long cap = 256LL * resident_per_cu<kern>(256 * kBf16GroupsWide);                  \
     const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);                               \
-    OIC_LAUNCH(t, KC_CONV_MID, s, kern, dim3(blocks), dim3(256 * kBf16GroupsWide), 0, N, n, m,    \
+    OIC_GLAUNCH(t, KC_CONV_MID, s, kern, dim3(blocks), dim3(256 * kBf16GroupsWide), 0, N, n, m,   \
                (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)qbuf, (const bf16_t*)wl2); \
   }
   OIC_BFL_CASE(32)
   OIC_BFL_CASE(64)
 #undef OIC_BFL_CASE
   const ObserveArgs oa = obs ? *obs : ObserveArgs{};
-  OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+  OIC_GLAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
              0, N, n, m, qbuf, bias_last, fo, oa);
 }
 
@@ -1885,7 +1918,7 @@ void launch_conv_mfma_fp8_last(hipStream_t s, Timer& t, int N, int n, int m, int
   OIC_F8L_CASE(64)
 #undef OIC_F8L_CASE
   const ObserveArgs oa = obs ? *obs : ObserveArgs{};
-  OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+  OIC_GLAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
              0, N, n, m, qbuf, bias_last, fo, oa);
 }
 
@@ -1968,7 +2001,7 @@ void launch_conv_mfma_last(hipStream_t s, Timer& t, int N, int n, int m, int cin
     OIC_LAUNCH(t, KC_CONV_MID, s, (k_conv_f32r<32, TRV, true>), dim3(blocks), dim3(256), 0, N, n, m, in_nhwc, wk,
                bias, act, qbuf, w_last);
   const ObserveArgs oa = obs ? *obs : ObserveArgs{};
-  OIC_LAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
+  OIC_GLAUNCH(t, KC_CONV_LAST, s, k_conv_last_sum, dim3((unsigned)(N * n), (unsigned)((m + 255) / 256)), dim3(256),
              0, N, n, m, qbuf, bias_last, fo, oa);
 }
 

@@ -14,7 +14,10 @@ namespace oic {
 namespace {
 
 // mean[row][x] = (1/N) sum_i A[row][i*m + x], accumulated in FP64.
-__global__ void k_means(const float* __restrict__ A, int rows, int N, int m, float* __restrict__ mean) {
+__global__ void k_means(const float* __restrict__ A, int rows, int N, int m, float* __restrict__ mean, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(mean);
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)rows * m) return;
   const int row = (int)(idx / m), x = (int)(idx - (long long)row * m);
@@ -28,7 +31,10 @@ __global__ void k_means(const float* __restrict__ A, int rows, int N, int m, flo
 // its members in FP64, and the 256/m partial sums of each column are added in a
 // fixed order in LDS.
 __global__ __launch_bounds__(256) void k_means_rows(const float* __restrict__ A, int N, int m,
-                                                    float* __restrict__ mean) {
+                                                    float* __restrict__ mean, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(mean);
   __shared__ double part[256];
   const int row = blockIdx.x;
   const long long NM = (long long)N * m;
@@ -53,7 +59,10 @@ typedef float f32x4m __attribute__((ext_vector_type(4)));
 // are added in a fixed order in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_means_rows_v4(const float* __restrict__ A, int N, int m,
-                                                       T* __restrict__ mean) {
+                                                       T* __restrict__ mean, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(mean);
   __shared__ double part[256][4];
   const int row = blockIdx.x;
   const int NM4 = (N * m) / 4;
@@ -95,7 +104,10 @@ __global__ __launch_bounds__(256) void k_means_rows_v4(const float* __restrict__
 
 // mean[row][x] in FP64 (same reduction order as k_means_rows).
 __global__ __launch_bounds__(256) void k_means_rows_f64(const float* __restrict__ A, int N, int m,
-                                                        double* __restrict__ mean) {
+                                                        double* __restrict__ mean, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(mean);
   __shared__ double part[256];
   const int row = blockIdx.x;
   const long long NM = (long long)N * m;
@@ -112,7 +124,11 @@ __global__ __launch_bounds__(256) void k_means_rows_f64(const float* __restrict_
   }
 }
 
-__global__ void k_means_f64(const float* __restrict__ A, int rows, int N, int m, double* __restrict__ mean) {
+__global__ void k_means_f64(const float* __restrict__ A, int rows, int N, int m, double* __restrict__ mean,
+                            Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(A);
+  OIC_GSH(mean);
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)rows * m) return;
   const int row = (int)(idx / m), x = (int)(idx - (long long)row * m);
@@ -539,7 +555,12 @@ template <int NB>
 __global__ __launch_bounds__(64 * SV_W) void k_stats_b3(Dims d, const float* __restrict__ traj, int Ma, int ny,
                                                         const float* __restrict__ Y, const float* __restrict__ Rc,
                                                         int p, int chunk, int xt, int ytiles, int tiles,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(traj);
+  OIC_GSH(Y);
+  OIC_GSH(Rc);
+  OIC_GSH(part);
   constexpr int RB = NB * 16, NT = 64 * SV_W;
   const int G = gridDim.x;
   const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
@@ -652,7 +673,12 @@ __global__ __launch_bounds__(64 * SV_W) void k_stats_b3(Dims d, const float* __r
 // in every workgroup's staging (there its FP64 mean loads sat between each stage's loads
 // and its barrier).
 __global__ __launch_bounds__(256) void k_center_rows(const float* __restrict__ R, int rows, int NM, int m,
-                                                     const double* __restrict__ mu, float* __restrict__ Rc) {
+                                                     const double* __restrict__ mu, float* __restrict__ Rc,
+                                                     Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(R);
+  OIC_GSH(mu);
+  OIC_GSH(Rc);
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;  // float4 index
   const long long total = (long long)rows * NM / 4;
   if (q >= total) return;
@@ -677,7 +703,10 @@ __global__ __launch_bounds__(256) void k_center_rows(const float* __restrict__ R
 constexpr int RG = 8;
 __global__ __launch_bounds__(64 * RG) void k_stats_reduce(const double* __restrict__ part, int splits,
                                                           long long count, double scale,
-                                                          double* __restrict__ S) {
+                                                          double* __restrict__ S, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(part);
+  OIC_GSH(S);
   __shared__ double sub[RG][64];
   const long long idx = (long long)blockIdx.x * 64 + threadIdx.x;
   const int y = threadIdx.y;
@@ -711,14 +740,14 @@ void launch_means(hipStream_t s, Timer& t, const float* A, int rows, int N, int 
   const long long total = (long long)rows * m;
   if (!total) return;
   if (means_v4_ok(N, m)) {
-    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows_v4<float>, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    OIC_GLAUNCH(t, KC_MEANS, s, k_means_rows_v4<float>, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
     return;
   }
   if (m <= 256 && 256 % m == 0) {
-    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    OIC_GLAUNCH(t, KC_MEANS, s, k_means_rows, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
     return;
   }
-  OIC_LAUNCH(t, KC_MEANS, s, k_means, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, A, rows,
+  OIC_GLAUNCH(t, KC_MEANS, s, k_means, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, A, rows,
              N, m, mean);
 }
 
@@ -726,21 +755,21 @@ void launch_means_f64(hipStream_t s, Timer& t, const float* A, int rows, int N, 
   const long long total = (long long)rows * m;
   if (!total) return;
   if (means_v4_ok(N, m)) {
-    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows_v4<double>, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    OIC_GLAUNCH(t, KC_MEANS, s, k_means_rows_v4<double>, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
     return;
   }
   if (m <= 256 && 256 % m == 0) {
-    OIC_LAUNCH(t, KC_MEANS, s, k_means_rows_f64, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
+    OIC_GLAUNCH(t, KC_MEANS, s, k_means_rows_f64, dim3((unsigned)rows), dim3(256), 0, A, N, m, mean);
     return;
   }
-  OIC_LAUNCH(t, KC_MEANS, s, k_means_f64, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, A,
+  OIC_GLAUNCH(t, KC_MEANS, s, k_means_f64, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, A,
              rows, N, m, mean);
 }
 
 void launch_center(hipStream_t s, Timer& t, const float* R, int rows, int NM, int m, const double* mu,
                    float* Rc) {
   const long long total = (long long)rows * NM / 4;
-  OIC_LAUNCH(t, KC_MEANS, s, k_center_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, R, rows, NM, m,
+  OIC_GLAUNCH(t, KC_MEANS, s, k_center_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, R, rows, NM, m,
              mu, Rc);
 }
 
@@ -798,7 +827,7 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 #define OIC_SV_CASE(NBV)                                                                                 \
   case NBV:                                                                                              \
     if (Rc && b3)                                                                                        \
-      OIC_LAUNCH(t, KC_STATS, s, k_stats_b3<NBV>, grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, Rc, p, chunk, \
+      OIC_GLAUNCH(t, KC_STATS, s, k_stats_b3<NBV>, grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, Rc, p, chunk, \
                  xt, ytiles, all, part);                                                                 \
     else if (Rc)                                                                                         \
       OIC_LAUNCH(t, KC_STATS, s, (k_stats_v4<NBV, true>), grid, dim3(64 * SV_W), 0, d, traj, Ma, ny, Y, Rc, p, \
@@ -812,7 +841,7 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 #undef OIC_SV_CASE
     }
     const long long count = (long long)Mtot * p;
-    OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 63) / 64)), dim3(64, RG), 0,
+    OIC_GLAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 63) / 64)), dim3(64, RG), 0,
                part, splits, count, scale, S);
     return;
   }
@@ -893,7 +922,7 @@ void launch_cross(hipStream_t s, Timer& t, const Dims& d, const float* traj, int
 #undef OIC_STATS_LAUNCH
 #undef OIC_STATS_LAUNCH_NV
   const long long count = (long long)Mtot * p;
-  OIC_LAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 63) / 64)), dim3(64, RG), 0,
+  OIC_GLAUNCH(t, KC_STATS_REDUCE, s, k_stats_reduce, dim3((unsigned)((count + 63) / 64)), dim3(64, RG), 0,
              part, splits, count, scale, S);
 }
 

@@ -109,7 +109,12 @@ template <int WR>  // waves along the rows: tiles of 16 WR rows
 __global__ __launch_bounds__(64 * WR) void k_update_rows(Dims d, float* __restrict__ traj, int Ma,
                                                      const float* __restrict__ K,
                                                      const float* __restrict__ Y,
-                                                     const float* __restrict__ xref) {
+                                                     const float* __restrict__ xref, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(traj);
+  OIC_GSH(K);
+  OIC_GSH(Y);
+  OIC_GSH(xref);
   constexpr int NT = 64 * WR, TR_ = 16 * WR;
   __shared__ float sK[TR_][PB + 1];
   __shared__ float sE[PB][UC + 1];
@@ -303,7 +308,10 @@ __device__ __forceinline__ void split2u(float v0, float v1, unsigned& hi, unsign
 // rows16 x P16 BF16 values (rows16 = Ma rounded up to 16), zeros past Ma and p.  One
 // thread per 8 consecutive values of a row.
 __global__ void k_split_gain(const float* __restrict__ K, int Ma, int p, int rows16, int P16,
-                             __bf16* __restrict__ Khl) {
+                             __bf16* __restrict__ Khl, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(K);
+  OIC_GSH(Khl);
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int groups = P16 / 8;
   if (e >= (long long)rows16 * groups) return;
@@ -333,7 +341,13 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_update_strip_b3(Dims d, fl
                                                                   const float* __restrict__ K,
                                                                   const __bf16* __restrict__ Khl,
                                                                   const float* __restrict__ Y,
-                                                                  const float* __restrict__ xref) {
+                                                                  const float* __restrict__ xref, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(traj);
+  OIC_GSH(K);
+  OIC_GSH(Khl);
+  OIC_GSH(Y);
+  OIC_GSH(xref);
   constexpr int NT = 64 * kStripWaves;
   constexpr int EP = P16 + 8;  // BF16 elements per column of a plane
   constexpr int S = P16 / 32;
@@ -436,7 +450,12 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_update_strip_b3(Dims d, fl
 
 // Smoothed means of every slice -> U_out (H+1, l, m), X_out (H+1, n, m) and U_hat_k.
 __global__ void k_extract(Dims d, const float* __restrict__ mu, float* __restrict__ Uout,
-                          float* __restrict__ Xout, float* __restrict__ Uprev) {
+                          float* __restrict__ Xout, float* __restrict__ Uprev, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(mu);
+  OIC_GSH(Uout);
+  OIC_GSH(Xout);
+  OIC_GSH(Uprev);
   const int rr = d.rr(), m = d.m, n = d.n, l = d.l;
   const long long total = (long long)(d.H + 1) * rr * m;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -465,7 +484,7 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
     // about two workgroups per CU (the register budget allows two) on 256 CUs
     const unsigned want = (512 + col_tiles - 1) / col_tiles;
     const unsigned groups = row_tiles < want ? row_tiles : want;
-    OIC_LAUNCH(t, KC_UPDATE, s, k_update_rows<WR>, dim3(col_tiles, groups), dim3(64 * WR), 0, d, traj, Ma, K, Y,
+    OIC_GLAUNCH(t, KC_UPDATE, s, k_update_rows<WR>, dim3(col_tiles, groups), dim3(64 * WR), 0, d, traj, Ma, K, Y,
                xref_t);
     return;
   }
@@ -480,10 +499,10 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
         if (scratch && (size_t)2 * rows16 * P16V * 2 <= scratch_bytes) {                                \
           khl = reinterpret_cast<__bf16*>(scratch);                                                     \
           const long long items = (long long)rows16 * (P16V / 8);                                      \
-          OIC_LAUNCH(t, KC_UPDATE, s, k_split_gain, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, K, Ma, \
+          OIC_GLAUNCH(t, KC_UPDATE, s, k_split_gain, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, K, Ma, \
                      d.p(), rows16, P16V, khl);                                                         \
         }                                                                                               \
-        OIC_LAUNCH(t, KC_UPDATE, s, k_update_strip_b3<P16V>, dim3(strips), dim3(64 * kStripWaves), 0, d, \
+        OIC_GLAUNCH(t, KC_UPDATE, s, k_update_strip_b3<P16V>, dim3(strips), dim3(64 * kStripWaves), 0, d, \
                    traj, Ma, K, khl, Y, xref_t);                                                        \
         return;                                                                                         \
       }                                                                                                 \
@@ -509,7 +528,7 @@ void launch_update(hipStream_t s, Timer& t, const Dims& d, float* traj, int Ma, 
 void launch_extract(hipStream_t s, Timer& t, const Dims& d, const float* mu_traj, float* Uout,
                     float* Xout, float* Uprev) {
   const long long total = (long long)(d.H + 1) * d.rr() * d.m;
-  OIC_LAUNCH(t, KC_EXTRACT, s, k_extract, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, d,
+  OIC_GLAUNCH(t, KC_EXTRACT, s, k_extract, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, d,
              mu_traj, Uout, Xout, Uprev);
 }
 

@@ -128,6 +128,13 @@ def lib():
             "oic_server_last_error": (ctypes.c_char_p, [vp]),
             "oic_footprint_bytes": (cs, [ctypes.POINTER(oic_config)]),
             "oic_stage_cost": (ci, [ci, ci, ci, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]),
+            "oic_group_footprint_bytes": (cs, [ctypes.POINTER(oic_config), ci]),
+            "oic_group_create": (ci, [ctypes.POINTER(oic_config), ci, ctypes.POINTER(vp)]),
+            "oic_group_destroy": (None, [vp]),
+            "oic_group_slot": (vp, [vp, ci]),
+            "oic_group_solve": (ci, [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(oic_solve_args),
+                                     ctypes.POINTER(ci)]),
+            "oic_group_last_error": (ctypes.c_char_p, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -152,7 +159,8 @@ EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "o
             "oic_normals", "oic_timing", "oic_kernel_class_count", "oic_kernel_stats", "oic_stream",
             "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
             "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
-            "oic_footprint_bytes", "oic_stage_cost"]
+            "oic_footprint_bytes", "oic_stage_cost", "oic_group_footprint_bytes", "oic_group_create",
+            "oic_group_destroy", "oic_group_slot", "oic_group_solve", "oic_group_last_error"]
 
 
 def _is_torch(x) -> bool:
@@ -167,27 +175,30 @@ class Controller:
                  max_N: int, max_H: int, precision: int = OIC_PREC_FP32,
                  mem_mode: int = OIC_MEM_HOST, stream: Optional[int] = None):
         self._h = None
-        cfg = oic_config()
-        cfg.n, cfg.m, cfg.l = n, m, l
-        cfg.n_layers = len(channels) - 1
-        for k, c in enumerate(channels):
-            cfg.channels[k] = c
-        cfg.activation, cfg.precision = activation, precision
-        cfg.max_N, cfg.max_H, cfg.mem_mode = max_N, max_H, mem_mode
-        if stream is None and mem_mode == OIC_MEM_DEVICE:
-            # device mode reads caller tensors: order the work after torch's queued kernels
-            import torch
-            stream = torch.cuda.current_stream().cuda_stream
-        cfg.stream = stream
+        cfg = _config(n, m, l, channels, activation, max_N, max_H, precision, mem_mode, stream)
         h = ctypes.c_void_p()
         rc = lib().oic_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != OIC_OK:
             raise OicError(rc, "oic_create failed")
         self._h = h
+        self._owned = True
         self.n, self.m, self.l = n, m, l
         self.channels = list(channels)
         self.mem_mode = mem_mode
         self.max_N, self.max_H = max_N, max_H
+
+    @classmethod
+    def _slot(cls, h, cfg, owner):
+        """The handle of a group slot (owned by the group `owner`, kept alive here)."""
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p(h)
+        self._owned = False
+        self._owner = owner
+        self.n, self.m, self.l = cfg.n, cfg.m, cfg.l
+        self.channels = [cfg.channels[k] for k in range(cfg.n_layers + 1)]
+        self.mem_mode = cfg.mem_mode
+        self.max_N, self.max_H = cfg.max_N, cfg.max_H
+        return self
 
     # -- helpers -------------------------------------------------------------
     def _check(self, rc: int):
@@ -271,6 +282,15 @@ class Controller:
                  noise=None, want_X: bool = True, Z_VZ=None, U_out=None, X_out=None):
         """Solve with explicit noise (a workloads.Noise or a 4-tuple) or, if noise is None,
         the seeded stream.  Returns (U_hat, X_hat), written into U_out / X_out if given."""
+        a, keep, U_out, X_out = self._args(X0, reference, Q, R, N, H, seed, U_prev, noise, want_X, Z_VZ,
+                                           U_out, X_out)
+        self._check(lib().oic_solve_ex(self._h, ctypes.byref(a)))
+        return U_out, X_out
+
+    def _args(self, X0, reference, Q, R, N, H, seed=0, U_prev=None, noise=None, want_X=True, Z_VZ=None,
+              U_out=None, X_out=None):
+        """oic_solve_args for one solve on this handle, the arrays it points to (keep them
+        alive until the call returns) and the output arrays."""
         Q = self._host(Q, (self.l, self.l))
         R = self._host(R, (self.n, self.n))
         a = oic_solve_args()
@@ -292,8 +312,7 @@ class Controller:
             X_out = self._new((H + 1, self.n, self.m))
         a.U_out = self._ptr(U_out, (H + 1, self.l, self.m), True)
         a.X_out = self._ptr(X_out, (H + 1, self.n, self.m), True) if X_out is not None else None
-        self._check(lib().oic_solve_ex(self._h, ctypes.byref(a)))
-        return U_out, X_out
+        return a, (Q, R), U_out, X_out
 
     def solve_cov(self, X0, reference, Q, R, N: int, H: int, seed: int = 0, U_prev=None, noise=None,
                   Z_VZ=None):
@@ -404,8 +423,87 @@ class Controller:
 
     def close(self):
         if self._h is not None:
-            lib().oic_destroy(self._h)
+            if self._owned:
+                lib().oic_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _config(n, m, l, channels, activation, max_N, max_H, precision, mem_mode, stream) -> oic_config:
+    cfg = oic_config()
+    cfg.n, cfg.m, cfg.l = n, m, l
+    cfg.n_layers = len(channels) - 1
+    for k, c in enumerate(channels):
+        cfg.channels[k] = c
+    cfg.activation, cfg.precision = activation, precision
+    cfg.max_N, cfg.max_H, cfg.mem_mode = max_N, max_H, mem_mode
+    if stream is None and mem_mode == OIC_MEM_DEVICE:
+        # device mode reads caller tensors: order the work after torch's queued kernels
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    cfg.stream = stream
+    return cfg
+
+
+class Group:
+    """oic_group: `slots` handles of one configuration whose solves run in shared launches.
+    group.slots[i] is slot i's Controller (weights, U_prev, solves of its own)."""
+
+    def __init__(self, n: int, m: int, l: int, channels: Sequence[int], activation: int,
+                 max_N: int, max_H: int, slots: int, precision: int = OIC_PREC_BF16,
+                 mem_mode: int = OIC_MEM_HOST, stream: Optional[int] = None):
+        self._g = None
+        cfg = _config(n, m, l, channels, activation, max_N, max_H, precision, mem_mode, stream)
+        g = ctypes.c_void_p()
+        rc = lib().oic_group_create(ctypes.byref(cfg), slots, ctypes.byref(g))
+        if rc != OIC_OK:
+            raise OicError(rc, "oic_group_create failed")
+        self._g = g
+        self.slots = [Controller._slot(lib().oic_group_slot(g, i), cfg, self) for i in range(slots)]
+
+    @staticmethod
+    def footprint(problem, N: int, H: int, slots: int, precision: int = OIC_PREC_BF16) -> int:
+        p = problem.preset
+        cfg = _config(p.n, p.m, p.l, p.channels, p.activation, N, H, precision, OIC_MEM_HOST, None)
+        return lib().oic_group_footprint_bytes(ctypes.byref(cfg), slots)
+
+    def solve(self, requests):
+        """One batch: requests is a list of (slot, kwargs of Controller.solve_ex).  Returns
+        the list of (U_hat, X_hat) in request order; raises OicError if any request failed
+        (rc_codes holds each request's status afterwards)."""
+        count = len(requests)
+        args = (oic_solve_args * count)()
+        slots = (ctypes.c_int * count)(*[r[0] for r in requests])
+        keep, outs = [], []
+        for i, (slot, kw) in enumerate(requests):
+            a, k, U_out, X_out = self.slots[slot]._args(**kw)
+            args[i] = a
+            keep.append(k)
+            outs.append((U_out, X_out))
+        rcs = (ctypes.c_int * count)()
+        rc = lib().oic_group_solve(self._g, count, slots, args, rcs)
+        self.rc_codes = list(rcs)
+        if rc != OIC_OK:
+            raise OicError(rc, lib().oic_group_last_error(self._g).decode())
+        return outs
+
+    def close(self):
+        if self._g is not None:
+            for c in self.slots:
+                c._h = None
+            lib().oic_group_destroy(self._g)
+            self._g = None
 
     def __del__(self):
         try:
