@@ -212,15 +212,16 @@ def cpu_baseline_sampled(p, prob, members):
 
 def serve_main(args):
     """Serving workload: many independent controllers (grids 32^2..256^2, N 64..256, H 5..20,
-    BF16 rollout) behind one request loop with continuous admission by HBM footprint.
-    Three runs over the same request list: (1) every request submitted at once (capacity,
-    solves/s); (2) Poisson arrivals at the offered rate (default 400 solves/s, above
-    capacity: latency is queue-dominated); (3) Poisson arrivals at 70% of the measured
-    capacity.  Then each distinct shape solved alone (resident, graph warm), summed over the
-    request list: the served makespan against that sum shows how much of the GPU time the
-    overlap of concurrent solves recovers.  Last, the same requests in the plain FP32
-    single-request form (one solve at a time, FP32 rollout), whose solves/s gives the
-    speed-up."""
+    BF16 rollout) behind one request loop with continuous admission by HBM footprint and
+    grouped solves of same-shape requests.  Runs over the same request list: (1) every
+    request submitted at once (capacity, solves/s); (2) Poisson arrivals at the offered rate
+    (default 400 solves/s, above capacity: latency is queue-dominated); (3) Poisson arrivals
+    at 70% of the measured capacity; (4) the requests of the grids below 256^2 alone, all at
+    once.  Runs (1) and (4) again on a server with one slot per pack (every request its own
+    solve, overlapping only as concurrent streams) give the gain of the grouped solves.
+    Then each distinct shape solved alone (resident, graph warm), summed over the request
+    list.  Last, the same requests in the plain FP32 single-request form (one solve at a
+    time, FP32 rollout), whose solves/s gives the speed-up."""
     from paper_2410_09663_amd import oic
     from paper_2410_09663_amd import workloads as wl
 
@@ -240,15 +241,16 @@ def serve_main(args):
         return (probs[c].X0 * (1.0 + 0.02 * k)).astype(np.float32), wl.reference_window(p, k), \
             p.noise_seed_base + k
 
-    def run(srv, ids, rate, seed):
-        arr = np.zeros(args.requests)
+    def run(srv, ids, rate, seed, reqs=None):
+        reqs = list(range(args.requests)) if reqs is None else reqs
+        arr = np.zeros(len(reqs))
         if rate:
-            arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, args.requests))
+            arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, len(reqs)))
         t0 = time.perf_counter()
         sub = []
-        for r in range(args.requests):
-            while time.perf_counter() - t0 < arr[r]:
-                time.sleep(min(1e-3, max(0.0, arr[r] - (time.perf_counter() - t0))))
+        for j, r in enumerate(reqs):
+            while time.perf_counter() - t0 < arr[j]:
+                time.sleep(min(1e-3, max(0.0, arr[j] - (time.perf_counter() - t0))))
             c = int(ctrl_of[r])
             X0, ref, sd = inputs(c, int(step_of[r]))
             sub.append((c, time.perf_counter() - t0, srv.submit(ids[c], X0, ref, sd)))
@@ -261,7 +263,7 @@ def serve_main(args):
             svc.append(ms - q)
             done.append(ts + 1e-3 * ms)
         span = max(done)
-        return {"solves_per_s": args.requests / span, "p50_ms": float(np.percentile(lat, 50)),
+        return {"solves_per_s": len(reqs) / span, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "service_p50_ms": float(np.percentile(svc, 50)),
                 "service_p99_ms": float(np.percentile(svc, 99)), "makespan_s": span}
 
@@ -279,6 +281,8 @@ def serve_main(args):
                                   f"{list(wl.SERVE_GRIDS)}, N {list(wl.SERVE_N)}, H {list(wl.SERVE_H)}, "
                                   f"BF16 rollout, FP64 gain; {args.requests} requests",
                       "hbm_budget_gb": args.hbm_gb, "max_inflight": args.inflight}}
+    # the requests of the controllers below 256x256 (whose solves leave the GPU partly idle)
+    small = [r for r in range(args.requests) if probs[int(ctrl_of[r])].preset.n < 256]
     with oic.Server(budget, max_inflight=args.inflight) as srv:
         ids = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in probs]
         warm(srv, ids)
@@ -286,10 +290,24 @@ def serve_main(args):
         offered = run(srv, ids, args.rate, 1)
         sustain_rate = 0.7 * cap["solves_per_s"]
         sustained = run(srv, ids, sustain_rate, 2)
+        small_cap = run(srv, ids, None, 3, small)
         st = srv.stats()
     out.update({"value": cap["solves_per_s"], "capacity": cap,
                 "offered": dict(offered, rate=args.rate),
-                "sustainable": dict(sustained, rate=sustain_rate), "server": st})
+                "sustainable": dict(sustained, rate=sustain_rate),
+                "small_grids_capacity": dict(small_cap, requests=len(small)), "server": st})
+    # the same server with one slot per pack: every request its own solve, requests overlapping
+    # only as concurrent streams (no shared launches)
+    print("[serve] one slot per pack (no grouped solves)", file=sys.stderr, flush=True)
+    with oic.Server(budget, max_inflight=args.inflight, group_slots=1) as srv:
+        ids = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in probs]
+        warm(srv, ids)
+        ung_cap = run(srv, ids, None, 0)
+        ung_small = run(srv, ids, None, 3, small)
+    out["one_slot_per_pack"] = {"capacity": ung_cap, "small_grids_capacity": ung_small,
+                                "grouped_over_one_slot": cap["solves_per_s"] / ung_cap["solves_per_s"],
+                                "small_grids_grouped_over_one_slot":
+                                    small_cap["solves_per_s"] / ung_small["solves_per_s"]}
     # each distinct (grid, N, H) solved alone on a resident controller (graph warm), summed
     # over the request list: the GPU time the requests need without any overlap
     print("[serve] solo solve times per shape", file=sys.stderr, flush=True)

@@ -294,20 +294,27 @@ const char* oic_group_last_error(oic_group_handle g);
 
 /* ---- Serving: one request loop for many independent controllers ----
  *
- * A server owns a set of controllers, each a handle of its own (own stream,
- * device-resident ensemble buffers, captured solve graph, applied-control state
- * U_prev carried from solve to solve).  Requests (one MPC solve each) are
- * admitted continuously: a pool of max_inflight worker threads runs the oldest
- * request whose controller is idle and whose device footprint fits the HBM
- * budget, evicting least-recently-used idle controllers (keeping their U_prev on
- * the host) to make room, or taking over the handle of an idle controller of the same
- * shape; otherwise the request waits.  Solves of different
- * controllers overlap on the device; solves of one controller run in submission
- * order.  Each result is the same as the controller's solve alone.  All array
- * arguments are HOST pointers, copied before the call returns. */
+ * A server owns a set of controllers.  Controllers of one shape (grid, control rows,
+ * layer widths, activation, precision, N, horizon) are resident in the slots of packs,
+ * each pack a group (see above) with its device-resident ensemble buffers, captured
+ * grouped solve and every slot's applied-control state U_prev, carried from solve to
+ * solve.  Requests (one MPC solve each) are admitted and batched continuously: a pool
+ * of max_inflight worker threads takes the oldest request whose controller can run
+ * (resident in a pack that is not solving, or placeable in a free slot, in the slot of
+ * an idle controller of its shape, or in a new pack whose footprint fits the HBM
+ * budget after evicting least-recently-used idle packs; U_prev of a controller that
+ * leaves its slot is kept on the host), then adds the oldest queued requests of other
+ * controllers that the pack can take, up to its slot count, and runs them as one
+ * grouped solve.  Otherwise the request waits.  Packs solve concurrently; solves of one
+ * controller run in submission order.  A pack has several slots where one solve of its
+ * shape leaves the GPU idle (BF16 rollout, fewer than about 2^22 pixels x members),
+ * no more than the controllers of the shape and the budget allow.  Each result is the
+ * same as the controller's solve alone.  All array arguments are HOST pointers,
+ * copied before the call returns. */
 typedef struct oic_server* oic_server_handle;
 
-/* Device bytes a handle created with cfg holds (the admission footprint). */
+/* Device bytes the server holds for a controller of cfg alone in its pack (the smallest
+ * admission footprint; a pack of k slots holds oic_group_footprint_bytes(cfg, k)). */
 size_t oic_footprint_bytes(const oic_config* cfg);
 
 /* hbm_budget_bytes: device bytes the server may hold for controller buffers.
@@ -316,6 +323,11 @@ int oic_server_create(size_t hbm_budget_bytes, int max_inflight, oic_server_hand
 
 /* Stops the workers (after their current solves) and frees every controller. NULL-safe. */
 void oic_server_destroy(oic_server_handle s);
+
+/* Largest slot count of a pack (1..OIC_MAX_GROUP_SLOTS, default 8; 1: every controller
+ * solves on its own, concurrently with the others).  Only before the first request:
+ * OIC_EINVAL afterwards. */
+int oic_server_set_group_slots(oic_server_handle s, int max_slots);
 
 /* Register a controller: cfg as for oic_create (mem_mode must be OIC_MEM_HOST;
  * max_N, max_H and stream are ignored), surrogate as for oic_set_weights, and the
@@ -337,12 +349,17 @@ int oic_server_submit(oic_server_handle s, int controller_id, const float* X0, c
 int oic_server_wait(oic_server_handle s, long long ticket, float* U_out, float* X_out,
                     double* latency_ms, double* queue_ms);
 
-/* Counters: completed solves, controller admissions and evictions, admissions that
- * took over the handle of an evicted controller of the same shape (weights and U_prev
- * swapped in place, no device allocation), device bytes held now and at peak. Any
- * pointer may be NULL. */
+/* Counters: completed solves, controller admissions into a slot and evictions from one,
+ * admissions that took over the slot of an idle controller of the same shape (weights
+ * and U_prev swapped in place, no device allocation), device bytes held now and at
+ * peak. Any pointer may be NULL. */
 int oic_server_stats(oic_server_handle s, long long* completed, long long* admissions,
                      long long* evictions, long long* recycled, size_t* bytes_in_use, size_t* peak_bytes);
+
+/* Batching counters: batches run (grouped solves, one or more requests each), requests
+ * solved in batches of two or more, and packs created.  Any pointer may be NULL. */
+int oic_server_batch_stats(oic_server_handle s, long long* batches, long long* grouped_solves,
+                           long long* packs_created);
 
 /* Reason for the last failed oic_server_wait. */
 const char* oic_server_last_error(oic_server_handle s);

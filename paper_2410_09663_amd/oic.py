@@ -126,6 +126,9 @@ def lib():
                                       ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
             "oic_server_last_error": (ctypes.c_char_p, [vp]),
+            "oic_server_set_group_slots": (ci, [vp, ci]),
+            "oic_server_batch_stats": (ci, [vp, ctypes.POINTER(ctypes.c_longlong),
+                                            ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
             "oic_footprint_bytes": (cs, [ctypes.POINTER(oic_config)]),
             "oic_stage_cost": (ci, [ci, ci, ci, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]),
             "oic_group_footprint_bytes": (cs, [ctypes.POINTER(oic_config), ci]),
@@ -160,7 +163,8 @@ EXPORTED = ["oic_create", "oic_destroy", "oic_last_error", "oic_set_weights", "o
             "oic_set_graph", "oic_server_create", "oic_server_destroy", "oic_server_add",
             "oic_server_submit", "oic_server_wait", "oic_server_stats", "oic_server_last_error",
             "oic_footprint_bytes", "oic_stage_cost", "oic_group_footprint_bytes", "oic_group_create",
-            "oic_group_destroy", "oic_group_slot", "oic_group_solve", "oic_group_last_error"]
+            "oic_group_destroy", "oic_group_slot", "oic_group_solve", "oic_group_last_error",
+            "oic_server_set_group_slots", "oic_server_batch_stats"]
 
 
 def _is_torch(x) -> bool:
@@ -576,7 +580,7 @@ def columns_project(U, T):
 class Server:
     """Request loop for many controllers (oic_server_*): host NumPy arrays in and out."""
 
-    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4):
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, group_slots: Optional[int] = None):
         self._s = None
         h = ctypes.c_void_p()
         rc = lib().oic_server_create(int(hbm_budget_bytes), int(max_inflight), ctypes.byref(h))
@@ -584,6 +588,10 @@ class Server:
             raise OicError(rc, "oic_server_create failed")
         self._s = h
         self._shapes = {}
+        if group_slots is not None:
+            rc = lib().oic_server_set_group_slots(h, int(group_slots))
+            if rc != OIC_OK:
+                raise OicError(rc, "oic_server_set_group_slots failed")
 
     @staticmethod
     def config_for(problem, N: int, H: int, precision: int = None) -> oic_config:
@@ -650,8 +658,11 @@ class Server:
         u, pk = ctypes.c_size_t(), ctypes.c_size_t()
         lib().oic_server_stats(self._s, ctypes.byref(c), ctypes.byref(a), ctypes.byref(e), ctypes.byref(r),
                                ctypes.byref(u), ctypes.byref(pk))
+        b, g, n = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        lib().oic_server_batch_stats(self._s, ctypes.byref(b), ctypes.byref(g), ctypes.byref(n))
         return {"completed": c.value, "admissions": a.value, "evictions": e.value, "recycled": r.value,
-                "bytes_in_use": u.value, "peak_bytes": pk.value}
+                "bytes_in_use": u.value, "peak_bytes": pk.value, "batches": b.value, "grouped": g.value,
+                "packs": n.value}
 
     def close(self):
         if self._s is not None:

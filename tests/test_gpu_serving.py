@@ -151,3 +151,60 @@ def test_same_shape_admission_takes_over_the_handle(shape):
     assert st["completed"] == len(reqs)
     assert st["admissions"] == len(reqs) and st["recycled"] == len(reqs) - 1
     assert st["peak_bytes"] == fp
+
+
+def _alone(problems, reqs):
+    """Each controller's results from a server that holds only it (one slot, its own
+    solves), in the order its requests appear in reqs."""
+    alone = {}
+    for cid, pr in enumerate(problems):
+        with oic.Server(hbm_budget_bytes=64 << 30, max_inflight=1) as srv:
+            sid = srv.add(pr, pr.preset.N, pr.preset.H)
+            for (c, X0, ref, seed) in reqs:
+                if c == cid:
+                    alone[(c, seed)] = srv.wait(sid, srv.submit(sid, X0, ref, seed))[:2]
+    return alone
+
+
+def test_same_shape_requests_run_as_grouped_batches():
+    """Four BF16 controllers of one small shape, all requests submitted at once: the server
+    puts them in one pack of four slots and solves queued requests of its controllers
+    together (one launch per kernel for the batch).  Each result is bitwise the
+    controller's solve alone."""
+    base = wl.small_preset(n=32, m=32, l=8, channels=(2, 16, 16, 1), N=32, H=3)
+    base = dataclasses.replace(base, precision=wl.PREC_BF16)
+    problems = [wl.make_problem(dataclasses.replace(base, name=f"g{k}", seed_W=61 + k, seed_B=71 + k,
+                                                    seed_X0=81 + k)) for k in range(4)]
+    reqs = _requests(problems, steps=3)
+    alone = _alone(problems, reqs)
+    with oic.Server(hbm_budget_bytes=8 << 30, max_inflight=2, group_slots=4) as srv:
+        ids = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in problems]
+        tickets = [(c, seed, srv.submit(ids[c], X0, ref, seed)) for (c, X0, ref, seed) in reqs]
+        for c, seed, t in tickets:
+            U, X, _, _ = srv.wait(ids[c], t)
+            assert np.array_equal(U, alone[(c, seed)][0]), (c, seed)
+            assert np.array_equal(X, alone[(c, seed)][1]), (c, seed)
+        st = srv.stats()
+    print("grouped serving stats", st, flush=True)
+    assert st["completed"] == len(reqs)
+    assert st["packs"] == 1 and st["grouped"] >= len(problems)
+    assert st["batches"] < len(reqs)
+
+
+def test_serving_mix_results_identical_alone_and_in_the_mix():
+    """Sixteen controllers drawn from the serving mix at full size (grids 32..256, N 64..256,
+    H 5..20, BF16; shapes that repeat share packs), two requests each, all submitted at
+    once with four workers: each result is bitwise the controller's solve alone."""
+    problems = [wl.make_problem(p) for p in wl.serving_mix(16, seed=10)]
+    reqs = _requests(problems, steps=2)
+    alone = _alone(problems, reqs)
+    with oic.Server(hbm_budget_bytes=96 << 30, max_inflight=4) as srv:
+        ids = [srv.add(pr, pr.preset.N, pr.preset.H) for pr in problems]
+        tickets = [(c, seed, srv.submit(ids[c], X0, ref, seed)) for (c, X0, ref, seed) in reqs]
+        for c, seed, t in tickets:
+            U, X, _, _ = srv.wait(ids[c], t)
+            assert np.array_equal(U, alone[(c, seed)][0]), (c, seed)
+            assert np.array_equal(X, alone[(c, seed)][1]), (c, seed)
+        st = srv.stats()
+    print("serving mix stats", st, flush=True)
+    assert st["completed"] == len(reqs) and st["grouped"] > 0
