@@ -56,6 +56,41 @@ def test_host_side_validation_needs_no_device():
 
 
 @pytest.mark.skipif(not os.path.exists(oic.LIB_PATH), reason="liboic.so not built")
+def test_group_and_server_argument_checks_need_no_device():
+    """Groups: slot counts outside 1..OIC_MAX_GROUP_SLOTS and several slots of a configuration
+    without grouped kernels (FP32) are rejected before any device call; the footprint of a
+    group is its slab times the slots; NULL handles are safe.  Server: the pack size is
+    checked and fixed once requests have started."""
+    L = oic.lib()
+    cfg = oic.oic_config()
+    cfg.n, cfg.m, cfg.l, cfg.n_layers = 32, 32, 8, 3
+    for k, c in enumerate((2, 16, 16, 1)):
+        cfg.channels[k] = c
+    cfg.activation, cfg.max_N, cfg.max_H = oic.OIC_ACT_TANH, 32, 3
+    g = ctypes.c_void_p()
+    cfg.precision = oic.OIC_PREC_BF16
+    assert L.oic_group_create(ctypes.byref(cfg), 0, ctypes.byref(g)) == oic.OIC_EINVAL
+    assert L.oic_group_create(ctypes.byref(cfg), 65, ctypes.byref(g)) == oic.OIC_EINVAL
+    cfg.precision = oic.OIC_PREC_FP32
+    assert L.oic_group_create(ctypes.byref(cfg), 2, ctypes.byref(g)) == oic.OIC_EINVAL
+    cfg.precision = oic.OIC_PREC_BF16
+    one = L.oic_group_footprint_bytes(ctypes.byref(cfg), 1)
+    four = L.oic_group_footprint_bytes(ctypes.byref(cfg), 4)
+    assert one > 0 and four - 4096 == 4 * (one - 4096) and (one - 4096) % (2 << 20) == 0
+    assert L.oic_footprint_bytes(ctypes.byref(cfg)) == one
+    L.oic_group_destroy(None)
+    assert L.oic_group_slot(None, 0) is None
+    assert L.oic_group_solve(None, 1, None, None, None) == oic.OIC_EINVAL
+    assert L.oic_group_last_error(None) == b"NULL group"
+    with oic.Server(1 << 30, max_inflight=1) as srv:
+        assert L.oic_server_set_group_slots(srv._s, 0) == oic.OIC_EINVAL
+        assert L.oic_server_set_group_slots(srv._s, 65) == oic.OIC_EINVAL
+        assert L.oic_server_set_group_slots(srv._s, 4) == oic.OIC_OK
+        st = srv.stats()
+        assert st["batches"] == 0 and st["packs"] == 0
+
+
+@pytest.mark.skipif(not os.path.exists(oic.LIB_PATH), reason="liboic.so not built")
 def test_stage_cost_matches_oracle_trace_form():
     """Host-side cost of the library vs the oracle's trace form (no device call)."""
     import numpy as np
