@@ -365,14 +365,15 @@ void worker(oic_server* s) {
     std::vector<int> rcs(count, rc);
     std::vector<Result> res(count);
     std::string err = rc == OIC_OK ? "" : "controller does not fit the HBM budget";
+    // evicted packs: save their residents' U_prev, free them; controllers that lose their
+    // slot to the batch: save their U_prev before the slot is loaded
+    for (auto& ep : plan.evicted) {
+      for (int k = 0; k < ep->slots; ++k)
+        if (Controller* o = ep->holder[k]) save_u_prev(o, oic_group_slot(ep->g, k));
+      oic_group_destroy(ep->g);
+    }
+    for (auto& d : plan.displaced) save_u_prev(d.first, d.second);
     if (rc == OIC_OK) {
-      // evicted packs: save their residents' U_prev, free them
-      for (auto& ep : plan.evicted) {
-        for (int k = 0; k < ep->slots; ++k)
-          if (Controller* o = ep->holder[k]) save_u_prev(o, oic_group_slot(ep->g, k));
-        oic_group_destroy(ep->g);
-      }
-      for (auto& d : plan.displaced) save_u_prev(d.first, d.second);
       if (plan.create) {
         oic_group_handle g = nullptr;
         rc = oic_group_create(&pk->cfg, pk->slots, &g);
