@@ -55,11 +55,16 @@ def algorithmic_work(p, H, precision="fp32"):
     L = len(p.channels) - 1
     folded = last_layer_folded(p, precision)
     px = n * m * N
+    # a 64-channel first layer takes its lift channel B U precomputed: the lift reads U and
+    # writes B U, the layer reads X and B U
+    lifted = L > 1 and p.channels[1] >= 64
     for t in range(1, H + 1):
+        if lifted:
+            add("lift", 2.0 * l * px, 4.0 * (l * m * N + px))
         Ma = (t + 1) * rr
         for k, (ci, co) in enumerate(zip(p.channels[:-1], p.channels[1:])):
             cls = "conv_first" if k == 0 else ("conv_last" if k == L - 1 else "conv_mid")
-            rd = 4.0 * (n + l) * m * N if k == 0 else ab * ci * px
+            rd = (4.0 * (2 * px if lifted else (n + l) * m * N)) if k == 0 else ab * ci * px
             wr = 4.0 * px if k == L - 1 else ab * co * px
             f = 2.0 * 9 * ci * co * px
             if folded and k == L - 2:
@@ -96,7 +101,8 @@ MATRIX_CLASSES = ("conv_first", "conv_mid", "stats", "gain", "update")
 SOURCE_OF = {"conv_first": "rollout.hip", "conv_mid": "rollout.hip", "conv_last": "rollout.hip",
              "stats": "stats.hip", "stats_reduce": "stats.hip",
              "means": "stats.hip", "chol": "gain.hip", "gain": "gain.hip", "update": "update.hip",
-             "noise": "noise.hip", "assemble": "noise.hip", "observe": "noise.hip", "init": "noise.hip"}
+             "noise": "noise.hip", "assemble": "noise.hip", "observe": "noise.hip", "init": "noise.hip",
+             "lift": "rollout.hip"}
 
 
 def roofline_for(cls, flops, nbytes, ms, launches, precision, tag=None, t_peak=None):
@@ -431,13 +437,13 @@ def run_precision(p, prob, precision, K, W, eager_steps, dev):
     # every class that does matrix work, and the two figures the method's targets name:
     # the whole rollout against the MFMA peak of its precision, the update against HBM
     by_class = {}
-    for cls in ("conv_first", "conv_mid", "conv_last", "stats", "gain", "update"):
+    for cls in ("lift", "conv_first", "conv_mid", "conv_last", "stats", "gain", "update"):
         if cls in per_class and per_class[cls]["flop"] > 0:
             c = per_class[cls]
             r = roofline_for(cls, c["flop"], c["bytes"], c["total_ms"], c["launches"], precision,
                              t_peak=c["t_peak"])
             by_class[cls] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_launch_us")}
-    conv = [per_class[c] for c in ("conv_first", "conv_mid", "conv_last") if c in per_class]
+    conv = [per_class[c] for c in ("lift", "conv_first", "conv_mid", "conv_last") if c in per_class]
     conv_s = sum(c["total_ms"] for c in conv) * 1e-3
     mfma_peak = {"bf16": PEAK["bf16"], "fp8": PEAK["fp8"]}.get(precision, PEAK["fp32"])
     rollout_frac = sum(c["flop"] for c in conv) / conv_s / mfma_peak if conv_s > 0 else None

@@ -509,7 +509,7 @@ int rollout(oic_ctx* h, int batch, FieldRef X, FieldRef U, FieldOut out, Rollout
     // per-layer activation maxima: slot k holds the largest |x| written by layer k
     if (f8) launch_zero_u32(h->stream, timer, amax, L * kAmaxSlots);
     launch_conv_first(h->stream, timer, batch, c.n, c.m, c.l, X, U, h->dB, c.channels[1], h->dW[0],
-                      h->dBias[0], c.activation, act[1], true, f8 ? amax : nullptr, obs);
+                      h->dBias[0], c.activation, act[1], true, act[0], f8 ? amax : nullptr, obs);
     int cur = 1;
     for (int k = 1; k < L - 1; ++k) {
       if (k == L - 2 && h->dWl2 && conv_last_folds_bf16(c.channels[k], c.channels[k + 1]) &&

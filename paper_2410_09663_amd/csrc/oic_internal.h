@@ -193,10 +193,11 @@ void launch_conv(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int c
 // First layer with the lift fused (2 -> cout) and last layer (cin -> 1) on tiles.
 bool conv_first_supported(int cout, int l);
 bool conv_last_supported(int cin);
-// bf16: activations are stored as BF16 (first layer output, last layer input).
+// bf16: activations are stored as BF16 (first layer output, last layer input).  lift:
+// N n m floats that the 64-channel layer uses for its lift channel B U (not read after).
 void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
                        const float* B, int cout, const float* w, const float* bias, int act,
-                       void* out_nhwc, bool bf16, unsigned* amax = nullptr,
+                       void* out_nhwc, bool bf16, float* lift, unsigned* amax = nullptr,
                        const ObserveArgs* obs = nullptr);
 void launch_conv_last(hipStream_t s, Timer& t, int N, int n, int m, int cin, const void* in_nhwc,
                       const float* w, const float* bias, FieldOut fo, bool bf16,

@@ -117,12 +117,16 @@ __device__ __forceinline__ void store_act(bf16_t* p, float v) { *p = to_bf16(v);
 // non-negative float orders like the float, so an integer max is exact and the
 // result does not depend on the order of the atomics).
 // The wave's maximum goes to one of the layer's kAmaxSlots slots, chosen by workgroup and
-// wave so that the atomics of a launch spread over all of them.
+// wave so that the atomics of a launch spread over all of them.  A slot only grows during
+// a launch, so a wave whose maximum does not exceed the value it reads there (current or
+// older) has nothing to add and skips its atomic: once the slots hold the layer's typical
+// maxima, few of the hundreds of thousands of waves of a first layer still queue on them.
 __device__ __forceinline__ void amax_publish(float v, unsigned* amax) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
   const unsigned slot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kAmaxSlots;
-  if ((threadIdx.x & 63) == 0) atomicMax(amax + slot, __float_as_uint(v));
+  const unsigned u = __float_as_uint(v);
+  if ((threadIdx.x & 63) == 0 && u > amax[slot]) atomicMax(amax + slot, u);
 }
 
 // The layer's largest |activation|: the maximum over its slots.
@@ -771,18 +775,58 @@ __global__ __launch_bounds__(256) void k_conv_last_sum(int N, int n, int m, cons
   if (obs.Y) obs.Y[y * obs.NM + (long long)i * m + x] = acc + noise_value(obs.vx, y, i, x, m);
 }
 
+// The lift channel of the first layer as a field of its own: bu[i][y][x] = sum_a B[y][a]
+// U_i[a][x], FP32 fused multiply-adds in ascending a from zero (the order k_conv_first
+// uses when it forms the lift itself).  One thread per column, YB rows per block: the
+// thread keeps its column of U in registers, B comes through scalar loads.
+template <int YB>
+__global__ __launch_bounds__(256) void k_lift_bu(int N, int n, int m, int l, FieldRef U, const float* __restrict__ B,
+                                                 float* __restrict__ bu, Grp grp) {
+  OIC_GROUP_ENTER(grp);
+  OIC_GSH(U);
+  OIC_GSH(B);
+  OIC_GSH(bu);
+  constexpr int LMAX = 64;
+  const int yblocks = (n + YB - 1) / YB;
+  const int i = blockIdx.x / yblocks, y0 = (blockIdx.x % yblocks) * YB;
+  const int x = blockIdx.y * 256 + threadIdx.x;
+  if (x >= m) return;
+  // the column of U: every load issued before the first use (the address stops at row
+  // l - 1, whose value the rows past l repeat unused)
+  float u[LMAX];
+  const float* up = U.base + i * U.si + x;
+#pragma unroll
+  for (int a = 0; a < LMAX; ++a) {
+    u[a] = *up;
+    if (a + 1 < l) up += U.sy;
+  }
+  const int y1 = min(n, y0 + YB);
+  for (int y = y0; y < y1; ++y) {
+    const float* brow = B + (size_t)y * l;
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < LMAX; ++a)
+      if (a < l) acc = fmaf(brow[a], u[a], acc);
+    bu[((size_t)i * n + y) * m + x] = acc;
+  }
+}
+
 // First layer with the lift fused: the block stages the 6 x 66 halo of X, the l rows
 // of U over the same columns and the 6 rows of B in LDS (all loads issued before the
 // stores), forms B U per halo cell from LDS, computes 4 x 64 output pixels x COUT
 // channels on the matrix cores (K = 2 channels x 9 taps, padded to 20), and writes the
-// NHWC rows out through LDS so that the global stores are contiguous.
+// NHWC rows out through LDS so that the global stores are contiguous.  With 64 output
+// channels the lift comes precomputed (bu_in, from k_lift_bu) and its 6 x 66 halo is
+// staged like X's: the block then loads neither U nor B, its LDS shrinks from 27 to 8.5
+// KiB and, held to 128 registers, four workgroups share a CU instead of three (at
+// 256 x 256, N = 512: 2.91 -> 2.14 ms per launch in FP32, plus 0.33 ms for the lift).
 template <int COUT, typename TOUT>
-__global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, FieldRef X,
+__global__ __launch_bounds__(256, COUT >= 64 ? 4 : 1) void k_conv_first(int N, int n, int m, int l, FieldRef X,
                                                     FieldRef U, const float* __restrict__ B,
                                                     const float* __restrict__ w,
                                                     const float* __restrict__ bias, int act,
                                                     TOUT* __restrict__ out, unsigned* __restrict__ amax,
-                                                    ObserveArgs obs, Grp grp) {
+                                                    ObserveArgs obs, const float* __restrict__ bu_in, Grp grp) {
   OIC_GROUP_ENTER(grp);
   OIC_GSH(X);
   OIC_GSH(U);
@@ -792,12 +836,14 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   OIC_GSH(out);
   OIC_GSH(amax);
   OIC_GSH(obs);
+  OIC_GSH(bu_in);
   constexpr int TR = 4, TC = 64, HR = TR + 2, HC = TC + 2;
   constexpr int LMAX = 64;
+  constexpr bool BUF = COUT >= 64;  // the lift precomputed
   __shared__ float s_x[HR * HC];
   __shared__ float s_bu[HR * HC];
-  __shared__ float s_u[LMAX * HC];
-  __shared__ float s_b[HR * LMAX];
+  __shared__ float s_u[BUF ? 1 : LMAX * HC];
+  __shared__ float s_b[BUF ? 1 : HR * LMAX];
   __shared__ float s_w[20 * COUT];  // [k = channel*9 + tap, zero-padded to 20][o]
   __shared__ float s_bias[COUT];
   // BF16 output with up to 32 channels leaves as 16-byte stores, so each pixel's channels
@@ -824,31 +870,34 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
   const int ne = obs.U_cur ? (a1 - a0) * TC : 0;
   float pw = 0.f, pv = 0.f;
   {
-    // X halo: 396 cells; U rows: l x 66; B rows: 6 x l  (l <= 64)
+    // X halo: 396 cells; U rows: l x 66; B rows: 6 x l  (l <= 64); or the lift's halo
     constexpr int XS = (HR * HC + 255) / 256;
-    constexpr int US = (LMAX * HC + 255) / 256;
-    float xv[XS], uv[US], bv[2];
+    constexpr int US = BUF ? 1 : (LMAX * HC + 255) / 256;
+    float xv[XS], uv[US], bv[2], qv[XS];
 #pragma unroll
     for (int u = 0; u < XS; ++u) {
       const int e = tid + 256 * u;
       const int yy = e / HC, xx = e % HC;
       const int gy = y0 + yy - 1, gx = x0 + xx - 1;
-      xv[u] = (e < HR * HC && gy >= 0 && gy < n && gx >= 0 && gx < m) ? X.base[i * X.si + gy * X.sy + gx]
-                                                                       : 0.f;
+      const bool in = e < HR * HC && gy >= 0 && gy < n && gx >= 0 && gx < m;
+      xv[u] = in ? X.base[i * X.si + gy * X.sy + gx] : 0.f;
+      if constexpr (BUF) qv[u] = in ? bu_in[((size_t)i * n + gy) * m + gx] : 0.f;
     }
+    if constexpr (!BUF) {
 #pragma unroll
-    for (int u = 0; u < US; ++u) {
-      const int e = tid + 256 * u;
-      const int a = e / HC, xx = e % HC;
-      const int gx = x0 + xx - 1;
-      uv[u] = (a < l && gx >= 0 && gx < m) ? U.base[i * U.si + a * U.sy + gx] : 0.f;
-    }
+      for (int u = 0; u < US; ++u) {
+        const int e = tid + 256 * u;
+        const int a = e / HC, xx = e % HC;
+        const int gx = x0 + xx - 1;
+        uv[u] = (a < l && gx >= 0 && gx < m) ? U.base[i * U.si + a * U.sy + gx] : 0.f;
+      }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int e = tid + 256 * u;
-      const int yy = e / LMAX, a = e % LMAX;
-      const int gy = y0 + yy - 1;
-      bv[u] = (yy < HR && a < l && gy >= 0 && gy < n) ? B[(size_t)gy * l + a] : 0.f;
+      for (int u = 0; u < 2; ++u) {
+        const int e = tid + 256 * u;
+        const int yy = e / LMAX, a = e % LMAX;
+        const int gy = y0 + yy - 1;
+        bv[u] = (yy < HR && a < l && gy >= 0 && gy < n) ? B[(size_t)gy * l + a] : 0.f;
+      }
     }
     constexpr int WS = (20 * COUT + 255) / 256;
     float wv[WS];
@@ -880,29 +929,36 @@ __global__ __launch_bounds__(256) void k_conv_first(int N, int n, int m, int l, 
     if (tid < COUT) s_bias[tid] = bias_v;
 #pragma unroll
     for (int u = 0; u < XS; ++u)
-      if (tid + 256 * u < HR * HC) s_x[tid + 256 * u] = xv[u];
+      if (tid + 256 * u < HR * HC) {
+        s_x[tid + 256 * u] = xv[u];
+        if constexpr (BUF) s_bu[tid + 256 * u] = qv[u];
+      }
+    if constexpr (!BUF) {
 #pragma unroll
-    for (int u = 0; u < US; ++u)
-      if (tid + 256 * u < LMAX * HC) s_u[tid + 256 * u] = uv[u];
+      for (int u = 0; u < US; ++u)
+        if (tid + 256 * u < LMAX * HC) s_u[tid + 256 * u] = uv[u];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (tid + 256 * u < HR * LMAX) s_b[tid + 256 * u] = bv[u];
+      for (int u = 0; u < 2; ++u)
+        if (tid + 256 * u < HR * LMAX) s_b[tid + 256 * u] = bv[u];
+    }
   }
   __syncthreads();
-  for (int e = tid; e < HR * HC; e += 256) {
-    const int yy = e / HC, xx = e % HC;
-    float bu = 0.f;
-    for (int a = 0; a < l; ++a) bu = fmaf(s_b[yy * LMAX + a], s_u[a * HC + xx], bu);
-    s_bu[e] = bu;
+  if constexpr (!BUF) {
+    for (int e = tid; e < HR * HC; e += 256) {
+      const int yy = e / HC, xx = e % HC;
+      float bu = 0.f;
+      for (int a = 0; a < l; ++a) bu = fmaf(s_b[yy * LMAX + a], s_u[a * HC + xx], bu);
+      s_bu[e] = bu;
+    }
   }
-  // the U rows of the new slice and their observations, once per column tile (row tile 0)
   // the U rows of the new slice and their observations: the l rows of this column tile
   // are shared out over its row tiles; the first 256 noise pairs were requested with the halo
   for (int e = tid; e < ne; e += 256) {
     const int a = a0 + e / TC, xx = e % TC, x = x0 + xx;
     if (x < m) {
       const long long col = (long long)i * m + x;
-      const float u = s_u[a * HC + xx + 1] + (e < 256 ? pw : noise_value(obs.w, a, i, x, m));
+      const float uprev = BUF ? U.base[i * U.si + a * U.sy + x] : s_u[a * HC + xx + 1];
+      const float u = uprev + (e < 256 ? pw : noise_value(obs.w, a, i, x, m));
       obs.U_cur[a * obs.NM + col] = u;
       obs.Y[(n + a) * obs.NM + col] = u + (e < 256 ? pv : noise_value(obs.vu, a, i, x, m));
     }
@@ -1313,18 +1369,22 @@ __global__ __launch_bounds__(256 * WG) void k_conv_mfma_bf16(int N, int n, int m
 // (fold_last_epilogue); otherwise the BF16 outputs leave straight from the accumulators.
 // Lane layout (16x16x32): A[i][k] for k = 8g..8g+7 from lane i + 16g, B[k][j] likewise
 // from lane j + 16g, element r of lane j + 16g holds D[4g + r][j].
-template <int CIN, int COUT, int TR, bool LASTQ>
+// GROUPED: the instance for grouped launches (the plain one leaves the group argument
+// alone, so that its code is exactly the single-solve kernel's).
+template <int CIN, int COUT, int TR, bool LASTQ, bool GROUPED>
 __global__ __launch_bounds__(256, 2) void k_conv_bf16r(int N, int n, int m, const bf16_t* __restrict__ in,
                                                        const bf16_t* __restrict__ wt,
                                                        const float* __restrict__ bias, int act,
                                                        bf16_t* __restrict__ out, const bf16_t* __restrict__ wl2,
                                                        Grp grp) {
-  OIC_GROUP_ENTER(grp);
-  OIC_GSH(in);
-  OIC_GSH(wt);
-  OIC_GSH(bias);
-  OIC_GSH(out);
-  OIC_GSH(wl2);
+  if constexpr (GROUPED) {
+    OIC_GROUP_ENTER(grp);
+    OIC_GSH(in);
+    OIC_GSH(wt);
+    OIC_GSH(bias);
+    OIC_GSH(out);
+    OIC_GSH(wl2);
+  }
   static_assert(CIN % 32 == 0 && COUT % 32 == 0, "32-channel K steps and channel groups");
   constexpr int TC = 64, HR = TR + 2, HC = TC + 2;
   constexpr int NG = COUT / 32;          // channel groups (one per wave of a row group)
@@ -1723,17 +1783,23 @@ bool conv_last_supported(int cin) { return cin == 8 || cin == 16 || cin == 32 ||
 
 void launch_conv_first(hipStream_t s, Timer& t, int N, int n, int m, int l, FieldRef X, FieldRef U,
                        const float* B, int cout, const float* w, const float* bias, int act,
-                       void* out_nhwc, bool bf16, unsigned* amax, const ObserveArgs* obs) {
+                       void* out_nhwc, bool bf16, float* lift, unsigned* amax, const ObserveArgs* obs) {
   const unsigned blocks = (unsigned)((long long)N * ((n + 3) / 4) * ((m + 63) / 64));
   const ObserveArgs oa = obs ? *obs : ObserveArgs{};
+  if (cout >= 64) {  // the lift as a field of its own first (k_conv_first reads its halo)
+    constexpr int YB = 16;
+    OIC_GLAUNCH(t, KC_LIFT, s, k_lift_bu<YB>, dim3((unsigned)((long long)N * ((n + YB - 1) / YB)),
+                                                   (unsigned)((m + 255) / 256)),
+                dim3(256), 0, N, n, m, l, U, B, lift);
+  }
 #define OIC_FIRST_CASE(CO)                                                                        \
   if (cout == CO) {                                                                               \
     if (bf16)                                                                                     \
       OIC_GLAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, bf16_t>), dim3(blocks), dim3(256), 0, N, n, \
-                 m, l, X, U, B, w, bias, act, (bf16_t*)out_nhwc, amax, oa);                       \
+                 m, l, X, U, B, w, bias, act, (bf16_t*)out_nhwc, amax, oa, (const float*)lift);   \
     else                                                                                          \
       OIC_GLAUNCH(t, KC_CONV_FIRST, s, (k_conv_first<CO, float>), dim3(blocks), dim3(256), 0, N, n,  \
-                 m, l, X, U, B, w, bias, act, (float*)out_nhwc, amax, oa);                        \
+                 m, l, X, U, B, w, bias, act, (float*)out_nhwc, amax, oa, (const float*)lift);    \
     return;                                                                                       \
   }
   OIC_FIRST_CASE(8)
@@ -1797,8 +1863,12 @@ void launch_bf16r(hipStream_t s, Timer& t, int kclass, int N, int n, int m, cons
   const long long tiles = (long long)N * ((n + TRV - 1) / TRV) * ((m + 63) / 64);
   const long long cap = 2LL * 256;
   const unsigned blocks = (unsigned)(tiles < cap ? tiles : cap);
-  OIC_GLAUNCH(t, kclass, s, (k_conv_bf16r<CI, CO, TRV, LASTQ>), dim3(blocks), dim3(256), 0, N, n, m,
-             (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out, (const bf16_t*)wl2);
+  if (launch_group().slots > 1)
+    OIC_GLAUNCH(t, kclass, s, (k_conv_bf16r<CI, CO, TRV, LASTQ, true>), dim3(blocks), dim3(256), 0, N, n, m,
+                (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out, (const bf16_t*)wl2);
+  else
+    OIC_GLAUNCH(t, kclass, s, (k_conv_bf16r<CI, CO, TRV, LASTQ, false>), dim3(blocks), dim3(256), 0, N, n, m,
+                (const bf16_t*)in_nhwc, (const bf16_t*)wt, bias, act, (bf16_t*)out, (const bf16_t*)wl2);
 }
 
 void launch_conv_mfma_bf16(hipStream_t s, Timer& t, int kclass, int N, int n, int m, int cin, int cout,
@@ -2015,7 +2085,7 @@ int rollout_fp32(hipStream_t s, Timer& t, const oic_config& c, const Fp32Net& ne
   if (L > 1 && conv_first_supported(c.channels[1], c.l)) {
     // lift fused into the first layer
     launch_conv_first(s, t, batch, c.n, c.m, c.l, X, U, net.B, c.channels[1], net.W[0], net.bias[0],
-                      c.activation, act[1], false, nullptr, obs);
+                      c.activation, act[1], false, act[0], nullptr, obs);
     if (obs && obs->U_cur) done |= ROLL_U_ASSEMBLED;
     cur = 1;
     k0 = 1;

@@ -46,6 +46,25 @@ def test_folded_last_layer_keeps_the_network_flops():
     assert b == pytest.approx(4.0 * 10 * px)
 
 
+def test_precomputed_lift_moves_its_bytes_and_flops():
+    """A 64-channel first layer reads X and the precomputed lift channel B U; the lift
+    class reads U and writes B U and does the l multiply-adds per pixel.  Narrower first
+    layers form the lift themselves and read X and U."""
+    p = wl.PRESETS["C4"]
+    px = p.n * p.m * p.N
+    work = bench.algorithmic_work(p, 1, "fp32")
+    f, b = work["lift"]
+    assert f == pytest.approx(2.0 * p.l * px)
+    assert b == pytest.approx(4.0 * (p.l * p.m * p.N + px))
+    _, bf = work["conv_first"]
+    assert bf == pytest.approx(4.0 * 2 * px + 4.0 * 64 * px)
+    q = wl.PRESETS["C2"]
+    work = bench.algorithmic_work(q, 1, "fp32")
+    assert "lift" not in work
+    _, bq = work["conv_first"]
+    assert bq == pytest.approx(4.0 * (q.n + q.l) * q.m * q.N + 4.0 * 16 * q.n * q.m * q.N)
+
+
 def test_statistics_peak_lies_between_the_two_matrix_core_peaks():
     p = wl.PRESETS["C2"]
     for prec, lo, hi in (("fp32", bench.PEAK["fp64"], bench.PEAK["fp32"]),
