@@ -138,3 +138,47 @@ def test_group_rejects_configurations_without_grouped_kernels():
             c.set_weights(prob.B, prob.weights)
             Uc, Xc = c.solve_ex(**req)
         assert np.array_equal(U, Uc) and np.array_equal(X, Xc)
+
+
+def test_new_weights_in_a_slot_reach_the_captured_grouped_solve():
+    """The captured grouped solve holds buffer addresses, not contents: after new weights
+    (and a bias switched on) are copied into a slot, the next batch uses them, bitwise as
+    the slot's own solve with the new weights."""
+    p = FAMILIES["c32"]
+    probs = _problems(p, 3)
+    with oic.Group(p.n, p.m, p.l, p.channels, p.activation, p.N, p.H, 2) as grp:
+        for i in range(2):
+            grp.slots[i].set_weights(probs[i].B, probs[i].weights)
+        reqs = [_request(probs[i], i) for i in range(2)]
+        grp.solve([(0, reqs[0]), (1, reqs[1])])  # captures the grouped solve
+        grp.slots[1].set_weights(probs[2].B, probs[2].weights, _biases(probs[2], 9))
+        alone = grp.slots[1].solve_ex(**reqs[1])
+        outs = grp.solve([(0, reqs[0]), (1, reqs[1])])
+        assert np.array_equal(outs[1][0], alone[0]) and np.array_equal(outs[1][1], alone[1])
+        with oic.Controller(p.n, p.m, p.l, p.channels, p.activation, p.N, p.H,
+                            precision=oic.OIC_PREC_BF16) as c:
+            c.set_weights(probs[2].B, probs[2].weights, _biases(probs[2], 9))
+            U, X = c.solve_ex(**reqs[1])
+        assert np.array_equal(U, alone[0]) and np.array_equal(X, alone[1])
+
+
+def test_device_memory_group_matches_host_memory_group():
+    """A group created for device memory (torch tensors in and out, its work ordered on the
+    caller's stream) gives the host-memory group's results bitwise."""
+    import torch
+    p = FAMILIES["c16_ragged"]
+    probs = _problems(p, 2)
+    reqs = [_request(pr, i) for i, pr in enumerate(probs)]
+    with oic.Group(p.n, p.m, p.l, p.channels, p.activation, p.N, p.H, 2) as grp:
+        for i, pr in enumerate(probs):
+            grp.slots[i].set_weights(pr.B, pr.weights)
+        host = grp.solve([(0, reqs[0]), (1, reqs[1])])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dreqs = [dict(r, X0=dev(r["X0"]), reference=dev(r["reference"]), U_prev=dev(r["U_prev"])) for r in reqs]
+    with oic.Group(p.n, p.m, p.l, p.channels, p.activation, p.N, p.H, 2, mem_mode=oic.OIC_MEM_DEVICE) as grp:
+        for i, pr in enumerate(probs):
+            grp.slots[i].set_weights(pr.B, pr.weights)
+        outs = grp.solve([(0, dreqs[0]), (1, dreqs[1])])
+        torch.cuda.synchronize()
+        for (U, X), (Uh, Xh) in zip(outs, host):
+            assert np.array_equal(U.cpu().numpy(), Uh) and np.array_equal(X.cpu().numpy(), Xh)
