@@ -193,27 +193,45 @@ def cpu_baseline(p, prob, seconds_budget=25.0):
                       f"{el:.1f} s wall"}, first
 
 
-def cpu_baseline_sampled(p, prob, members):
+def cpu_baseline_sampled(p, prob, members, members_one_thread=None):
     """The FP64 oracle on a bounded sample of a workload whose full solve takes the
     oracle minutes: one oracle solve with one horizon step (H = 1: the rollout of every
     sampled member, then one analysis of the two stored slices) on the full grid and CNN
     with `members` of the N members, i.e. `members` member-steps of the same per-member
     work; member-steps/s = members / wall time.  The analysis's share of a member-step
     grows with the stored slices (j = 2 here, up to H + 1 in a full solve), which this
-    sample does not include."""
+    sample does not include.  Beside it the same sample with `members_one_thread` members
+    (default: the fewest whose pooled covariance can be positive definite, at least 3) on
+    one BLAS thread."""
     from oracle import enks, philox
     from paper_2410_09663_amd import workloads as wl
     threads = _blas_threads()
-    z = philox.solve_noise(p.noise_seed_base, p.n, p.m, p.l, members, 1)
-    t0 = time.perf_counter()
-    enks.solve(prob.B, prob.weights, p.activation, prob.X0, wl.reference_window(p, 0, 1), prob.Q, prob.Q,
-               prob.R, members, 1, *z)
-    el = time.perf_counter() - t0
-    return {"value": members / el, "unit": "member-steps/s", "cores": int(threads), "kind": "oracle",
-            "solves_per_s": members / el / (p.N * p.H),
-            "sample": f"one FP64 NumPy oracle solve with H = 1 and {members} of the {p.N} members on the "
-                      f"full {p.n}x{p.m} grid and CNN ({members} member-steps, one analysis at j = 2), "
-                      f"{el:.1f} s wall; solves/s scaled by N H = {p.N * p.H}"}
+    if members_one_thread is None:
+        members_one_thread = max(3, -(-(p.n + p.l) // p.m) + 1)
+
+    def timed(k):
+        z = philox.solve_noise(p.noise_seed_base, p.n, p.m, p.l, k, 1)
+        t0 = time.perf_counter()
+        enks.solve(prob.B, prob.weights, p.activation, prob.X0, wl.reference_window(p, 0, 1), prob.Q, prob.Q,
+                   prob.R, k, 1, *z)
+        return time.perf_counter() - t0
+
+    el = timed(members)
+    out = {"value": members / el, "unit": "member-steps/s", "cores": int(threads), "kind": "oracle",
+           "solves_per_s": members / el / (p.N * p.H),
+           "sample": f"one FP64 NumPy oracle solve with H = 1 and {members} of the {p.N} members on the "
+                     f"full {p.n}x{p.m} grid and CNN ({members} member-steps, one analysis at j = 2), "
+                     f"{el:.1f} s wall; solves/s scaled by N H = {p.N * p.H}"}
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        return out
+    with threadpool_limits(limits=1):
+        el1 = timed(members_one_thread)
+    out["one_thread"] = {"value": members_one_thread / el1, "unit": "member-steps/s", "cores": 1,
+                         "sample": f"the same with {members_one_thread} members on one BLAS thread, "
+                                   f"{el1:.1f} s wall"}
+    return out
 
 
 def serve_main(args):
