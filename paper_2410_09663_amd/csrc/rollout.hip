@@ -778,7 +778,8 @@ __global__ __launch_bounds__(256) void k_conv_last_sum(int N, int n, int m, cons
 // The lift channel of the first layer as a field of its own: bu[i][y][x] = sum_a B[y][a]
 // U_i[a][x], FP32 fused multiply-adds in ascending a from zero (the order k_conv_first
 // uses when it forms the lift itself).  One thread per column, YB rows per block: the
-// thread keeps its column of U in registers, B comes through scalar loads.
+// thread keeps its column of U in registers; the block's YB rows of B sit in LDS (zero
+// past l), read as broadcasts.
 template <int YB>
 __global__ __launch_bounds__(256) void k_lift_bu(int N, int n, int m, int l, FieldRef U, const float* __restrict__ B,
                                                  float* __restrict__ bu, Grp grp) {
@@ -787,8 +788,15 @@ __global__ __launch_bounds__(256) void k_lift_bu(int N, int n, int m, int l, Fie
   OIC_GSH(B);
   OIC_GSH(bu);
   constexpr int LMAX = 64;
+  __shared__ __attribute__((aligned(16))) float s_b[YB][LMAX];
   const int yblocks = (n + YB - 1) / YB;
   const int i = blockIdx.x / yblocks, y0 = (blockIdx.x % yblocks) * YB;
+  const int y1 = min(n, y0 + YB);
+  for (int e = threadIdx.x; e < YB * LMAX; e += 256) {
+    const int r = e / LMAX, a = e % LMAX;
+    s_b[r][a] = (y0 + r < y1 && a < l) ? B[(size_t)(y0 + r) * l + a] : 0.f;
+  }
+  __syncthreads();
   const int x = blockIdx.y * 256 + threadIdx.x;
   if (x >= m) return;
   // the column of U: every load issued before the first use (the address stops at row
@@ -800,13 +808,16 @@ __global__ __launch_bounds__(256) void k_lift_bu(int N, int n, int m, int l, Fie
     u[a] = *up;
     if (a + 1 < l) up += U.sy;
   }
-  const int y1 = min(n, y0 + YB);
   for (int y = y0; y < y1; ++y) {
-    const float* brow = B + (size_t)y * l;
+    const float* brow = s_b[y - y0];
     float acc = 0.f;
 #pragma unroll
-    for (int a = 0; a < LMAX; ++a)
-      if (a < l) acc = fmaf(brow[a], u[a], acc);
+    for (int a = 0; a < LMAX; a += 4) {
+      const f32x4 b4 = *(const f32x4*)(brow + a);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (a + q < l) acc = fmaf(b4[q], u[a + q], acc);
+    }
     bu[((size_t)i * n + y) * m + x] = acc;
   }
 }
@@ -819,7 +830,7 @@ __global__ __launch_bounds__(256) void k_lift_bu(int N, int n, int m, int l, Fie
 // channels the lift comes precomputed (bu_in, from k_lift_bu) and its 6 x 66 halo is
 // staged like X's: the block then loads neither U nor B, its LDS shrinks from 27 to 8.5
 // KiB and, held to 128 registers, four workgroups share a CU instead of three (at
-// 256 x 256, N = 512: 2.91 -> 2.14 ms per launch in FP32, plus 0.33 ms for the lift).
+// 256 x 256, N = 512: 2.91 -> 2.15 ms per launch in FP32, plus 0.15 ms for the lift).
 template <int COUT, typename TOUT>
 __global__ __launch_bounds__(256, COUT >= 64 ? 4 : 1) void k_conv_first(int N, int n, int m, int l, FieldRef X,
                                                     FieldRef U, const float* __restrict__ B,
