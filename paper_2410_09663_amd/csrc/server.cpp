@@ -5,8 +5,10 @@
 // per kernel of a solve (oic_group_solve).  Requests (one MPC solve each: X_k, the
 // reference window and a seed) enter a FIFO queue.  A pool of worker threads takes the
 // oldest request whose controller can run: resident in a pack that is not solving, or
-// placeable (a free slot of a same-shape pack, the slot of an idle controller of that
-// shape, or a new pack whose HBM footprint fits the budget after evicting idle packs).
+// placeable in a free slot of such a pack of its shape (while a solving pack of its shape
+// has a free slot it waits for that pack's next batch), else in a new pack whose HBM
+// footprint fits the budget beside the resident packs, else in the slot of an idle
+// controller of its shape, else in a new pack after evicting idle packs.
 // The worker then adds the oldest queued requests of other controllers of that pack (or
 // that fit its free slots) up to its slot count, and runs them as one grouped solve;
 // requests that arrive meanwhile queue for the next batch.  Packs of different shapes
