@@ -507,6 +507,9 @@ __global__ __launch_bounds__(256 * WGM) void k_conv_mfma_f32p(int N, int n, int 
       for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[rw][mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the matrix-core phase at raised wave priority, as in k_conv_f32r (64 x 64 FP32 solve:
+    // 1.75 -> 1.73 ms; the BF16 and FP8 hidden layers with weights in LDS gain nothing)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll 2
     for (int kb = 0; kb < KD / 4; ++kb) {
       const int k = kb * 4 + lk;
@@ -527,6 +530,7 @@ __global__ __launch_bounds__(256 * WGM) void k_conv_mfma_f32p(int N, int n, int 
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int rw = 0; rw < RPW; ++rw) {
       const int y = y0 + w + NW * rw;
