@@ -802,7 +802,7 @@ int solve_end(oic_ctx* h, const oic_solve_args* a, hipStream_t s, int* flag_host
   return OIC_OK;
 }
 
-// Last stage, after stream s is synchronised: the flag's verdict, and the outputs of a
+// Last stage, after stream s is synchronised: the flag's outcome, and the outputs of a
 // host-memory solve.
 int solve_finish(oic_ctx* h, const oic_solve_args* a, hipStream_t s, int flag) {
   const oic_config& c = h->cfg;
