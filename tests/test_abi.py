@@ -82,6 +82,13 @@ def test_group_and_server_argument_checks_need_no_device():
     assert L.oic_group_slot(None, 0) is None
     assert L.oic_group_solve(None, 1, None, None, None) == oic.OIC_EINVAL
     assert L.oic_group_last_error(None) == b"NULL group"
+    # the binding raises on the same checks
+    with pytest.raises(oic.OicError):
+        oic.Group(32, 32, 8, (2, 16, 16, 1), oic.OIC_ACT_TANH, 32, 3, 0)
+    with pytest.raises(oic.OicError):
+        oic.Group(32, 32, 8, (2, 16, 16, 1), oic.OIC_ACT_TANH, 32, 3, 2, precision=oic.OIC_PREC_FP32)
+    with pytest.raises(oic.OicError):
+        oic.Server(1 << 30, max_inflight=1, group_slots=0)
     with oic.Server(1 << 30, max_inflight=1) as srv:
         assert L.oic_server_set_group_slots(srv._s, 0) == oic.OIC_EINVAL
         assert L.oic_server_set_group_slots(srv._s, 65) == oic.OIC_EINVAL
