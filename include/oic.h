@@ -261,7 +261,9 @@ int oic_columns_project(int l, int m, int q, const float* U, const float* T, flo
  * and a slot without bias for a layer holds a zero bias (identical results).  A group
  * solve and calls on its slots must not overlap.  Several slots per group need
  * precision OIC_PREC_BF16 with a BF16 kernel for every layer (OIC_EINVAL otherwise);
- * one slot takes any configuration. */
+ * one slot takes any configuration.  A batch whose solve would need a kernel without a
+ * grouped form (N*m not a multiple of 4, n + l above 448) fails with OIC_EINVAL and
+ * writes no output; its slots can still solve one at a time. */
 #define OIC_MAX_GROUP_SLOTS 64
 typedef struct oic_group* oic_group_handle;
 
