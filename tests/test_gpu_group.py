@@ -182,3 +182,26 @@ def test_device_memory_group_matches_host_memory_group():
         torch.cuda.synchronize()
         for (U, X), (Uh, Xh) in zip(outs, host):
             assert np.array_equal(U.cpu().numpy(), Uh) and np.array_equal(X.cpu().numpy(), Xh)
+
+
+def test_dense_noise_factors_in_a_batch():
+    """Requests with dense Q and R (their Cholesky factors drive the noise as full
+    triangles) batch together like diagonal ones, bitwise as each slot's own solve; a
+    request whose factor layout differs from the batch's fails alone."""
+    p = FAMILIES["c16_ragged"]
+    probs = _problems(p, 3)
+    dense = [dict(Q=wl.random_spd(p.l, 50 + i, scale=0.05), R=wl.random_spd(p.n, 60 + i, scale=0.005))
+             for i in range(3)]
+    with oic.Group(p.n, p.m, p.l, p.channels, p.activation, p.N, p.H, 3) as grp:
+        for i, pr in enumerate(probs):
+            grp.slots[i].set_weights(pr.B, pr.weights)
+        reqs = [dict(_request(pr, i), **dense[i]) for i, pr in enumerate(probs)]
+        alone = [grp.slots[i].solve_ex(**reqs[i]) for i in range(3)]
+        outs = grp.solve([(i, reqs[i]) for i in range(3)])
+        for i in range(3):
+            assert np.array_equal(outs[i][0], alone[i][0]) and np.array_equal(outs[i][1], alone[i][1]), i
+        # slot 1 back to diagonal factors: the batch takes slot 0's dense layout, slot 1 fails
+        mixed = [reqs[0], _request(probs[1], 1), reqs[2]]
+        with pytest.raises(oic.OicError):
+            grp.solve([(i, mixed[i]) for i in range(3)])
+        assert grp.rc_codes == [0, oic.OIC_EINVAL, 0]
