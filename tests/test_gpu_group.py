@@ -205,3 +205,26 @@ def test_dense_noise_factors_in_a_batch():
         with pytest.raises(oic.OicError):
             grp.solve([(i, mixed[i]) for i in range(3)])
         assert grp.rc_codes == [0, oic.OIC_EINVAL, 0]
+
+
+def test_a_slot_with_a_constraint_fails_alone_and_solves_on_its_own():
+    """A constraint adds an observation row that the grouped kernels do not carry: a slot
+    with one set fails in a batch (the others run), still solves on its own, and joins
+    batches again once the constraint is removed."""
+    p = FAMILIES["c16_ragged"]
+    probs = _problems(p, 2)
+    with oic.Group(p.n, p.m, p.l, p.channels, p.activation, p.N, p.H, 2) as grp:
+        for i, pr in enumerate(probs):
+            grp.slots[i].set_weights(pr.B, pr.weights)
+        reqs = [_request(pr, i) for i, pr in enumerate(probs)]
+        alone = [grp.slots[i].solve_ex(**reqs[i]) for i in range(2)]
+        grp.slots[1].set_constraint(np.full(p.n, 0.1, np.float32), np.full(p.l, 0.2, np.float32), b=1.0)
+        with pytest.raises(oic.OicError):
+            grp.solve([(0, reqs[0]), (1, reqs[1])])
+        assert grp.rc_codes == [0, oic.OIC_EINVAL]
+        constrained = grp.slots[1].solve_ex(**reqs[1])
+        assert not np.array_equal(constrained[0], alone[1][0])
+        grp.slots[1].set_constraint()
+        outs = grp.solve([(0, reqs[0]), (1, reqs[1])])
+        for i in range(2):
+            assert np.array_equal(outs[i][0], alone[i][0]) and np.array_equal(outs[i][1], alone[i][1]), i
