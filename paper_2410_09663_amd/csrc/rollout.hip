@@ -995,6 +995,9 @@ __global__ __launch_bounds__(256, COUT >= 64 ? 4 : 1) void k_conv_first(int N, i
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the matrix-core phase at raised wave priority, as in k_conv_f32r (256 x 256 FP32
+    // solve: 1410.4 -> 1408.1 ms)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int kb = 0; kb < 5; ++kb) {
       const int kq = kb * 4 + lk;
@@ -1017,6 +1020,7 @@ __global__ __launch_bounds__(256, COUT >= 64 ? 4 : 1) void k_conv_first(int N, i
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[mb][nb], 0, 0, 0);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if constexpr (DIRECT) {
       // wave w owns output row w of the tile; lane (li, lk) holds channels NB li .. NB li + NB-1
       // of pixels 16 mb + 4 lk + r and stores them as one vector (16 B FP32, 8 B BF16)
